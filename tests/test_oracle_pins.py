@@ -1,0 +1,316 @@
+"""Pins of the oracle against what the mathematics and the paper fix.
+
+None of these re-derive the oracle's own formulas: they check textbook
+closed forms, invariants of the continuous problem that the discrete one
+inherits exactly, special cases that reduce to a direct solve, and the worked
+example the paper prints for the DSS cascade.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import basis, element, operators, patches, solver
+from oracle.mesh import Mesh
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def graded_mesh(p, n, seed=11):
+    rng = np.random.default_rng(seed)
+    n3 = (n, n, n) if isinstance(n, int) else n
+    w = []
+    for nd in n3:
+        v = rng.uniform(0.5, 1.5, nd)
+        w.append(v / v.sum())
+    return Mesh(p, n3, w)
+
+
+# ---------------------------------------------------------------- 1D rules
+def test_gll_nodes_textbook():
+    np.testing.assert_allclose(basis.gll_nodes(1), [0, 1], atol=0)
+    np.testing.assert_allclose(basis.gll_nodes(2), [0, 0.5, 1], atol=1e-15)
+    s = 1 / math.sqrt(5)
+    np.testing.assert_allclose(basis.gll_nodes(3), [0, (1 - s) / 2, (1 + s) / 2, 1], atol=1e-15)
+    t = math.sqrt(3 / 7)
+    np.testing.assert_allclose(basis.gll_nodes(4), [0, (1 - t) / 2, 0.5, (1 + t) / 2, 1], atol=1e-15)
+    for p in range(2, 8):
+        x = basis.gll_nodes(p)
+        # GLL quadrature (weights from integrating the Lagrange basis) is
+        # exact for polynomials of degree 2p-1.
+        xq, wq = basis.gauss_rule(p + 1)
+        wg = (basis.lagrange_values(x, xq).T * wq).sum(axis=1)
+        for m in range(2 * p):
+            assert abs(wg @ x ** m - 1 / (m + 1)) < 1e-14
+
+
+def test_gauss_rule_exact_to_degree_2n_minus_1():
+    for nq in range(1, 9):
+        x, w = basis.gauss_rule(nq)
+        for m in range(2 * nq):
+            assert abs(w @ x ** m - 1 / (m + 1)) < 1e-14
+        assert abs(w @ x ** (2 * nq) - 1 / (2 * nq + 1)) > 1e-12
+
+
+def test_q2_1d_matrices_closed_form():
+    # textbook P2 element on [0,1] with nodes 0, 1/2, 1
+    M = np.array([[4, 2, -1], [2, 16, 2], [-1, 2, 4]]) / 30
+    K = np.array([[7, -8, 1], [-8, 16, -8], [1, -8, 7]]) / 3
+    np.testing.assert_allclose(basis.mass_1d(2), M, atol=1e-15)
+    np.testing.assert_allclose(basis.stiffness_1d(2), K, atol=1e-14)
+    np.testing.assert_allclose(basis.mass_1d(2).sum(axis=1), [1 / 6, 2 / 3, 1 / 6], atol=1e-15)
+    # the 3D plain-quadrature element on the unit cube is the Kronecker sum
+    # of these textbook matrices (x fastest in the local numbering)
+    A = element.element_stiffness(2, 1.0, 1.0, 1.0)
+    ref = np.kron(np.kron(M, M), K) + np.kron(np.kron(M, K), M) + np.kron(np.kron(K, M), M)
+    np.testing.assert_allclose(A, ref, atol=1e-13)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 7])
+def test_1d_invariants(p):
+    h = 0.37
+    K = basis.stiffness_1d(p, h)
+    M = basis.mass_1d(p, h)
+    np.testing.assert_allclose(K @ np.ones(p + 1), 0, atol=1e-12)
+    assert abs(M.sum() - h) < 1e-14
+    x = basis.gll_nodes(p) * h
+    # stiffness on a linear function: only the end rows see the flux
+    lin = K @ x
+    np.testing.assert_allclose(lin[1:-1], 0, atol=1e-12)
+    np.testing.assert_allclose([lin[0], lin[-1]], [-1, 1], atol=1e-12)
+
+
+@pytest.mark.parametrize("p", [3, 7])
+def test_element_factorisation_identity(p):
+    hx, hy, hz = 0.31, 0.07, 0.55
+    A = element.element_stiffness(p, hx, hy, hz)
+    Kx, Ky, Kz = (basis.stiffness_1d(p, h) for h in (hx, hy, hz))
+    Mx, My, Mz = (basis.mass_1d(p, h) for h in (hx, hy, hz))
+    ref = np.kron(np.kron(Mz, My), Kx) + np.kron(np.kron(Mz, Ky), Mx) + np.kron(np.kron(Kz, My), Mx)
+    np.testing.assert_allclose(A, ref, atol=1e-12 * np.abs(ref).max())
+    # the regrouped form the oracle uses for large meshes
+    Ax, Ay, Az, M3 = element.reference_directional(p)
+    A2 = hy * hz / hx * Ax + hx * hz / hy * Ay + hx * hy / hz * Az
+    np.testing.assert_allclose(A, A2, atol=1e-12 * np.abs(A).max())
+    np.testing.assert_allclose(element.element_mass(p, hx, hy, hz),
+                               np.kron(np.kron(Mz, My), Mx), atol=1e-15)
+    assert np.allclose(A, A.T, atol=1e-13 * np.abs(A).max())
+
+
+# ---------------------------------------------------------- global operator
+@pytest.mark.parametrize("p", [2, 3])
+def test_neumann_null_space(p):
+    m = graded_mesh(p, 4)
+    y = operators.apply_global(m, np.ones(m.nglob), dirichlet=False)
+    A = operators.assemble(m)
+    assert np.abs(y).max() <= 1e-13 * abs(A).max()
+
+
+@pytest.mark.parametrize("p", [2, 3, 7])
+def test_quadratics_exact(p):
+    m = graded_mesh(p, 3 if p == 7 else 4)
+    X, Y, Z = (m.coords_1d(d) for d in range(3))
+    XX = np.tile(X, m.N[1] * m.N[2])
+    YY = np.tile(np.repeat(Y, m.N[0]), m.N[2])
+    interior = ~m.boundary_mask()
+    # harmonic quadratic: every interior row of A u vanishes
+    y = operators.apply_global(m, XX ** 2 - YY ** 2, dirichlet=False)
+    assert np.abs(y[interior]).max() < 1e-12
+    # -Laplace(x^2) = -2: interior rows equal -2 M 1
+    y = operators.apply_global(m, XX ** 2, dirichlet=False)
+    mass1 = operators.mass_global(m, np.ones(m.nglob), dirichlet=False)
+    np.testing.assert_allclose(y[interior], -2 * mass1[interior], atol=1e-12)
+    # energy of x^2 over the unit cube: int |grad x^2|^2 = 4/3
+    u = XX ** 2
+    assert abs(u @ operators.apply_global(m, u, dirichlet=False) - 4 / 3) < 1e-12
+
+
+def bubble(m):
+    X, Y, Z = (m.coords_1d(d) for d in range(3))
+    bx, by, bz = X * (1 - X), Y * (1 - Y), Z * (1 - Z)
+    return np.kron(np.kron(bz, by), bx), (bx, by, bz)
+
+
+@pytest.mark.parametrize("p,n", [(2, 3), (3, 4), (7, 2)])
+def test_bubble_energy(p, n):
+    m = graded_mesh(p, n)
+    u, _ = bubble(m)
+    e = u @ operators.apply_global(m, u)
+    assert abs(e - 1 / 900) < 1e-14
+
+
+def test_dirichlet_operator_spd_and_symmetric():
+    m = graded_mesh(2, 3)
+    A = operators.assemble(m, dirichlet=True).toarray()
+    assert np.abs(A - A.T).max() < 1e-14 * np.abs(A).max()
+    inner = ~m.boundary_mask()
+    ev = np.linalg.eigvalsh(A[np.ix_(inner, inner)])
+    assert ev.min() > 0
+    x = np.random.default_rng(5).uniform(-1, 1, m.nglob)
+    np.testing.assert_allclose(A @ x, operators.apply_global(m, x), atol=1e-12)
+
+
+# ------------------------------------------------------------------ DSS
+def test_dss_multiplicity():
+    m = graded_mesh(3, 3)
+    s = operators.dss(m, np.ones((m.ncells, m.n1 ** 3)))
+    # copies of interior vertex/edge/face/cell nodes
+    counts = set(np.unique(s).astype(int))
+    assert counts == {1, 2, 4, 8}
+    mult = m.multiplicity()
+    I = np.arange(m.nglob) % m.N[0]
+    J = (np.arange(m.nglob) // m.N[0]) % m.N[1]
+    K = np.arange(m.nglob) // (m.N[0] * m.N[1])
+
+    def c(Ix, N):
+        return np.where((Ix % m.p == 0) & (Ix > 0) & (Ix < N - 1), 2, 1)
+    np.testing.assert_array_equal(mult, c(I, m.N[0]) * c(J, m.N[1]) * c(K, m.N[2]))
+
+
+def test_dss_worked_example_2d():
+    rows = {}
+    with open(os.path.join(GOLDEN, "dss_vertex_2d.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                t = line.split()
+                rows[t[0]] = [float(v) for v in t[1:]]
+    m = Mesh(1, (2, 2, 1))
+    v = np.zeros((m.ncells, 8))
+    # the shared vertex (1,1,0): local corner of each cell
+    g = m.gidx(1, 1, 0)
+    names = {"nw": 2, "ne": 3, "sw": 0, "se": 1}
+    for key, val in zip(["nw", "ne", "sw", "se"], rows["initial"]):
+        e = names[key]
+        l = int(np.nonzero(m.dofs[e] == g)[0][0])
+        v[e, l] = val
+    s = operators.dss(m, v)
+    for key, val in zip(["nw", "ne", "sw", "se"], rows["after_y"]):
+        e = names[key]
+        l = int(np.nonzero(m.dofs[e] == g)[0][0])
+        assert s[e, l] == val
+
+
+def test_duality_pairing_lemma():
+    m = graded_mesh(3, 3)
+    rng = np.random.default_rng(9)
+    f = rng.standard_normal((m.ncells, m.n1 ** 3))
+    ug = rng.standard_normal(m.nglob)
+    lhs = np.sum(f * operators.gather(m, ug))
+    rhs = operators.scatter(m, f) @ ug
+    assert abs(lhs - rhs) <= 1e-13 * abs(rhs)
+
+
+# ------------------------------------------------------------- patches
+@pytest.mark.parametrize("p", [2, 3])
+def test_patch_matrix_is_restricted_global(p):
+    m = graded_mesh(p, 3)
+    A = operators.assemble(m).tocsr()
+    for v in patches.interior_vertices(m):
+        idx = patches.patch_nodes(m, v)
+        ref = A[idx][:, idx].toarray()
+        np.testing.assert_allclose(patches.patch_matrix(m, v), ref, atol=1e-12 * abs(ref).max())
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_single_patch_is_exact_inverse(p):
+    # n = 2: one interior vertex whose patch interior is the whole interior
+    m = graded_mesh(p, 2)
+    A = operators.assemble(m, dirichlet=True).tocsr()
+    inner = np.nonzero(~m.boundary_mask())[0]
+    r = np.zeros(m.nglob)
+    r[inner] = np.random.default_rng(3).standard_normal(len(inner))
+    z = patches.additive_schwarz(m, r)
+    ref = np.zeros(m.nglob)
+    ref[inner] = spla.spsolve(A[inner][:, inner].tocsc(), r[inner])
+    np.testing.assert_allclose(z, ref, atol=1e-12 * np.abs(ref).max())
+    # omega = 1, one sweep of the smoother is then an exact solve
+    zs = solver.smoother(m, r, sweeps=1, omega=1.0)
+    np.testing.assert_allclose(zs, ref, atol=1e-12 * np.abs(ref).max())
+
+
+def test_schwarz_symmetric_positive_and_bounded():
+    m = graded_mesh(2, 4)
+    inner = np.nonzero(~m.boundary_mask())[0]
+    nI = len(inner)
+    f = patches.SchwarzFactors(m)
+    P = np.zeros((nI, nI))
+    for t in range(nI):
+        e = np.zeros(m.nglob)
+        e[inner[t]] = 1
+        P[:, t] = f(e)[inner]
+    assert np.abs(P - P.T).max() < 1e-12 * np.abs(P).max()
+    A = operators.assemble(m, dirichlet=True).toarray()[np.ix_(inner, inner)]
+    # eigenvalues of P A lie in (0, 8]: each node is covered by at most 8
+    # patches and same-parity patches are disjoint
+    L = np.linalg.cholesky(A)
+    ev = np.linalg.eigvalsh(L.T @ P @ L)
+    assert ev.min() > 0 and ev.max() <= 8 + 1e-10
+    # multiplicity: P_AS applied to A_P-range vectors reproduces them
+    v = patches.interior_vertices(m)[5]
+    idx = patches.patch_nodes(m, v)
+    assert set(idx) <= set(inner)
+
+
+def test_at_cells_matches_full():
+    m = graded_mesh(3, 4)
+    r = np.random.default_rng(1).standard_normal(m.nglob) * (~m.boundary_mask())
+    z = patches.SchwarzFactors(m)(r)
+    cells = [0, 5, 21, 63]
+    np.testing.assert_allclose(patches.additive_schwarz_at_cells(m, r, cells),
+                               z[m.cell_dofs(cells)], atol=1e-13 * np.abs(z).max())
+
+
+# --------------------------------------------------------------- solver
+def test_cg_matches_textbook_cg_iterates():
+    m = graded_mesh(2, 4)
+    A = operators.assemble(m, dirichlet=True).tocsr()
+    inner = np.nonzero(~m.boundary_mask())[0]
+    Ai = A[inner][:, inner]
+    b = np.random.default_rng(2).standard_normal(len(inner))
+    ref = []
+    spla.cg(Ai, b, rtol=1e-12, maxiter=8, callback=lambda xk: ref.append(xk.copy()))
+    _, _, _, its = solver.fcg(lambda v: Ai @ v, lambda v: v, b, rtol=1e-30, maxit=8,
+                              variant="pcg", record=True)
+    for k in range(1, 8):
+        np.testing.assert_allclose(its[k], ref[k - 1], rtol=0, atol=1e-10 * np.abs(ref[k - 1]).max())
+
+
+def test_fcg_equals_pcg_for_static_preconditioner():
+    m = graded_mesh(2, 4)
+    b = operators.mass_global(m, np.random.default_rng(4).uniform(-1, 1, m.nglob))
+    u1, k1, h1, it1 = solver.solve_poisson(m, b, rtol=1e-10, variant="pcg", record=True)
+    u2, k2, h2, it2 = solver.solve_poisson(m, b, rtol=1e-10, variant="fcg", record=True)
+    assert abs(k1 - k2) <= 1
+    for k in range(min(k1, k2, 6)):
+        np.testing.assert_allclose(it1[k], it2[k], atol=1e-8 * np.abs(u1).max())
+    A = operators.assemble(m, dirichlet=True)
+    assert np.linalg.norm(b - A @ u1) <= 1e-10 * np.linalg.norm(b) * 1.0001
+
+
+@pytest.mark.parametrize("p,n", [(2, 4), (3, 3)])
+def test_bubble_solve_is_galerkin_exact(p, n):
+    m = graded_mesh(p, n)
+    u, (bx, by, bz) = bubble(m)
+    # f = -Laplace(u) = 2 (Y Z + X Z + X Y) in Q2 subset of Qp
+    f = 2 * (np.kron(np.kron(bz, by), np.ones_like(bx)) + np.kron(np.kron(bz, np.ones_like(by)), bx)
+             + np.kron(np.kron(np.ones_like(bz), by), bx))
+    b = operators.mass_global(m, f)
+    uh, k, hist, _ = solver.solve_poisson(m, b, rtol=1e-12)
+    assert hist[-1] <= 1e-12
+    assert np.abs(uh - u).max() < 1e-10
+
+
+# ------------------------------------------------ storage ratio table
+def test_storage_ratio_table():
+    with open(os.path.join(GOLDEN, "storage_ratios.txt")) as f:
+        rows = [l.split() for l in f if l.strip() and not l.startswith("#")]
+    for name, edge, stored, unique, sr, tr in rows:
+        edge, stored, unique = int(edge), int(stored), int(unique)
+        assert stored == edge ** 3
+        assert unique == (edge - 1) ** 3
+        assert abs(stored / unique - float(sr)) < 0.006
+        # cell-wise apply moves read+write per stored DoF, the assembled one
+        # read + read-accumulate-write per unique DoF: ratio 2/3 of storage
+        assert abs(2 * stored / (3 * unique) - float(tr)) < 0.006
