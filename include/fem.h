@@ -1,0 +1,267 @@
+/*
+ * fem.h -- C ABI of the MI355X cell-wise matrix-free Q_p Laplacian library.
+ *
+ * The library keeps continuous high-order finite-element fields in redundant
+ * cell-wise storage (every hexahedral cell owns all (p+1)^3 of its nodal
+ * values; Section 2.2 of the paper) and provides, on that storage:
+ *
+ *   fe_apply       the local Laplace operator A: V_cell -> V_cell^*
+ *                  (Eq. "Laplace operator" of Section 2.3; Section 3.1),
+ *   fe_mass_apply  the local mass operator (Eq. "mass operator", Section 2.3),
+ *   fem_dss        direct stiffness summation S = G G^T (Section 3.3) by the
+ *                  dimensionally-split cascade of Section 4.1,
+ *   patch_inverse  one additive Schwarz application over 2x2x2-cell vertex
+ *                  patches, each patch operator inverted by fast
+ *                  diagonalisation (the overlapping Schwarz patch smoothers of
+ *                  the Remark "Beyond DSS", Section 3.2),
+ *   smoother_step  damped Richardson sweeps on that Schwarz operator,
+ *   pcg_solve      the primal-dual (flexible) preconditioned CG of the
+ *                  Algorithm "Communication-Free (F)PCG" (Section 3.2),
+ * plus batched launches over many independent problems and a continuous-
+ * batching solve server.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Mesh.    A box [0,Lx]x[0,Ly]x[0,Lz] split into n[0] x n[1] x n[2]
+ *          axis-aligned cells with per-direction widths.  Q_p Lagrange
+ *          elements on Gauss-Lobatto-Legendre nodes, (p+1)-point Gauss
+ *          quadrature (exact for these operators on boxes).
+ * Global.  Global node (I,J,K), 0 <= I <= n[0] p, is numbered
+ *          g = I + (n[0]p+1) (J + (n[1]p+1) K).  Cell (i,j,k) is numbered
+ *          e = i + n[0] (j + n[1] k); its local node (a,b,c) (a along x) is
+ *          l = a + (p+1)(b + (p+1) c) and sits at global node
+ *          (i p + a, j p + b, k p + c).
+ * Cell-wise vectors.  fem_cell_len() elements of the precision in use
+ *          (FEM_F64: double, FEM_F32: float, FEM_BF16: bfloat16 bit pattern
+ *          in uint16_t).  The order inside is private to the library; use
+ *          fem_pack/fem_unpack (canonical [cell][local node] order) or
+ *          fem_gather/fem_scatter/fem_extract (global order) to move data in
+ *          and out.  Padding entries are kept at zero by every call.
+ * Primal/dual.  A primal (continuous) cell-wise vector holds equal values in
+ *          all copies of a node; a dual vector holds unassembled per-cell
+ *          contributions (Section 3.1).
+ * Boundary. FEM_BC_DIRICHLET imposes homogeneous Dirichlet conditions by
+ *          masking: copies on the domain boundary are read as zero and
+ *          written as zero (A_D = P_I A P_I).  FEM_BC_NEUMANN applies the
+ *          plain operator.
+ * Memory.  Every vector argument is a device pointer to caller-owned memory,
+ *          256-byte aligned.  The library owns only its handle-internal
+ *          workspace (geometry, patch eigen-data, temporaries).
+ * Streams. Calls are asynchronous on the handle's stream unless stated.
+ *          Calls on one handle must not overlap (they share its workspace).
+ * Errors.  Every call returns fem_status; fem_last_error() returns a
+ *          thread-local message for the most recent failure.  No C++
+ *          exception crosses this ABI.
+ */
+#ifndef FEM_MI355X_H
+#define FEM_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fem_status {
+    FEM_OK = 0,
+    FEM_EINVAL = 1,       /* bad argument (degree, sizes, pointers, aliasing)  */
+    FEM_ENOMEM = 2,       /* device allocation failed / request exceeds budget */
+    FEM_EHIP = 3,         /* HIP runtime error (message in fem_last_error)     */
+    FEM_ENOTCONV = 4,     /* pcg_solve reached maxit without converging        */
+    FEM_EBREAKDOWN = 5,   /* pcg_solve: non-finite or non-positive <q,p>       */
+    FEM_EAGAIN = 6,       /* server: result not ready / request queued         */
+    FEM_ENOTFOUND = 7     /* server: unknown ticket                            */
+} fem_status;
+
+typedef enum fem_prec { FEM_F64 = 0, FEM_F32 = 1, FEM_BF16 = 2 } fem_prec;
+typedef enum fem_bc { FEM_BC_DIRICHLET = 0, FEM_BC_NEUMANN = 1 } fem_bc;
+typedef enum fem_cg_variant { FEM_CG_AUTO = 0, FEM_CG_PCG = 1, FEM_CG_FCG = 2 } fem_cg_variant;
+
+/* Problem description.  p in 1..7, n[d] >= 1 (>= 2 for patch_inverse to be
+ * non-trivial).  widths[d]: host array of n[d] positive cell widths along
+ * direction d, copied at create time; NULL means n[d] equal cells of width
+ * 1/n[d]. */
+typedef struct fem_desc {
+    int p;
+    int n[3];
+    const double* widths[3];
+    int bc;                  /* fem_bc */
+} fem_desc;
+
+typedef struct fem_problem fem_problem;
+
+/* Result record of pcg_solve and of the server. */
+typedef struct fem_solve_info {
+    int iters;               /* iterations performed                       */
+    int status;              /* fem_status of the solve                    */
+    double relres;           /* ||G^T r_k||_2 / ||G^T b||_2 at exit        */
+    double seconds;          /* wall time of the solve (host clock)        */
+} fem_solve_info;
+
+/* ---------------------------------------------------------------- setup */
+
+/* Create a problem on the current HIP device.  Copies the widths, builds
+ * the 1D reference matrices and the per-vertex-line fast-diagonalisation
+ * data on the host, uploads them, and allocates the handle's workspace.
+ * stream: a hipStream_t (NULL = default stream).
+ * Errors: FEM_EINVAL (p outside 1..7, n < 1, non-positive width),
+ * FEM_ENOMEM, FEM_EHIP. */
+fem_status fem_problem_create(const fem_desc* desc, void* stream, fem_problem** out);
+fem_status fem_problem_destroy(fem_problem* P);
+fem_status fem_set_stream(fem_problem* P, void* stream);
+
+size_t fem_cell_len(const fem_problem* P);     /* elements per cell-wise vector (with padding) */
+size_t fem_global_len(const fem_problem* P);   /* (n0 p+1)(n1 p+1)(n2 p+1)                      */
+size_t fem_num_cells(const fem_problem* P);
+size_t fem_num_patches(const fem_problem* P);  /* (n0-1)(n1-1)(n2-1) interior vertices          */
+/* Device bytes a problem's handle plus a pcg_solve with the given smoother
+ * precision needs (handle workspace + solver vectors), for admission. */
+size_t fem_footprint_bytes(const fem_desc* desc, int smoother_prec);
+/* Bytes one element of a precision occupies (8, 4, 2). */
+size_t fem_prec_bytes(int prec);
+
+/* ----------------------------------------------------------- converters */
+
+/* x_cell = G x_glob (primal gather).  x_glob: device double[global_len]. */
+fem_status fem_gather(fem_problem* P, const double* x_glob, void* x_cell, int prec);
+/* y_glob = G^T y_cell (dual assembly: sums all copies of each node). */
+fem_status fem_scatter(fem_problem* P, const void* y_cell, double* y_glob, int prec);
+/* u_glob[g] = the copy of node g held by the lowest-numbered cell containing
+ * it (reads a primal vector back to global order). */
+fem_status fem_extract(fem_problem* P, const void* u_cell, double* u_glob, int prec);
+/* Canonical cell-major order [num_cells][(p+1)^3] <-> library layout. */
+fem_status fem_pack(fem_problem* P, const double* canon, void* v_cell, int prec);
+fem_status fem_unpack(fem_problem* P, const void* v_cell, double* canon, int prec);
+/* out = G^T r / m per copy (m = number of cells sharing the node): the
+ * assembled residual spread evenly over its copies, summed in FP64 and then
+ * rounded to `prec`.  r: dual FP64 vector.  Use it to hand a residual to a
+ * reduced-precision smoother: a converging solve's unassembled residual has
+ * per-copy values that cancel under assembly, and rounding them before
+ * assembly would put an absolute error floor into the smoother's input.
+ * smoother_step and patch_inverse see r only through G^T r, so the result
+ * is the same operator input. */
+fem_status fem_distribute_assembled(fem_problem* P, const double* r, void* out, int prec);
+/* dst = src converted between precisions (round to nearest even). */
+fem_status fem_convert(fem_problem* P, const void* src, int src_prec, void* dst, int dst_prec);
+
+/* ------------------------------------------------------------ operators */
+
+/* y = A x: per-cell sum-factorised Laplace apply (Eq. "Laplace operator",
+ * Section 2.3) with per-cell coefficients hy hz/hx, hx hz/hy, hx hy/hz.
+ * x primal (read), y dual (written).  x == y is FEM_EINVAL. */
+fem_status fe_apply(fem_problem* P, const void* x_cell, void* y_cell, int prec);
+/* y = M x: per-cell sum-factorised mass apply (Eq. "mass operator").  With
+ * Dirichlet conditions x is read in full and y's boundary copies are zero
+ * (P_I M), so fe_mass_apply(G f) is the load vector of nodal values f. */
+fem_status fe_mass_apply(fem_problem* P, const void* x_cell, void* y_cell, int prec);
+/* s = G G^T v: every copy receives the sum of all copies of its node
+ * (Section 3.3), computed by three axis passes z, y, x (Algorithm
+ * "Dimensionally-Split Structured Summation").  s may equal v (in place). */
+fem_status fem_dss(fem_problem* P, const void* v, void* s, int prec);
+/* One in-place axis pass of that cascade (axis 0 = x, 1 = y, 2 = z): each
+ * pair of coincident face copies across interfaces normal to the axis is
+ * replaced by its sum on both sides. */
+fem_status fem_dss_axis(fem_problem* P, void* v, int axis, int prec);
+/* z = sum_P R_P^T A_P^{-1} R_P G^T r: one additive Schwarz application over
+ * all interior-vertex patches.  r dual (read), z primal (written), zero on
+ * the Dirichlet boundary, every copy of a node bitwise equal.  r == z is
+ * FEM_EINVAL. */
+fem_status patch_inverse(fem_problem* P, const void* r_cell, void* z_cell, int prec);
+/* z = Richardson(r): z_0 = 0, z_{j+1} = z_j + omega P_AS (r - A z_j), for
+ * `sweeps` sweeps (>= 1).  r dual, z primal, both in `prec`. */
+fem_status smoother_step(fem_problem* P, const void* r_cell, void* z_cell, int prec,
+                         int sweeps, double omega);
+
+/* ------------------------------------------------------------ reductions */
+
+/* *result = <a, b> over all cell-wise entries, accumulated in FP64 with a
+ * fixed reduction order.  Synchronises the stream.  prec_a/prec_b may
+ * differ. */
+fem_status fem_dot(fem_problem* P, const void* a, int prec_a, const void* b, int prec_b,
+                   double* result);
+/* *result = ||G^T r||_2 (assembled l2 norm of a dual vector).  Synchronises. */
+fem_status fem_assembled_norm(fem_problem* P, const void* r, int prec, double* result);
+
+/* --------------------------------------------------------------- solver */
+
+/* Solve A u = b with the (F)PCG of the paper's Algorithm "Communication-Free
+ * (F)PCG", preconditioned by smoother_step(sweeps, omega) in
+ * `smoother_prec`.  b: dual FP64 cell-wise vector (read); u: primal FP64
+ * cell-wise vector, initial guess in and solution out.  All vectors, pairings
+ * and scalars stay on the device in FP64; the stopping test is
+ * ||G^T r_k||_2 <= rtol ||G^T b||_2.  variant FEM_CG_AUTO uses PCG for an
+ * FP64 smoother and FCG otherwise.  Synchronises the stream at exit.
+ * Returns FEM_ENOTCONV at maxit, FEM_EBREAKDOWN on a non-finite or
+ * non-positive <q,p>; info (may be NULL) is filled in every case. */
+fem_status pcg_solve(fem_problem* P, const double* b_cell, double* u_cell, double rtol,
+                     int maxit, int smoother_prec, int sweeps, double omega, int variant,
+                     fem_solve_info* info);
+
+/* ------------------------------------------------------- batched launches */
+
+typedef struct fem_batch fem_batch;
+
+/* A batch of independent problems sharing one stream; batched calls run
+ * every problem of one degree in a single persistent launch. */
+fem_status fem_batch_create(int count, const fem_desc* descs, void* stream, fem_batch** out);
+fem_status fem_batch_destroy(fem_batch* B);
+/* Borrow problem i of the batch (owned by the batch) for per-problem calls. */
+fem_status fem_batch_problem(fem_batch* B, int i, fem_problem** out);
+/* y[i] = A x[i] for every problem i; x, y: host arrays of `count` device
+ * pointers, each a cell-wise vector of that problem in `prec`. */
+fem_status fem_batch_apply(fem_batch* B, void* const* x, void* const* y, int prec);
+/* z[i] = P_AS r[i] for every problem i. */
+fem_status fem_batch_patch_inverse(fem_batch* B, void* const* r, void* const* z, int prec);
+/* Tile-shape autotuner: time the candidate tile shapes of each degree
+ * present in the batch on its own problems and keep the fastest.  Writes the
+ * chosen configuration index per degree 1..7 into choice[7] (may be NULL). */
+fem_status fem_batch_autotune(fem_batch* B, int prec, int* choice);
+
+/* ---------------------------------------------------- solve server */
+
+typedef struct fem_server fem_server;
+
+/* A continuous-batching solve server on the current device.  hbm_budget:
+ * bytes of device memory its active solves may hold; max_active: slot
+ * count.  smoother_prec/sweeps/omega: smoother of every solve. */
+fem_status fem_server_create(size_t hbm_budget, int max_active, int smoother_prec, int sweeps,
+                             double omega, void* stream, fem_server** out);
+fem_status fem_server_destroy(fem_server* S);
+/* Queue a solve of A u = P_I M f (f: host double[global_len] nodal source
+ * values, copied).  Returns FEM_ENOMEM if the request can never fit the
+ * budget, FEM_OK otherwise (it is admitted when memory and a slot free up). */
+fem_status fem_server_submit(fem_server* S, const fem_desc* desc, const double* f_glob,
+                             double rtol, int maxit, uint64_t* ticket);
+/* Admit queued requests that fit, then advance every active solve by one
+ * iteration (one batched launch per degree and kernel), retire converged
+ * ones.  n_active/n_queued/n_done (may be NULL) report the counts after the
+ * step. */
+fem_status fem_server_step(fem_server* S, int* n_active, int* n_queued, int* n_done);
+/* FEM_OK and the solution (global order, host double[global_len]; may be
+ * NULL) if the ticket's solve has finished; FEM_EAGAIN if not yet;
+ * FEM_ENOTFOUND for an unknown or already collected ticket. */
+fem_status fem_server_poll(fem_server* S, uint64_t ticket, double* u_glob, fem_solve_info* info);
+/* Device bytes currently held by admitted solves, and the high-water mark. */
+fem_status fem_server_memory(fem_server* S, size_t* in_use, size_t* high_water);
+
+/* ------------------------------------------------------- host utilities */
+
+/* Host-only (no device use): the 1D reference mass and stiffness matrices
+ * of degree p on [0,1] (row-major (p+1)x(p+1)), and the fast-diagonalisation
+ * data of the 1D patch operator of two cells of widths h0, h1 restricted to
+ * the 2p-1 interior nodes: S (row-major (2p-1)x(2p-1), columns are
+ * eigenvectors) and lambda (2p-1) with S^T M S = I, S^T K S = diag(lambda). */
+fem_status fem_host_1d_matrices(int p, double* mass, double* stiff);
+/* Host-only: the p+1 Gauss-Lobatto-Legendre nodes of [0,1] the element uses
+ * (ascending), e.g. to place nodal source values. */
+fem_status fem_host_gll_nodes(int p, double* nodes);
+fem_status fem_host_fd_1d(int p, double h0, double h1, double* S, double* lambda);
+
+const char* fem_last_error(void);
+const char* fem_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FEM_MI355X_H */

@@ -1,0 +1,38 @@
+// Internal host declarations shared by the C-ABI translation units.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "fem_internal.h"
+
+namespace fem {
+
+fem_status set_error(fem_status st, const std::string& msg);
+fem_status hip_error(hipError_t e, const char* what);
+
+std::vector<double> host_gll_nodes(int p);
+void host_gauss(int nq, std::vector<double>& x, std::vector<double>& w);
+void host_ref_matrices(int p, double* M, double* K);
+void host_patch_1d(int p, double h0, double h1, std::vector<double>& M, std::vector<double>& K);
+int host_fd_1d(int p, double h0, double h1, double* S, double* lam);
+
+// Validate a description; on failure sets the error message.
+fem_status check_desc(const fem_desc* d);
+// Bytes of the handle workspace of a description (geometry, FD data,
+// reductions, patch buffer, smoother scratch).
+size_t workspace_bytes(const fem_desc* d);
+// Bytes of pcg_solve's own vectors for a smoother precision.
+size_t solve_vector_bytes(const fem_desc* d, int smoother_prec);
+size_t desc_cell_len(const fem_desc* d);
+
+// Solver pieces reused by the server (all asynchronous on P->stream).
+fem_status smoother_run(fem_problem* P, const void* r, void* z, int prec, int sweeps, double omega);
+
+#define FEM_HIP(call, what)                                   \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return ::fem::hip_error(e_, what); \
+    } while (0)
+
+}  // namespace fem

@@ -1,0 +1,426 @@
+// Sum-factorised local operator apply on cell-wise storage.
+//
+// Laplace (Eq. "Laplace operator", Section 2.3) on a box cell of widths
+// (hx, hy, hz) with 1D reference mass M and stiffness K on [0,1]:
+//
+//   y = cx (K x M x M) u + cy (M x K x M) u + cz (M x M x K) u,
+//   cx = hy hz / hx,  cy = hx hz / hy,  cz = hx hy / hz,
+//
+// (the first factor acts along x).  Evaluated as seven 1D contractions:
+//   A = Mz u,  Bz = Kz u,  C = cy Ky A + cz My Bz,  D = My A,
+//   y = Mx C + cx Kx D.
+// Mass (Eq. "mass operator"):  y = hx hy hz (M x M x M) u, three contractions.
+// With Dirichlet conditions the Laplacian is P_I A P_I (boundary copies read
+// and written as zero) while the mass apply is P_I M (input read in full), so
+// that P_I M f is the load vector of nodal source values f.
+//
+// Two kernel shapes:
+//  * k_apply_reg (p <= 3): one thread per cell.  The cell's (p+1)^3 values
+//    are loaded into registers (one coalesced 64-cell segment per node), and
+//    the output is produced one z-plane at a time, so the live state is the
+//    input cell plus a few planes.
+//  * k_apply_lds (any p): a workgroup owns CB cells staged in LDS and walks
+//    the three directions with one thread per 1D line.
+#include "fem_internal.h"
+#include "launch.h"
+
+namespace fem {
+
+enum ApplyMode { kApplyLaplace = 0, kApplyResidual = 1, kApplyMass = 2 };
+
+template <typename C>
+struct CellGeom {
+    C cx, cy, cz, vol;
+    bool xlo, xhi, ylo, yhi, zlo, zhi;
+};
+
+template <typename C>
+__device__ __forceinline__ CellGeom<C> cell_geom(const ProbEntry& pe, int e) {
+    const int n0 = pe.n[0], n1 = pe.n[1];
+    const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
+    const double hx = pe.h[0][i], hy = pe.h[1][j], hz = pe.h[2][k];
+    CellGeom<C> g;
+    g.cx = (C)(hy * hz / hx);
+    g.cy = (C)(hx * hz / hy);
+    g.cz = (C)(hx * hy / hz);
+    g.vol = (C)(hx * hy * hz);
+    const bool d = pe.dirichlet != 0;
+    g.xlo = d && i == 0;
+    g.xhi = d && i == n0 - 1;
+    g.ylo = d && j == 0;
+    g.yhi = d && j == n1 - 1;
+    g.zlo = d && k == 0;
+    g.zhi = d && k == pe.n[2] - 1;
+    return g;
+}
+
+template <int P, typename C>
+__device__ __forceinline__ bool on_boundary(const CellGeom<C>& g, int a, int b, int c) {
+    return (a == 0 && g.xlo) || (a == P && g.xhi) || (b == 0 && g.ylo) || (b == P && g.yhi) ||
+           (c == 0 && g.zlo) || (c == P && g.zhi);
+}
+
+// ---------------------------------------------------------------------------
+// One thread per cell, register resident.  Tile = one storage block (64
+// cells) per wavefront.
+template <int P, typename S, int MODE, bool MULTI>
+__global__ void __launch_bounds__(256)
+k_apply_reg(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
+    using C = typename Prec<S>::C;
+    constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    for (int tile = blockIdx.x * 4 + wv; tile < L.total_tiles; tile += gridDim.x * 4) {
+        const ProbEntry& pe = entry<MULTI>(L, tile);
+        const int blk = tile - pe.tile_begin;
+        const int e = blk * kLanes + lane;
+        const size_t base = (size_t)blk * NN * kLanes + lane;
+        const S* __restrict__ x = static_cast<const S*>(pe.a) + base;
+        S* __restrict__ y = static_cast<S*>(pe.c) + base;
+        if (e >= pe.ncells) {
+            for (int l = 0; l < NN; ++l) store_from(y + l * kLanes, (C)0);
+            continue;
+        }
+        const CellGeom<C> g = cell_geom<C>(pe, e);
+        C u[NN];
+#pragma unroll
+        for (int l = 0; l < NN; ++l) u[l] = load_as<C>(x + l * kLanes);
+        if (MODE != kApplyMass) {      // A_D = P_I A P_I; the mass apply is P_I M
+#pragma unroll
+            for (int c = 0; c < N; ++c)
+#pragma unroll
+                for (int b = 0; b < N; ++b)
+#pragma unroll
+                    for (int a = 0; a < N; ++a)
+                        if (on_boundary<P>(g, a, b, c)) u[a + N * b + N2 * c] = (C)0;
+        }
+
+        const S* __restrict__ rres = (MODE == kApplyResidual)
+            ? static_cast<const S*>(pe.b) + base : nullptr;
+
+#pragma unroll
+        for (int cz = 0; cz < N; ++cz) {
+            C out[N2];
+            if (MODE == kApplyMass) {
+                C A[N2], Bp[N2];
+#pragma unroll
+                for (int ab = 0; ab < N2; ++ab) {
+                    C s = 0;
+#pragma unroll
+                    for (int c = 0; c < N; ++c) s += R.M[cz * N + c] * u[ab + N2 * c];
+                    A[ab] = s;
+                }
+#pragma unroll
+                for (int a = 0; a < N; ++a)
+#pragma unroll
+                    for (int bb = 0; bb < N; ++bb) {
+                        C s = 0;
+#pragma unroll
+                        for (int b = 0; b < N; ++b) s += R.M[bb * N + b] * A[a + N * b];
+                        Bp[a + N * bb] = s;
+                    }
+#pragma unroll
+                for (int b = 0; b < N; ++b)
+#pragma unroll
+                    for (int aa = 0; aa < N; ++aa) {
+                        C s = 0;
+#pragma unroll
+                        for (int a = 0; a < N; ++a) s += R.M[aa * N + a] * Bp[a + N * b];
+                        out[aa + N * b] = g.vol * s;
+                    }
+            } else {
+                // z contraction onto output plane cz
+                C A[N2], Bz[N2];
+#pragma unroll
+                for (int ab = 0; ab < N2; ++ab) {
+                    C sm = 0, sk = 0;
+#pragma unroll
+                    for (int c = 0; c < N; ++c) {
+                        sm += R.M[cz * N + c] * u[ab + N2 * c];
+                        sk += R.K[cz * N + c] * u[ab + N2 * c];
+                    }
+                    A[ab] = sm;
+                    Bz[ab] = sk;
+                }
+                // y contraction within the plane
+                C Cc[N2], D[N2];
+#pragma unroll
+                for (int a = 0; a < N; ++a)
+#pragma unroll
+                    for (int bb = 0; bb < N; ++bb) {
+                        C sky = 0, smb = 0, sma = 0;
+#pragma unroll
+                        for (int b = 0; b < N; ++b) {
+                            sky += R.K[bb * N + b] * A[a + N * b];
+                            smb += R.M[bb * N + b] * Bz[a + N * b];
+                            sma += R.M[bb * N + b] * A[a + N * b];
+                        }
+                        Cc[a + N * bb] = g.cy * sky + g.cz * smb;
+                        D[a + N * bb] = sma;
+                    }
+                // x contraction
+#pragma unroll
+                for (int b = 0; b < N; ++b)
+#pragma unroll
+                    for (int aa = 0; aa < N; ++aa) {
+                        C sm = 0, sk = 0;
+#pragma unroll
+                        for (int a = 0; a < N; ++a) {
+                            sm += R.M[aa * N + a] * Cc[a + N * b];
+                            sk += R.K[aa * N + a] * D[a + N * b];
+                        }
+                        out[aa + N * b] = sm + g.cx * sk;
+                    }
+            }
+#pragma unroll
+            for (int b = 0; b < N; ++b)
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    const int l = a + N * b + N2 * cz;
+                    C v = out[a + N * b];
+                    if (MODE == kApplyResidual) v = load_as<C>(rres + l * kLanes) - v;
+                    if (on_boundary<P>(g, a, b, cz)) v = (C)0;
+                    store_from(y + l * kLanes, v);
+                }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// LDS line kernel.  Tile = CB consecutive cells of one storage block.
+// LDS layout: value of local node l of tile cell c at [l * CB + c], so
+// threads that differ in c touch consecutive words.
+template <int P, typename S, int MODE, int CB, bool MULTI>
+__global__ void __launch_bounds__(256)
+k_apply_lds(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
+    using C = typename Prec<S>::C;
+    constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
+    constexpr int NT = 256;
+    static_assert(NT % CB == 0, "tile cells must divide the workgroup");
+    __shared__ C s0[NN * CB];
+    __shared__ C s1[NN * CB];
+    const int tid = threadIdx.x;
+    const int c = tid % CB;            // the tile cell this thread serves in every loop
+    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+        const ProbEntry& pe = entry<MULTI>(L, tile);
+        const int t = tile - pe.tile_begin;
+        const int e0 = t * CB;                         // first cell of the tile
+        const int blk = e0 / kLanes, lane0 = e0 % kLanes;
+        const size_t base = (size_t)blk * NN * kLanes + lane0 + c;
+        const S* __restrict__ x = static_cast<const S*>(pe.a) + base;
+        S* __restrict__ y = static_cast<S*>(pe.c) + base;
+        const S* __restrict__ rres = (MODE == kApplyResidual) ? static_cast<const S*>(pe.b) + base : nullptr;
+        const int e = e0 + c;
+        const bool valid = e < pe.ncells;
+        CellGeom<C> g{};
+        if (valid) g = cell_geom<C>(pe, e);
+        // load (boundary copies of x read as zero)
+        for (int l = tid / CB; l < NN; l += NT / CB) {
+            C v = (C)0;
+            if (valid && (MODE == kApplyMass || !on_boundary<P>(g, l % N, (l / N) % N, l / N2)))
+                v = load_as<C>(x + (size_t)l * kLanes);
+            s0[l * CB + c] = v;
+        }
+        __syncthreads();
+        if (MODE == kApplyMass) {
+            for (int ab = tid / CB; ab < N2; ab += NT / CB) {          // z lines
+                C v[N];
+#pragma unroll
+                for (int k = 0; k < N; ++k) v[k] = s0[(ab + N2 * k) * CB + c];
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    C s = 0;
+#pragma unroll
+                    for (int m = 0; m < N; ++m) s += R.M[k * N + m] * v[m];
+                    s0[(ab + N2 * k) * CB + c] = s;
+                }
+            }
+            __syncthreads();
+            for (int r = tid / CB; r < N2; r += NT / CB) {             // y lines, r = a + N k
+                const int a = r % N, k = r / N;
+                C v[N];
+#pragma unroll
+                for (int b = 0; b < N; ++b) v[b] = s0[(a + N * b + N2 * k) * CB + c];
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    C s = 0;
+#pragma unroll
+                    for (int m = 0; m < N; ++m) s += R.M[b * N + m] * v[m];
+                    s0[(a + N * b + N2 * k) * CB + c] = s;
+                }
+            }
+            __syncthreads();
+            for (int r = tid / CB; r < N2; r += NT / CB) {             // x lines, r = b + N k
+                C v[N];
+#pragma unroll
+                for (int a = 0; a < N; ++a) v[a] = s0[(a + N * r) * CB + c];
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    C s = 0;
+#pragma unroll
+                    for (int m = 0; m < N; ++m) s += R.M[a * N + m] * v[m];
+                    s *= g.vol;
+                    if (!valid || on_boundary<P>(g, a, r % N, r / N)) s = (C)0;
+                    store_from(y + (size_t)(a + N * r) * kLanes, s);
+                }
+            }
+            __syncthreads();
+            continue;
+        }
+        // z pass: s0 <- A = Mz u, s1 <- Bz = Kz u
+        for (int ab = tid / CB; ab < N2; ab += NT / CB) {
+            C v[N];
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] = s0[(ab + N2 * k) * CB + c];
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                C sm = 0, sk = 0;
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    sm += R.M[k * N + m] * v[m];
+                    sk += R.K[k * N + m] * v[m];
+                }
+                s0[(ab + N2 * k) * CB + c] = sm;
+                s1[(ab + N2 * k) * CB + c] = sk;
+            }
+        }
+        __syncthreads();
+        // y pass: s1 <- C = cy Ky A + cz My Bz, s0 <- D = My A
+        for (int r = tid / CB; r < N2; r += NT / CB) {
+            const int a = r % N, k = r / N;
+            C va[N], vb[N];
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                va[b] = s0[(a + N * b + N2 * k) * CB + c];
+                vb[b] = s1[(a + N * b + N2 * k) * CB + c];
+            }
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                C sky = 0, smb = 0, sma = 0;
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    sky += R.K[b * N + m] * va[m];
+                    smb += R.M[b * N + m] * vb[m];
+                    sma += R.M[b * N + m] * va[m];
+                }
+                s1[(a + N * b + N2 * k) * CB + c] = g.cy * sky + g.cz * smb;
+                s0[(a + N * b + N2 * k) * CB + c] = sma;
+            }
+        }
+        __syncthreads();
+        // x pass: y = Mx C + cx Kx D, store
+        for (int r = tid / CB; r < N2; r += NT / CB) {                 // r = b + N k
+            C vc[N], vd[N];
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                vc[a] = s1[(a + N * r) * CB + c];
+                vd[a] = s0[(a + N * r) * CB + c];
+            }
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                C sm = 0, sk = 0;
+#pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    sm += R.M[a * N + m] * vc[m];
+                    sk += R.K[a * N + m] * vd[m];
+                }
+                C v = sm + g.cx * sk;
+                const size_t off = (size_t)(a + N * r) * kLanes;
+                if (MODE == kApplyResidual) v = load_as<C>(rres + off) - v;
+                if (!valid || on_boundary<P>(g, a, r % N, r / N)) v = (C)0;
+                store_from(y + off, v);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launch selection.
+template <int P, typename C>
+static RefMats<P, C> ref_mats() {
+    RefMats<P, C> R;
+    const double* M = ref_mass(P);
+    const double* K = ref_stiff(P);
+    for (int i = 0; i < (P + 1) * (P + 1); ++i) {
+        R.M[i] = (C)M[i];
+        R.K[i] = (C)K[i];
+    }
+    return R;
+}
+
+template <int P> constexpr int lds_cells(int bytes) {
+    // largest power of two <= 64 with two LDS arrays within 64 KiB
+    int cb = 64;
+    while (cb > 1 && 2 * cb * (P + 1) * (P + 1) * (P + 1) * bytes > 65536) cb >>= 1;
+    return cb;
+}
+
+template <int P, typename S, int MODE>
+static hipError_t launch_apply_t(ProbEntry* ents, int nprob, ProbEntry* d_tab, hipStream_t s,
+                                 int force_lds) {
+    using C = typename Prec<S>::C;
+    const RefMats<P, C> R = ref_mats<P, C>();
+    const bool use_reg = (P <= 3) && !force_lds;
+    constexpr int CB = lds_cells<P>((int)sizeof(C));
+    LaunchTable L{};
+    int tiles = 0;
+    for (int i = 0; i < nprob; ++i) {
+        ents[i].tile_begin = tiles;
+        ents[i].ntiles = use_reg ? ents[i].nblk : ents[i].nblk * (kLanes / CB);
+        tiles += ents[i].ntiles;
+    }
+    L.nprob = nprob;
+    L.total_tiles = tiles;
+    if (tiles == 0) return hipSuccess;
+    hipError_t err = stage_table(L, ents, nprob, d_tab, s);
+    if (err != hipSuccess) return err;
+    if constexpr (P <= 3) {
+        if (use_reg) {
+            const int grid = (tiles + 3) / 4 < kMaxGrid ? (tiles + 3) / 4 : kMaxGrid;
+            if (nprob > 1) hipLaunchKernelGGL((k_apply_reg<P, S, MODE, true>), dim3(grid), dim3(256), 0, s, L, R);
+            else hipLaunchKernelGGL((k_apply_reg<P, S, MODE, false>), dim3(grid), dim3(256), 0, s, L, R);
+            return hipGetLastError();
+        }
+    }
+    {
+        const int grid = tiles < kMaxGrid ? tiles : kMaxGrid;
+        if (nprob > 1) hipLaunchKernelGGL((k_apply_lds<P, S, MODE, CB, true>), dim3(grid), dim3(256), 0, s, L, R);
+        else hipLaunchKernelGGL((k_apply_lds<P, S, MODE, CB, false>), dim3(grid), dim3(256), 0, s, L, R);
+    }
+    return hipGetLastError();
+}
+
+template <int P, typename S>
+static hipError_t launch_apply_m(int mode, ProbEntry* e, int n, ProbEntry* t, hipStream_t s, int fl) {
+    switch (mode) {
+        case kApplyLaplace: return launch_apply_t<P, S, kApplyLaplace>(e, n, t, s, fl);
+        case kApplyResidual: return launch_apply_t<P, S, kApplyResidual>(e, n, t, s, fl);
+        default: return launch_apply_t<P, S, kApplyMass>(e, n, t, s, fl);
+    }
+}
+
+template <int P>
+static hipError_t launch_apply_p(int prec, int mode, ProbEntry* e, int n, ProbEntry* t, hipStream_t s, int fl) {
+    switch (prec) {
+        case FEM_F64: return launch_apply_m<P, double>(mode, e, n, t, s, fl);
+        case FEM_F32: return launch_apply_m<P, float>(mode, e, n, t, s, fl);
+        default: return launch_apply_m<P, bf16_t>(mode, e, n, t, s, fl);
+    }
+}
+
+hipError_t launch_apply(int p, int prec, int mode, ProbEntry* ents, int nprob, ProbEntry* d_tab,
+                        hipStream_t s, int force_lds) {
+    switch (p) {
+        case 1: return launch_apply_p<1>(prec, mode, ents, nprob, d_tab, s, force_lds);
+        case 2: return launch_apply_p<2>(prec, mode, ents, nprob, d_tab, s, force_lds);
+        case 3: return launch_apply_p<3>(prec, mode, ents, nprob, d_tab, s, force_lds);
+        case 4: return launch_apply_p<4>(prec, mode, ents, nprob, d_tab, s, force_lds);
+        case 5: return launch_apply_p<5>(prec, mode, ents, nprob, d_tab, s, force_lds);
+        case 6: return launch_apply_p<6>(prec, mode, ents, nprob, d_tab, s, force_lds);
+        case 7: return launch_apply_p<7>(prec, mode, ents, nprob, d_tab, s, force_lds);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace fem

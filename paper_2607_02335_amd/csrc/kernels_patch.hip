@@ -1,0 +1,303 @@
+// Additive Schwarz over 2x2x2-cell vertex patches with fast-diagonalisation
+// patch inverses.
+//
+// Patch of interior vertex (vi, vj, vk): the (2p-1)^3 nodes strictly inside
+// the cells [vi-1, vi] x [vj-1, vj] x [vk-1, vk]; patch-local node
+// (qx, qy, qz), qx = I - (vi-1) p - 1 for global node plane I.
+//
+// Phase 1 (k_pi_solve), one workgroup per CBP consecutive patches along x:
+//   restrict:  r_P(q) = sum of the coincident cell copies of node q among the
+//              patch's eight cells (= (G^T r)(q): every cell holding q lies in
+//              the patch), so the smoother sees r only through its assembly,
+//              the consistency the paper's equivalence theorem asks of a
+//              preconditioner (Section 3.2, Remarks after the theorem);
+//   solve:     z_P = (Sx (x) Sy (x) Sz) diag(1/(lx+ly+lz)) (Sx (x) Sy (x) Sz)^T r_P,
+//              six 1D contractions staged in LDS, one thread per line;
+//   store z_P in a patch buffer.
+// Phase 2 (k_pi_combine), one thread per cell copy:
+//   z(node) = sum of z_P(node) over the patches whose interior contains the
+//   node, added in increasing vertex order.  That order depends only on the
+//   global node, so all copies of a node receive bitwise identical values:
+//   the output is continuous exactly, not just to rounding.
+#include "fem_internal.h"
+#include "launch.h"
+
+namespace fem {
+
+template <int P, typename C> constexpr int pi_patches_per_tile() {
+    constexpr int nP = 2 * P - 1;
+    int cb = 64;
+    while (cb > 1 && cb * nP * nP * nP * (int)sizeof(C) > 40 * 1024) cb >>= 1;
+    return cb;
+}
+
+// pe: a = r (S), d = patch buffer (C), fd[0..2] = FD records (C) per
+// direction, indexed by vertex line v-1.
+template <int P, typename S, int CBP, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_solve(LaunchTable L) {
+    using C = typename Prec<S>::C;
+    constexpr int N = P + 1, NN = N * N * N;
+    constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
+    constexpr int REC = fd_record(P);
+    constexpr int NT = 256, LPT = NT / CBP;     // lines per tile-thread stride
+    static_assert(NT % CBP == 0, "patches per tile must divide the workgroup");
+    __shared__ C sv[nP3 * CBP];
+    __shared__ C sS[3][CBP][nP2];
+    __shared__ C sL[3][CBP][nP];
+    const int tid = threadIdx.x;
+    const int pc = tid % CBP;
+    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+        const ProbEntry& pe = entry<MULTI>(L, tile);
+        const int t = tile - pe.tile_begin;
+        const int npx = pe.n[0] - 1, npy = pe.n[1] - 1;
+        const int tpr = (npx + CBP - 1) / CBP;
+        const int row = t / tpr, xt = t % tpr;
+        const int vj = 1 + row % npy, vk = 1 + row / npy;
+        const int vi = 1 + xt * CBP + pc;
+        const bool valid = vi <= npx;
+        // FD data of this patch's three vertex lines
+        for (int idx = tid / CBP; idx < 3 * (nP2 + nP); idx += LPT) {
+            const int d = idx / (nP2 + nP), w = idx % (nP2 + nP);
+            const int line = (d == 0 ? (valid ? vi : npx) : d == 1 ? vj : vk) - 1;
+            const C v = static_cast<const C*>(pe.fd[d])[(size_t)line * REC + w];
+            if (w < nP2) sS[d][pc][w] = v; else sL[d][pc][w - nP2] = v;
+        }
+        // restrict: sum coincident copies from the eight cells
+        const S* r = static_cast<const S*>(pe.a);
+        const int n0 = pe.n[0], n1 = pe.n[1];
+        for (int q = tid / CBP; q < nP3; q += LPT) {
+            const int qx = q % nP, qy = (q / nP) % nP, qz = q / nP2;
+            C s = 0;
+            if (valid) {
+#pragma unroll
+                for (int s3 = 0; s3 < 2; ++s3) {
+                    const int c = qz + 1 - s3 * P;
+                    if (c < 0 || c > P) continue;
+#pragma unroll
+                    for (int s2 = 0; s2 < 2; ++s2) {
+                        const int b = qy + 1 - s2 * P;
+                        if (b < 0 || b > P) continue;
+#pragma unroll
+                        for (int s1 = 0; s1 < 2; ++s1) {
+                            const int a = qx + 1 - s1 * P;
+                            if (a < 0 || a > P) continue;
+                            const int e = (vi - 1 + s1) + n0 * ((vj - 1 + s2) + n1 * (vk - 1 + s3));
+                            s += load_as<C>(r + cell_offset(e, a + N * (b + N * c), NN));
+                        }
+                    }
+                }
+            }
+            sv[q * CBP + pc] = s;
+        }
+        __syncthreads();
+        // forward z: v <- Sz^T v along z lines
+        for (int ln = tid / CBP; ln < nP2; ln += LPT) {
+            C v[nP];
+#pragma unroll
+            for (int i = 0; i < nP; ++i) v[i] = sv[(ln + nP2 * i) * CBP + pc];
+#pragma unroll
+            for (int j = 0; j < nP; ++j) {
+                C s = 0;
+#pragma unroll
+                for (int i = 0; i < nP; ++i) s += sS[2][pc][i * nP + j] * v[i];
+                sv[(ln + nP2 * j) * CBP + pc] = s;
+            }
+        }
+        __syncthreads();
+        // forward y
+        for (int ln = tid / CBP; ln < nP2; ln += LPT) {
+            const int qx = ln % nP, qz = ln / nP;
+            C v[nP];
+#pragma unroll
+            for (int i = 0; i < nP; ++i) v[i] = sv[(qx + nP * i + nP2 * qz) * CBP + pc];
+#pragma unroll
+            for (int j = 0; j < nP; ++j) {
+                C s = 0;
+#pragma unroll
+                for (int i = 0; i < nP; ++i) s += sS[1][pc][i * nP + j] * v[i];
+                sv[(qx + nP * j + nP2 * qz) * CBP + pc] = s;
+            }
+        }
+        __syncthreads();
+        // forward x, scale by 1/(lx+ly+lz), backward x (same line, no sync)
+        for (int ln = tid / CBP; ln < nP2; ln += LPT) {
+            const int qy = ln % nP, qz = ln / nP;
+            C v[nP], w[nP];
+#pragma unroll
+            for (int i = 0; i < nP; ++i) v[i] = sv[(i + nP * ln) * CBP + pc];
+            const C lyz = sL[1][pc][qy] + sL[2][pc][qz];
+#pragma unroll
+            for (int j = 0; j < nP; ++j) {
+                C s = 0;
+#pragma unroll
+                for (int i = 0; i < nP; ++i) s += sS[0][pc][i * nP + j] * v[i];
+                w[j] = s / (sL[0][pc][j] + lyz);
+            }
+#pragma unroll
+            for (int i = 0; i < nP; ++i) {
+                C s = 0;
+#pragma unroll
+                for (int j = 0; j < nP; ++j) s += sS[0][pc][i * nP + j] * w[j];
+                sv[(i + nP * ln) * CBP + pc] = s;
+            }
+        }
+        __syncthreads();
+        // backward y
+        for (int ln = tid / CBP; ln < nP2; ln += LPT) {
+            const int qx = ln % nP, qz = ln / nP;
+            C v[nP];
+#pragma unroll
+            for (int j = 0; j < nP; ++j) v[j] = sv[(qx + nP * j + nP2 * qz) * CBP + pc];
+#pragma unroll
+            for (int i = 0; i < nP; ++i) {
+                C s = 0;
+#pragma unroll
+                for (int j = 0; j < nP; ++j) s += sS[1][pc][i * nP + j] * v[j];
+                sv[(qx + nP * i + nP2 * qz) * CBP + pc] = s;
+            }
+        }
+        __syncthreads();
+        // backward z and store to the patch buffer
+        C* pbuf = static_cast<C*>(pe.d);
+        const int pidx = (vi - 1) + npx * ((vj - 1) + npy * (vk - 1));
+        C* out = pbuf + (size_t)(pidx / kLanes) * nP3 * kLanes + (pidx % kLanes);
+        for (int ln = tid / CBP; ln < nP2; ln += LPT) {
+            C v[nP];
+#pragma unroll
+            for (int j = 0; j < nP; ++j) v[j] = sv[(ln + nP2 * j) * CBP + pc];
+#pragma unroll
+            for (int i = 0; i < nP; ++i) {
+                C s = 0;
+#pragma unroll
+                for (int j = 0; j < nP; ++j) s += sS[2][pc][i * nP + j] * v[j];
+                if (valid) out[(size_t)(ln + nP2 * i) * kLanes] = s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// pe: c = z (S), d = patch buffer (C), alpha = damping; ACC: z += alpha sum.
+template <int P, typename S, int ACC, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_combine(LaunchTable L) {
+    using C = typename Prec<S>::C;
+    constexpr int N = P + 1, NN = N * N * N;
+    constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
+    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+        const ProbEntry& pe = entry<MULTI>(L, tile);
+        const int blk = tile - pe.tile_begin;
+        const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+        const int npx = n0 - 1, npy = n1 - 1;
+        const C* pbuf = static_cast<const C*>(pe.d);
+        S* z = static_cast<S*>(pe.c) + (size_t)blk * NN * kLanes;
+        const C alpha = (C)pe.alpha;
+        for (int idx = threadIdx.x; idx < NN * kLanes; idx += 256) {
+            const int l = idx / kLanes, lane = idx % kLanes;
+            const int e = blk * kLanes + lane;
+            C sum = 0;
+            if (e < pe.ncells) {
+                const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
+                const int a = l % N, b = (l / N) % N, c = l / (N * N);
+                // per direction: up to two (vertex, patch-local index) pairs,
+                // increasing vertex order
+                int vx[2], qx[2], nx = 0, vy[2], qy[2], ny = 0, vz[2], qz[2], nz = 0;
+                if (a == 0) { vx[0] = i; qx[0] = P - 1; nx = 1; }
+                else if (a == P) { vx[0] = i + 1; qx[0] = P - 1; nx = 1; }
+                else { vx[0] = i; qx[0] = P - 1 + a; vx[1] = i + 1; qx[1] = a - 1; nx = 2; }
+                if (b == 0) { vy[0] = j; qy[0] = P - 1; ny = 1; }
+                else if (b == P) { vy[0] = j + 1; qy[0] = P - 1; ny = 1; }
+                else { vy[0] = j; qy[0] = P - 1 + b; vy[1] = j + 1; qy[1] = b - 1; ny = 2; }
+                if (c == 0) { vz[0] = k; qz[0] = P - 1; nz = 1; }
+                else if (c == P) { vz[0] = k + 1; qz[0] = P - 1; nz = 1; }
+                else { vz[0] = k; qz[0] = P - 1 + c; vz[1] = k + 1; qz[1] = c - 1; nz = 2; }
+                for (int sz = 0; sz < nz; ++sz) {
+                    if (vz[sz] < 1 || vz[sz] > n2 - 1) continue;
+                    for (int sy = 0; sy < ny; ++sy) {
+                        if (vy[sy] < 1 || vy[sy] > npy) continue;
+                        for (int sx = 0; sx < nx; ++sx) {
+                            if (vx[sx] < 1 || vx[sx] > npx) continue;
+                            const int pidx = (vx[sx] - 1) + npx * ((vy[sy] - 1) + npy * (vz[sz] - 1));
+                            const int q = qx[sx] + nP * (qy[sy] + nP * qz[sz]);
+                            sum += pbuf[(size_t)(pidx / kLanes) * nP3 * kLanes + (size_t)q * kLanes + (pidx % kLanes)];
+                        }
+                    }
+                }
+            }
+            C out = alpha * sum;
+            if (ACC) out = load_as<C>(z + idx) + out;
+            if (e >= pe.ncells) out = (C)0;
+            store_from(z + idx, out);
+        }
+    }
+}
+
+template <int P, typename S>
+static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, ProbEntry* d_tab, hipStream_t s) {
+    using C = typename Prec<S>::C;
+    constexpr int CBP = pi_patches_per_tile<P, C>();
+    LaunchTable L{};
+    int tiles = 0;
+    for (int i = 0; i < nprob; ++i) {
+        const int npx = ents[i].n[0] - 1, npy = ents[i].n[1] - 1, npz = ents[i].n[2] - 1;
+        ents[i].tile_begin = tiles;
+        ents[i].ntiles = (npx > 0 && npy > 0 && npz > 0) ? ((npx + CBP - 1) / CBP) * npy * npz : 0;
+        tiles += ents[i].ntiles;
+    }
+    L.nprob = nprob;
+    L.total_tiles = tiles;
+    hipError_t err = stage_table(L, ents, nprob, d_tab, s);
+    if (err != hipSuccess) return err;
+    if (tiles > 0) {
+        const int grid = tiles < kMaxGrid ? tiles : kMaxGrid;
+        if (nprob > 1) hipLaunchKernelGGL((k_pi_solve<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, L);
+        else hipLaunchKernelGGL((k_pi_solve<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, L);
+        err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    // phase 2 over storage blocks (separate table: tile ranges differ)
+    int tiles2 = 0;
+    for (int i = 0; i < nprob; ++i) {
+        ents[i].tile_begin = tiles2;
+        ents[i].ntiles = ents[i].nblk;
+        tiles2 += ents[i].nblk;
+    }
+    LaunchTable L2{};
+    L2.nprob = nprob;
+    L2.total_tiles = tiles2;
+    err = stage_table(L2, ents, nprob, nprob > 1 ? d_tab + nprob : d_tab, s);
+    if (err != hipSuccess) return err;
+    const int grid2 = tiles2 < kMaxGrid ? tiles2 : kMaxGrid;
+    if (nprob > 1) {
+        if (accumulate) hipLaunchKernelGGL((k_pi_combine<P, S, 1, true>), dim3(grid2), dim3(256), 0, s, L2);
+        else hipLaunchKernelGGL((k_pi_combine<P, S, 0, true>), dim3(grid2), dim3(256), 0, s, L2);
+    } else {
+        if (accumulate) hipLaunchKernelGGL((k_pi_combine<P, S, 1, false>), dim3(grid2), dim3(256), 0, s, L2);
+        else hipLaunchKernelGGL((k_pi_combine<P, S, 0, false>), dim3(grid2), dim3(256), 0, s, L2);
+    }
+    return hipGetLastError();
+}
+
+template <int P>
+static hipError_t launch_pi_p(int prec, int acc, ProbEntry* e, int n, ProbEntry* t, hipStream_t s) {
+    switch (prec) {
+        case FEM_F64: return launch_pi_t<P, double>(acc, e, n, t, s);
+        case FEM_F32: return launch_pi_t<P, float>(acc, e, n, t, s);
+        default: return launch_pi_t<P, bf16_t>(acc, e, n, t, s);
+    }
+}
+
+hipError_t launch_patch_inverse(int p, int prec, int accumulate, ProbEntry* ents, int nprob,
+                                ProbEntry* d_tab, hipStream_t s) {
+    switch (p) {
+        case 1: return launch_pi_p<1>(prec, accumulate, ents, nprob, d_tab, s);
+        case 2: return launch_pi_p<2>(prec, accumulate, ents, nprob, d_tab, s);
+        case 3: return launch_pi_p<3>(prec, accumulate, ents, nprob, d_tab, s);
+        case 4: return launch_pi_p<4>(prec, accumulate, ents, nprob, d_tab, s);
+        case 5: return launch_pi_p<5>(prec, accumulate, ents, nprob, d_tab, s);
+        case 6: return launch_pi_p<6>(prec, accumulate, ents, nprob, d_tab, s);
+        case 7: return launch_pi_p<7>(prec, accumulate, ents, nprob, d_tab, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace fem

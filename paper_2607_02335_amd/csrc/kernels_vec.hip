@@ -1,0 +1,610 @@
+// Cell-wise vector kernels: layout converters, deterministic reductions, the
+// assembled residual norm, the DSS axis pass and the fused (F)PCG updates.
+//
+// Every pairing in the solver is a plain local dot product over all cell-wise
+// entries: for a dual f and a primal u, <f, u> = <G^T f, u_global> (Lemma
+// "Duality Pairing Identity", Section 3.1), so no assembly is needed.
+// Reductions are deterministic: a problem's vector is cut into a fixed number
+// of tiles (independent of anything else in the launch), each tile is summed
+// in a fixed order (thread-strided sums, a fixed shuffle tree, four wave
+// partials), and a final kernel adds the tile partials in index order.
+#include "fem_internal.h"
+#include "launch.h"
+
+namespace fem {
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) r = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+    __syncthreads();
+    return r;
+}
+
+// ------------------------------------------------------------------- dots
+// partial[group][t] = sum over tile t of a[i] * b[i]
+template <typename SA, typename SB, bool MULTI>
+__global__ void __launch_bounds__(256) k_dot(LaunchTable L, int group) {
+    __shared__ double sh[4];
+    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+        const ProbEntry& pe = entry<MULTI>(L, tile);
+        const int t = tile - pe.tile_begin;
+        const size_t bs = pe.len / pe.nblk;                       // elements per storage block
+        const size_t lo = (size_t)t * pe.blocks_per_red * bs;
+        size_t hi = lo + (size_t)pe.blocks_per_red * bs;
+        if (hi > pe.len) hi = pe.len;
+        const SA* a = static_cast<const SA*>(pe.a);
+        const SB* b = static_cast<const SB*>(pe.b);
+        double acc = 0.0;
+        for (size_t i = lo + threadIdx.x; i < hi; i += 256)
+            acc += (double)load_as<double>(a + i) * (double)load_as<double>(b + i);
+        const double s = block_sum(acc, sh);
+        if (threadIdx.x == 0) pe.red[group * kRedParts + t] = s;
+    }
+}
+
+// slots[slot] = sum of the group's tile partials (one workgroup per problem)
+template <bool MULTI>
+__global__ void __launch_bounds__(256) k_red_final(LaunchTable L, int group, int slot) {
+    __shared__ double sh[4];
+    const int i = blockIdx.x;
+    const ProbEntry& pe = entry_at<MULTI>(L, i);
+    double acc = 0.0;
+    for (int t = threadIdx.x; t < pe.ntiles_red; t += 256) acc += pe.red[group * kRedParts + t];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) red_slots(pe.red)[slot] = s;
+}
+
+// -------------------------------------------------- assembled norm ||G^T r||^2
+// Each global node is owned by its copy in the lowest-numbered cell along
+// every direction; the owner sums all copies (fixed order) and squares.
+template <int P, typename S, bool MULTI>
+__global__ void __launch_bounds__(256) k_anorm(LaunchTable L, int group) {
+    constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
+    __shared__ double sh[4];
+    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+        const ProbEntry& pe = entry<MULTI>(L, tile);
+        const int t = tile - pe.tile_begin;
+        const int b0 = t * pe.blocks_per_red;
+        int b1 = b0 + pe.blocks_per_red;
+        if (b1 > pe.nblk) b1 = pe.nblk;
+        const S* v = static_cast<const S*>(pe.a);
+        const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+        double acc = 0.0;
+        for (long idx = (long)b0 * NN * kLanes + threadIdx.x; idx < (long)b1 * NN * kLanes; idx += 256) {
+            const int blk = (int)(idx / (NN * kLanes));
+            const int rem = (int)(idx % (NN * kLanes));
+            const int l = rem / kLanes, lane = rem % kLanes;
+            const int e = blk * kLanes + lane;
+            if (e >= pe.ncells) continue;
+            const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
+            const int a = l % N, b = (l / N) % N, c = l / N2;
+            if ((a == P && i < n0 - 1) || (b == P && j < n1 - 1) || (c == P && k < n2 - 1)) continue;
+            const int cx = (a == 0 && i > 0) ? 2 : 1;
+            const int cy = (b == 0 && j > 0) ? 2 : 1;
+            const int cz = (c == 0 && k > 0) ? 2 : 1;
+            double s = 0.0;
+            for (int sz = 0; sz < cz; ++sz)
+                for (int sy = 0; sy < cy; ++sy)
+                    for (int sx = 0; sx < cx; ++sx) {
+                        const int ee = (i - sx) + n0 * ((j - sy) + n1 * (k - sz));
+                        const int ll = (sx ? P : a) + N * ((sy ? P : b) + N * (sz ? P : c));
+                        s += load_as<double>(v + cell_offset(ee, ll, NN));
+                    }
+            acc += s * s;
+        }
+        const double r = block_sum(acc, sh);
+        if (threadIdx.x == 0) pe.red[group * kRedParts + t] = r;
+    }
+}
+
+// ------------------------------------- assembled residual for a demoted smoother
+// rs(copy) = (G^T r)(node) / multiplicity(node), summed in FP64 over all copies
+// in ascending cell order (the same order for every copy), then rounded to
+// the smoother precision RS; owner copies add (G^T r)^2 to the norm partials.
+// The unassembled dual residual of a converging solve carries per-copy
+// values far larger than its assembly (they cancel across interfaces), so
+// rounding copies before assembling would leave an absolute error of
+// eps(RS) times those values in the smoother's input.
+template <int P, typename RS, bool MULTI>
+__global__ void __launch_bounds__(256) k_distribute(LaunchTable L, int group) {
+    constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
+    __shared__ double sh[4];
+    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+        const ProbEntry& pe = entry<MULTI>(L, tile);
+        const int t = tile - pe.tile_begin;
+        const int b0 = t * pe.blocks_per_red;
+        int b1 = b0 + pe.blocks_per_red;
+        if (b1 > pe.nblk) b1 = pe.nblk;
+        const double* v = static_cast<const double*>(pe.a);
+        RS* out = static_cast<RS*>(pe.c);
+        const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+        double acc = 0.0;
+        for (long idx = (long)b0 * NN * kLanes + threadIdx.x; idx < (long)b1 * NN * kLanes; idx += 256) {
+            const int blk = (int)(idx / (NN * kLanes));
+            const int rem = (int)(idx % (NN * kLanes));
+            const int l = rem / kLanes, lane = rem % kLanes;
+            const int e = blk * kLanes + lane;
+            if (e >= pe.ncells) {
+                store_from(out + idx, (typename Prec<RS>::C)0);
+                continue;
+            }
+            const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
+            const int a = l % N, b = (l / N) % N, c = l / N2;
+            // sharing cells per direction: (cell, local index), ascending cell
+            int ci[2], ai[2], nx, cj[2], bj[2], ny, ck[2], ck_l[2], nz;
+            if (a == 0 && i > 0) { ci[0] = i - 1; ai[0] = P; ci[1] = i; ai[1] = 0; nx = 2; }
+            else if (a == P && i < n0 - 1) { ci[0] = i; ai[0] = P; ci[1] = i + 1; ai[1] = 0; nx = 2; }
+            else { ci[0] = i; ai[0] = a; nx = 1; }
+            if (b == 0 && j > 0) { cj[0] = j - 1; bj[0] = P; cj[1] = j; bj[1] = 0; ny = 2; }
+            else if (b == P && j < n1 - 1) { cj[0] = j; bj[0] = P; cj[1] = j + 1; bj[1] = 0; ny = 2; }
+            else { cj[0] = j; bj[0] = b; ny = 1; }
+            if (c == 0 && k > 0) { ck[0] = k - 1; ck_l[0] = P; ck[1] = k; ck_l[1] = 0; nz = 2; }
+            else if (c == P && k < n2 - 1) { ck[0] = k; ck_l[0] = P; ck[1] = k + 1; ck_l[1] = 0; nz = 2; }
+            else { ck[0] = k; ck_l[0] = c; nz = 1; }
+            double s = 0.0;
+            for (int z = 0; z < nz; ++z)
+                for (int y = 0; y < ny; ++y)
+                    for (int x = 0; x < nx; ++x) {
+                        const int ee = ci[x] + n0 * (cj[y] + n1 * ck[z]);
+                        const int ll = ai[x] + N * (bj[y] + N * ck_l[z]);
+                        s += v[cell_offset(ee, ll, NN)];
+                    }
+            store_from(out + idx, (typename Prec<RS>::C)(s / (double)(nx * ny * nz)));
+            // owner copy: lowest cell along every direction
+            if (ci[0] == i && cj[0] == j && ck[0] == k) acc += s * s;
+        }
+        const double r = block_sum(acc, sh);
+        if (threadIdx.x == 0) pe.red[group * kRedParts + t] = r;
+    }
+}
+
+// ------------------------------------------------------------ DSS axis pass
+// One thread per (interface, face node): both coincident copies receive their
+// sum (Algorithm "Dimensionally-Split Structured Summation").
+template <int P, typename S>
+__global__ void __launch_bounds__(256) k_dss_axis(ProbEntry pe, int axis, long total) {
+    using C = typename Prec<S>::C;
+    constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
+    const long t = (long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= total) return;
+    const int n0 = pe.n[0], n1 = pe.n[1];
+    int eL, lL, eR, lR;
+    if (axis == 0) {
+        const int ii = t % (n0 - 1);
+        long r = t / (n0 - 1);
+        const int fn = r % N2;
+        r /= N2;
+        const int j = r % n1, k = r / n1;
+        const int b = fn % N, c = fn / N;
+        eL = ii + n0 * (j + n1 * k);
+        eR = eL + 1;
+        lL = P + N * (b + N * c);
+        lR = 0 + N * (b + N * c);
+    } else if (axis == 1) {
+        const int i = t % n0;
+        long r = t / n0;
+        const int jj = r % (n1 - 1);
+        r /= (n1 - 1);
+        const int fn = r % N2;
+        const int k = r / N2;
+        const int a = fn % N, c = fn / N;
+        eL = i + n0 * (jj + n1 * k);
+        eR = eL + n0;
+        lL = a + N * (P + N * c);
+        lR = a + N * (0 + N * c);
+    } else {
+        const int i = t % n0;
+        long r = t / n0;
+        const int j = r % n1;
+        r /= n1;
+        const int kk = r % (pe.n[2] - 1);
+        const int fn = r / (pe.n[2] - 1);
+        const int a = fn % N, b = fn / N;
+        eL = i + n0 * (j + n1 * kk);
+        eR = eL + n0 * n1;
+        lL = a + N * (b + N * P);
+        lR = a + N * (b + N * 0);
+    }
+    S* v = static_cast<S*>(pe.c);
+    S* pL = v + cell_offset(eL, lL, NN);
+    S* pR = v + cell_offset(eR, lR, NN);
+    const C s = load_as<C>(pL) + load_as<C>(pR);
+    store_from(pL, s);
+    store_from(pR, s);
+}
+
+// ------------------------------------------------------------ converters
+template <typename S>
+__global__ void __launch_bounds__(256) k_gather(ProbEntry pe, const double* __restrict__ xg) {
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= pe.len) return;
+    const int p = pe.p, N = p + 1, NN = N * N * N;
+    const int blk = t / ((size_t)NN * kLanes);
+    const int rem = t % ((size_t)NN * kLanes);
+    const int l = rem / kLanes, lane = rem % kLanes;
+    const int e = blk * kLanes + lane;
+    double v = 0.0;
+    if (e < pe.ncells) {
+        const int n0 = pe.n[0], n1 = pe.n[1];
+        const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
+        const int a = l % N, b = (l / N) % N, c = l / (N * N);
+        const size_t G0 = (size_t)n0 * p + 1, G1 = (size_t)n1 * p + 1;
+        v = xg[(size_t)(i * p + a) + G0 * ((size_t)(j * p + b) + G1 * (size_t)(k * p + c))];
+    }
+    store_from(static_cast<S*>(pe.c) + t, v);
+}
+
+// mode 0: sum all copies (G^T); mode 1: copy of the lowest-numbered cell
+template <typename S>
+__global__ void __launch_bounds__(256) k_to_global(ProbEntry pe, double* __restrict__ yg, int mode) {
+    const int p = pe.p, N = p + 1, NN = N * N * N;
+    const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+    const size_t G0 = (size_t)n0 * p + 1, G1 = (size_t)n1 * p + 1, G2 = (size_t)n2 * p + 1;
+    const size_t g = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (g >= G0 * G1 * G2) return;
+    const int I = g % G0, J = (g / G0) % G1, K = g / (G0 * G1);
+    int ci[3][2], li[3][2], cnt[3];
+    const int idx[3] = {I, J, K};
+    const int nn[3] = {n0, n1, n2};
+    for (int d = 0; d < 3; ++d) {
+        cnt[d] = 0;
+        const int q = idx[d] / p, r = idx[d] % p;
+        if (r == 0 && q >= 1) { ci[d][cnt[d]] = q - 1; li[d][cnt[d]] = p; ++cnt[d]; }
+        if (q <= nn[d] - 1) { ci[d][cnt[d]] = q; li[d][cnt[d]] = r; ++cnt[d]; }
+        if (mode == 1) cnt[d] = 1;
+    }
+    const S* v = static_cast<const S*>(pe.a);
+    double s = 0.0;
+    for (int z = 0; z < cnt[2]; ++z)
+        for (int y = 0; y < cnt[1]; ++y)
+            for (int x = 0; x < cnt[0]; ++x) {
+                const int e = ci[0][x] + n0 * (ci[1][y] + n1 * ci[2][z]);
+                const int l = li[0][x] + N * (li[1][y] + N * li[2][z]);
+                s += load_as<double>(v + cell_offset(e, l, NN));
+            }
+    yg[g] = s;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_pack(ProbEntry pe, const double* __restrict__ canon,
+                                              double* __restrict__ out_canon, int unpack) {
+    const int N = pe.p + 1, NN = N * N * N;
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (size_t)pe.ncells * NN) return;
+    const int e = t / NN, l = t % NN;
+    const size_t off = cell_offset(e, l, NN);
+    if (unpack) out_canon[t] = load_as<double>(static_cast<const S*>(pe.a) + off);
+    else store_from(static_cast<S*>(pe.c) + off, canon[t]);
+}
+
+template <typename SA, typename SB>
+__global__ void __launch_bounds__(256) k_convert(const SA* __restrict__ a, SB* __restrict__ b, size_t n) {
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < n) store_from(b + t, load_as<typename Prec<SB>::C>(a + t));
+}
+
+template <typename S>
+__global__ void __launch_bounds__(256) k_fill_zero(S* __restrict__ a, size_t n) {
+    const size_t t = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (t < n) store_from(a + t, (typename Prec<S>::C)0);
+}
+
+// --------------------------------------------------------- (F)PCG updates
+// u += alpha p; r -= alpha q with alpha = <r,z>/<q,p> from the slots; the
+// smoother's copy of r (precision RS) is written in the same pass.
+template <typename RS, bool MULTI>
+__global__ void __launch_bounds__(256) k_cg_ur(LaunchTable L) {
+    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+        const ProbEntry& pe = entry<MULTI>(L, tile);
+        const int t = tile - pe.tile_begin;
+        const double* sl = red_slots(pe.red);
+        const double alpha = sl[kSlotRZ] / sl[kSlotQP];
+        const size_t bs = pe.len / pe.nblk;
+        const size_t lo = (size_t)t * bs, hi = lo + bs;
+        const double* p = static_cast<const double*>(pe.a);
+        const double* q = static_cast<const double*>(pe.b);
+        double* u = static_cast<double*>(pe.c);
+        double* r = static_cast<double*>(pe.d);
+        RS* rs = static_cast<RS*>(pe.e);
+        for (size_t i = lo + threadIdx.x; i < hi; i += 256) {
+            u[i] = u[i] + alpha * p[i];
+            const double rn = r[i] - alpha * q[i];
+            r[i] = rn;
+            if (rs) store_from(rs + i, (typename Prec<RS>::C)rn);
+        }
+    }
+}
+
+// p = z + beta p; beta = <r',z'>/<r,z> (PCG) or -<q,z'>/<q,p> (FCG)
+template <typename SZ, bool MULTI>
+__global__ void __launch_bounds__(256) k_cg_p(LaunchTable L, int variant) {
+    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+        const ProbEntry& pe = entry<MULTI>(L, tile);
+        const int t = tile - pe.tile_begin;
+        const double* sl = red_slots(pe.red);
+        const double beta = variant == FEM_CG_PCG ? sl[kSlotRZ] / sl[kSlotRZOld] : -sl[kSlotQZ] / sl[kSlotQP];
+        const size_t bs = pe.len / pe.nblk;
+        const size_t lo = (size_t)t * bs, hi = lo + bs;
+        const SZ* z = static_cast<const SZ*>(pe.a);
+        double* p = static_cast<double*>(pe.c);
+        for (size_t i = lo + threadIdx.x; i < hi; i += 256)
+            p[i] = load_as<double>(z + i) + beta * p[i];
+    }
+}
+
+// p = z (initial direction), z in precision SZ
+template <bool MULTI>
+__global__ void k_slot_copy(LaunchTable L, int dst, int src) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.nprob) return;
+    const ProbEntry& pe = entry_at<MULTI>(L, i);
+    double* sl = red_slots(pe.red);
+    sl[dst] = sl[src];
+}
+
+// =========================================================================
+// Host launchers
+static inline int grid_for(size_t n) { return (int)((n + 255) / 256); }
+
+ProbEntry entry_of(const fem_problem* P) {
+    ProbEntry e{};
+    e.n[0] = P->n[0];
+    e.n[1] = P->n[1];
+    e.n[2] = P->n[2];
+    e.p = P->p;
+    e.len = P->cell_len;
+    e.ncells = P->ncells;
+    e.nblk = P->nblk;
+    e.dirichlet = P->bc == FEM_BC_DIRICHLET;
+    e.h[0] = P->d_h;
+    e.h[1] = P->d_h + P->n[0];
+    e.h[2] = P->d_h + P->n[0] + P->n[1];
+    e.red = P->d_red;
+    e.blocks_per_red = (P->nblk + kRedParts - 1) / kRedParts;
+    e.ntiles_red = (P->nblk + e.blocks_per_red - 1) / e.blocks_per_red;
+    return e;
+}
+
+template <typename F>
+static hipError_t dispatch_prec(int prec, F&& f) {
+    switch (prec) {
+        case FEM_F64: return f(double{});
+        case FEM_F32: return f(float{});
+        case FEM_BF16: return f(bf16_t{});
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t run_fill_zero(fem_problem* P, void* v, int prec) {
+    return dispatch_prec(prec, [&](auto tag) {
+        using S = decltype(tag);
+        hipLaunchKernelGGL((k_fill_zero<S>), dim3(grid_for(P->cell_len)), dim3(256), 0, P->stream,
+                           static_cast<S*>(v), P->cell_len);
+        return hipGetLastError();
+    });
+}
+
+hipError_t run_convert(fem_problem* P, const void* src, int sp, void* dst, int dp) {
+    return dispatch_prec(sp, [&](auto ta) {
+        using SA = decltype(ta);
+        return dispatch_prec(dp, [&](auto tb) {
+            using SB = decltype(tb);
+            hipLaunchKernelGGL((k_convert<SA, SB>), dim3(grid_for(P->cell_len)), dim3(256), 0, P->stream,
+                               static_cast<const SA*>(src), static_cast<SB*>(dst), P->cell_len);
+            return hipGetLastError();
+        });
+    });
+}
+
+hipError_t run_gather(fem_problem* P, const double* xg, void* xc, int prec) {
+    ProbEntry e = entry_of(P);
+    e.c = xc;
+    return dispatch_prec(prec, [&](auto tag) {
+        using S = decltype(tag);
+        hipLaunchKernelGGL((k_gather<S>), dim3(grid_for(P->cell_len)), dim3(256), 0, P->stream, e, xg);
+        return hipGetLastError();
+    });
+}
+
+static hipError_t run_to_global(fem_problem* P, const void* yc, double* yg, int prec, int mode) {
+    ProbEntry e = entry_of(P);
+    e.a = yc;
+    return dispatch_prec(prec, [&](auto tag) {
+        using S = decltype(tag);
+        hipLaunchKernelGGL((k_to_global<S>), dim3(grid_for(P->global_len)), dim3(256), 0, P->stream, e, yg, mode);
+        return hipGetLastError();
+    });
+}
+hipError_t run_scatter(fem_problem* P, const void* yc, double* yg, int prec) {
+    return run_to_global(P, yc, yg, prec, 0);
+}
+hipError_t run_extract(fem_problem* P, const void* uc, double* ug, int prec) {
+    return run_to_global(P, uc, ug, prec, 1);
+}
+
+hipError_t run_pack(fem_problem* P, const double* canon, void* vc, int prec, int unpack) {
+    ProbEntry e = entry_of(P);
+    const int N = P->p + 1;
+    const size_t n = (size_t)P->ncells * N * N * N;
+    if (unpack) e.a = vc; else e.c = vc;
+    return dispatch_prec(prec, [&](auto tag) {
+        using S = decltype(tag);
+        hipError_t err = hipSuccess;
+        if (!unpack) {      // padding entries must be zero
+            hipLaunchKernelGGL((k_fill_zero<S>), dim3(grid_for(P->cell_len)), dim3(256), 0, P->stream,
+                               static_cast<S*>(vc), P->cell_len);
+            err = hipGetLastError();
+            if (err != hipSuccess) return err;
+        }
+        hipLaunchKernelGGL((k_pack<S>), dim3(grid_for(n)), dim3(256), 0, P->stream, e, canon,
+                           const_cast<double*>(canon), unpack);
+        return hipGetLastError();
+    });
+}
+
+template <int P_, typename S>
+static void launch_dss_axis(const ProbEntry& e, int axis, long total, hipStream_t s) {
+    hipLaunchKernelGGL((k_dss_axis<P_, S>), dim3((total + 255) / 256), dim3(256), 0, s, e, axis, total);
+}
+
+hipError_t run_dss_axis(fem_problem* P, void* v, int axis, int prec) {
+    ProbEntry e = entry_of(P);
+    e.c = v;
+    const int N = P->p + 1;
+    long total;
+    if (axis == 0) total = (long)(P->n[0] - 1) * P->n[1] * P->n[2] * N * N;
+    else if (axis == 1) total = (long)P->n[0] * (P->n[1] - 1) * P->n[2] * N * N;
+    else total = (long)P->n[0] * P->n[1] * (P->n[2] - 1) * N * N;
+    if (total <= 0) return hipSuccess;
+    return dispatch_prec(prec, [&](auto tag) {
+        using S = decltype(tag);
+        switch (P->p) {
+            case 1: launch_dss_axis<1, S>(e, axis, total, P->stream); break;
+            case 2: launch_dss_axis<2, S>(e, axis, total, P->stream); break;
+            case 3: launch_dss_axis<3, S>(e, axis, total, P->stream); break;
+            case 4: launch_dss_axis<4, S>(e, axis, total, P->stream); break;
+            case 5: launch_dss_axis<5, S>(e, axis, total, P->stream); break;
+            case 6: launch_dss_axis<6, S>(e, axis, total, P->stream); break;
+            case 7: launch_dss_axis<7, S>(e, axis, total, P->stream); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    });
+}
+
+static hipError_t finish_reduction(fem_problem* P, const ProbEntry& e, int group, int slot) {
+    LaunchTable L{};
+    L.nprob = 1;
+    L.one = e;
+    hipLaunchKernelGGL(k_red_final<false>, dim3(1), dim3(256), 0, P->stream, L, group, slot);
+    return hipGetLastError();
+}
+
+hipError_t run_dot(fem_problem* P, const void* a, int pa, const void* b, int pb, int slot) {
+    ProbEntry e = entry_of(P);
+    e.a = a;
+    e.b = b;
+    e.tile_begin = 0;
+    LaunchTable L{};
+    L.nprob = 1;
+    L.total_tiles = e.ntiles_red;
+    L.one = e;
+    hipError_t err = dispatch_prec(pa, [&](auto ta) {
+        using SA = decltype(ta);
+        return dispatch_prec(pb, [&](auto tb) {
+            using SB = decltype(tb);
+            hipLaunchKernelGGL((k_dot<SA, SB, false>), dim3(L.total_tiles), dim3(256), 0, P->stream, L, 0);
+            return hipGetLastError();
+        });
+    });
+    if (err != hipSuccess) return err;
+    return finish_reduction(P, e, 0, slot);
+}
+
+hipError_t run_assembled_norm2(fem_problem* P, const void* r, int prec, int slot) {
+    ProbEntry e = entry_of(P);
+    e.a = r;
+    e.tile_begin = 0;
+    LaunchTable L{};
+    L.nprob = 1;
+    L.total_tiles = e.ntiles_red;
+    L.one = e;
+    hipError_t err = dispatch_prec(prec, [&](auto tag) {
+        using S = decltype(tag);
+        dim3 g(L.total_tiles), b(256);
+        switch (P->p) {
+            case 1: hipLaunchKernelGGL((k_anorm<1, S, false>), g, b, 0, P->stream, L, 1); break;
+            case 2: hipLaunchKernelGGL((k_anorm<2, S, false>), g, b, 0, P->stream, L, 1); break;
+            case 3: hipLaunchKernelGGL((k_anorm<3, S, false>), g, b, 0, P->stream, L, 1); break;
+            case 4: hipLaunchKernelGGL((k_anorm<4, S, false>), g, b, 0, P->stream, L, 1); break;
+            case 5: hipLaunchKernelGGL((k_anorm<5, S, false>), g, b, 0, P->stream, L, 1); break;
+            case 6: hipLaunchKernelGGL((k_anorm<6, S, false>), g, b, 0, P->stream, L, 1); break;
+            case 7: hipLaunchKernelGGL((k_anorm<7, S, false>), g, b, 0, P->stream, L, 1); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    });
+    if (err != hipSuccess) return err;
+    return finish_reduction(P, e, 1, slot);
+}
+
+hipError_t run_distribute(fem_problem* P, const double* r, void* out, int prec, int slot) {
+    ProbEntry e = entry_of(P);
+    e.a = r;
+    e.c = out;
+    e.tile_begin = 0;
+    LaunchTable L{};
+    L.nprob = 1;
+    L.total_tiles = e.ntiles_red;
+    L.one = e;
+    hipError_t err = dispatch_prec(prec, [&](auto tag) {
+        using S = decltype(tag);
+        dim3 g(L.total_tiles), b(256);
+        switch (P->p) {
+            case 1: hipLaunchKernelGGL((k_distribute<1, S, false>), g, b, 0, P->stream, L, 2); break;
+            case 2: hipLaunchKernelGGL((k_distribute<2, S, false>), g, b, 0, P->stream, L, 2); break;
+            case 3: hipLaunchKernelGGL((k_distribute<3, S, false>), g, b, 0, P->stream, L, 2); break;
+            case 4: hipLaunchKernelGGL((k_distribute<4, S, false>), g, b, 0, P->stream, L, 2); break;
+            case 5: hipLaunchKernelGGL((k_distribute<5, S, false>), g, b, 0, P->stream, L, 2); break;
+            case 6: hipLaunchKernelGGL((k_distribute<6, S, false>), g, b, 0, P->stream, L, 2); break;
+            case 7: hipLaunchKernelGGL((k_distribute<7, S, false>), g, b, 0, P->stream, L, 2); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    });
+    if (err != hipSuccess) return err;
+    return finish_reduction(P, e, 2, slot);
+}
+
+hipError_t run_cg_update_ur(fem_problem* P, double* u, double* r, const double* p, const double* q,
+                            void* rs, int rs_prec) {
+    ProbEntry e = entry_of(P);
+    e.a = p;
+    e.b = q;
+    e.c = u;
+    e.d = r;
+    e.e = rs;
+    e.tile_begin = 0;
+    LaunchTable L{};
+    L.nprob = 1;
+    L.total_tiles = e.nblk;
+    L.one = e;
+    const int grid = e.nblk < kMaxGrid ? e.nblk : kMaxGrid;
+    return dispatch_prec(rs ? rs_prec : FEM_F64, [&](auto tag) {
+        using S = decltype(tag);
+        hipLaunchKernelGGL((k_cg_ur<S, false>), dim3(grid), dim3(256), 0, P->stream, L);
+        return hipGetLastError();
+    });
+}
+
+hipError_t run_cg_update_p(fem_problem* P, double* p, const void* z, int zprec, int variant) {
+    ProbEntry e = entry_of(P);
+    e.a = z;
+    e.c = p;
+    e.tile_begin = 0;
+    LaunchTable L{};
+    L.nprob = 1;
+    L.total_tiles = e.nblk;
+    L.one = e;
+    const int grid = e.nblk < kMaxGrid ? e.nblk : kMaxGrid;
+    return dispatch_prec(zprec, [&](auto tag) {
+        using S = decltype(tag);
+        hipLaunchKernelGGL((k_cg_p<S, false>), dim3(grid), dim3(256), 0, P->stream, L, variant);
+        return hipGetLastError();
+    });
+}
+
+hipError_t run_slot_copy(fem_problem* P, int dst, int src) {
+    LaunchTable L{};
+    L.nprob = 1;
+    L.one = entry_of(P);
+    hipLaunchKernelGGL(k_slot_copy<false>, dim3(1), dim3(64), 0, P->stream, L, dst, src);
+    return hipGetLastError();
+}
+
+}  // namespace fem

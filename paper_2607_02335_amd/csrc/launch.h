@@ -1,0 +1,82 @@
+// Host-side launch helpers shared by the kernel translation units.
+#pragma once
+
+#include "fem_internal.h"
+
+namespace fem {
+
+// Cap on persistent grids: kernels loop over their tiles, so a grid of a few
+// workgroups per compute unit (256 CUs) keeps every CU busy.
+constexpr int kMaxGrid = 256 * 8;
+// Number of workgroup partial sums of one reduction (fixed, so the
+// reduction order of a problem never depends on what else is launched).
+constexpr int kRedParts = 512;
+// Scalar slots after the partials in a problem's reduction area.
+enum RedSlot {
+    kSlotRZ = 0,      // <r, z>
+    kSlotQP = 1,      // <q, p>
+    kSlotQZ = 2,      // <q, z>
+    kSlotRN = 3,      // ||G^T r||^2
+    kSlotRZOld = 4,   // previous <r, z>
+    kSlotTmp = 5,     // generic dot result
+    kSlotB2 = 6,      // ||G^T b||^2
+    kSlotCount = 8
+};
+constexpr int kRedStride = kRedParts * 4 + kSlotCount;   // 4 partial groups + slots
+__host__ __device__ inline double* red_slots(double* red) { return red + kRedParts * 4; }
+
+// 1D reference matrices of degree p on [0,1] (row-major, (p+1)^2), built on
+// the host once per process.
+const double* ref_mass(int p);
+const double* ref_stiff(int p);
+
+// Put the entry table where the kernel reads it: by value for a single
+// problem, else copied to d_tab on the stream (from host memory that must
+// stay valid until the copy has run).
+inline hipError_t stage_table(LaunchTable& L, const ProbEntry* ents, int nprob, ProbEntry* d_tab,
+                              hipStream_t s) {
+    if (nprob == 1) {
+        L.one = ents[0];
+        L.tab = nullptr;
+        return hipSuccess;
+    }
+    L.tab = d_tab;
+    return hipMemcpyAsync(d_tab, ents, sizeof(ProbEntry) * nprob, hipMemcpyHostToDevice, s);
+}
+
+// Kernel launchers.  Each fills tile_begin/ntiles of the entries.
+// apply: mode 0 y=Ax (a=x, c=y), 1 y=b-Ax (a=x, b=b, c=y), 2 y=Mx.
+hipError_t launch_apply(int p, int prec, int mode, ProbEntry* ents, int nprob, ProbEntry* d_tab,
+                        hipStream_t s, int force_lds);
+// patch inverse: a = r (dual), c = z (primal), d = patch buffer,
+// alpha = damping; accumulate: z = (acc ? z : 0) + alpha * P_AS r.
+hipError_t launch_patch_inverse(int p, int prec, int accumulate, ProbEntry* ents, int nprob,
+                                ProbEntry* d_tab, hipStream_t s);
+
+// Single-problem helpers (problem handle in, stream of the handle).
+ProbEntry entry_of(const fem_problem* P);
+hipError_t run_dss_axis(fem_problem* P, void* v, int axis, int prec);
+hipError_t run_gather(fem_problem* P, const double* xg, void* xc, int prec);
+hipError_t run_scatter(fem_problem* P, const void* yc, double* yg, int prec);
+hipError_t run_extract(fem_problem* P, const void* uc, double* ug, int prec);
+hipError_t run_pack(fem_problem* P, const double* canon, void* vc, int prec, int unpack);
+hipError_t run_convert(fem_problem* P, const void* src, int sp, void* dst, int dp);
+hipError_t run_fill_zero(fem_problem* P, void* v, int prec);
+// Dot product of two cell vectors into slot `slot` of the problem's
+// reduction area (device), deterministic order.
+hipError_t run_dot(fem_problem* P, const void* a, int pa, const void* b, int pb, int slot);
+// ||G^T r||^2 into slot `slot`.
+hipError_t run_assembled_norm2(fem_problem* P, const void* r, int prec, int slot);
+// out = G^T r / multiplicity per copy, assembled in FP64 and rounded to
+// `prec`; ||G^T r||^2 into slot `slot` (same pass).
+hipError_t run_distribute(fem_problem* P, const double* r, void* out, int prec, int slot);
+// (F)PCG vector updates, scalars read from the device slots.
+// u += alpha p; r -= alpha q; optionally rs = (smoother precision) r.
+hipError_t run_cg_update_ur(fem_problem* P, double* u, double* r, const double* p, const double* q,
+                            void* rs, int rs_prec);
+// p = z + beta p  (beta from slots, variant 1 = PCG, 2 = FCG); z in zprec.
+hipError_t run_cg_update_p(fem_problem* P, double* p, const void* z, int zprec, int variant);
+// rz_old <- rz (slot copy), on device
+hipError_t run_slot_copy(fem_problem* P, int dst, int src);
+
+}  // namespace fem

@@ -1,0 +1,351 @@
+"""Thin ctypes binding of libfem_mi355x.so (argument marshalling only).
+
+PyTorch supplies device memory and the current stream; every step of the
+computation runs in the library's HIP kernels.  The binding fails loudly if
+the library has not been built: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfem_mi355x.so")
+HEADER = os.path.join(HERE, "..", "include", "fem.h")
+
+FEM_OK, FEM_EINVAL, FEM_ENOMEM, FEM_EHIP, FEM_ENOTCONV, FEM_EBREAKDOWN, FEM_EAGAIN, FEM_ENOTFOUND = range(8)
+F64, F32, BF16 = 0, 1, 2
+DIRICHLET, NEUMANN = 0, 1
+CG_AUTO, CG_PCG, CG_FCG = 0, 1, 2
+STATUS_NAMES = {0: "FEM_OK", 1: "FEM_EINVAL", 2: "FEM_ENOMEM", 3: "FEM_EHIP", 4: "FEM_ENOTCONV",
+                5: "FEM_EBREAKDOWN", 6: "FEM_EAGAIN", 7: "FEM_ENOTFOUND"}
+
+
+class FemError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Desc(ct.Structure):
+    _fields_ = [("p", ct.c_int), ("n", ct.c_int * 3), ("widths", ct.POINTER(ct.c_double) * 3),
+                ("bc", ct.c_int)]
+
+
+class SolveInfo(ct.Structure):
+    _fields_ = [("iters", ct.c_int), ("status", ct.c_int), ("relres", ct.c_double),
+                ("seconds", ct.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load the HIP library (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_2607_02335_amd.build first")
+    L = ct.CDLL(LIB_PATH)
+    vp, i, d, sz = ct.c_void_p, ct.c_int, ct.c_double, ct.c_size_t
+    pp = ct.POINTER(vp)
+    sigs = {
+        "fem_problem_create": ([ct.POINTER(Desc), vp, pp], i),
+        "fem_problem_destroy": ([vp], i),
+        "fem_set_stream": ([vp, vp], i),
+        "fem_cell_len": ([vp], sz), "fem_global_len": ([vp], sz),
+        "fem_num_cells": ([vp], sz), "fem_num_patches": ([vp], sz),
+        "fem_footprint_bytes": ([ct.POINTER(Desc), i], sz),
+        "fem_prec_bytes": ([i], sz),
+        "fem_gather": ([vp, vp, vp, i], i), "fem_scatter": ([vp, vp, vp, i], i),
+        "fem_extract": ([vp, vp, vp, i], i), "fem_pack": ([vp, vp, vp, i], i),
+        "fem_unpack": ([vp, vp, vp, i], i), "fem_convert": ([vp, vp, i, vp, i], i),
+        "fem_distribute_assembled": ([vp, vp, vp, i], i),
+        "fe_apply": ([vp, vp, vp, i], i), "fe_mass_apply": ([vp, vp, vp, i], i),
+        "fem_dss": ([vp, vp, vp, i], i), "fem_dss_axis": ([vp, vp, i, i], i),
+        "patch_inverse": ([vp, vp, vp, i], i),
+        "smoother_step": ([vp, vp, vp, i, i, d], i),
+        "fem_dot": ([vp, vp, i, vp, i, ct.POINTER(d)], i),
+        "fem_assembled_norm": ([vp, vp, i, ct.POINTER(d)], i),
+        "pcg_solve": ([vp, vp, vp, d, i, i, i, d, i, ct.POINTER(SolveInfo)], i),
+        "fem_batch_create": ([i, ct.POINTER(Desc), vp, pp], i),
+        "fem_batch_destroy": ([vp], i),
+        "fem_batch_problem": ([vp, i, pp], i),
+        "fem_batch_apply": ([vp, pp, pp, i], i),
+        "fem_batch_patch_inverse": ([vp, pp, pp, i], i),
+        "fem_batch_autotune": ([vp, i, ct.POINTER(i)], i),
+        "fem_server_create": ([sz, i, i, i, d, vp, pp], i),
+        "fem_server_destroy": ([vp], i),
+        "fem_server_submit": ([vp, ct.POINTER(Desc), vp, d, i, ct.POINTER(ct.c_uint64)], i),
+        "fem_server_step": ([vp, ct.POINTER(i), ct.POINTER(i), ct.POINTER(i)], i),
+        "fem_server_poll": ([vp, ct.c_uint64, vp, ct.POINTER(SolveInfo)], i),
+        "fem_server_memory": ([vp, ct.POINTER(sz), ct.POINTER(sz)], i),
+        "fem_host_1d_matrices": ([i, vp, vp], i),
+        "fem_host_fd_1d": ([i, d, d, vp, vp], i),
+        "fem_host_gll_nodes": ([i, vp], i),
+        "fem_last_error": ([], ct.c_char_p),
+        "fem_version": ([], ct.c_char_p),
+    }
+    for name, (args, res) in sigs.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def header_functions():
+    """Names of the functions include/fem.h declares."""
+    with open(HEADER) as f:
+        src = f.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b([A-Za-z_][A-Za-z0-9_]*)\s*\([^;{]*\)\s*;", src)) -
+                  {"if", "while", "for", "return", "sizeof"})
+
+
+def check(status, what=""):
+    if status != FEM_OK:
+        msg = lib().fem_last_error().decode()
+        raise FemError(status, f"{what}: {msg}" if what else msg)
+    return status
+
+
+# ---------------------------------------------------------------- helpers
+def _ptr(t):
+    """Device address of a torch tensor (or None)."""
+    if t is None:
+        return None
+    return ct.c_void_p(t.data_ptr())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def torch_dtype(prec):
+    torch = _torch()
+    return {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}[prec]
+
+
+def prec_of(t):
+    torch = _torch()
+    return {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}[t.dtype]
+
+
+def _stream():
+    torch = _torch()
+    return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def make_desc(p, n, widths=None, bc=DIRICHLET):
+    if isinstance(n, int):
+        n = (n, n, n)
+    d = Desc()
+    d.p = int(p)
+    for k in range(3):
+        d.n[k] = int(n[k])
+    keep = []
+    for k in range(3):
+        if widths is None or widths[k] is None:
+            d.widths[k] = ct.POINTER(ct.c_double)()
+        else:
+            w = np.ascontiguousarray(widths[k], dtype=np.float64)
+            keep.append(w)
+            d.widths[k] = w.ctypes.data_as(ct.POINTER(ct.c_double))
+    d.bc = int(bc)
+    d._keep = keep
+    return d
+
+
+def host_1d_matrices(p):
+    n1 = p + 1
+    M = np.zeros((n1, n1))
+    K = np.zeros((n1, n1))
+    check(lib().fem_host_1d_matrices(p, M.ctypes.data, K.ctypes.data), "fem_host_1d_matrices")
+    return M, K
+
+
+def host_gll_nodes(p):
+    x = np.zeros(p + 1)
+    check(lib().fem_host_gll_nodes(p, x.ctypes.data), "fem_host_gll_nodes")
+    return x
+
+
+def node_coords(p, widths):
+    """Coordinates of the global node planes along one direction."""
+    xi = host_gll_nodes(p)
+    w = np.asarray(widths, dtype=np.float64)
+    v = np.concatenate(([0.0], np.cumsum(w)))
+    X = np.empty(len(w) * p + 1)
+    for i in range(len(w)):
+        X[i * p:(i + 1) * p + 1] = v[i] + w[i] * xi
+    X[::p] = v
+    return X
+
+
+def host_fd_1d(p, h0, h1):
+    nP = 2 * p - 1
+    S = np.zeros((nP, nP))
+    lam = np.zeros(nP)
+    check(lib().fem_host_fd_1d(p, h0, h1, S.ctypes.data, lam.ctypes.data), "fem_host_fd_1d")
+    return S, lam
+
+
+def footprint_bytes(p, n, smoother_prec=F32, widths=None):
+    d = make_desc(p, n, widths)
+    return lib().fem_footprint_bytes(ct.byref(d), smoother_prec)
+
+
+class Problem:
+    """A Q_p Poisson problem on a graded box mesh, resident on the GPU."""
+
+    def __init__(self, p, n, widths=None, bc=DIRICHLET, _handle=None):
+        self.p = int(p)
+        self.n = (n, n, n) if isinstance(n, int) else tuple(int(v) for v in n)
+        self.widths = widths
+        self.bc = bc
+        self._owned = _handle is None
+        if _handle is None:
+            d = make_desc(p, self.n, widths, bc)
+            h = ct.c_void_p()
+            check(lib().fem_problem_create(ct.byref(d), _stream(), ct.byref(h)), "fem_problem_create")
+            self.h = h
+        else:
+            self.h = _handle
+        L = lib()
+        self.cell_len = L.fem_cell_len(self.h)
+        self.global_len = L.fem_global_len(self.h)
+        self.num_cells = L.fem_num_cells(self.h)
+        self.num_patches = L.fem_num_patches(self.h)
+
+    def close(self):
+        if getattr(self, "h", None) and self._owned:
+            lib().fem_problem_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        lib().fem_set_stream(self.h, _stream())
+
+    # vectors -------------------------------------------------------------
+    def cell_vector(self, prec=F64):
+        torch = _torch()
+        return torch.zeros(self.cell_len, dtype=torch_dtype(prec), device="cuda")
+
+    def gather(self, x_glob, prec=F64):
+        self._sync_stream()
+        out = self.cell_vector(prec)
+        check(lib().fem_gather(self.h, _ptr(x_glob), _ptr(out), prec), "fem_gather")
+        return out
+
+    def scatter(self, y_cell):
+        self._sync_stream()
+        torch = _torch()
+        out = torch.empty(self.global_len, dtype=torch.float64, device="cuda")
+        check(lib().fem_scatter(self.h, _ptr(y_cell), _ptr(out), prec_of(y_cell)), "fem_scatter")
+        return out
+
+    def extract(self, u_cell):
+        self._sync_stream()
+        torch = _torch()
+        out = torch.empty(self.global_len, dtype=torch.float64, device="cuda")
+        check(lib().fem_extract(self.h, _ptr(u_cell), _ptr(out), prec_of(u_cell)), "fem_extract")
+        return out
+
+    def pack(self, canon, prec=F64):
+        self._sync_stream()
+        out = self.cell_vector(prec)
+        check(lib().fem_pack(self.h, _ptr(canon), _ptr(out), prec), "fem_pack")
+        return out
+
+    def unpack(self, v_cell):
+        self._sync_stream()
+        torch = _torch()
+        nn = (self.p + 1) ** 3
+        out = torch.empty(self.num_cells * nn, dtype=torch.float64, device="cuda")
+        check(lib().fem_unpack(self.h, _ptr(v_cell), _ptr(out), prec_of(v_cell)), "fem_unpack")
+        return out.view(self.num_cells, nn)
+
+    def convert(self, src, prec):
+        self._sync_stream()
+        out = self.cell_vector(prec)
+        check(lib().fem_convert(self.h, _ptr(src), prec_of(src), _ptr(out), prec), "fem_convert")
+        return out
+
+    def distribute_assembled(self, r, prec):
+        """G^T r / multiplicity per copy in `prec` (r dual FP64)."""
+        self._sync_stream()
+        out = self.cell_vector(prec)
+        check(lib().fem_distribute_assembled(self.h, _ptr(r), _ptr(out), prec), "fem_distribute_assembled")
+        return out
+
+    # operators -----------------------------------------------------------
+    def apply(self, x, y=None):
+        self._sync_stream()
+        y = self.cell_vector(prec_of(x)) if y is None else y
+        check(lib().fe_apply(self.h, _ptr(x), _ptr(y), prec_of(x)), "fe_apply")
+        return y
+
+    def mass_apply(self, x, y=None):
+        self._sync_stream()
+        y = self.cell_vector(prec_of(x)) if y is None else y
+        check(lib().fe_mass_apply(self.h, _ptr(x), _ptr(y), prec_of(x)), "fe_mass_apply")
+        return y
+
+    def dss(self, v, s=None):
+        self._sync_stream()
+        s = self.cell_vector(prec_of(v)) if s is None else s
+        check(lib().fem_dss(self.h, _ptr(v), _ptr(s), prec_of(v)), "fem_dss")
+        return s
+
+    def dss_axis(self, v, axis):
+        self._sync_stream()
+        check(lib().fem_dss_axis(self.h, _ptr(v), axis, prec_of(v)), "fem_dss_axis")
+        return v
+
+    def patch_inverse(self, r, z=None):
+        self._sync_stream()
+        z = self.cell_vector(prec_of(r)) if z is None else z
+        check(lib().patch_inverse(self.h, _ptr(r), _ptr(z), prec_of(r)), "patch_inverse")
+        return z
+
+    def smoother_step(self, r, z=None, sweeps=2, omega=0.125):
+        self._sync_stream()
+        z = self.cell_vector(prec_of(r)) if z is None else z
+        check(lib().smoother_step(self.h, _ptr(r), _ptr(z), prec_of(r), sweeps, omega), "smoother_step")
+        return z
+
+    def dot(self, a, b):
+        self._sync_stream()
+        out = ct.c_double()
+        check(lib().fem_dot(self.h, _ptr(a), prec_of(a), _ptr(b), prec_of(b), ct.byref(out)), "fem_dot")
+        return out.value
+
+    def assembled_norm(self, r):
+        self._sync_stream()
+        out = ct.c_double()
+        check(lib().fem_assembled_norm(self.h, _ptr(r), prec_of(r), ct.byref(out)), "fem_assembled_norm")
+        return out.value
+
+    def pcg_solve(self, b, u=None, rtol=1e-8, maxit=1000, smoother_prec=F64, sweeps=2,
+                  omega=0.125, variant=CG_AUTO, raise_on_error=True):
+        """Solve A u = b (b dual, FP64).  Returns (u, info dict)."""
+        self._sync_stream()
+        u = self.cell_vector(F64) if u is None else u
+        info = SolveInfo()
+        st = lib().pcg_solve(self.h, _ptr(b), _ptr(u), rtol, maxit, smoother_prec, sweeps, omega,
+                             variant, ct.byref(info))
+        res = dict(iters=info.iters, status=info.status, relres=info.relres, seconds=info.seconds)
+        if raise_on_error and st not in (FEM_OK,):
+            check(st, "pcg_solve")
+        return u, res

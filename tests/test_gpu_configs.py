@@ -1,0 +1,124 @@
+"""Parity at the full workload sizes, in the launch configuration the
+benchmark times.
+
+* Q3, 64^3 graded cells (seed 1): full cell-wise apply vs the oracle; the
+  patch inverse on sampled cells (first, last, ragged-block and random
+  cells) vs dense LU of the eight surrounding patch operators.
+* Q7, 24^3 graded cells (seed 1): full apply; patch inverse on sampled
+  cells; solves of the sine + noise right-hand side to 1e-8 with FP64, FP32
+  and BF16 smoothers, each checked by the oracle's own apply (true residual).
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import operators, patches
+from oracle.mesh import Mesh
+from tests.gpu_util import l2_rel, note, rel_err, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    from paper_2607_02335_amd import fem
+    assert torch.cuda.is_available()
+    return fem
+
+
+def sample_cells(m, k, seed):
+    rng = np.random.default_rng(seed)
+    pick = set([0, m.ncells - 1, m.ncells // 2, 63, 64]) | set(rng.integers(0, m.ncells, k).tolist())
+    return np.array(sorted(c for c in pick if 0 <= c < m.ncells))
+
+
+def test_q2_8cubed_patch_sweep_full(F):
+    """Q2 8^3 uniform: one full vertex-patch sweep on x ~ U[-1,1] (seed 0)."""
+    note("q2 8^3 full patch sweep")
+    wl = synth.workload_apply_q2_small(0)
+    m = Mesh(2, wl.n, wl.widths)
+    P = F.Problem(2, wl.n, wl.widths)
+    r = P.gather(to_dev(wl.x))
+    z = to_np(P.unpack(P.patch_inverse(r)))
+    ref = patches.SchwarzFactors(m)(operators.scatter(m, operators.gather(m, wl.x)))
+    assert rel_err(z, ref[m.dofs]) <= 1e-11
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_q3_64_apply_full(F, prec):
+    note(f"q3 64^3 apply prec={prec}")
+    wl = synth.workload_q3_graded()
+    m = Mesh(3, wl.n, wl.widths)
+    P = F.Problem(3, wl.n, wl.widths)
+    xd = P.gather(to_dev(wl.x), prec)
+    y = to_np(P.unpack(P.apply(xd)))
+    ref = operators.apply_cells(m, to_np(P.unpack(xd)))
+    assert rel_err(y, ref) <= {0: 1e-12, 1: 1e-5}[prec]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_q3_64_patch_inverse_sampled(F, prec):
+    note(f"q3 64^3 patch inverse prec={prec}")
+    wl = synth.workload_q3_graded()
+    m = Mesh(3, wl.n, wl.widths)
+    P = F.Problem(3, wl.n, wl.widths)
+    y = P.apply(P.gather(to_dev(wl.x), prec))          # a dual input, as in the smoother
+    z = P.patch_inverse(y)
+    cells = sample_cells(m, 40, 1)
+    zc = to_np(P.unpack(z))[cells]
+    r = operators.scatter(m, to_np(P.unpack(y)))
+    ref = patches.additive_schwarz_at_cells(m, r, cells)
+    assert rel_err(zc, ref) <= {0: 1e-11, 1: 2e-5}[prec]
+    # the whole output is continuous to the bit
+    zz = P.unpack(P.gather(P.extract(z), prec))
+    assert bool((zz == P.unpack(z)).all())
+
+
+def test_q7_24_apply_full(F):
+    note("q7 24^3 apply")
+    wl = synth.workload_q7_graded()
+    m = Mesh(7, wl.n, wl.widths)
+    P = F.Problem(7, wl.n, wl.widths)
+    xd = P.gather(to_dev(wl.x))
+    y = to_np(P.unpack(P.apply(xd)))
+    ref = operators.apply_cells(m, operators.gather(m, wl.x))
+    assert rel_err(y, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_q7_24_patch_inverse_sampled(F, prec):
+    note(f"q7 24^3 patch inverse prec={prec}")
+    wl = synth.workload_q7_graded()
+    m = Mesh(7, wl.n, wl.widths)
+    P = F.Problem(7, wl.n, wl.widths)
+    y = P.apply(P.gather(to_dev(wl.x), prec))
+    z = P.patch_inverse(y)
+    cells = np.array([0, 24 * 24 * 12 + 24 * 5 + 7, m.ncells - 1])
+    zc = to_np(P.unpack(z))[cells]
+    ref = patches.additive_schwarz_at_cells(m, operators.scatter(m, to_np(P.unpack(y))), cells)
+    assert rel_err(zc, ref) <= {0: 1e-10, 1: 5e-5}[prec]
+
+
+def test_q7_24_solves_mixed_precision(F):
+    wl = synth.workload_q7_graded()
+    m = Mesh(7, wl.n, wl.widths)
+    P = F.Problem(7, wl.n, wl.widths)
+    X = [F.node_coords(7, wl.widths[d]) for d in range(3)]
+    f = np.kron(np.kron(np.sin(np.pi * X[2]), np.sin(np.pi * X[1])), np.sin(np.pi * X[0])) + 0.01 * wl.noise
+    bd = P.mass_apply(P.gather(to_dev(f)))
+    b_glob = operators.mass_global(m, f)
+    assert l2_rel(to_np(P.scatter(bd)), b_glob) <= 1e-13
+    sol = {}
+    for name, sp in (("fp64", 0), ("fp32", 1), ("bf16", 2)):
+        note(f"q7 24^3 solve smoother={name}")
+        u, info = P.pcg_solve(bd, rtol=1e-8, maxit=3000, smoother_prec=sp)
+        assert info["status"] == 0 and info["relres"] <= 1e-8, info
+        ug = to_np(P.extract(u))
+        true = np.linalg.norm(b_glob - operators.apply_global(m, ug)) / np.linalg.norm(b_glob)
+        assert true <= 2e-8, (name, true)
+        sol[name] = ug
+        print(f"{name}: {info['iters']} iterations, recursive {info['relres']:.2e}, true {true:.2e}, "
+              f"{info['seconds']:.3f} s", flush=True)
+    for name in ("fp32", "bf16"):
+        assert l2_rel(sol[name], sol["fp64"]) <= 1e-5

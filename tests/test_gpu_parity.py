@@ -1,0 +1,258 @@
+"""Parity of the HIP path against the oracle on small meshes that span
+several storage blocks and end in a ragged block.
+
+Tolerances (max-abs error relative to the largest oracle entry): FP64
+1e-12 (apply) / 1e-11 (patch inverse, which divides by eigenvalue sums of
+size up to ~1e3 and sums up to 8 patch results); FP32 1e-5; BF16 storage with
+FP32 arithmetic 3e-2 (one BF16 rounding of input and output, 2^-8 each).
+"""
+import numpy as np
+import pytest
+
+from oracle import operators, patches, solver
+from oracle.mesh import Mesh
+from tests.gpu_util import graded, l2_rel, note, rel_err, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5, 2: 3e-2}
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    from paper_2607_02335_amd import fem
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    fem.lib()
+    return fem
+
+
+def make(F, mesh, widths=None, bc=0):
+    return F.Problem(mesh.p, mesh.n, widths if widths is not None else mesh.h, bc)
+
+
+# ------------------------------------------------------------ apply
+def test_apply_q2_8cubed_uniform(F):
+    """Q2, 8^3 uniform cells, Dirichlet, x ~ U[-1,1] seed 0."""
+    note("apply q2 8^3 uniform")
+    m = Mesh(2, (8, 8, 8))
+    x = np.random.default_rng(0).uniform(-1, 1, m.nglob)
+    P = make(F, m)
+    y = P.apply(P.gather(to_dev(x)))
+    yc = to_np(P.unpack(y))
+    ref = operators.apply_cells(m, operators.gather(m, x))
+    assert rel_err(yc, ref) <= 1e-12
+    yg = to_np(P.scatter(y))
+    assert l2_rel(yg, operators.apply_global(m, x)) <= 1e-12
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_apply_all_degrees_ragged(F, p, prec):
+    n = (5, 3, 4) if p < 6 else (3, 2, 3)
+    note(f"apply p={p} prec={prec} n={n}")
+    m, w, rng = graded(p, n, 100 + p)
+    xc = rng.uniform(-1, 1, (m.ncells, m.n1 ** 3))      # broken (dual-like) input: every copy differs
+    P = make(F, m)
+    xd = P.pack(to_dev(xc.ravel()), prec)
+    xin = to_np(P.unpack(xd))                            # what the device holds after rounding
+    y = to_np(P.unpack(P.apply(xd)))
+    ref = operators.apply_cells(m, xin)
+    assert rel_err(y, ref) <= TOL[prec] * (3 if prec == 1 and p == 7 else 1)
+
+
+@pytest.mark.parametrize("p", [2, 3, 7])
+def test_apply_neumann_and_mass(F, p):
+    n = (4, 3, 5) if p < 7 else (3, 2, 2)
+    note(f"neumann/mass p={p}")
+    m, w, rng = graded(p, n, 7)
+    x = rng.uniform(-1, 1, m.nglob)
+    Pn = make(F, m, bc=1)
+    y = to_np(Pn.scatter(Pn.apply(Pn.gather(to_dev(x)))))
+    assert rel_err(y, operators.apply_global(m, x, dirichlet=False)) <= 1e-12
+    ones = to_np(Pn.scatter(Pn.apply(Pn.gather(to_dev(np.ones(m.nglob))))))
+    assert np.abs(ones).max() <= 1e-12 * np.abs(y).max()
+    Pd = make(F, m)
+    ym = to_np(Pd.scatter(Pd.mass_apply(Pd.gather(to_dev(x)))))
+    assert rel_err(ym, operators.mass_global(m, x)) <= 1e-12
+
+
+# ------------------------------------------------ converters, DSS, reductions
+@pytest.mark.parametrize("p", [1, 3, 7])
+def test_converters_and_dss(F, p):
+    n = (6, 3, 4) if p < 7 else (3, 2, 3)
+    note(f"converters/dss p={p}")
+    m, w, rng = graded(p, n, 3)
+    P = make(F, m)
+    x = rng.standard_normal(m.nglob)
+    xc = P.gather(to_dev(x))
+    np.testing.assert_array_equal(to_np(P.unpack(xc)), operators.gather(m, x))
+    np.testing.assert_array_equal(to_np(P.extract(xc)), x)
+    v = rng.standard_normal((m.ncells, m.n1 ** 3))
+    vd = P.pack(to_dev(v.ravel()))
+    np.testing.assert_allclose(to_np(P.scatter(vd)), operators.scatter(m, v), rtol=0, atol=1e-12)
+    s = to_np(P.unpack(P.dss(vd)))
+    np.testing.assert_allclose(s, operators.dss(m, v), rtol=0, atol=1e-12)
+    # every copy of a node holds the identical bits after the cascade
+    sd = P.dss(vd)
+    np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(sd)))), to_np(P.unpack(sd)))
+    mult = to_np(P.unpack(P.dss(P.pack(to_dev(np.ones(v.size))))))
+    np.testing.assert_array_equal(mult, m.multiplicity()[m.dofs])
+
+
+def test_dss_cascade_worked_example(F):
+    """The 2D four-cell example of Section 4.1, one axis pass at a time."""
+    import os
+    rows = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "dss_vertex_2d.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                t = line.split()
+                rows[t[0]] = [float(q) for q in t[1:]]
+    note("dss worked example")
+    m = Mesh(1, (2, 2, 1))
+    P = make(F, m)
+    g = m.gidx(1, 1, 0)
+    cells = {"nw": 2, "ne": 3, "sw": 0, "se": 1}
+    v = np.zeros((4, 8))
+    loc = {}
+    for key, val in zip(["nw", "ne", "sw", "se"], rows["initial"]):
+        e = cells[key]
+        loc[key] = int(np.nonzero(m.dofs[e] == g)[0][0])
+        v[e, loc[key]] = val
+    vd = P.pack(to_dev(v.ravel()))
+    for axis, stage in ((0, "after_x"), (1, "after_y")):
+        P.dss_axis(vd, axis)
+        got = to_np(P.unpack(vd))
+        assert [got[cells[k], loc[k]] for k in ["nw", "ne", "sw", "se"]] == rows[stage]
+
+
+def test_dot_and_assembled_norm(F):
+    note("dot/norm")
+    m, w, rng = graded(3, (7, 5, 3), 9)
+    P = make(F, m)
+    a = rng.standard_normal((m.ncells, m.n1 ** 3))
+    u = rng.standard_normal(m.nglob)
+    ad = P.pack(to_dev(a.ravel()))
+    ud = P.gather(to_dev(u))
+    ref = np.sum(a * operators.gather(m, u))
+    assert abs(P.dot(ad, ud) - ref) <= 1e-12 * abs(ref) + 1e-12
+    # pairing lemma on the device: <f, G u> = <G^T f, u>
+    assert abs(P.dot(ad, ud) - operators.scatter(m, a) @ u) <= 1e-11 * np.abs(a).sum()
+    nrm = np.linalg.norm(operators.scatter(m, a))
+    assert abs(P.assembled_norm(ad) - nrm) <= 1e-12 * nrm
+    assert P.dot(ad, P.convert(ud, 1)) == pytest.approx(ref, rel=1e-6)
+
+
+# ---------------------------------------------------------- patch inverse
+@pytest.mark.parametrize("p,n", [(1, (4, 3, 5)), (2, (5, 4, 3)), (3, (4, 5, 3)), (4, (3, 4, 3)),
+                                 (7, (3, 3, 2)), (2, (2, 2, 2)), (3, (9, 2, 3))])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_patch_inverse_matches_lu(F, p, n, prec):
+    note(f"patch_inverse p={p} n={n} prec={prec}")
+    m, w, rng = graded(p, n, 20 + p)
+    P = make(F, m)
+    rc = rng.uniform(-1, 1, (m.ncells, m.n1 ** 3)) * ~operators.boundary_copies(m)
+    rd = P.pack(to_dev(rc.ravel()), prec)
+    rin = to_np(P.unpack(rd))
+    z = P.patch_inverse(rd)
+    zc = to_np(P.unpack(z))
+    ref = patches.SchwarzFactors(m)(operators.scatter(m, rin))
+    tol = {0: 1e-11, 1: 2e-5, 2: 3e-2}[prec]
+    assert rel_err(zc, ref[m.dofs]) <= tol
+    # exact continuity: every copy of a node holds the same bits
+    zz = to_np(P.unpack(P.gather(P.extract(z), prec)))
+    np.testing.assert_array_equal(zz, zc)
+
+
+def test_patch_inverse_sees_only_the_assembly(F):
+    """Two cell-wise residuals with the same assembly give the same output."""
+    note("patch_inverse consistency")
+    m, w, rng = graded(3, (4, 4, 3), 5)
+    P = make(F, m)
+    r = rng.standard_normal(m.nglob) * ~m.boundary_mask()
+    split = rng.standard_normal((m.ncells, m.n1 ** 3))
+    a = operators.gather(m, r) / m.multiplicity()[m.dofs]
+    b = a + split - operators.gather(m, operators.scatter(m, split)) / m.multiplicity()[m.dofs]
+    np.testing.assert_allclose(operators.scatter(m, b), operators.scatter(m, a), atol=1e-12)
+    za = to_np(P.unpack(P.patch_inverse(P.pack(to_dev(a.ravel())))))
+    zb = to_np(P.unpack(P.patch_inverse(P.pack(to_dev(b.ravel())))))
+    assert rel_err(za, zb) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_smoother_matches_oracle(F, prec):
+    note(f"smoother prec={prec}")
+    m, w, rng = graded(2, (4, 5, 4), 31)
+    P = make(F, m)
+    rc = rng.uniform(-1, 1, (m.ncells, m.n1 ** 3)) * ~operators.boundary_copies(m)
+    rd = P.pack(to_dev(rc.ravel()), prec)
+    z = to_np(P.unpack(P.smoother_step(rd, sweeps=2, omega=0.125)))
+    f = patches.SchwarzFactors(m)
+    ref = solver.smoother(m, operators.scatter(m, to_np(P.unpack(rd))), 2, 0.125, schwarz=f)
+    assert rel_err(z, ref[m.dofs]) <= {0: 1e-11, 1: 2e-5}[prec]
+    z3 = to_np(P.unpack(P.smoother_step(rd, sweeps=3, omega=0.2)))
+    ref3 = solver.smoother(m, operators.scatter(m, to_np(P.unpack(rd))), 3, 0.2, schwarz=f)
+    assert rel_err(z3, ref3[m.dofs]) <= {0: 1e-11, 1: 2e-5}[prec]
+
+
+# ---------------------------------------------------------------- solver
+def test_pcg_iterates_equal_assembled_iterates(F):
+    """Equivalence theorem (Section 3.2): cell-wise iterates = G (assembled
+    iterates), checked for the first iterations with the FP64 smoother."""
+    m, w, rng = graded(2, (4, 4, 5), 41)
+    P = make(F, m)
+    f = rng.uniform(-1, 1, m.nglob)
+    b_glob = operators.mass_global(m, f)
+    _, _, _, its = solver.solve_poisson(m, b_glob, rtol=1e-30, maxit=6, variant="pcg", record=True)
+    bd = P.mass_apply(P.gather(to_dev(f)))
+    for k in range(1, 7):
+        note(f"pcg iterate k={k}")
+        u, info = P.pcg_solve(bd, rtol=1e-30, maxit=k, smoother_prec=0, raise_on_error=False)
+        assert info["status"] == 4 and info["iters"] == k
+        uk = to_np(P.extract(u))
+        assert l2_rel(uk, its[k]) <= 1e-10
+        np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(u)))), to_np(P.unpack(u)))
+
+
+@pytest.mark.parametrize("p,n", [(2, (4, 3, 5)), (3, (3, 4, 3)), (7, (2, 3, 2))])
+@pytest.mark.parametrize("sp", [0, 1, 2])
+def test_bubble_solve(F, p, n, sp):
+    """u = x(1-x)y(1-y)z(1-z) lies in Q_p: the discrete solution is its
+    interpolant, whatever the smoother precision."""
+    note(f"bubble p={p} n={n} sp={sp}")
+    m, w, rng = graded(p, n, 50 + p)
+    X, Y, Z = (m.coords_1d(d) for d in range(3))
+    bx, by, bz = X * (1 - X), Y * (1 - Y), Z * (1 - Z)
+    u_ex = np.kron(np.kron(bz, by), bx)
+    one = np.ones_like
+    f = 2 * (np.kron(np.kron(bz, by), one(bx)) + np.kron(np.kron(bz, one(by)), bx) + np.kron(np.kron(one(bz), by), bx))
+    P = make(F, m)
+    bd = P.mass_apply(P.gather(to_dev(f)))
+    u, info = P.pcg_solve(bd, rtol=1e-10, maxit=500, smoother_prec=sp)
+    assert info["status"] == 0 and info["relres"] <= 1e-10
+    assert np.abs(to_np(P.extract(u)) - u_ex).max() <= 1e-9
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+def test_distribute_assembled_before_demotion(F, prec):
+    """A dual vector whose copies cancel under assembly (as a converging
+    residual's do): demoting it copy by copy loses its assembly, assembling
+    in FP64 first keeps it to the precision's relative accuracy."""
+    note(f"distribute prec={prec}")
+    m, w, rng = graded(3, (5, 4, 3), 77)
+    P = make(F, m)
+    small = rng.standard_normal(m.nglob) * ~m.boundary_mask() * 1e-8
+    noise = rng.standard_normal((m.ncells, m.n1 ** 3)) * ~operators.boundary_copies(m)
+    cancel = noise - operators.gather(m, operators.scatter(m, noise)) / m.multiplicity()[m.dofs]
+    rc = operators.gather(m, small) / m.multiplicity()[m.dofs] + cancel     # G^T rc = small
+    rd = P.pack(to_dev(rc.ravel()))
+    exact = operators.scatter(m, rc)
+    d = P.distribute_assembled(rd, prec)
+    got = to_np(P.scatter(d))
+    tol = {1: 1e-6, 2: 1e-2}[prec]
+    assert l2_rel(got, exact) <= tol
+    naive = to_np(P.scatter(P.convert(rd, prec)))
+    assert l2_rel(naive, exact) > 10 * tol          # the floor the FP64 assembly avoids
+    # every copy of a node holds the same value
+    np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(d), prec))), to_np(P.unpack(d)))
