@@ -231,6 +231,241 @@ __global__ void __launch_bounds__(256) k_pi_combine(LaunchTable L) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Low-degree variants (p <= 4): the 1D eigenbasis of the current direction is
+// held in registers during each pass (the y and z bases are shared by the
+// whole tile and read as LDS broadcasts), so LDS carries only line data.
+// Tiles are spread so that consecutive tiles (neighbouring patch rows that
+// share cells) run on the same XCD and reuse its L2.
+__device__ __forceinline__ int xcd_tile(int b, int G) {
+    const int per = G / 8;               // G is a multiple of 8
+    return (b % 8) * per + b / 8;
+}
+
+template <int P, typename S, int CBP, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_solve_r(LaunchTable L) {
+    using C = typename Prec<S>::C;
+    constexpr int N = P + 1, NN = N * N * N;
+    constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
+    constexpr int REC = fd_record(P);
+    constexpr int NT = 256, LPT = NT / CBP;
+    static_assert(NT % CBP == 0, "patches per tile must divide the workgroup");
+    __shared__ C sv[nP3 * CBP];
+    __shared__ C sSx[CBP][nP2 + 1];
+    __shared__ C sLx[CBP][nP];
+    __shared__ C sSyz[2][nP2];
+    __shared__ C sLyz[2][nP];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= L.total_tiles) return;
+    const int tid = threadIdx.x;
+    const int pc = tid % CBP;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int t = tile - pe.tile_begin;
+    const int npx = pe.n[0] - 1, npy = pe.n[1] - 1;
+    const int tpr = (npx + CBP - 1) / CBP;
+    const int row = t / tpr, xt = t % tpr;
+    const int vj = 1 + row % npy, vk = 1 + row / npy;
+    const int vi = 1 + xt * CBP + pc;
+    const bool valid = vi <= npx;
+    {
+        const C* fx = static_cast<const C*>(pe.fd[0]) + (size_t)((valid ? vi : npx) - 1) * REC;
+        for (int w = tid / CBP; w < nP2 + nP; w += LPT) {
+            const C v = fx[w];
+            if (w < nP2) sSx[pc][w] = v; else sLx[pc][w - nP2] = v;
+        }
+        for (int w = tid; w < 2 * (nP2 + nP); w += NT) {
+            const int d = w / (nP2 + nP), o = w % (nP2 + nP);
+            const C v = static_cast<const C*>(pe.fd[1 + d])[(size_t)((d == 0 ? vj : vk) - 1) * REC + o];
+            if (o < nP2) sSyz[d][o] = v; else sLyz[d][o - nP2] = v;
+        }
+    }
+    const S* r = static_cast<const S*>(pe.a);
+    const int n0 = pe.n[0], n1 = pe.n[1];
+    for (int q = tid / CBP; q < nP3; q += LPT) {
+        const int qx = q % nP, qy = (q / nP) % nP, qz = q / nP2;
+        C s = 0;
+        if (valid) {
+#pragma unroll
+            for (int s3 = 0; s3 < 2; ++s3) {
+                const int c = qz + 1 - s3 * P;
+                if (c < 0 || c > P) continue;
+#pragma unroll
+                for (int s2 = 0; s2 < 2; ++s2) {
+                    const int b = qy + 1 - s2 * P;
+                    if (b < 0 || b > P) continue;
+#pragma unroll
+                    for (int s1 = 0; s1 < 2; ++s1) {
+                        const int a = qx + 1 - s1 * P;
+                        if (a < 0 || a > P) continue;
+                        const int e = (vi - 1 + s1) + n0 * ((vj - 1 + s2) + n1 * (vk - 1 + s3));
+                        s += load_as<C>(r + cell_offset(e, a + N * (b + N * c), NN));
+                    }
+                }
+            }
+        }
+        sv[q * CBP + pc] = s;
+    }
+    __syncthreads();
+    C Sm[nP2];
+    // forward z (broadcast basis)
+#pragma unroll
+    for (int i = 0; i < nP2; ++i) Sm[i] = sSyz[1][i];
+    for (int ln = tid / CBP; ln < nP2; ln += LPT) {
+        C v[nP];
+#pragma unroll
+        for (int i = 0; i < nP; ++i) v[i] = sv[(ln + nP2 * i) * CBP + pc];
+#pragma unroll
+        for (int j = 0; j < nP; ++j) {
+            C s = 0;
+#pragma unroll
+            for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
+            sv[(ln + nP2 * j) * CBP + pc] = s;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < nP2; ++i) Sm[i] = sSyz[0][i];
+    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // forward y
+        const int qx = ln % nP, qz = ln / nP;
+        C v[nP];
+#pragma unroll
+        for (int i = 0; i < nP; ++i) v[i] = sv[(qx + nP * i + nP2 * qz) * CBP + pc];
+#pragma unroll
+        for (int j = 0; j < nP; ++j) {
+            C s = 0;
+#pragma unroll
+            for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
+            sv[(qx + nP * j + nP2 * qz) * CBP + pc] = s;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < nP2; ++i) Sm[i] = sSx[pc][i];
+    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // x: forward, scale, backward
+        const int qy = ln % nP, qz = ln / nP;
+        C v[nP], w[nP];
+#pragma unroll
+        for (int i = 0; i < nP; ++i) v[i] = sv[(i + nP * ln) * CBP + pc];
+        const C lyz = sLyz[0][qy] + sLyz[1][qz];
+#pragma unroll
+        for (int j = 0; j < nP; ++j) {
+            C s = 0;
+#pragma unroll
+            for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
+            w[j] = s / (sLx[pc][j] + lyz);
+        }
+#pragma unroll
+        for (int i = 0; i < nP; ++i) {
+            C s = 0;
+#pragma unroll
+            for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * w[j];
+            sv[(i + nP * ln) * CBP + pc] = s;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < nP2; ++i) Sm[i] = sSyz[0][i];
+    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // backward y
+        const int qx = ln % nP, qz = ln / nP;
+        C v[nP];
+#pragma unroll
+        for (int j = 0; j < nP; ++j) v[j] = sv[(qx + nP * j + nP2 * qz) * CBP + pc];
+#pragma unroll
+        for (int i = 0; i < nP; ++i) {
+            C s = 0;
+#pragma unroll
+            for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * v[j];
+            sv[(qx + nP * i + nP2 * qz) * CBP + pc] = s;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < nP2; ++i) Sm[i] = sSyz[1][i];
+    C* pbuf = static_cast<C*>(pe.d);
+    const int pidx = (vi - 1) + npx * ((vj - 1) + npy * (vk - 1));
+    C* out = pbuf + (size_t)(pidx / kLanes) * nP3 * kLanes + (pidx % kLanes);
+    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // backward z, store
+        C v[nP];
+#pragma unroll
+        for (int j = 0; j < nP; ++j) v[j] = sv[(ln + nP2 * j) * CBP + pc];
+#pragma unroll
+        for (int i = 0; i < nP; ++i) {
+            C s = 0;
+#pragma unroll
+            for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * v[j];
+            if (valid) out[(size_t)(ln + nP2 * i) * kLanes] = s;
+        }
+    }
+}
+
+// One thread per cell (p <= 3): the eight corner patches' buffer addresses
+// are formed once per cell, node loops are unrolled at compile time.
+template <int P, typename S, int ACC, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_combine_cell(LaunchTable L) {
+    using C = typename Prec<S>::C;
+    constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
+    constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int tile = blockIdx.x * 4 + wv;
+    if (tile >= L.total_tiles) return;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int blk = tile - pe.tile_begin;
+    const int e = blk * kLanes + lane;
+    S* z = static_cast<S*>(pe.c) + (size_t)blk * NN * kLanes + lane;
+    if (e >= pe.ncells) {
+#pragma unroll
+        for (int l = 0; l < NN; ++l) store_from(z + l * kLanes, (C)0);
+        return;
+    }
+    const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+    const int npx = n0 - 1, npy = n1 - 1;
+    const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
+    const C* pbuf = static_cast<const C*>(pe.d);
+    const C* corner[2][2][2];
+#pragma unroll
+    for (int sz = 0; sz < 2; ++sz)
+#pragma unroll
+        for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+            for (int sx = 0; sx < 2; ++sx) {
+                const int vx = i + sx, vy = j + sy, vz = k + sz;
+                const bool ok = vx >= 1 && vx <= npx && vy >= 1 && vy <= npy && vz >= 1 && vz <= n2 - 1;
+                const int pidx = ok ? (vx - 1) + npx * ((vy - 1) + npy * (vz - 1)) : 0;
+                corner[sz][sy][sx] = ok ? pbuf + (size_t)(pidx / kLanes) * nP3 * kLanes + (pidx % kLanes) : nullptr;
+            }
+    const C alpha = (C)pe.alpha;
+#pragma unroll
+    for (int c = 0; c < N; ++c)
+#pragma unroll
+        for (int b = 0; b < N; ++b)
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                C sum = 0;
+#pragma unroll
+                for (int sz = 0; sz < 2; ++sz) {
+                    if ((sz == 0 && c == P) || (sz == 1 && c == 0)) continue;
+                    const int qz = sz == 0 ? P - 1 + c : c - 1;
+#pragma unroll
+                    for (int sy = 0; sy < 2; ++sy) {
+                        if ((sy == 0 && b == P) || (sy == 1 && b == 0)) continue;
+                        const int qy = sy == 0 ? P - 1 + b : b - 1;
+#pragma unroll
+                        for (int sx = 0; sx < 2; ++sx) {
+                            if ((sx == 0 && a == P) || (sx == 1 && a == 0)) continue;
+                            const int qx = sx == 0 ? P - 1 + a : a - 1;
+                            const C* src = corner[sz][sy][sx];
+                            if (src) sum += src[(size_t)(qx + nP * (qy + nP * qz)) * kLanes];
+                        }
+                    }
+                }
+                const int l = a + N * b + N2 * c;
+                C out = alpha * sum;
+                if (ACC) out = load_as<C>(z + l * kLanes) + out;
+                store_from(z + l * kLanes, out);
+            }
+}
+
 template <int P, typename S>
 static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, ProbEntry* d_tab, hipStream_t s) {
     using C = typename Prec<S>::C;
@@ -248,9 +483,15 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, ProbEn
     hipError_t err = stage_table(L, ents, nprob, d_tab, s);
     if (err != hipSuccess) return err;
     if (tiles > 0) {
-        const int grid = tiles < kMaxGrid ? tiles : kMaxGrid;
-        if (nprob > 1) hipLaunchKernelGGL((k_pi_solve<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, L);
-        else hipLaunchKernelGGL((k_pi_solve<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, L);
+        if constexpr (P <= 4) {
+            const int grid = (tiles + 7) / 8 * 8;
+            if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_r<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, L);
+            else hipLaunchKernelGGL((k_pi_solve_r<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, L);
+        } else {
+            const int grid = tiles < kMaxGrid ? tiles : kMaxGrid;
+            if (nprob > 1) hipLaunchKernelGGL((k_pi_solve<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, L);
+            else hipLaunchKernelGGL((k_pi_solve<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, L);
+        }
         err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
@@ -266,6 +507,17 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, ProbEn
     L2.total_tiles = tiles2;
     err = stage_table(L2, ents, nprob, nprob > 1 ? d_tab + nprob : d_tab, s);
     if (err != hipSuccess) return err;
+    if constexpr (P <= 3) {
+        const int grid = (tiles2 + 3) / 4;
+        if (nprob > 1) {
+            if (accumulate) hipLaunchKernelGGL((k_pi_combine_cell<P, S, 1, true>), dim3(grid), dim3(256), 0, s, L2);
+            else hipLaunchKernelGGL((k_pi_combine_cell<P, S, 0, true>), dim3(grid), dim3(256), 0, s, L2);
+        } else {
+            if (accumulate) hipLaunchKernelGGL((k_pi_combine_cell<P, S, 1, false>), dim3(grid), dim3(256), 0, s, L2);
+            else hipLaunchKernelGGL((k_pi_combine_cell<P, S, 0, false>), dim3(grid), dim3(256), 0, s, L2);
+        }
+        return hipGetLastError();
+    }
     const int grid2 = tiles2 < kMaxGrid ? tiles2 : kMaxGrid;
     if (nprob > 1) {
         if (accumulate) hipLaunchKernelGGL((k_pi_combine<P, S, 1, true>), dim3(grid2), dim3(256), 0, s, L2);
