@@ -258,6 +258,13 @@ fem_status fem_host_1d_matrices(int p, double* mass, double* stiff);
 fem_status fem_host_gll_nodes(int p, double* nodes);
 fem_status fem_host_fd_1d(int p, double h0, double h1, double* S, double* lambda);
 
+/* Process-wide tuning switches (for comparisons and the autotuner).
+ * FEM_OPT_PI_FUSED = 1 runs patch_inverse for p <= 3 as one fused sweep that
+ * keeps patch results on chip; 0 (default) solves patches into a buffer and
+ * combines them in a second launch.  Unknown options are FEM_EINVAL. */
+typedef enum fem_option { FEM_OPT_PI_FUSED = 1 } fem_option;
+fem_status fem_set_option(int option, int value);
+
 const char* fem_last_error(void);
 const char* fem_version(void);
 

@@ -86,6 +86,7 @@ struct ProbEntry {
     double alpha;        // scalar operand (e.g. damping)
     int ntiles_red;      // tiles of the reduction kernels (<= kRedParts)
     int blocks_per_red;  // storage blocks per reduction tile
+    int zchunk;          // cell layers per z-chunk of the fused patch sweep
 };
 
 struct LaunchTable {

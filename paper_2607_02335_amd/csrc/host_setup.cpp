@@ -276,6 +276,15 @@ int host_fd_1d(int p, double h0, double h1, double* S, double* lam) {
 
 using namespace fem;
 
+namespace fem { extern int g_pi_fused; }
+
+extern "C" fem_status fem_set_option(int option, int value) {
+    switch (option) {
+        case FEM_OPT_PI_FUSED: fem::g_pi_fused = value ? 1 : 0; return FEM_OK;
+        default: return set_error(FEM_EINVAL, "fem_set_option: unknown option");
+    }
+}
+
 extern "C" const char* fem_last_error(void) { return g_last_error.c_str(); }
 extern "C" const char* fem_version(void) { return "fem-mi355x 0.1 (gfx950)"; }
 

@@ -19,10 +19,17 @@
 //   node, added in increasing vertex order.  That order depends only on the
 //   global node, so all copies of a node receive bitwise identical values:
 //   the output is continuous exactly, not just to rounding.
+#include <algorithm>
+
 #include "fem_internal.h"
 #include "launch.h"
 
 namespace fem {
+
+// 1: use the fused sweep (no patch buffer) for p <= 3; selected by
+// fem_set_option.  The two-phase path is the default: on MI355X it is faster
+// for every measured workload (the sweep's per-layer chain is latency-bound).
+int g_pi_fused = 0;
 
 template <int P, typename C> constexpr int pi_patches_per_tile() {
     constexpr int nP = 2 * P - 1;
@@ -466,8 +473,359 @@ __global__ void __launch_bounds__(256) k_pi_combine_cell(LaunchTable L) {
             }
 }
 
+// ---------------------------------------------------------------------------
+// Fused sweep (p <= 3): no patch buffer.  A workgroup owns TX x TY cell
+// columns and a chunk of cell layers [k0, k1) and walks the vertex layers
+// k0..k1 in order.  Per vertex layer vk:
+//   * cell layers vk-1 and vk sit in an LDS ring (TX+2 x TY+2 cells each,
+//     loaded with coalesced reads); the next cell layer is fetched into
+//     registers while this layer is solved, hiding its latency;
+//   * the (TX+1) x (TY+1) patches of the layer are restricted from the ring,
+//     solved by fast diagonalisation (five LDS passes) and combined at once:
+//     cell layer vk-1 is finished (its partial sum from vertex layer vk-1
+//     plus this layer's terms) and written out, and cell layer vk starts a
+//     partial sum with this layer's terms.
+// Terms are added in ascending vertex order along z, y and x for every copy
+// of a node, so the copies of a node stay bitwise equal.  Patches on the
+// border of a tile are solved by both neighbouring tiles; that extra
+// arithmetic is the price of never writing patch results to memory.
+template <int P, typename S, int TX, int TY, int NST, int ACC, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_sweep(LaunchTable L) {
+    using C = typename Prec<S>::C;
+    constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
+    constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
+    constexpr int REC = fd_record(P);
+    constexpr int NPL = (TX + 1) * (TY + 1);      // patches per vertex layer
+    constexpr int LG = 256 / NST;                 // line groups
+    constexpr int CX = TX + 2, CY = TY + 2;       // cell window per layer
+    constexpr int NCW = CX * CY;
+    constexpr int NLOAD = NCW * NN;               // values per cell layer
+    constexpr int PF = (NLOAD + 255) / 256;       // prefetch registers per thread
+    static_assert(NPL <= NST && 256 % NST == 0, "patch slots must cover a layer and divide the workgroup");
+    __shared__ C cells[2][NLOAD];                 // [node][cell window] per layer
+    __shared__ C pv[nP3 * NPL];                   // current patch layer [q][patch]
+    __shared__ C part[TX * TY * NN];              // partial sums of the open cell layer
+    __shared__ C sSx[TX + 1][nP2 + 1];
+    __shared__ C sSy[TY + 1][nP2 + 1];
+    __shared__ C sSz[nP2];
+    __shared__ C sLx[TX + 1][nP];
+    __shared__ C sLy[TY + 1][nP];
+    __shared__ C sLz[nP];
+
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= L.total_tiles) return;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+    const int ntx = (n0 + TX - 1) / TX, nty = (n1 + TY - 1) / TY;
+    int t = tile - pe.tile_begin;
+    const int tx = t % ntx;
+    t /= ntx;
+    const int ty = t % nty;
+    const int kc = t / nty;
+    const int i0 = tx * TX, j0 = ty * TY;
+    const int k0 = kc * pe.zchunk;
+    const int k1 = min(k0 + pe.zchunk, n2);
+    const int tid = threadIdx.x, ps = tid % NST, lg = tid / NST;
+    const int pxo = ps % (TX + 1), pyo = min(ps / (TX + 1), TY);
+    const int vi = i0 + pxo, vj = j0 + pyo;
+    const bool slot_ok = ps < NPL && vi >= 1 && vi <= n0 - 1 && vj >= 1 && vj <= n1 - 1;
+    const S* r = static_cast<const S*>(pe.a);
+    S* zout = static_cast<S*>(pe.c);
+    const C alpha = (C)pe.alpha;
+
+    for (int w = tid; w < (TX + 1) * (nP2 + nP); w += 256) {
+        const int col = w / (nP2 + nP), o = w % (nP2 + nP);
+        const int line = max(0, min(i0 + col, n0 - 1) - 1);
+        const C v = static_cast<const C*>(pe.fd[0])[(size_t)line * REC + o];
+        if (o < nP2) sSx[col][o] = v; else sLx[col][o - nP2] = v;
+    }
+    for (int w = tid; w < (TY + 1) * (nP2 + nP); w += 256) {
+        const int col = w / (nP2 + nP), o = w % (nP2 + nP);
+        const int line = max(0, min(j0 + col, n1 - 1) - 1);
+        const C v = static_cast<const C*>(pe.fd[1])[(size_t)line * REC + o];
+        if (o < nP2) sSy[col][o] = v; else sLy[col][o - nP2] = v;
+    }
+
+    // load of one cell layer: item = window cell + NCW * node (x fastest)
+    auto fetch = [&](int k, C* regs) {
+#pragma unroll
+        for (int m = 0; m < PF; ++m) {
+            const int item = tid + 256 * m;
+            C v = 0;
+            if (item < NLOAD && k >= 0 && k < n2) {
+                const int w = item % NCW, l = item / NCW;
+                const int i = i0 - 1 + w % CX, j = j0 - 1 + w / CX;
+                if (i >= 0 && i < n0 && j >= 0 && j < n1)
+                    v = load_as<C>(r + cell_offset(i + n0 * (j + n1 * k), l, NN));
+            }
+            regs[m] = v;
+        }
+    };
+    auto stash = [&](C* dst, const C* regs) {
+#pragma unroll
+        for (int m = 0; m < PF; ++m) {
+            const int item = tid + 256 * m;
+            if (item < NLOAD) dst[item] = regs[m];
+        }
+    };
+    {
+        C reg[PF];
+        fetch(k0 - 1, reg);
+        stash(cells[(k0 + 1) & 1], reg);           // slot of layer k0-1
+        fetch(k0, reg);
+        stash(cells[k0 & 1], reg);
+    }
+    __syncthreads();
+
+    for (int vk = k0; vk <= k1; ++vk) {
+        C nxt[PF];
+        fetch(vk + 1, nxt);                            // in flight during this layer
+        const bool layer_ok = vk >= 1 && vk <= n2 - 1; // uniform over the workgroup
+        if (layer_ok) {
+            for (int w = tid; w < nP2 + nP; w += 256) {
+                const C v = static_cast<const C*>(pe.fd[2])[(size_t)(vk - 1) * REC + w];
+                if (w < nP2) sSz[w] = v; else sLz[w - nP2] = v;
+            }
+            // restrict from the ring: layer vk-1 is s3 = 0, layer vk is s3 = 1
+            if (ps < NPL) {
+                const C* lay[2] = {cells[(vk + 1) & 1], cells[vk & 1]};
+                for (int q = lg; q < nP3; q += LG) {
+                    const int qx = q % nP, qy = (q / nP) % nP, qz = q / nP2;
+                    C s = 0;
+                    if (slot_ok) {
+#pragma unroll
+                        for (int s3 = 0; s3 < 2; ++s3) {
+                            const int c = qz + 1 - s3 * P;
+                            if (c < 0 || c > P) continue;
+#pragma unroll
+                            for (int s2 = 0; s2 < 2; ++s2) {
+                                const int b = qy + 1 - s2 * P;
+                                if (b < 0 || b > P) continue;
+#pragma unroll
+                                for (int s1 = 0; s1 < 2; ++s1) {
+                                    const int a = qx + 1 - s1 * P;
+                                    if (a < 0 || a > P) continue;
+                                    const int wcell = (pxo + s1) + CX * (pyo + s2);
+                                    s += lay[s3][(a + N * (b + N * c)) * NCW + wcell];
+                                }
+                            }
+                        }
+                    }
+                    pv[q * NPL + ps] = s;
+                }
+            }
+            __syncthreads();
+            if (ps < NPL) {
+                C Sm[nP2];
+#pragma unroll
+                for (int i = 0; i < nP2; ++i) Sm[i] = sSz[i];
+                for (int ln = lg; ln < nP2; ln += LG) {                 // forward z
+                    C v[nP];
+#pragma unroll
+                    for (int i = 0; i < nP; ++i) v[i] = pv[(ln + nP2 * i) * NPL + ps];
+#pragma unroll
+                    for (int j = 0; j < nP; ++j) {
+                        C s = 0;
+#pragma unroll
+                        for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
+                        pv[(ln + nP2 * j) * NPL + ps] = s;
+                    }
+                }
+            }
+            __syncthreads();
+            if (ps < NPL) {
+                C Sm[nP2];
+#pragma unroll
+                for (int i = 0; i < nP2; ++i) Sm[i] = sSy[pyo][i];
+                for (int ln = lg; ln < nP2; ln += LG) {                 // forward y
+                    const int qx = ln % nP, qz = ln / nP;
+                    C v[nP];
+#pragma unroll
+                    for (int i = 0; i < nP; ++i) v[i] = pv[(qx + nP * i + nP2 * qz) * NPL + ps];
+#pragma unroll
+                    for (int j = 0; j < nP; ++j) {
+                        C s = 0;
+#pragma unroll
+                        for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
+                        pv[(qx + nP * j + nP2 * qz) * NPL + ps] = s;
+                    }
+                }
+            }
+            __syncthreads();
+            if (ps < NPL) {
+                C Sm[nP2];
+#pragma unroll
+                for (int i = 0; i < nP2; ++i) Sm[i] = sSx[pxo][i];
+                for (int ln = lg; ln < nP2; ln += LG) {                 // x: forward, scale, back
+                    const int qy = ln % nP, qz = ln / nP;
+                    C v[nP], w[nP];
+#pragma unroll
+                    for (int i = 0; i < nP; ++i) v[i] = pv[(i + nP * ln) * NPL + ps];
+                    const C lyz = sLy[pyo][qy] + sLz[qz];
+#pragma unroll
+                    for (int j = 0; j < nP; ++j) {
+                        C s = 0;
+#pragma unroll
+                        for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
+                        w[j] = s / (sLx[pxo][j] + lyz);
+                    }
+#pragma unroll
+                    for (int i = 0; i < nP; ++i) {
+                        C s = 0;
+#pragma unroll
+                        for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * w[j];
+                        pv[(i + nP * ln) * NPL + ps] = s;
+                    }
+                }
+            }
+            __syncthreads();
+            if (ps < NPL) {
+                C Sm[nP2];
+#pragma unroll
+                for (int i = 0; i < nP2; ++i) Sm[i] = sSy[pyo][i];
+                for (int ln = lg; ln < nP2; ln += LG) {                 // backward y
+                    const int qx = ln % nP, qz = ln / nP;
+                    C v[nP];
+#pragma unroll
+                    for (int j = 0; j < nP; ++j) v[j] = pv[(qx + nP * j + nP2 * qz) * NPL + ps];
+#pragma unroll
+                    for (int i = 0; i < nP; ++i) {
+                        C s = 0;
+#pragma unroll
+                        for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * v[j];
+                        pv[(qx + nP * i + nP2 * qz) * NPL + ps] = s;
+                    }
+                }
+            }
+            __syncthreads();
+            if (ps < NPL) {
+                C Sm[nP2];
+#pragma unroll
+                for (int i = 0; i < nP2; ++i) Sm[i] = sSz[i];
+                for (int ln = lg; ln < nP2; ln += LG) {                 // backward z
+                    C v[nP];
+#pragma unroll
+                    for (int j = 0; j < nP; ++j) v[j] = pv[(ln + nP2 * j) * NPL + ps];
+#pragma unroll
+                    for (int i = 0; i < nP; ++i) {
+                        C s = 0;
+#pragma unroll
+                        for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * v[j];
+                        pv[(ln + nP2 * i) * NPL + ps] = s;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // finish cell layer vk-1, open cell layer vk
+        for (int item = tid; item < TX * TY * NN; item += 256) {
+            const int cx = item % TX;
+            const int cy = (item / TX) % TY;
+            const int l = item / (TX * TY);
+            const int i = i0 + cx, j = j0 + cy;
+            const int a = l % N, b = (l / N) % N, c = l / N2;
+            // this layer's terms for a node of cell layer k at plane offset sz
+            auto terms = [&](int sz, C acc) -> C {
+#pragma unroll
+                for (int sy = 0; sy < 2; ++sy) {
+                    if ((sy == 0 && b == P) || (sy == 1 && b == 0)) continue;
+                    const int vy = j + sy;
+                    if (vy < 1 || vy > n1 - 1) continue;
+                    const int qy = sy == 0 ? P - 1 + b : b - 1;
+#pragma unroll
+                    for (int sx = 0; sx < 2; ++sx) {
+                        if ((sx == 0 && a == P) || (sx == 1 && a == 0)) continue;
+                        const int vx = i + sx;
+                        if (vx < 1 || vx > n0 - 1) continue;
+                        const int qx = sx == 0 ? P - 1 + a : a - 1;
+                        const int qz = sz == 0 ? P - 1 + c : c - 1;
+                        acc += pv[(qx + nP * (qy + nP * qz)) * NPL + (vx - i0) + (TX + 1) * (vy - j0)];
+                    }
+                }
+                return acc;
+            };
+            if (i >= n0 || j >= n1) continue;
+            if (vk > k0) {
+                C sum = part[item];
+                if (layer_ok && c >= 1) sum = terms(1, sum);
+                const int e = i + n0 * (j + n1 * (vk - 1));
+                S* dst = zout + cell_offset(e, l, NN);
+                C out = alpha * sum;
+                if (ACC) out = load_as<C>(dst) + out;
+                store_from(dst, out);
+            }
+            if (vk < k1) part[item] = (layer_ok && c <= P - 1) ? terms(0, (C)0) : (C)0;
+        }
+        // cell layer vk-1 is no longer read: the prefetched layer vk+1 takes its slot
+        stash(cells[(vk + 1) & 1], nxt);
+        __syncthreads();
+    }
+}
+
+// Zero the padding cells of the last storage block.
+template <typename S>
+__global__ void k_zero_padding(S* v, int ncells, int nblk, int nn) {
+    const int lane = threadIdx.x;                  // 64 threads
+    const int e = (nblk - 1) * kLanes + lane;
+    if (e < ncells) return;
+    for (int l = blockIdx.x; l < nn; l += gridDim.x)
+        store_from(v + (size_t)(nblk - 1) * nn * kLanes + (size_t)l * kLanes + lane, (typename Prec<S>::C)0);
+}
+
+template <int P, typename S> struct SweepShape;
+template <typename S> struct SweepShape<1, S> { static constexpr int TX = 16, TY = 4, NS = 128; };
+template <typename S> struct SweepShape<2, S> { static constexpr int TX = 16, TY = 4, NS = 128; };
+template <> struct SweepShape<2, double> { static constexpr int TX = 16, TY = 2, NS = 64; };
+template <> struct SweepShape<3, double> { static constexpr int TX = 8, TY = 2, NS = 32; };
+template <> struct SweepShape<3, float> { static constexpr int TX = 8, TY = 4, NS = 64; };
+template <> struct SweepShape<3, bf16_t> { static constexpr int TX = 8, TY = 4, NS = 64; };
+
+template <int P, typename S>
+static hipError_t launch_pi_sweep(int accumulate, ProbEntry* ents, int nprob, ProbEntry* d_tab, hipStream_t s) {
+    using Sh = SweepShape<P, S>;
+    constexpr int TX = Sh::TX, TY = Sh::TY, NS = Sh::NS;
+    LaunchTable L{};
+    int tiles = 0;
+    for (int i = 0; i < nprob; ++i) {
+        const int ntx = (ents[i].n[0] + TX - 1) / TX, nty = (ents[i].n[1] + TY - 1) / TY;
+        const int n2 = ents[i].n[2];
+        // z-chunks: enough workgroups to fill the chip, at least 4 layers each
+        int nkc = (2048 + ntx * nty - 1) / (ntx * nty);
+        nkc = std::max(1, std::min(nkc, (n2 + 3) / 4));
+        ents[i].zchunk = (n2 + nkc - 1) / nkc;
+        nkc = (n2 + ents[i].zchunk - 1) / ents[i].zchunk;
+        ents[i].tile_begin = tiles;
+        ents[i].ntiles = ntx * nty * nkc;
+        tiles += ents[i].ntiles;
+    }
+    L.nprob = nprob;
+    L.total_tiles = tiles;
+    hipError_t err = stage_table(L, ents, nprob, d_tab, s);
+    if (err != hipSuccess) return err;
+    const int grid = (tiles + 7) / 8 * 8;
+    if (nprob > 1) {
+        if (accumulate) hipLaunchKernelGGL((k_pi_sweep<P, S, TX, TY, NS, 1, true>), dim3(grid), dim3(256), 0, s, L);
+        else hipLaunchKernelGGL((k_pi_sweep<P, S, TX, TY, NS, 0, true>), dim3(grid), dim3(256), 0, s, L);
+    } else {
+        if (accumulate) hipLaunchKernelGGL((k_pi_sweep<P, S, TX, TY, NS, 1, false>), dim3(grid), dim3(256), 0, s, L);
+        else hipLaunchKernelGGL((k_pi_sweep<P, S, TX, TY, NS, 0, false>), dim3(grid), dim3(256), 0, s, L);
+    }
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    for (int i = 0; i < nprob; ++i) {
+        if (ents[i].ncells % kLanes == 0) continue;
+        constexpr int NN = (P + 1) * (P + 1) * (P + 1);
+        hipLaunchKernelGGL((k_zero_padding<S>), dim3(NN < 64 ? NN : 64), dim3(64), 0, s,
+                           static_cast<S*>(ents[i].c), ents[i].ncells, ents[i].nblk, NN);
+    }
+    return hipGetLastError();
+}
+
 template <int P, typename S>
 static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, ProbEntry* d_tab, hipStream_t s) {
+    if constexpr (P <= 3) {
+        if (g_pi_fused) return launch_pi_sweep<P, S>(accumulate, ents, nprob, d_tab, s);
+    }
     using C = typename Prec<S>::C;
     constexpr int CBP = pi_patches_per_tile<P, C>();
     LaunchTable L{};

@@ -87,6 +87,7 @@ def lib():
         "fem_host_1d_matrices": ([i, vp, vp], i),
         "fem_host_fd_1d": ([i, d, d, vp, vp], i),
         "fem_host_gll_nodes": ([i, vp], i),
+        "fem_set_option": ([i, i], i),
         "fem_last_error": ([], ct.c_char_p),
         "fem_version": ([], ct.c_char_p),
     }
@@ -160,6 +161,13 @@ def make_desc(p, n, widths=None, bc=DIRICHLET):
     d.bc = int(bc)
     d._keep = keep
     return d
+
+
+OPT_PI_FUSED = 1
+
+
+def set_option(option, value):
+    check(lib().fem_set_option(option, value), "fem_set_option")
 
 
 def host_1d_matrices(p):
