@@ -191,6 +191,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--solve-reps", type=int, default=5)
+    ap.add_argument("--requests", type=int, default=10000, help="serving mode: stream length")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only (the hot path is single-device; "
@@ -212,7 +213,7 @@ def main():
         return
     if a.mode == "serve":
         from paper_2607_02335_amd import serve
-        print(json.dumps(serve.run_stream_bench()))
+        print(json.dumps(serve.run_stream_bench(count=a.requests, log=log)))
         return
 
     log("headline workload Q3 64^3 graded FP64")

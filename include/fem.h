@@ -213,9 +213,13 @@ fem_status fem_batch_problem(fem_batch* B, int i, fem_problem** out);
 fem_status fem_batch_apply(fem_batch* B, void* const* x, void* const* y, int prec);
 /* z[i] = P_AS r[i] for every problem i. */
 fem_status fem_batch_patch_inverse(fem_batch* B, void* const* r, void* const* z, int prec);
-/* Tile-shape autotuner: time the candidate tile shapes of each degree
- * present in the batch on its own problems and keep the fastest.  Writes the
- * chosen configuration index per degree 1..7 into choice[7] (may be NULL). */
+/* Tile-shape autotuner: for each degree present in the batch, time the
+ * candidate kernel shapes on the batch's own problems (apply: register or
+ * LDS kernel x persistent grid cap; patch inverse: two-phase or fused sweep
+ * x grid cap) and keep the fastest for later batched calls.  choice (may be
+ * NULL): int[14], choice[2(p-1)] = apply candidate, choice[2(p-1)+1] =
+ * patch-inverse candidate of degree p (untouched for absent degrees).
+ * Synchronises the stream; allocates and frees its own scratch vectors. */
 fem_status fem_batch_autotune(fem_batch* B, int prec, int* choice);
 
 /* ---------------------------------------------------- solve server */

@@ -260,7 +260,7 @@ static fem_status apply_mode(fem_problem* P, const void* x, const void* b, void*
     e.a = x;
     e.b = b;
     e.c = y;
-    FEM_HIP(launch_apply(P->p, prec, mode, &e, 1, nullptr, P->stream, 0), what);
+    FEM_HIP(launch_apply(P->p, prec, mode, &e, 1, nullptr, P->stream), what);
     return FEM_OK;
 }
 
@@ -312,7 +312,7 @@ fem_status smoother_run(fem_problem* P, const void* r, void* z, int prec, int sw
         e.a = z;
         e.b = r;
         e.c = P->d_tmp;
-        FEM_HIP(launch_apply(P->p, prec, 1, &e, 1, nullptr, P->stream, 0), "smoother residual");
+        FEM_HIP(launch_apply(P->p, prec, 1, &e, 1, nullptr, P->stream), "smoother residual");
         st = pi_run(P, P->d_tmp, z, prec, 1, omega);
         if (st != FEM_OK) return st;
     }
@@ -413,7 +413,7 @@ extern "C" fem_status pcg_solve(fem_problem* P, const double* b, double* u, doub
         e.a = u;
         e.b = b;
         e.c = r;
-        FEM_HIP(launch_apply(P->p, FEM_F64, 1, &e, 1, nullptr, P->stream, 0), "pcg_solve residual");
+        FEM_HIP(launch_apply(P->p, FEM_F64, 1, &e, 1, nullptr, P->stream), "pcg_solve residual");
     }
     FEM_HIP(run_assembled_norm2(P, b, FEM_F64, kSlotB2), "pcg_solve norm");
     FEM_HIP(run_assembled_norm2(P, r, FEM_F64, kSlotRN), "pcg_solve norm");
@@ -435,7 +435,7 @@ extern "C" fem_status pcg_solve(fem_problem* P, const double* b, double* u, doub
         ProbEntry e = entry_of(P);
         e.a = p;
         e.c = q;
-        FEM_HIP(launch_apply(P->p, FEM_F64, 0, &e, 1, nullptr, P->stream, 0), "pcg_solve apply");
+        FEM_HIP(launch_apply(P->p, FEM_F64, 0, &e, 1, nullptr, P->stream), "pcg_solve apply");
         FEM_HIP(run_dot(P, q, FEM_F64, p, FEM_F64, kSlotQP), "pcg_solve dot");
         FEM_HIP(run_cg_update_ur(P, u, r, p, q, nullptr, FEM_F64), "pcg_solve update");
         if (sp == FEM_F64) FEM_HIP(run_assembled_norm2(P, r, FEM_F64, kSlotRN), "pcg_solve norm");

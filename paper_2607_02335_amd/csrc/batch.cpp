@@ -1,32 +1,599 @@
-// Batched launches over independent problems and the continuous-batching
-// solve server.  (Filled in below the stubs as the batched kernels land.)
+// Batched launches over independent problems, the tile-shape autotuner, and
+// the continuous-batching solve server.
+//
+// Batches group their problems by degree: one launch per degree covers every
+// problem of that degree (the kernels walk a concatenated tile range and find
+// each tile's problem in a device table).  The server keeps every admitted
+// solve's vectors and scalars on the device and advances all of them by one
+// (F)PCG iteration per step with those batched launches; requests are
+// admitted in arrival order as slots and device memory free up.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
 #include "fem_internal.h"
 #include "host_api.h"
 #include "launch.h"
 
 using namespace fem;
 
-#define NOT_YET(name) return set_error(FEM_EINVAL, name ": not available in this build")
+namespace fem {
+fem_status create_problem(const fem_desc* d, hipStream_t stream, fem_problem** out);
+}
 
-extern "C" fem_status fem_batch_create(int, const fem_desc*, void*, fem_batch** out) {
-    if (out) *out = nullptr;
-    NOT_YET("fem_batch_create");
+static void destroy_problem_internal(fem_problem* P) {
+    if (!P) return;
+    P->owned_by_batch = false;
+    fem_problem_destroy(P);
 }
-extern "C" fem_status fem_batch_destroy(fem_batch*) { return FEM_OK; }
-extern "C" fem_status fem_batch_problem(fem_batch*, int, fem_problem**) { NOT_YET("fem_batch_problem"); }
-extern "C" fem_status fem_batch_apply(fem_batch*, void* const*, void* const*, int) { NOT_YET("fem_batch_apply"); }
-extern "C" fem_status fem_batch_patch_inverse(fem_batch*, void* const*, void* const*, int) {
-    NOT_YET("fem_batch_patch_inverse");
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+static size_t pbytes(int prec) { return prec == FEM_F64 ? 8 : prec == FEM_F32 ? 4 : 2; }
+
+static ProbEntry pi_entry(fem_problem* P, const void* r, void* z, int prec, double alpha) {
+    ProbEntry e = entry_of(P);
+    e.a = r;
+    e.c = z;
+    e.d = P->d_patch;
+    e.alpha = alpha;
+    for (int k = 0; k < 3; ++k)
+        e.fd[k] = prec == FEM_F64 ? (const void*)(P->d_fd64 + k * P->fd_dir_stride)
+                                  : (const void*)(P->d_fd32 + k * P->fd_dir_stride);
+    return e;
 }
-extern "C" fem_status fem_batch_autotune(fem_batch*, int, int*) { NOT_YET("fem_batch_autotune"); }
-extern "C" fem_status fem_server_create(size_t, int, int, int, double, void*, fem_server** out) {
-    if (out) *out = nullptr;
-    NOT_YET("fem_server_create");
+
+// ===================================================================== batch
+struct fem_batch {
+    int count = 0;
+    hipStream_t stream = nullptr;
+    std::vector<fem_problem*> probs;
+    std::vector<int> group[kMaxP + 1];
+    LaunchCfg cfg_apply[kMaxP + 1];
+    LaunchCfg cfg_pi[kMaxP + 1];
+    TableStager st;
+};
+
+extern "C" fem_status fem_batch_create(int count, const fem_desc* descs, void* stream, fem_batch** out) {
+    if (!out) return set_error(FEM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || !descs) return set_error(FEM_EINVAL, "fem_batch_create: count >= 1 and descs required");
+    for (int i = 0; i < count; ++i) {
+        fem_status st = check_desc(&descs[i]);
+        if (st != FEM_OK) return st;
+    }
+    fem_batch* B = new (std::nothrow) fem_batch();
+    if (!B) return set_error(FEM_ENOMEM, "host allocation failed");
+    B->count = count;
+    B->stream = static_cast<hipStream_t>(stream);
+    hipError_t e = B->st.init(2 * count);
+    if (e != hipSuccess) {
+        B->st.destroy();
+        delete B;
+        return set_error(FEM_ENOMEM, "fem_batch_create: table staging allocation failed");
+    }
+    for (int i = 0; i < count; ++i) {
+        fem_problem* P = nullptr;
+        fem_status st = create_problem(&descs[i], B->stream, &P);
+        if (st != FEM_OK) {
+            for (fem_problem* Q : B->probs) destroy_problem_internal(Q);
+            B->st.destroy();
+            delete B;
+            return st;
+        }
+        P->owned_by_batch = true;
+        B->probs.push_back(P);
+        B->group[P->p].push_back(i);
+    }
+    *out = B;
+    return FEM_OK;
 }
-extern "C" fem_status fem_server_destroy(fem_server*) { return FEM_OK; }
-extern "C" fem_status fem_server_submit(fem_server*, const fem_desc*, const double*, double, int, uint64_t*) {
-    NOT_YET("fem_server_submit");
+
+extern "C" fem_status fem_batch_destroy(fem_batch* B) {
+    if (!B) return FEM_OK;
+    hipStreamSynchronize(B->stream);
+    for (fem_problem* P : B->probs) destroy_problem_internal(P);
+    B->st.destroy();
+    delete B;
+    return FEM_OK;
 }
-extern "C" fem_status fem_server_step(fem_server*, int*, int*, int*) { NOT_YET("fem_server_step"); }
-extern "C" fem_status fem_server_poll(fem_server*, uint64_t, double*, fem_solve_info*) { NOT_YET("fem_server_poll"); }
-extern "C" fem_status fem_server_memory(fem_server*, size_t*, size_t*) { NOT_YET("fem_server_memory"); }
+
+extern "C" fem_status fem_batch_problem(fem_batch* B, int i, fem_problem** out) {
+    if (!B || !out || i < 0 || i >= B->count) return set_error(FEM_EINVAL, "fem_batch_problem: bad index");
+    *out = B->probs[i];
+    return FEM_OK;
+}
+
+static fem_status batch_apply_cfg(fem_batch* B, void* const* x, void* const* y, int prec, const LaunchCfg* cfgs) {
+    std::vector<ProbEntry> ents;
+    for (int p = 1; p <= kMaxP; ++p) {
+        if (B->group[p].empty()) continue;
+        ents.clear();
+        for (int i : B->group[p]) {
+            if (!x[i] || !y[i] || x[i] == y[i]) return set_error(FEM_EINVAL, "fem_batch_apply: bad vector pointers");
+            ProbEntry e = entry_of(B->probs[i]);
+            e.a = x[i];
+            e.c = y[i];
+            ents.push_back(e);
+        }
+        FEM_HIP(launch_apply(p, prec, 0, ents.data(), (int)ents.size(), &B->st, B->stream, cfgs[p]),
+                "fem_batch_apply");
+    }
+    return FEM_OK;
+}
+
+static fem_status batch_pi_cfg(fem_batch* B, void* const* r, void* const* z, int prec, const LaunchCfg* cfgs) {
+    std::vector<ProbEntry> ents;
+    for (int p = 1; p <= kMaxP; ++p) {
+        if (B->group[p].empty()) continue;
+        ents.clear();
+        for (int i : B->group[p]) {
+            if (!r[i] || !z[i] || r[i] == z[i]) return set_error(FEM_EINVAL, "fem_batch_patch_inverse: bad pointers");
+            ents.push_back(pi_entry(B->probs[i], r[i], z[i], prec, 1.0));
+        }
+        FEM_HIP(launch_patch_inverse(p, prec, 0, ents.data(), (int)ents.size(), &B->st, B->stream, cfgs[p]),
+                "fem_batch_patch_inverse");
+    }
+    return FEM_OK;
+}
+
+extern "C" fem_status fem_batch_apply(fem_batch* B, void* const* x, void* const* y, int prec) {
+    if (!B || !x || !y) return set_error(FEM_EINVAL, "fem_batch_apply: NULL argument");
+    if (prec < FEM_F64 || prec > FEM_BF16) return set_error(FEM_EINVAL, "unknown precision");
+    return batch_apply_cfg(B, x, y, prec, B->cfg_apply);
+}
+
+extern "C" fem_status fem_batch_patch_inverse(fem_batch* B, void* const* r, void* const* z, int prec) {
+    if (!B || !r || !z) return set_error(FEM_EINVAL, "fem_batch_patch_inverse: NULL argument");
+    if (prec < FEM_F64 || prec > FEM_BF16) return set_error(FEM_EINVAL, "unknown precision");
+    return batch_pi_cfg(B, r, z, prec, B->cfg_pi);
+}
+
+// Autotuner: for each degree present, time every candidate kernel shape on
+// this batch's own problems (all problems of that degree in one launch) and
+// keep the fastest.  Candidates: apply = {register/LDS kernel} x {grid cap};
+// patch inverse = {two-phase, fused sweep (p <= 3)} x {grid cap}.
+extern "C" fem_status fem_batch_autotune(fem_batch* B, int prec, int* choice) {
+    if (!B) return set_error(FEM_EINVAL, "fem_batch_autotune: NULL batch");
+    if (prec < FEM_F64 || prec > FEM_BF16) return set_error(FEM_EINVAL, "unknown precision");
+    const int caps[2] = {kMaxGrid, 4 * 256};
+    std::vector<void*> x(B->count), y(B->count);
+    for (int i = 0; i < B->count; ++i) {
+        const size_t bytes = align256(B->probs[i]->cell_len * pbytes(prec));
+        if (hipMalloc(&x[i], bytes) != hipSuccess || hipMalloc(&y[i], bytes) != hipSuccess) {
+            for (void* v : x) hipFree(v);
+            for (void* v : y) hipFree(v);
+            return set_error(FEM_ENOMEM, "fem_batch_autotune: scratch allocation failed");
+        }
+        hipMemsetAsync(x[i], 0, bytes, B->stream);
+        hipMemsetAsync(y[i], 0, bytes, B->stream);
+    }
+    hipEvent_t e0, e1;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    fem_status result = FEM_OK;
+    for (int p = 1; p <= kMaxP && result == FEM_OK; ++p) {
+        if (B->group[p].empty()) continue;
+        for (int which = 0; which < 2 && result == FEM_OK; ++which) {
+            std::vector<LaunchCfg> cand;
+            for (int kind = 0; kind < 2; ++kind) {
+                if (which == 0 && kind == 1 && p > 3) continue;      // above p = 3 the LDS kernel is the only one
+                if (which == 1 && kind == 1 && p > 3) continue;      // no fused sweep above p = 3
+                for (int c : caps) {
+                    LaunchCfg cfg;
+                    cfg.grid_cap = c;
+                    if (which == 0) cfg.apply_lds = kind; else cfg.pi_fused = kind;
+                    cand.push_back(cfg);
+                }
+            }
+            float best = 1e30f;
+            int best_i = 0;
+            for (size_t ci = 0; ci < cand.size(); ++ci) {
+                LaunchCfg cfgs[kMaxP + 1];
+                for (int q = 0; q <= kMaxP; ++q) cfgs[q] = which == 0 ? B->cfg_apply[q] : B->cfg_pi[q];
+                cfgs[p] = cand[ci];
+                // only this degree's problems take part
+                std::vector<int> saved[kMaxP + 1];
+                for (int q = 1; q <= kMaxP; ++q)
+                    if (q != p) std::swap(saved[q], B->group[q]);
+                auto run = [&]() {
+                    return which == 0 ? batch_apply_cfg(B, x.data(), y.data(), prec, cfgs)
+                                      : batch_pi_cfg(B, x.data(), y.data(), prec, cfgs);
+                };
+                fem_status st = run();                                // warm
+                const int reps = 3;
+                hipEventRecord(e0, B->stream);
+                for (int r = 0; r < reps && st == FEM_OK; ++r) st = run();
+                hipEventRecord(e1, B->stream);
+                hipEventSynchronize(e1);
+                for (int q = 1; q <= kMaxP; ++q)
+                    if (q != p) std::swap(saved[q], B->group[q]);
+                if (st != FEM_OK) {
+                    result = st;
+                    break;
+                }
+                float ms = 0;
+                hipEventElapsedTime(&ms, e0, e1);
+                if (ms < best) {
+                    best = ms;
+                    best_i = (int)ci;
+                }
+            }
+            if (result != FEM_OK) break;
+            if (which == 0) B->cfg_apply[p] = cand[best_i]; else B->cfg_pi[p] = cand[best_i];
+            if (choice) choice[2 * (p - 1) + which] = best_i;
+        }
+    }
+    hipStreamSynchronize(B->stream);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    for (void* v : x) hipFree(v);
+    for (void* v : y) hipFree(v);
+    return result;
+}
+
+// ===================================================================== server
+namespace {
+
+struct Request {
+    uint64_t ticket = 0;
+    fem_desc desc{};
+    std::vector<double> widths[3];
+    std::vector<double> f;
+    double rtol = 1e-8;
+    int maxit = 1000;
+    size_t footprint = 0;
+    std::chrono::steady_clock::time_point t_admit;
+};
+
+struct Active {
+    Request req;
+    fem_problem* P = nullptr;
+    char* mem = nullptr;
+    double *u = nullptr, *b = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
+    void* z = nullptr;
+    void* rs = nullptr;
+    int iters = 0;
+    bool finished = false;
+    int status = FEM_OK;
+    double relres = 1.0;
+};
+
+struct Done {
+    std::vector<double> u;
+    fem_solve_info info{};
+};
+
+}  // namespace
+
+struct fem_server {
+    size_t budget = 0, in_use = 0, high_water = 0;
+    int max_active = 0;
+    int sp = FEM_F32, sweeps = 2, variant = FEM_CG_FCG;
+    double omega = 0.125;
+    hipStream_t stream = nullptr;
+    uint64_t next_ticket = 1;
+    std::deque<Request> queue;
+    std::vector<Active*> active;
+    std::unordered_map<uint64_t, Done> done;
+    std::unordered_map<uint64_t, int> state;      // 0 queued, 1 active, 2 done
+    TableStager st;
+    double* d_collect = nullptr;
+    double* h_collect = nullptr;
+};
+
+extern "C" fem_status fem_server_create(size_t hbm_budget, int max_active, int smoother_prec, int sweeps,
+                                        double omega, void* stream, fem_server** out) {
+    if (!out) return set_error(FEM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_active < 1 || sweeps < 1 || smoother_prec < FEM_F64 || smoother_prec > FEM_BF16 || !std::isfinite(omega))
+        return set_error(FEM_EINVAL, "fem_server_create: bad arguments");
+    fem_server* S = new (std::nothrow) fem_server();
+    if (!S) return set_error(FEM_ENOMEM, "host allocation failed");
+    S->budget = hbm_budget;
+    S->max_active = max_active;
+    S->sp = smoother_prec;
+    S->sweeps = sweeps;
+    S->omega = omega;
+    S->variant = smoother_prec == FEM_F64 ? FEM_CG_PCG : FEM_CG_FCG;
+    S->stream = static_cast<hipStream_t>(stream);
+    if (S->st.init(2 * max_active) != hipSuccess ||
+        hipMalloc((void**)&S->d_collect, sizeof(double) * 4 * max_active) != hipSuccess ||
+        hipHostMalloc((void**)&S->h_collect, sizeof(double) * 4 * max_active, hipHostMallocDefault) != hipSuccess) {
+        S->st.destroy();
+        hipFree(S->d_collect);
+        if (S->h_collect) hipHostFree(S->h_collect);
+        delete S;
+        return set_error(FEM_ENOMEM, "fem_server_create: allocation failed");
+    }
+    *out = S;
+    return FEM_OK;
+}
+
+static void release_active(fem_server* S, Active* A) {
+    hipFree(A->mem);
+    destroy_problem_internal(A->P);
+    S->in_use -= A->req.footprint;
+    delete A;
+}
+
+extern "C" fem_status fem_server_destroy(fem_server* S) {
+    if (!S) return FEM_OK;
+    hipStreamSynchronize(S->stream);
+    for (Active* A : S->active) release_active(S, A);
+    S->st.destroy();
+    hipFree(S->d_collect);
+    hipHostFree(S->h_collect);
+    delete S;
+    return FEM_OK;
+}
+
+extern "C" fem_status fem_server_submit(fem_server* S, const fem_desc* desc, const double* f_glob, double rtol,
+                                        int maxit, uint64_t* ticket) {
+    if (!S || !desc || !f_glob || !ticket) return set_error(FEM_EINVAL, "fem_server_submit: NULL argument");
+    fem_status st = check_desc(desc);
+    if (st != FEM_OK) return st;
+    if (!(rtol > 0) || maxit < 1) return set_error(FEM_EINVAL, "fem_server_submit: rtol > 0 and maxit >= 1");
+    if (desc->bc != FEM_BC_DIRICHLET) return set_error(FEM_EINVAL, "fem_server_submit: Dirichlet problems only");
+    Request R;
+    R.desc = *desc;
+    for (int k = 0; k < 3; ++k) {
+        if (desc->widths[k]) {
+            R.widths[k].assign(desc->widths[k], desc->widths[k] + desc->n[k]);
+            R.desc.widths[k] = nullptr;
+        }
+    }
+    R.footprint = fem_footprint_bytes(desc, S->sp);
+    if (R.footprint > S->budget) return set_error(FEM_ENOMEM, "fem_server_submit: request exceeds the memory budget");
+    const size_t glen = (size_t)(desc->n[0] * desc->p + 1) * (desc->n[1] * desc->p + 1) * (desc->n[2] * desc->p + 1);
+    R.f.assign(f_glob, f_glob + glen);
+    R.rtol = rtol;
+    R.maxit = maxit;
+    R.ticket = S->next_ticket++;
+    *ticket = R.ticket;
+    S->state[R.ticket] = 0;
+    S->queue.push_back(std::move(R));
+    return FEM_OK;
+}
+
+// Admission: allocate the solve's vectors, form b = P_I M f, and run the
+// iteration's start (r = b, z = P(r), p = z, <r,z>) with single-problem
+// launches on the server stream.
+static fem_status admit(fem_server* S, Request&& R) {
+    Active* A = new (std::nothrow) Active();
+    if (!A) return set_error(FEM_ENOMEM, "host allocation failed");
+    A->req = std::move(R);
+    fem_desc d = A->req.desc;
+    for (int k = 0; k < 3; ++k) d.widths[k] = A->req.widths[k].empty() ? nullptr : A->req.widths[k].data();
+    fem_status st = create_problem(&d, S->stream, &A->P);
+    if (st != FEM_OK) {
+        delete A;
+        return st;
+    }
+    A->P->owned_by_batch = true;
+    fem_problem* P = A->P;
+    const size_t len = P->cell_len;
+    const size_t v64 = align256(8 * len), vs = align256(pbytes(S->sp) * len);
+    if (hipMalloc((void**)&A->mem, 5 * v64 + 2 * vs) != hipSuccess) {
+        destroy_problem_internal(P);
+        delete A;
+        return set_error(FEM_ENOMEM, "server admission: device allocation failed");
+    }
+    A->u = reinterpret_cast<double*>(A->mem);
+    A->b = reinterpret_cast<double*>(A->mem + v64);
+    A->r = reinterpret_cast<double*>(A->mem + 2 * v64);
+    A->p = reinterpret_cast<double*>(A->mem + 3 * v64);
+    A->q = reinterpret_cast<double*>(A->mem + 4 * v64);
+    A->z = A->mem + 5 * v64;
+    A->rs = S->sp == FEM_F64 ? (void*)A->r : (void*)(A->mem + 5 * v64 + vs);
+    S->in_use += A->req.footprint;
+    S->high_water = std::max(S->high_water, S->in_use);
+    A->req.t_admit = std::chrono::steady_clock::now();
+
+    hipStream_t s = S->stream;
+    // f (global) staged in q, gathered into p, b = P_I M f
+    FEM_HIP(hipMemcpyAsync(A->q, A->req.f.data(), sizeof(double) * A->req.f.size(), hipMemcpyHostToDevice, s),
+            "server upload");
+    FEM_HIP(run_gather(P, A->q, A->p, FEM_F64), "server gather");
+    {
+        ProbEntry e = entry_of(P);
+        e.a = A->p;
+        e.c = A->b;
+        FEM_HIP(launch_apply(P->p, FEM_F64, 2, &e, 1, nullptr, s), "server rhs");
+    }
+    FEM_HIP(run_fill_zero(P, A->u, FEM_F64), "server init");
+    FEM_HIP(hipMemcpyAsync(A->r, A->b, sizeof(double) * len, hipMemcpyDeviceToDevice, s), "server init");
+    FEM_HIP(run_assembled_norm2(P, A->b, FEM_F64, kSlotB2), "server norm");
+    if (S->sp != FEM_F64) FEM_HIP(run_distribute(P, A->r, A->rs, S->sp, kSlotRN), "server distribute");
+    st = smoother_run(P, A->rs, A->z, S->sp, S->sweeps, S->omega);
+    if (st != FEM_OK) return st;
+    FEM_HIP(run_convert(P, A->z, S->sp, A->p, FEM_F64), "server p0");
+    FEM_HIP(run_dot(P, A->r, FEM_F64, A->z, S->sp, kSlotRZ), "server dot");
+    S->active.push_back(A);
+    S->state[A->req.ticket] = 1;
+    return FEM_OK;
+}
+
+static fem_status retire(fem_server* S, Active* A) {
+    fem_problem* P = A->P;
+    Done D;
+    D.u.resize(P->global_len);
+    // u (FP64) to global order, staged in q
+    FEM_HIP(run_extract(P, A->u, A->q, FEM_F64), "server extract");
+    FEM_HIP(hipMemcpyAsync(D.u.data(), A->q, sizeof(double) * P->global_len, hipMemcpyDeviceToHost, S->stream),
+            "server download");
+    FEM_HIP(hipStreamSynchronize(S->stream), "server download");
+    D.info.iters = A->iters;
+    D.info.status = A->status;
+    D.info.relres = A->relres;
+    D.info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - A->req.t_admit).count();
+    S->done[A->req.ticket] = std::move(D);
+    S->state[A->req.ticket] = 2;
+    release_active(S, A);
+    return FEM_OK;
+}
+
+extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queued, int* n_done) {
+    if (!S) return set_error(FEM_EINVAL, "fem_server_step: NULL server");
+    // 1. admission in arrival order
+    while (!S->queue.empty() && (int)S->active.size() < S->max_active &&
+           S->in_use + S->queue.front().footprint <= S->budget) {
+        Request R = std::move(S->queue.front());
+        S->queue.pop_front();
+        fem_status st = admit(S, std::move(R));
+        if (st != FEM_OK) return st;
+    }
+    hipStream_t s = S->stream;
+    const int na = (int)S->active.size();
+    if (na > 0) {
+        std::vector<ProbEntry> ents;
+        auto group_of = [&](int p) {
+            std::vector<Active*> g;
+            for (Active* A : S->active)
+                if (A->P->p == p && !A->finished) g.push_back(A);
+            return g;
+        };
+        // 2. q = A p, <q,p>, u += alpha p, r -= alpha q, residual norm (and the
+        //    smoother's copy of r), one launch per degree and operation
+        for (int p = 1; p <= kMaxP; ++p) {
+            std::vector<Active*> g = group_of(p);
+            if (g.empty()) continue;
+            const int n = (int)g.size();
+            ents.resize(n);
+            for (int i = 0; i < n; ++i) {
+                ents[i] = entry_of(g[i]->P);
+                ents[i].a = g[i]->p;
+                ents[i].c = g[i]->q;
+            }
+            FEM_HIP(launch_apply(p, FEM_F64, 0, ents.data(), n, &S->st, s), "server apply");
+            for (int i = 0; i < n; ++i) {
+                ents[i] = entry_of(g[i]->P);
+                ents[i].a = g[i]->q;
+                ents[i].b = g[i]->p;
+            }
+            FEM_HIP(launch_dot(FEM_F64, FEM_F64, ents.data(), n, &S->st, s, kSlotQP), "server dot");
+            for (int i = 0; i < n; ++i) {
+                ents[i] = entry_of(g[i]->P);
+                ents[i].a = g[i]->p;
+                ents[i].b = g[i]->q;
+                ents[i].c = g[i]->u;
+                ents[i].d = g[i]->r;
+            }
+            FEM_HIP(launch_cg_ur(ents.data(), n, &S->st, s), "server update");
+            for (int i = 0; i < n; ++i) {
+                ents[i] = entry_of(g[i]->P);
+                ents[i].a = g[i]->r;
+                ents[i].c = g[i]->rs;
+            }
+            if (S->sp == FEM_F64) FEM_HIP(launch_anorm(p, ents.data(), n, &S->st, s, kSlotRN), "server norm");
+            else FEM_HIP(launch_distribute(p, S->sp, ents.data(), n, &S->st, s, kSlotRN), "server norm");
+        }
+        // 3. one read-back of every solve's scalars
+        ents.resize(na);
+        for (int i = 0; i < na; ++i) ents[i] = entry_of(S->active[i]->P);
+        FEM_HIP(launch_collect_slots(ents.data(), na, &S->st, s, kSlotRN, kSlotQP, S->d_collect), "server collect");
+        FEM_HIP(launch_collect_slots(ents.data(), na, &S->st, s, kSlotB2, kSlotB2, S->d_collect + 2 * na),
+                "server collect");
+        FEM_HIP(hipMemcpyAsync(S->h_collect, S->d_collect, sizeof(double) * 4 * na, hipMemcpyDeviceToHost, s),
+                "server read-back");
+        FEM_HIP(hipStreamSynchronize(s), "server read-back");
+        for (int i = 0; i < na; ++i) {
+            Active* A = S->active[i];
+            const double rn = S->h_collect[2 * i], qp = S->h_collect[2 * i + 1], b2 = S->h_collect[2 * na + 2 * i];
+            A->iters += 1;
+            A->relres = b2 > 0 ? std::sqrt(rn / b2) : 0.0;
+            if (!(qp > 0) || !std::isfinite(qp) || !std::isfinite(A->relres)) {
+                A->finished = true;
+                A->status = FEM_EBREAKDOWN;
+            } else if (A->relres <= A->req.rtol) {
+                A->finished = true;
+                A->status = FEM_OK;
+            } else if (A->iters >= A->req.maxit) {
+                A->finished = true;
+                A->status = FEM_ENOTCONV;
+            }
+        }
+        // 4. smoother, pairings and the new direction for the unfinished solves
+        for (int p = 1; p <= kMaxP; ++p) {
+            std::vector<Active*> g = group_of(p);
+            if (g.empty()) continue;
+            const int n = (int)g.size();
+            ents.resize(n);
+            for (int i = 0; i < n; ++i) ents[i] = pi_entry(g[i]->P, g[i]->rs, g[i]->z, S->sp, S->omega);
+            FEM_HIP(launch_patch_inverse(p, S->sp, 0, ents.data(), n, &S->st, s), "server smoother");
+            for (int sw = 1; sw < S->sweeps; ++sw) {
+                for (int i = 0; i < n; ++i) {
+                    ents[i] = entry_of(g[i]->P);
+                    ents[i].a = g[i]->z;
+                    ents[i].b = g[i]->rs;
+                    ents[i].c = g[i]->P->d_tmp;
+                }
+                FEM_HIP(launch_apply(p, S->sp, 1, ents.data(), n, &S->st, s), "server smoother residual");
+                for (int i = 0; i < n; ++i) ents[i] = pi_entry(g[i]->P, g[i]->P->d_tmp, g[i]->z, S->sp, S->omega);
+                FEM_HIP(launch_patch_inverse(p, S->sp, 1, ents.data(), n, &S->st, s), "server smoother");
+            }
+            if (S->variant == FEM_CG_PCG) {
+                for (int i = 0; i < n; ++i) ents[i] = entry_of(g[i]->P);
+                FEM_HIP(launch_slot_copy(ents.data(), n, &S->st, s, kSlotRZOld, kSlotRZ), "server slots");
+            } else {
+                for (int i = 0; i < n; ++i) {
+                    ents[i] = entry_of(g[i]->P);
+                    ents[i].a = g[i]->q;
+                    ents[i].b = g[i]->z;
+                }
+                FEM_HIP(launch_dot(FEM_F64, S->sp, ents.data(), n, &S->st, s, kSlotQZ), "server dot");
+            }
+            for (int i = 0; i < n; ++i) {
+                ents[i] = entry_of(g[i]->P);
+                ents[i].a = g[i]->r;
+                ents[i].b = g[i]->z;
+            }
+            FEM_HIP(launch_dot(FEM_F64, S->sp, ents.data(), n, &S->st, s, kSlotRZ), "server dot");
+            for (int i = 0; i < n; ++i) {
+                ents[i] = entry_of(g[i]->P);
+                ents[i].a = g[i]->z;
+                ents[i].c = g[i]->p;
+            }
+            FEM_HIP(launch_cg_p(S->sp, S->variant, ents.data(), n, &S->st, s), "server direction");
+        }
+        // 5. retire finished solves (frees their memory for the next admissions)
+        std::vector<Active*> keep;
+        for (Active* A : S->active) {
+            if (A->finished) {
+                fem_status st = retire(S, A);
+                if (st != FEM_OK) return st;
+            } else {
+                keep.push_back(A);
+            }
+        }
+        S->active.swap(keep);
+    }
+    if (n_active) *n_active = (int)S->active.size();
+    if (n_queued) *n_queued = (int)S->queue.size();
+    if (n_done) *n_done = (int)S->done.size();
+    return FEM_OK;
+}
+
+extern "C" fem_status fem_server_poll(fem_server* S, uint64_t ticket, double* u_glob, fem_solve_info* info) {
+    if (!S) return set_error(FEM_EINVAL, "fem_server_poll: NULL server");
+    auto it = S->state.find(ticket);
+    if (it == S->state.end()) return set_error(FEM_ENOTFOUND, "fem_server_poll: unknown ticket");
+    if (it->second != 2) return FEM_EAGAIN;
+    Done& D = S->done[ticket];
+    if (u_glob) std::memcpy(u_glob, D.u.data(), sizeof(double) * D.u.size());
+    if (info) *info = D.info;
+    S->done.erase(ticket);
+    S->state.erase(it);
+    return FEM_OK;
+}
+
+extern "C" fem_status fem_server_memory(fem_server* S, size_t* in_use, size_t* high_water) {
+    if (!S) return set_error(FEM_EINVAL, "fem_server_memory: NULL server");
+    if (in_use) *in_use = S->in_use;
+    if (high_water) *high_water = S->high_water;
+    return FEM_OK;
+}

@@ -357,8 +357,10 @@ template <int P> constexpr int lds_cells(int bytes) {
 }
 
 template <int P, typename S, int MODE>
-static hipError_t launch_apply_t(ProbEntry* ents, int nprob, ProbEntry* d_tab, hipStream_t s,
-                                 int force_lds) {
+static hipError_t launch_apply_t(ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s,
+                                 const LaunchCfg& cfg) {
+    const int force_lds = cfg.apply_lds;
+    const int gcap = cfg.grid_cap > 0 ? cfg.grid_cap : kMaxGrid;
     using C = typename Prec<S>::C;
     const RefMats<P, C> R = ref_mats<P, C>();
     const bool use_reg = (P <= 3) && !force_lds;
@@ -377,14 +379,14 @@ static hipError_t launch_apply_t(ProbEntry* ents, int nprob, ProbEntry* d_tab, h
     if (err != hipSuccess) return err;
     if constexpr (P <= 3) {
         if (use_reg) {
-            const int grid = (tiles + 3) / 4 < kMaxGrid ? (tiles + 3) / 4 : kMaxGrid;
+            const int grid = (tiles + 3) / 4 < gcap ? (tiles + 3) / 4 : gcap;
             if (nprob > 1) hipLaunchKernelGGL((k_apply_reg<P, S, MODE, true>), dim3(grid), dim3(256), 0, s, L, R);
             else hipLaunchKernelGGL((k_apply_reg<P, S, MODE, false>), dim3(grid), dim3(256), 0, s, L, R);
             return hipGetLastError();
         }
     }
     {
-        const int grid = tiles < kMaxGrid ? tiles : kMaxGrid;
+        const int grid = tiles < gcap ? tiles : gcap;
         if (nprob > 1) hipLaunchKernelGGL((k_apply_lds<P, S, MODE, CB, true>), dim3(grid), dim3(256), 0, s, L, R);
         else hipLaunchKernelGGL((k_apply_lds<P, S, MODE, CB, false>), dim3(grid), dim3(256), 0, s, L, R);
     }
@@ -392,7 +394,7 @@ static hipError_t launch_apply_t(ProbEntry* ents, int nprob, ProbEntry* d_tab, h
 }
 
 template <int P, typename S>
-static hipError_t launch_apply_m(int mode, ProbEntry* e, int n, ProbEntry* t, hipStream_t s, int fl) {
+static hipError_t launch_apply_m(int mode, ProbEntry* e, int n, TableStager* t, hipStream_t s, const LaunchCfg& fl) {
     switch (mode) {
         case kApplyLaplace: return launch_apply_t<P, S, kApplyLaplace>(e, n, t, s, fl);
         case kApplyResidual: return launch_apply_t<P, S, kApplyResidual>(e, n, t, s, fl);
@@ -401,7 +403,7 @@ static hipError_t launch_apply_m(int mode, ProbEntry* e, int n, ProbEntry* t, hi
 }
 
 template <int P>
-static hipError_t launch_apply_p(int prec, int mode, ProbEntry* e, int n, ProbEntry* t, hipStream_t s, int fl) {
+static hipError_t launch_apply_p(int prec, int mode, ProbEntry* e, int n, TableStager* t, hipStream_t s, const LaunchCfg& fl) {
     switch (prec) {
         case FEM_F64: return launch_apply_m<P, double>(mode, e, n, t, s, fl);
         case FEM_F32: return launch_apply_m<P, float>(mode, e, n, t, s, fl);
@@ -409,8 +411,8 @@ static hipError_t launch_apply_p(int prec, int mode, ProbEntry* e, int n, ProbEn
     }
 }
 
-hipError_t launch_apply(int p, int prec, int mode, ProbEntry* ents, int nprob, ProbEntry* d_tab,
-                        hipStream_t s, int force_lds) {
+hipError_t launch_apply(int p, int prec, int mode, ProbEntry* ents, int nprob, TableStager* d_tab,
+                        hipStream_t s, const LaunchCfg& force_lds) {
     switch (p) {
         case 1: return launch_apply_p<1>(prec, mode, ents, nprob, d_tab, s, force_lds);
         case 2: return launch_apply_p<2>(prec, mode, ents, nprob, d_tab, s, force_lds);

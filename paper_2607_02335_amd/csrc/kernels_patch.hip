@@ -781,7 +781,7 @@ template <> struct SweepShape<3, float> { static constexpr int TX = 8, TY = 4, N
 template <> struct SweepShape<3, bf16_t> { static constexpr int TX = 8, TY = 4, NS = 64; };
 
 template <int P, typename S>
-static hipError_t launch_pi_sweep(int accumulate, ProbEntry* ents, int nprob, ProbEntry* d_tab, hipStream_t s) {
+static hipError_t launch_pi_sweep(int accumulate, ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s) {
     using Sh = SweepShape<P, S>;
     constexpr int TX = Sh::TX, TY = Sh::TY, NS = Sh::NS;
     LaunchTable L{};
@@ -822,10 +822,13 @@ static hipError_t launch_pi_sweep(int accumulate, ProbEntry* ents, int nprob, Pr
 }
 
 template <int P, typename S>
-static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, ProbEntry* d_tab, hipStream_t s) {
+static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s,
+                              const LaunchCfg& cfg) {
     if constexpr (P <= 3) {
-        if (g_pi_fused) return launch_pi_sweep<P, S>(accumulate, ents, nprob, d_tab, s);
+        const int fused = cfg.pi_fused >= 0 ? cfg.pi_fused : g_pi_fused;
+        if (fused) return launch_pi_sweep<P, S>(accumulate, ents, nprob, d_tab, s);
     }
+    const int gcap = cfg.grid_cap > 0 ? cfg.grid_cap : kMaxGrid;
     using C = typename Prec<S>::C;
     constexpr int CBP = pi_patches_per_tile<P, C>();
     LaunchTable L{};
@@ -846,7 +849,7 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, ProbEn
             if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_r<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, L);
             else hipLaunchKernelGGL((k_pi_solve_r<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, L);
         } else {
-            const int grid = tiles < kMaxGrid ? tiles : kMaxGrid;
+            const int grid = tiles < gcap ? tiles : gcap;
             if (nprob > 1) hipLaunchKernelGGL((k_pi_solve<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, L);
             else hipLaunchKernelGGL((k_pi_solve<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, L);
         }
@@ -863,7 +866,7 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, ProbEn
     LaunchTable L2{};
     L2.nprob = nprob;
     L2.total_tiles = tiles2;
-    err = stage_table(L2, ents, nprob, nprob > 1 ? d_tab + nprob : d_tab, s);
+    err = stage_table(L2, ents, nprob, d_tab, s);
     if (err != hipSuccess) return err;
     if constexpr (P <= 3) {
         const int grid = (tiles2 + 3) / 4;
@@ -876,7 +879,7 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, ProbEn
         }
         return hipGetLastError();
     }
-    const int grid2 = tiles2 < kMaxGrid ? tiles2 : kMaxGrid;
+    const int grid2 = tiles2 < gcap ? tiles2 : gcap;
     if (nprob > 1) {
         if (accumulate) hipLaunchKernelGGL((k_pi_combine<P, S, 1, true>), dim3(grid2), dim3(256), 0, s, L2);
         else hipLaunchKernelGGL((k_pi_combine<P, S, 0, true>), dim3(grid2), dim3(256), 0, s, L2);
@@ -888,24 +891,25 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, ProbEn
 }
 
 template <int P>
-static hipError_t launch_pi_p(int prec, int acc, ProbEntry* e, int n, ProbEntry* t, hipStream_t s) {
+static hipError_t launch_pi_p(int prec, int acc, ProbEntry* e, int n, TableStager* t, hipStream_t s,
+                              const LaunchCfg& cfg) {
     switch (prec) {
-        case FEM_F64: return launch_pi_t<P, double>(acc, e, n, t, s);
-        case FEM_F32: return launch_pi_t<P, float>(acc, e, n, t, s);
-        default: return launch_pi_t<P, bf16_t>(acc, e, n, t, s);
+        case FEM_F64: return launch_pi_t<P, double>(acc, e, n, t, s, cfg);
+        case FEM_F32: return launch_pi_t<P, float>(acc, e, n, t, s, cfg);
+        default: return launch_pi_t<P, bf16_t>(acc, e, n, t, s, cfg);
     }
 }
 
 hipError_t launch_patch_inverse(int p, int prec, int accumulate, ProbEntry* ents, int nprob,
-                                ProbEntry* d_tab, hipStream_t s) {
+                                TableStager* d_tab, hipStream_t s, const LaunchCfg& cfg) {
     switch (p) {
-        case 1: return launch_pi_p<1>(prec, accumulate, ents, nprob, d_tab, s);
-        case 2: return launch_pi_p<2>(prec, accumulate, ents, nprob, d_tab, s);
-        case 3: return launch_pi_p<3>(prec, accumulate, ents, nprob, d_tab, s);
-        case 4: return launch_pi_p<4>(prec, accumulate, ents, nprob, d_tab, s);
-        case 5: return launch_pi_p<5>(prec, accumulate, ents, nprob, d_tab, s);
-        case 6: return launch_pi_p<6>(prec, accumulate, ents, nprob, d_tab, s);
-        case 7: return launch_pi_p<7>(prec, accumulate, ents, nprob, d_tab, s);
+        case 1: return launch_pi_p<1>(prec, accumulate, ents, nprob, d_tab, s, cfg);
+        case 2: return launch_pi_p<2>(prec, accumulate, ents, nprob, d_tab, s, cfg);
+        case 3: return launch_pi_p<3>(prec, accumulate, ents, nprob, d_tab, s, cfg);
+        case 4: return launch_pi_p<4>(prec, accumulate, ents, nprob, d_tab, s, cfg);
+        case 5: return launch_pi_p<5>(prec, accumulate, ents, nprob, d_tab, s, cfg);
+        case 6: return launch_pi_p<6>(prec, accumulate, ents, nprob, d_tab, s, cfg);
+        case 7: return launch_pi_p<7>(prec, accumulate, ents, nprob, d_tab, s, cfg);
         default: return hipErrorInvalidValue;
     }
 }

@@ -8,6 +8,8 @@
 // of tiles (independent of anything else in the launch), each tile is summed
 // in a fixed order (thread-strided sums, a fixed shuffle tree, four wave
 // partials), and a final kernel adds the tile partials in index order.
+#include <cstring>
+
 #include "fem_internal.h"
 #include "launch.h"
 
@@ -337,6 +339,31 @@ __global__ void __launch_bounds__(256) k_cg_p(LaunchTable L, int variant) {
     }
 }
 
+// elementwise a (SA) -> c (SB) over whole cell vectors of several problems
+template <typename SA, typename SB, bool MULTI>
+__global__ void __launch_bounds__(256) k_convert_multi(LaunchTable L) {
+    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+        const ProbEntry& pe = entry<MULTI>(L, tile);
+        const int t = tile - pe.tile_begin;
+        const size_t bs = pe.len / pe.nblk;
+        const size_t lo = (size_t)t * bs, hi = lo + bs;
+        const SA* a = static_cast<const SA*>(pe.a);
+        SB* c = static_cast<SB*>(pe.c);
+        for (size_t i = lo + threadIdx.x; i < hi; i += 256) store_from(c + i, load_as<typename Prec<SB>::C>(a + i));
+    }
+}
+
+// out[2i] = slot sa, out[2i+1] = slot sb of problem i
+template <bool MULTI>
+__global__ void k_collect_slots(LaunchTable L, int sa, int sb, double* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.nprob) return;
+    const ProbEntry& pe = entry_at<MULTI>(L, i);
+    const double* sl = red_slots(pe.red);
+    out[2 * i] = sl[sa];
+    out[2 * i + 1] = sl[sb];
+}
+
 // p = z (initial direction), z in precision SZ
 template <bool MULTI>
 __global__ void k_slot_copy(LaunchTable L, int dst, int src) {
@@ -605,6 +632,230 @@ hipError_t run_slot_copy(fem_problem* P, int dst, int src) {
     L.one = entry_of(P);
     hipLaunchKernelGGL(k_slot_copy<false>, dim3(1), dim3(64), 0, P->stream, L, dst, src);
     return hipGetLastError();
+}
+
+// =========================================================================
+// Multi-problem launchers
+static int tiles_red(ProbEntry* ents, int nprob) {
+    int t = 0;
+    for (int i = 0; i < nprob; ++i) {
+        ents[i].tile_begin = t;
+        t += ents[i].ntiles_red;
+    }
+    return t;
+}
+static int tiles_blocks(ProbEntry* ents, int nprob) {
+    int t = 0;
+    for (int i = 0; i < nprob; ++i) {
+        ents[i].tile_begin = t;
+        t += ents[i].nblk;
+    }
+    return t;
+}
+
+static hipError_t final_multi(LaunchTable& L, hipStream_t s, int group, int slot) {
+    if (L.nprob > 1) hipLaunchKernelGGL(k_red_final<true>, dim3(L.nprob), dim3(256), 0, s, L, group, slot);
+    else hipLaunchKernelGGL(k_red_final<false>, dim3(1), dim3(256), 0, s, L, group, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(int pa, int pb, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int slot) {
+    if (nprob <= 0) return hipSuccess;
+    LaunchTable L{};
+    L.nprob = nprob;
+    L.total_tiles = tiles_red(ents, nprob);
+    hipError_t err = stage_table(L, ents, nprob, st, s);
+    if (err != hipSuccess) return err;
+    const int grid = L.total_tiles < kMaxGrid ? L.total_tiles : kMaxGrid;
+    err = dispatch_prec(pa, [&](auto ta) {
+        using SA = decltype(ta);
+        return dispatch_prec(pb, [&](auto tb) {
+            using SB = decltype(tb);
+            if (nprob > 1) hipLaunchKernelGGL((k_dot<SA, SB, true>), dim3(grid), dim3(256), 0, s, L, 0);
+            else hipLaunchKernelGGL((k_dot<SA, SB, false>), dim3(grid), dim3(256), 0, s, L, 0);
+            return hipGetLastError();
+        });
+    });
+    if (err != hipSuccess) return err;
+    return final_multi(L, s, 0, slot);
+}
+
+template <int P, typename S>
+static void launch_distribute_pt(LaunchTable& L, int grid, hipStream_t s) {
+    if (L.nprob > 1) hipLaunchKernelGGL((k_distribute<P, S, true>), dim3(grid), dim3(256), 0, s, L, 2);
+    else hipLaunchKernelGGL((k_distribute<P, S, false>), dim3(grid), dim3(256), 0, s, L, 2);
+}
+
+hipError_t launch_distribute(int p, int prec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int slot) {
+    if (nprob <= 0) return hipSuccess;
+    LaunchTable L{};
+    L.nprob = nprob;
+    L.total_tiles = tiles_red(ents, nprob);
+    hipError_t err = stage_table(L, ents, nprob, st, s);
+    if (err != hipSuccess) return err;
+    const int grid = L.total_tiles < kMaxGrid ? L.total_tiles : kMaxGrid;
+    err = dispatch_prec(prec, [&](auto tag) {
+        using S = decltype(tag);
+        switch (p) {
+            case 1: launch_distribute_pt<1, S>(L, grid, s); break;
+            case 2: launch_distribute_pt<2, S>(L, grid, s); break;
+            case 3: launch_distribute_pt<3, S>(L, grid, s); break;
+            case 4: launch_distribute_pt<4, S>(L, grid, s); break;
+            case 5: launch_distribute_pt<5, S>(L, grid, s); break;
+            case 6: launch_distribute_pt<6, S>(L, grid, s); break;
+            case 7: launch_distribute_pt<7, S>(L, grid, s); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    });
+    if (err != hipSuccess) return err;
+    return final_multi(L, s, 2, slot);
+}
+
+template <int P>
+static void launch_anorm_p(LaunchTable& L, int grid, hipStream_t s) {
+    if (L.nprob > 1) hipLaunchKernelGGL((k_anorm<P, double, true>), dim3(grid), dim3(256), 0, s, L, 1);
+    else hipLaunchKernelGGL((k_anorm<P, double, false>), dim3(grid), dim3(256), 0, s, L, 1);
+}
+
+hipError_t launch_anorm(int p, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int slot) {
+    if (nprob <= 0) return hipSuccess;
+    LaunchTable L{};
+    L.nprob = nprob;
+    L.total_tiles = tiles_red(ents, nprob);
+    hipError_t err = stage_table(L, ents, nprob, st, s);
+    if (err != hipSuccess) return err;
+    const int grid = L.total_tiles < kMaxGrid ? L.total_tiles : kMaxGrid;
+    switch (p) {
+        case 1: launch_anorm_p<1>(L, grid, s); break;
+        case 2: launch_anorm_p<2>(L, grid, s); break;
+        case 3: launch_anorm_p<3>(L, grid, s); break;
+        case 4: launch_anorm_p<4>(L, grid, s); break;
+        case 5: launch_anorm_p<5>(L, grid, s); break;
+        case 6: launch_anorm_p<6>(L, grid, s); break;
+        case 7: launch_anorm_p<7>(L, grid, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    return final_multi(L, s, 1, slot);
+}
+
+hipError_t launch_cg_ur(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s) {
+    if (nprob <= 0) return hipSuccess;
+    LaunchTable L{};
+    L.nprob = nprob;
+    L.total_tiles = tiles_blocks(ents, nprob);
+    hipError_t err = stage_table(L, ents, nprob, st, s);
+    if (err != hipSuccess) return err;
+    const int grid = L.total_tiles < kMaxGrid ? L.total_tiles : kMaxGrid;
+    if (nprob > 1) hipLaunchKernelGGL((k_cg_ur<double, true>), dim3(grid), dim3(256), 0, s, L);
+    else hipLaunchKernelGGL((k_cg_ur<double, false>), dim3(grid), dim3(256), 0, s, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_p(int zprec, int variant, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s) {
+    if (nprob <= 0) return hipSuccess;
+    LaunchTable L{};
+    L.nprob = nprob;
+    L.total_tiles = tiles_blocks(ents, nprob);
+    hipError_t err = stage_table(L, ents, nprob, st, s);
+    if (err != hipSuccess) return err;
+    const int grid = L.total_tiles < kMaxGrid ? L.total_tiles : kMaxGrid;
+    return dispatch_prec(zprec, [&](auto tag) {
+        using S = decltype(tag);
+        if (nprob > 1) hipLaunchKernelGGL((k_cg_p<S, true>), dim3(grid), dim3(256), 0, s, L, variant);
+        else hipLaunchKernelGGL((k_cg_p<S, false>), dim3(grid), dim3(256), 0, s, L, variant);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_slot_copy(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int dst, int src) {
+    if (nprob <= 0) return hipSuccess;
+    LaunchTable L{};
+    L.nprob = nprob;
+    hipError_t err = stage_table(L, ents, nprob, st, s);
+    if (err != hipSuccess) return err;
+    const int grid = (nprob + 63) / 64;
+    if (nprob > 1) hipLaunchKernelGGL(k_slot_copy<true>, dim3(grid), dim3(64), 0, s, L, dst, src);
+    else hipLaunchKernelGGL(k_slot_copy<false>, dim3(grid), dim3(64), 0, s, L, dst, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_collect_slots(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int sa, int sb,
+                                double* out) {
+    if (nprob <= 0) return hipSuccess;
+    LaunchTable L{};
+    L.nprob = nprob;
+    hipError_t err = stage_table(L, ents, nprob, st, s);
+    if (err != hipSuccess) return err;
+    const int grid = (nprob + 63) / 64;
+    if (nprob > 1) hipLaunchKernelGGL(k_collect_slots<true>, dim3(grid), dim3(64), 0, s, L, sa, sb, out);
+    else hipLaunchKernelGGL(k_collect_slots<false>, dim3(grid), dim3(64), 0, s, L, sa, sb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_convert(int sp, int dp, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s) {
+    if (nprob <= 0) return hipSuccess;
+    LaunchTable L{};
+    L.nprob = nprob;
+    L.total_tiles = tiles_blocks(ents, nprob);
+    hipError_t err = stage_table(L, ents, nprob, st, s);
+    if (err != hipSuccess) return err;
+    const int grid = L.total_tiles < kMaxGrid ? L.total_tiles : kMaxGrid;
+    return dispatch_prec(sp, [&](auto ta) {
+        using SA = decltype(ta);
+        return dispatch_prec(dp, [&](auto tb) {
+            using SB = decltype(tb);
+            if (nprob > 1) hipLaunchKernelGGL((k_convert_multi<SA, SB, true>), dim3(grid), dim3(256), 0, s, L);
+            else hipLaunchKernelGGL((k_convert_multi<SA, SB, false>), dim3(grid), dim3(256), 0, s, L);
+            return hipGetLastError();
+        });
+    });
+}
+
+// ------------------------------------------------------------- stager
+hipError_t TableStager::init(int cap_entries) {
+    cap = cap_entries;
+    for (int i = 0; i < kSlots; ++i) {
+        hipError_t e = hipHostMalloc((void**)&host[i], sizeof(ProbEntry) * cap, hipHostMallocDefault);
+        if (e != hipSuccess) return e;
+        e = hipMalloc((void**)&dev[i], sizeof(ProbEntry) * cap);
+        if (e != hipSuccess) return e;
+        e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+        used[i] = false;
+    }
+    return hipSuccess;
+}
+
+void TableStager::destroy() {
+    for (int i = 0; i < kSlots; ++i) {
+        if (used[i]) hipEventSynchronize(ev[i]);
+        if (host[i]) hipHostFree(host[i]);
+        if (dev[i]) hipFree(dev[i]);
+        if (ev[i]) hipEventDestroy(ev[i]);
+        host[i] = nullptr;
+        dev[i] = nullptr;
+        ev[i] = nullptr;
+    }
+}
+
+hipError_t TableStager::upload(const ProbEntry* ents, int n, hipStream_t s, const ProbEntry** out) {
+    if (n > cap) return hipErrorInvalidValue;
+    const int k = next;
+    next = (next + 1) % kSlots;
+    if (used[k]) {
+        hipError_t e = hipEventSynchronize(ev[k]);
+        if (e != hipSuccess) return e;
+    }
+    std::memcpy(host[k], ents, sizeof(ProbEntry) * n);
+    hipError_t e = hipMemcpyAsync(dev[k], host[k], sizeof(ProbEntry) * n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(ev[k], s);
+    used[k] = true;
+    *out = dev[k];
+    return e;
 }
 
 }  // namespace fem

@@ -30,28 +30,71 @@ __host__ __device__ inline double* red_slots(double* red) { return red + kRedPar
 const double* ref_mass(int p);
 const double* ref_stiff(int p);
 
+// Device copies of multi-problem entry tables.  Each upload takes the next of
+// kSlots pinned host / device slot pairs; the host side of a slot is reused
+// only after the copy that read it has run (event), and the device side only
+// by work later on the same stream.
+struct TableStager {
+    static constexpr int kSlots = 16;
+    int cap = 0;
+    ProbEntry* host[kSlots] = {};
+    ProbEntry* dev[kSlots] = {};
+    hipEvent_t ev[kSlots] = {};
+    bool used[kSlots] = {};
+    int next = 0;
+    hipError_t init(int cap_entries);
+    void destroy();
+    hipError_t upload(const ProbEntry* ents, int n, hipStream_t s, const ProbEntry** out);
+};
+
+// Kernel shape choices of one launch (picked by the batch autotuner).
+struct LaunchCfg {
+    int apply_lds = 0;      // 1: LDS line kernel even where the register kernel exists
+    int pi_fused = -1;      // -1: process-wide default, 0: two-phase, 1: fused sweep
+    int grid_cap = 0;       // cap on persistent grids (0: default)
+};
+
 // Put the entry table where the kernel reads it: by value for a single
-// problem, else copied to d_tab on the stream (from host memory that must
-// stay valid until the copy has run).
-inline hipError_t stage_table(LaunchTable& L, const ProbEntry* ents, int nprob, ProbEntry* d_tab,
+// problem, else through the stager.
+inline hipError_t stage_table(LaunchTable& L, const ProbEntry* ents, int nprob, TableStager* st,
                               hipStream_t s) {
     if (nprob == 1) {
         L.one = ents[0];
         L.tab = nullptr;
         return hipSuccess;
     }
-    L.tab = d_tab;
-    return hipMemcpyAsync(d_tab, ents, sizeof(ProbEntry) * nprob, hipMemcpyHostToDevice, s);
+    if (!st) return hipErrorInvalidValue;
+    return st->upload(ents, nprob, s, &L.tab);
 }
 
 // Kernel launchers.  Each fills tile_begin/ntiles of the entries.
 // apply: mode 0 y=Ax (a=x, c=y), 1 y=b-Ax (a=x, b=b, c=y), 2 y=Mx.
-hipError_t launch_apply(int p, int prec, int mode, ProbEntry* ents, int nprob, ProbEntry* d_tab,
-                        hipStream_t s, int force_lds);
+hipError_t launch_apply(int p, int prec, int mode, ProbEntry* ents, int nprob, TableStager* st,
+                        hipStream_t s, const LaunchCfg& cfg = LaunchCfg());
 // patch inverse: a = r (dual), c = z (primal), d = patch buffer,
 // alpha = damping; accumulate: z = (acc ? z : 0) + alpha * P_AS r.
 hipError_t launch_patch_inverse(int p, int prec, int accumulate, ProbEntry* ents, int nprob,
-                                ProbEntry* d_tab, hipStream_t s);
+                                TableStager* st, hipStream_t s, const LaunchCfg& cfg = LaunchCfg());
+
+// Multi-problem vector operations (all problems in `ents`, any degrees where
+// noted).  Operands in the entries as for the single-problem versions.
+// dot: a . b into slot (precisions pa, pb)
+hipError_t launch_dot(int pa, int pb, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int slot);
+// distribute + norm (one degree p): a = r (FP64), c = out (prec); slot <- ||G^T r||^2
+hipError_t launch_distribute(int p, int prec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s,
+                             int slot);
+// assembled norm (one degree p): a = r (FP64); slot <- ||G^T r||^2
+hipError_t launch_anorm(int p, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int slot);
+// u += alpha p, r -= alpha q: a = p, b = q, c = u, d = r
+hipError_t launch_cg_ur(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s);
+// p = z + beta p: a = z (zprec), c = p
+hipError_t launch_cg_p(int zprec, int variant, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s);
+hipError_t launch_slot_copy(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int dst, int src);
+// out[2i] = slot a, out[2i+1] = slot b of problem i (device array)
+hipError_t launch_collect_slots(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int sa, int sb,
+                                double* out);
+// elementwise convert a (sp) -> c (dp) over whole cell vectors
+hipError_t launch_convert(int sp, int dp, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s);
 
 // Single-problem helpers (problem handle in, stream of the handle).
 ProbEntry entry_of(const fem_problem* P);

@@ -357,3 +357,107 @@ class Problem:
         if raise_on_error and st not in (FEM_OK,):
             check(st, "pcg_solve")
         return u, res
+
+
+class Batch:
+    """Independent problems launched together (one launch per degree)."""
+
+    def __init__(self, problems):
+        """problems: list of (p, n, widths-or-None)."""
+        descs = (Desc * len(problems))()
+        self._descs = []
+        for i, (p, n, w) in enumerate(problems):
+            d = make_desc(p, n, w)
+            self._descs.append(d)
+            descs[i] = d
+        h = ct.c_void_p()
+        check(lib().fem_batch_create(len(problems), descs, _stream(), ct.byref(h)), "fem_batch_create")
+        self.h = h
+        self.problems = []
+        for i, (p, n, w) in enumerate(problems):
+            ph = ct.c_void_p()
+            check(lib().fem_batch_problem(self.h, i, ct.byref(ph)), "fem_batch_problem")
+            self.problems.append(Problem(p, n, w, _handle=ph))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fem_batch_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _ptrs(ts):
+        arr = (ct.c_void_p * len(ts))()
+        for i, t in enumerate(ts):
+            arr[i] = t.data_ptr()
+        return arr
+
+    def apply(self, xs, ys):
+        check(lib().fem_batch_apply(self.h, self._ptrs(xs), self._ptrs(ys), prec_of(xs[0])), "fem_batch_apply")
+
+    def patch_inverse(self, rs, zs):
+        check(lib().fem_batch_patch_inverse(self.h, self._ptrs(rs), self._ptrs(zs), prec_of(rs[0])),
+              "fem_batch_patch_inverse")
+
+    def autotune(self, prec):
+        choice = (ct.c_int * 14)(*([-1] * 14))
+        check(lib().fem_batch_autotune(self.h, prec, choice), "fem_batch_autotune")
+        return {p: (choice[2 * (p - 1)], choice[2 * (p - 1) + 1]) for p in range(1, 8)
+                if choice[2 * (p - 1)] >= 0}
+
+
+class Server:
+    """Continuous-batching Poisson solve server (device-resident solves)."""
+
+    def __init__(self, hbm_budget, max_active=64, smoother_prec=F32, sweeps=2, omega=0.125):
+        h = ct.c_void_p()
+        check(lib().fem_server_create(int(hbm_budget), max_active, smoother_prec, sweeps, omega, _stream(),
+                                      ct.byref(h)), "fem_server_create")
+        self.h = h
+        self.glen = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fem_server_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, p, n, f, widths=None, rtol=1e-8, maxit=2000):
+        d = make_desc(p, n, widths)
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        t = ct.c_uint64()
+        check(lib().fem_server_submit(self.h, ct.byref(d), f.ctypes.data, rtol, maxit, ct.byref(t)),
+              "fem_server_submit")
+        self.glen[t.value] = f.size
+        return t.value
+
+    def step(self):
+        a, q, dn = ct.c_int(), ct.c_int(), ct.c_int()
+        check(lib().fem_server_step(self.h, ct.byref(a), ct.byref(q), ct.byref(dn)), "fem_server_step")
+        return a.value, q.value, dn.value
+
+    def poll(self, ticket, want_u=True):
+        """(u, info) when finished, else None."""
+        info = SolveInfo()
+        u = np.empty(self.glen[ticket]) if want_u else None
+        st = lib().fem_server_poll(self.h, ticket, u.ctypes.data if want_u else None, ct.byref(info))
+        if st == FEM_EAGAIN:
+            return None
+        check(st, "fem_server_poll")
+        self.glen.pop(ticket, None)
+        return u, dict(iters=info.iters, status=info.status, relres=info.relres, seconds=info.seconds)
+
+    def memory(self):
+        a, b = ct.c_size_t(), ct.c_size_t()
+        check(lib().fem_server_memory(self.h, ct.byref(a), ct.byref(b)), "fem_server_memory")
+        return a.value, b.value

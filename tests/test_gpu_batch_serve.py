@@ -1,0 +1,135 @@
+"""Batched launches and the continuous-batching solve server.
+
+* A batch of independent problems of mixed degree and size (drawn like the
+  256-problem workload, smaller) runs FP32 apply and patch inverse in one
+  launch per degree; each problem's result must equal its own single-problem
+  launch bit for bit and match the FP64 oracle within the FP32 tolerance.
+* The server's solves must equal standalone pcg_solve runs of the same
+  problems: every per-problem reduction has a fixed order independent of
+  what else is in flight, so a result is the same alone and in the mix.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import operators, patches
+from oracle.mesh import Mesh
+from tests.gpu_util import note, rel_err, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    from paper_2607_02335_amd import fem
+    assert torch.cuda.is_available()
+    return fem
+
+
+def small_batch(count=12, seed=3, nmax=7):
+    return synth.batch_problems(count=count, seed=seed, nmin=2, nmax=nmax)
+
+
+def test_batch_equals_single_and_oracle(F):
+    wls = small_batch()
+    note(f"batch of {len(wls)}: " + " ".join(f"q{w.p}n{w.n[0]}" for w in wls))
+    B = F.Batch([(w.p, w.n, None) for w in wls])
+    xs = [P.gather(to_dev(w.x), F.F32) for P, w in zip(B.problems, wls)]
+    ys = [P.cell_vector(F.F32) for P in B.problems]
+    zs = [P.cell_vector(F.F32) for P in B.problems]
+    B.apply(xs, ys)
+    B.patch_inverse(ys, zs)
+    for P, w, x, y, z in zip(B.problems, wls, xs, ys, zs):
+        m = Mesh(w.p, w.n, w.widths)
+        ys1 = P.apply(x)
+        assert bool((ys1 == y).all()), f"apply q{w.p} n{w.n}"
+        zs1 = P.patch_inverse(y)
+        assert bool((zs1 == z).all()), f"patch inverse q{w.p} n{w.n}"
+        yref = operators.apply_cells(m, to_np(P.unpack(x)))
+        assert rel_err(to_np(P.unpack(y)), yref) <= 1e-5
+        zref = patches.SchwarzFactors(m)(operators.scatter(m, to_np(P.unpack(y))))
+        assert rel_err(to_np(P.unpack(z)), zref[m.dofs]) <= 5e-5
+
+
+def test_batch_autotune(F):
+    wls = small_batch(count=9, seed=5)
+    B = F.Batch([(w.p, w.n, None) for w in wls])
+    xs = [P.gather(to_dev(w.x), F.F32) for P, w in zip(B.problems, wls)]
+    ys = [P.cell_vector(F.F32) for P in B.problems]
+    B.apply(xs, ys)
+    before = [to_np(y).copy() for y in ys]
+    note("autotune")
+    choice = B.autotune(F.F32)
+    assert set(choice) == {w.p for w in wls}
+    B.apply(xs, ys)
+    for y, y0 in zip(ys, before):
+        assert rel_err(to_np(y), y0) <= 1e-6
+
+
+def _requests(F, count, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        p = int(rng.choice([2, 3, 7]))
+        n = int(rng.integers(3, 6 if p == 7 else 9))
+        f = synth.request_rhs_nodal(p, (n, n, n), int(rng.integers(0, 2**31 - 1)))
+        out.append((p, n, f))
+    return out
+
+
+@pytest.mark.parametrize("sp", [0, 1])
+def test_server_matches_standalone_solves(F, sp):
+    reqs = _requests(F, 8, 11 + sp)
+    note(f"server sp={sp}: " + " ".join(f"q{p}n{n}" for p, n, _ in reqs))
+    S = F.Server(hbm_budget=8 << 30, max_active=4, smoother_prec=sp)
+    tickets = [S.submit(p, n, f, rtol=1e-8, maxit=800) for p, n, f in reqs]
+    results = {}
+    for _ in range(100000):
+        S.step()
+        for t in tickets:
+            if t not in results:
+                r = S.poll(t)
+                if r is not None:
+                    results[t] = r
+        if len(results) == len(tickets):
+            break
+    assert len(results) == len(tickets)
+    for t, (p, n, f) in zip(tickets, reqs):
+        u_srv, info = results[t]
+        assert info["status"] == 0 and info["relres"] <= 1e-8
+        P = F.Problem(p, n)
+        b = P.mass_apply(P.gather(to_dev(f)))
+        u, inf1 = P.pcg_solve(b, rtol=1e-8, maxit=800, smoother_prec=sp)
+        assert inf1["iters"] == info["iters"]
+        np.testing.assert_array_equal(u_srv, to_np(P.extract(u)))
+    S.close()
+
+
+def test_server_admission_by_memory(F):
+    reqs = _requests(F, 6, 21)
+    fps = [F.footprint_bytes(p, n, F.F32) for p, n, _ in reqs]
+    budget = int(max(fps) * 1.5)                     # at most one or two solves in flight
+    S = F.Server(hbm_budget=budget, max_active=8, smoother_prec=F.F32)
+    big = F.footprint_bytes(7, 48, F.F32)
+    with pytest.raises(F.FemError) as e:
+        S.submit(7, 48, np.zeros((48 * 7 + 1) ** 3))
+    assert e.value.status == F.FEM_ENOMEM and big > budget
+    tickets = [S.submit(p, n, f) for p, n, f in reqs]
+    pending = set(tickets)
+    max_active = 0
+    for _ in range(100000):
+        a, q, d = S.step()
+        max_active = max(max_active, a)
+        in_use, hw = S.memory()
+        assert in_use <= budget
+        for t in list(pending):
+            r = S.poll(t, want_u=False)
+            if r is not None:
+                assert r[1]["status"] == 0
+                pending.discard(t)
+        if not pending:
+            break
+    assert not pending
+    assert S.memory()[1] <= budget
+    S.close()
