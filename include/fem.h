@@ -265,8 +265,17 @@ fem_status fem_host_fd_1d(int p, double h0, double h1, double* S, double* lambda
 /* Process-wide tuning switches (for comparisons and the autotuner).
  * FEM_OPT_PI_FUSED = 1 runs patch_inverse for p <= 3 as one fused sweep that
  * keeps patch results on chip; 0 (default) solves patches into a buffer and
- * combines them in a second launch.  Unknown options are FEM_EINVAL. */
-typedef enum fem_option { FEM_OPT_PI_FUSED = 1 } fem_option;
+ * combines them in a second launch.  FEM_OPT_COMBINE_PER_CELL = 1 makes that
+ * second launch use one wavefront per 64-cell block (all node planes)
+ * instead of one per (block, plane) for p <= 3.  FEM_OPT_RESTRICT_FROM_CELLS
+ * = 1 makes the p <= 3 patch solves sum the residual copies from the cell
+ * vector instead of reading the owner-assembled global-node array.  Unknown
+ * options are FEM_EINVAL. */
+typedef enum fem_option {
+    FEM_OPT_PI_FUSED = 1,
+    FEM_OPT_COMBINE_PER_CELL = 2,
+    FEM_OPT_RESTRICT_FROM_CELLS = 3
+} fem_option;
 fem_status fem_set_option(int option, int value);
 
 const char* fem_last_error(void);

@@ -60,6 +60,7 @@ size_t workspace_bytes(const fem_desc* d) {
     b += align256(sizeof(double) * kRedStride);
     b += align256(sizeof(double) * std::max<size_t>(desc_patch_len(d), 1));
     b += align256(sizeof(double) * desc_cell_len(d));
+    b += align256(sizeof(double) * (size_t)(d->n[0] * d->p + 1) * (d->n[1] * d->p + 1) * (d->n[2] * d->p + 1));
     return b;
 }
 
@@ -87,6 +88,7 @@ static void free_problem(fem_problem* P) {
     hipFree(P->d_red);
     hipFree(P->d_patch);
     hipFree(P->d_tmp);
+    hipFree(P->d_glob);
     hipFree(P->d_solve);
     if (P->h_red) hipHostFree(P->h_red);
     delete P;
@@ -150,6 +152,7 @@ fem_status create_problem(const fem_desc* d, hipStream_t stream, fem_problem** o
     ALLOC(P->d_red, sizeof(double) * kRedStride);
     ALLOC(P->d_patch, sizeof(double) * std::max<size_t>(P->patch_len, 1));
     ALLOC(P->d_tmp, sizeof(double) * P->cell_len);
+    ALLOC(P->d_glob, sizeof(double) * P->global_len);
 #undef ALLOC
     e = hipHostMalloc((void**)&P->h_red, sizeof(double) * kSlotCount, hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -295,6 +298,7 @@ static fem_status pi_run(fem_problem* P, const void* r, void* z, int prec, int a
     e.a = r;
     e.c = z;
     e.d = P->d_patch;
+    e.e = P->d_glob;
     e.alpha = alpha;
     for (int k = 0; k < 3; ++k)
         e.fd[k] = prec == FEM_F64 ? (const void*)(P->d_fd64 + k * P->fd_dir_stride)

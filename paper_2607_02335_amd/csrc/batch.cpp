@@ -40,6 +40,7 @@ static ProbEntry pi_entry(fem_problem* P, const void* r, void* z, int prec, doub
     e.a = r;
     e.c = z;
     e.d = P->d_patch;
+    e.e = P->d_glob;
     e.alpha = alpha;
     for (int k = 0; k < 3; ++k)
         e.fd[k] = prec == FEM_F64 ? (const void*)(P->d_fd64 + k * P->fd_dir_stride)

@@ -160,6 +160,7 @@ struct fem_problem {
     void* d_patch;         // patch-result buffer (sized for FP64)
     size_t patch_len;      // elements of the patch buffer
     void* d_tmp;           // smoother scratch: one cell vector (sized for FP64)
+    void* d_glob;          // assembled residual in global-node order (FP64 size; p >= 4 patch solves)
     void* d_solve;         // pcg_solve vectors, allocated on first use
     size_t solve_bytes;
     double* h_red;         // pinned host mirror of the scalar slots

@@ -30,6 +30,12 @@ namespace fem {
 // fem_set_option.  The two-phase path is the default: on MI355X it is faster
 // for every measured workload (the sweep's per-layer chain is latency-bound).
 int g_pi_fused = 0;
+// 1: combine the two-phase patch results with one wavefront per storage
+// block (all planes) instead of one per (block, plane).
+int g_combine_per_cell = 0;
+// 1: phase 1 of the p <= 3 patch inverse sums the copies from the cell-wise
+// vector itself instead of reading the owner-assembled global-node array.
+int g_restrict_from_cells = 0;
 
 template <int P, typename C> constexpr int pi_patches_per_tile() {
     constexpr int nP = 2 * P - 1;
@@ -780,6 +786,197 @@ template <> struct SweepShape<3, double> { static constexpr int TX = 8, TY = 2, 
 template <> struct SweepShape<3, float> { static constexpr int TX = 8, TY = 4, NS = 64; };
 template <> struct SweepShape<3, bf16_t> { static constexpr int TX = 8, TY = 4, NS = 64; };
 
+// Owner-copy assembly: each global node is written once, by its copy in the
+// lowest-numbered cell along every direction, as the sum of all its copies
+// (ascending cell order).  Threads walk the cell-wise vector (coalesced reads
+// of their own copies); pe: a = r (S), e = global-node array (C).
+template <int P, typename S, typename C, bool MULTI>
+__global__ void __launch_bounds__(256) k_assemble_owner(LaunchTable L) {
+    constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
+    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+        const ProbEntry& pe = entry<MULTI>(L, tile);
+        const int blk = tile - pe.tile_begin;
+        const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+        const size_t G0 = (size_t)n0 * P + 1, G1 = (size_t)n1 * P + 1;
+        const S* v = static_cast<const S*>(pe.a);
+        C* out = static_cast<C*>(pe.e);
+        for (int idx = threadIdx.x; idx < NN * kLanes; idx += 256) {
+            const int l = idx / kLanes, lane = idx % kLanes;
+            const int e = blk * kLanes + lane;
+            if (e >= pe.ncells) continue;
+            const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
+            const int a = l % N, b = (l / N) % N, c = l / N2;
+            if ((a == P && i < n0 - 1) || (b == P && j < n1 - 1) || (c == P && k < n2 - 1)) continue;
+            const int cx = (a == 0 && i > 0) ? 2 : 1;
+            const int cy = (b == 0 && j > 0) ? 2 : 1;
+            const int cz = (c == 0 && k > 0) ? 2 : 1;
+            double s = 0.0;
+            for (int sz = cz - 1; sz >= 0; --sz)
+                for (int sy = cy - 1; sy >= 0; --sy)
+                    for (int sx = cx - 1; sx >= 0; --sx) {
+                        const int ee = (i - sx) + n0 * ((j - sy) + n1 * (k - sz));
+                        const int ll = (sx ? P : a) + N * ((sy ? P : b) + N * (sz ? P : c));
+                        s += load_as<double>(v + cell_offset(ee, ll, NN));
+                    }
+            out[(size_t)(i * P + a) + G0 * ((size_t)(j * P + b) + G1 * (size_t)(k * P + c))] = (C)s;
+        }
+    }
+}
+
+// Phase 1 for p <= 3 reading the assembled residual: the tile's CBP patches
+// along x cover, for each of their (2p-1)^2 (y, z) rows, one contiguous run
+// of CBP*p + p - 1 global nodes; each node is loaded once (coalesced) and
+// placed in the one or two patches that contain it.  Then the FD solve as
+// in k_pi_solve_r.
+template <int P, typename S, int CBP, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_solve_g(LaunchTable L) {
+    using C = typename Prec<S>::C;
+    constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
+    constexpr int REC = fd_record(P);
+    constexpr int NT = 256, LPT = NT / CBP;
+    constexpr int RUN = CBP * P + P - 1;
+    static_assert(NT % CBP == 0, "patches per tile must divide the workgroup");
+    __shared__ C sv[nP3 * CBP];
+    __shared__ C sSx[CBP][nP2 + 1];
+    __shared__ C sLx[CBP][nP];
+    __shared__ C sSyz[2][nP2];
+    __shared__ C sLyz[2][nP];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= L.total_tiles) return;
+    const int tid = threadIdx.x;
+    const int pc = tid % CBP;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int t = tile - pe.tile_begin;
+    const int npx = pe.n[0] - 1, npy = pe.n[1] - 1;
+    const int tpr = (npx + CBP - 1) / CBP;
+    const int row = t / tpr, xt = t % tpr;
+    const int vj = 1 + row % npy, vk = 1 + row / npy;
+    const int vi0 = 1 + xt * CBP;
+    const int vi = vi0 + pc;
+    const bool valid = vi <= npx;
+    {
+        const C* fx = static_cast<const C*>(pe.fd[0]) + (size_t)((valid ? vi : npx) - 1) * REC;
+        for (int w = tid / CBP; w < nP2 + nP; w += LPT) {
+            const C v = fx[w];
+            if (w < nP2) sSx[pc][w] = v; else sLx[pc][w - nP2] = v;
+        }
+        for (int w = tid; w < 2 * (nP2 + nP); w += NT) {
+            const int d = w / (nP2 + nP), o = w % (nP2 + nP);
+            const C v = static_cast<const C*>(pe.fd[1 + d])[(size_t)((d == 0 ? vj : vk) - 1) * REC + o];
+            if (o < nP2) sSyz[d][o] = v; else sLyz[d][o - nP2] = v;
+        }
+    }
+    {
+        const C* g = static_cast<const C*>(pe.e);
+        const size_t G0 = (size_t)pe.n[0] * P + 1, G1 = (size_t)pe.n[1] * P + 1;
+        const int Ibase = (vi0 - 1) * P + 1;
+        const int Iend = min(Ibase + RUN, npx * P + P);          // last interior node plane + 1
+        for (int item = tid; item < RUN * nP2; item += NT) {
+            const int x = item % RUN, yz = item / RUN;
+            const int qy = yz % nP, qz = yz / nP;
+            if (Ibase + x >= Iend) continue;
+            const C v = g[(size_t)(Ibase + x) + G0 * ((size_t)((vj - 1) * P + 1 + qy) + G1 * (size_t)((vk - 1) * P + 1 + qz))];
+            const int p1 = x / P;                                // patch whose qx = x - p1 P lies in [0, P-1]
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                const int pp = p1 - d;
+                const int qx = x - pp * P;
+                if (pp >= 0 && pp < CBP && qx >= 0 && qx < nP) sv[(qx + nP * (qy + nP * qz)) * CBP + pp] = v;
+            }
+        }
+    }
+    __syncthreads();
+    C Sm[nP2];
+#pragma unroll
+    for (int i = 0; i < nP2; ++i) Sm[i] = sSyz[1][i];
+    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // forward z
+        C v[nP];
+#pragma unroll
+        for (int i = 0; i < nP; ++i) v[i] = sv[(ln + nP2 * i) * CBP + pc];
+#pragma unroll
+        for (int j = 0; j < nP; ++j) {
+            C s = 0;
+#pragma unroll
+            for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
+            sv[(ln + nP2 * j) * CBP + pc] = s;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < nP2; ++i) Sm[i] = sSyz[0][i];
+    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // forward y
+        const int qx = ln % nP, qz = ln / nP;
+        C v[nP];
+#pragma unroll
+        for (int i = 0; i < nP; ++i) v[i] = sv[(qx + nP * i + nP2 * qz) * CBP + pc];
+#pragma unroll
+        for (int j = 0; j < nP; ++j) {
+            C s = 0;
+#pragma unroll
+            for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
+            sv[(qx + nP * j + nP2 * qz) * CBP + pc] = s;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < nP2; ++i) Sm[i] = sSx[pc][i];
+    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // x: forward, scale, backward
+        const int qy = ln % nP, qz = ln / nP;
+        C v[nP], w[nP];
+#pragma unroll
+        for (int i = 0; i < nP; ++i) v[i] = sv[(i + nP * ln) * CBP + pc];
+        const C lyz = sLyz[0][qy] + sLyz[1][qz];
+#pragma unroll
+        for (int j = 0; j < nP; ++j) {
+            C s = 0;
+#pragma unroll
+            for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
+            w[j] = s / (sLx[pc][j] + lyz);
+        }
+#pragma unroll
+        for (int i = 0; i < nP; ++i) {
+            C s = 0;
+#pragma unroll
+            for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * w[j];
+            sv[(i + nP * ln) * CBP + pc] = s;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < nP2; ++i) Sm[i] = sSyz[0][i];
+    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // backward y
+        const int qx = ln % nP, qz = ln / nP;
+        C v[nP];
+#pragma unroll
+        for (int j = 0; j < nP; ++j) v[j] = sv[(qx + nP * j + nP2 * qz) * CBP + pc];
+#pragma unroll
+        for (int i = 0; i < nP; ++i) {
+            C s = 0;
+#pragma unroll
+            for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * v[j];
+            sv[(qx + nP * i + nP2 * qz) * CBP + pc] = s;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < nP2; ++i) Sm[i] = sSyz[1][i];
+    C* pbuf = static_cast<C*>(pe.d);
+    const int pidx = (vi - 1) + npx * ((vj - 1) + npy * (vk - 1));
+    C* out = pbuf + (size_t)(pidx / kLanes) * nP3 * kLanes + (pidx % kLanes);
+    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // backward z, store
+        C v[nP];
+#pragma unroll
+        for (int j = 0; j < nP; ++j) v[j] = sv[(ln + nP2 * j) * CBP + pc];
+#pragma unroll
+        for (int i = 0; i < nP; ++i) {
+            C s = 0;
+#pragma unroll
+            for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * v[j];
+            if (valid) out[(size_t)(ln + nP2 * i) * kLanes] = s;
+        }
+    }
+}
+
 template <int P, typename S>
 static hipError_t launch_pi_sweep(int accumulate, ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s) {
     using Sh = SweepShape<P, S>;
@@ -821,6 +1018,323 @@ static hipError_t launch_pi_sweep(int accumulate, ProbEntry* ents, int nprob, Ta
     return hipGetLastError();
 }
 
+// One thread per cell and z-plane, any degree: a wavefront takes the 64
+// cells of a storage block at one plane c of their nodes (tile = block * N +
+// c), so even small meshes give N times as many wavefronts as blocks; the
+// eight corner-patch addresses are formed once per cell, (a, b) loops are
+// unrolled.
+template <int P, typename S, int ACC, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_combine_planes(LaunchTable L) {
+    using C = typename Prec<S>::C;
+    constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
+    constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
+    const int lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= L.total_tiles) return;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int blk = (tile - pe.tile_begin) / N;
+    const int c = (tile - pe.tile_begin) % N;
+    const int e = blk * kLanes + lane;
+    S* z = static_cast<S*>(pe.c) + (size_t)blk * NN * kLanes + (size_t)c * N2 * kLanes + lane;
+    if (e >= pe.ncells) {
+#pragma unroll
+        for (int l = 0; l < N2; ++l) store_from(z + l * kLanes, (C)0);
+        return;
+    }
+    const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+    const int npx = n0 - 1, npy = n1 - 1;
+    const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
+    const C* pbuf = static_cast<const C*>(pe.d);
+    const C alpha = (C)pe.alpha;
+    // the z-plane c selects the vertex layers (and their patch-local qz)
+    int nz = 0, szs[2], qzs[2];
+    if (c != P) { szs[nz] = 0; qzs[nz] = P - 1 + c; ++nz; }
+    if (c != 0) { szs[nz] = 1; qzs[nz] = c - 1; ++nz; }
+    const C* corner[2][2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int sy = 0; sy < 2; ++sy)
+#pragma unroll
+            for (int sx = 0; sx < 2; ++sx) {
+                corner[t][sy][sx] = nullptr;
+                if (t < nz) {
+                    const int vx = i + sx, vy = j + sy, vz = k + szs[t];
+                    const bool ok = vx >= 1 && vx <= npx && vy >= 1 && vy <= npy && vz >= 1 && vz <= n2 - 1;
+                    const int pidx = ok ? (vx - 1) + npx * ((vy - 1) + npy * (vz - 1)) : 0;
+                    if (ok)
+                        corner[t][sy][sx] = pbuf + (size_t)(pidx / kLanes) * nP3 * kLanes + (pidx % kLanes) +
+                                            (size_t)nP2 * qzs[t] * kLanes;
+                }
+            }
+#pragma unroll
+    for (int b = 0; b < N; ++b)
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            C sum = 0;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+#pragma unroll
+                for (int sy = 0; sy < 2; ++sy) {
+                    if ((sy == 0 && b == P) || (sy == 1 && b == 0)) continue;
+                    const int qy = sy == 0 ? P - 1 + b : b - 1;
+#pragma unroll
+                    for (int sx = 0; sx < 2; ++sx) {
+                        if ((sx == 0 && a == P) || (sx == 1 && a == 0)) continue;
+                        const int qx = sx == 0 ? P - 1 + a : a - 1;
+                        const C* src = corner[t][sy][sx];
+                        if (src) sum += src[(size_t)(qx + nP * qy) * kLanes];
+                    }
+                }
+            }
+            const int l = a + N * b;
+            C out = alpha * sum;
+            if (ACC) out = load_as<C>(z + l * kLanes) + out;
+            store_from(z + l * kLanes, out);
+        }
+}
+
+// ---------------------------------------------------------------------------
+// High-degree variant (4 <= p <= 7): the six 1D contractions of a patch are
+// dense products of a (2p-1)x(2p-1) eigenbasis with the (2p-1) x (2p-1)^2
+// matrix of the patch's lines, so they run on the matrix cores: 16x16x4
+// MFMA tiles (FP64 or FP32), the basis zero-padded to 16x16 as the register
+// A operand and 16 patch lines per tile as the B operand read from LDS.
+// One wavefront owns one patch; four per workgroup, no workgroup barriers.
+// The residual is first assembled into a global-node array (k_assemble), so
+// a patch reads its (2p-1)^3 box without summing copies.
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+
+template <typename C> struct Mfma;
+template <> struct Mfma<double> {
+    using V = v4d_t;
+    __device__ static V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    // row of output register r held by lane l (column l % 16)
+    __device__ static int row(int l, int r) { return 4 * r + l / 16; }
+};
+template <> struct Mfma<float> {
+    using V = v4f_t;
+    __device__ static V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int l, int r) { return 4 * (l / 16) + r; }
+};
+
+// 1/d for the positive eigenvalue sums: hardware reciprocal refined by two
+// Newton steps (about 1 ulp; the patch solve does not need IEEE division).
+__device__ __forceinline__ double recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = r * (2.0 - d * r);
+    return r * (2.0 - d * r);
+}
+__device__ __forceinline__ float recip(float d) {
+    float r = __builtin_amdgcn_rcpf(d);
+    return r * (2.0f - d * r);
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// out(j, line) = sum_i Op(j, i) v(i, line) in place over all lines of the
+// wave's patch; Op's 16x4 slices for the four k-steps are in `a`.  MODE 1
+// additionally divides by lambda_x(j) + lambda_y(y) + lambda_z(z) (x pass).
+template <typename C, int nP, int DIR, int MODE>
+__device__ __forceinline__ void mfma_pass(C* pv, const C (&a)[4], int lane, const C* lx, const C* ly,
+                                          const C* lz) {
+    using M = Mfma<C>;
+    constexpr int NL = nP * nP, NT = (NL + 15) / 16;
+    auto addr = [](int i, int line) -> int {
+        if (DIR == 2) return line + NL * i;                                 // z lines: line = qx + nP qy
+        if (DIR == 1) return (line % nP) + nP * i + NL * (line / nP);       // y lines: line = qx + nP qz
+        return i + nP * line;                                               // x lines: line = qy + nP qz
+    };
+    const int col = lane % 16;
+    for (int t = 0; t < NT; ++t) {
+        const int line = 16 * t + col;
+        typename M::V acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int k = 4 * ks + lane / 16;
+            const C b = (k < nP && line < NL) ? pv[addr(k, line)] : (C)0;
+            acc = M::mma(a[ks], b, acc);
+        }
+        if (line < NL) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = M::row(lane, r);
+                if (j < nP) {
+                    C v = acc[r];
+                    if (MODE == 1) v = v * recip(lx[j] + ly[line % nP] + lz[line / nP]);
+                    pv[addr(j, line)] = v;
+                }
+            }
+        }
+    }
+    wave_sync();
+}
+
+// pe: e = assembled global residual (C), d = patch buffer (C), fd = FD data (C)
+template <int P, typename S, typename C, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_solve_mfma(LaunchTable L) {
+    constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
+    constexpr int REC = fd_record(P);
+    static_assert(nP <= 16, "one MFMA tile per contraction");
+    __shared__ C spv[4][nP3];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int tile = blockIdx.x * 4 + wv;
+    if (tile >= L.total_tiles) return;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int pidx = tile - pe.tile_begin;
+    const int npx = pe.n[0] - 1, npy = pe.n[1] - 1;
+    const int vi = 1 + pidx % npx, vj = 1 + (pidx / npx) % npy, vk = 1 + pidx / (npx * npy);
+    const C* fx = static_cast<const C*>(pe.fd[0]) + (size_t)(vi - 1) * REC;
+    const C* fy = static_cast<const C*>(pe.fd[1]) + (size_t)(vj - 1) * REC;
+    const C* fz = static_cast<const C*>(pe.fd[2]) + (size_t)(vk - 1) * REC;
+    // A operands: forward uses S^T (A[j][i] = S[i][j]), backward uses S
+    C afx[4], afy[4], afz[4], abx[4], aby[4], abz[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        const int rr = lane % 16, kk = 4 * ks + lane / 16;
+        const bool ok = rr < nP && kk < nP;
+        afx[ks] = ok ? fx[kk * nP + rr] : (C)0;
+        afy[ks] = ok ? fy[kk * nP + rr] : (C)0;
+        afz[ks] = ok ? fz[kk * nP + rr] : (C)0;
+        abx[ks] = ok ? fx[rr * nP + kk] : (C)0;
+        aby[ks] = ok ? fy[rr * nP + kk] : (C)0;
+        abz[ks] = ok ? fz[rr * nP + kk] : (C)0;
+    }
+    C* pv = spv[wv];
+    // restrict: the patch's box of the assembled residual
+    {
+        const C* g = static_cast<const C*>(pe.e);
+        const size_t G0 = (size_t)pe.n[0] * P + 1, G1 = (size_t)pe.n[1] * P + 1;
+        const size_t I0 = (size_t)(vi - 1) * P + 1, J0 = (size_t)(vj - 1) * P + 1, K0 = (size_t)(vk - 1) * P + 1;
+        for (int q = lane; q < nP3; q += 64) {
+            const int qx = q % nP, qy = (q / nP) % nP, qz = q / nP2;
+            pv[q] = g[(I0 + qx) + G0 * ((J0 + qy) + G1 * (K0 + qz))];
+        }
+    }
+    wave_sync();
+    const C* lx = fx + nP2;
+    const C* ly = fy + nP2;
+    const C* lz = fz + nP2;
+    mfma_pass<C, nP, 2, 0>(pv, afz, lane, lx, ly, lz);
+    mfma_pass<C, nP, 1, 0>(pv, afy, lane, lx, ly, lz);
+    mfma_pass<C, nP, 0, 1>(pv, afx, lane, lx, ly, lz);
+    mfma_pass<C, nP, 0, 0>(pv, abx, lane, lx, ly, lz);
+    mfma_pass<C, nP, 1, 0>(pv, aby, lane, lx, ly, lz);
+    mfma_pass<C, nP, 2, 0>(pv, abz, lane, lx, ly, lz);
+    C* out = static_cast<C*>(pe.d) + (size_t)(pidx / kLanes) * nP3 * kLanes + (pidx % kLanes);
+    for (int q = lane; q < nP3; q += 64) out[(size_t)q * kLanes] = pv[q];
+}
+
+// Assemble a dual cell-wise vector into the global-node array (sum of all
+// copies, fixed order), in the compute precision C.  pe: a = r (S), e = out.
+template <typename S, typename C, bool MULTI>
+__global__ void __launch_bounds__(256) k_assemble(LaunchTable L) {
+    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+        const ProbEntry& pe = entry<MULTI>(L, tile);
+        const int p = pe.p, N = p + 1, NN = N * N * N;
+        const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+        const size_t G0 = (size_t)n0 * p + 1, G1 = (size_t)n1 * p + 1, G2 = (size_t)n2 * p + 1;
+        const size_t g = (size_t)(tile - pe.tile_begin) * 256 + threadIdx.x;
+        if (g >= G0 * G1 * G2) continue;
+        const int I = g % G0, J = (g / G0) % G1, K = g / (G0 * G1);
+        int ci[3][2], li[3][2], cnt[3];
+        const int idx[3] = {I, J, K};
+        const int nn[3] = {n0, n1, n2};
+        for (int d = 0; d < 3; ++d) {
+            cnt[d] = 0;
+            const int q = idx[d] / p, rr = idx[d] % p;
+            if (rr == 0 && q >= 1) { ci[d][cnt[d]] = q - 1; li[d][cnt[d]] = p; ++cnt[d]; }
+            if (q <= nn[d] - 1) { ci[d][cnt[d]] = q; li[d][cnt[d]] = rr; ++cnt[d]; }
+        }
+        const S* v = static_cast<const S*>(pe.a);
+        double s = 0.0;
+        for (int z = 0; z < cnt[2]; ++z)
+            for (int y = 0; y < cnt[1]; ++y)
+                for (int x = 0; x < cnt[0]; ++x) {
+                    const int e = ci[0][x] + n0 * (ci[1][y] + n1 * ci[2][z]);
+                    const int l = li[0][x] + N * (li[1][y] + N * li[2][z]);
+                    s += load_as<double>(v + cell_offset(e, l, NN));
+                }
+        static_cast<C*>(pe.e)[g] = (C)s;
+    }
+}
+
+template <int P, typename S>
+static hipError_t launch_assemble_owner(ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s, int gcap) {
+    using C = typename Prec<S>::C;
+    int tiles = 0;
+    for (int i = 0; i < nprob; ++i) {
+        ents[i].tile_begin = tiles;
+        ents[i].ntiles = ents[i].nblk;
+        tiles += ents[i].nblk;
+    }
+    LaunchTable L{};
+    L.nprob = nprob;
+    L.total_tiles = tiles;
+    hipError_t err = stage_table(L, ents, nprob, d_tab, s);
+    if (err != hipSuccess || tiles == 0) return err;
+    const int grid = tiles < gcap ? tiles : gcap;
+    if (nprob > 1) hipLaunchKernelGGL((k_assemble_owner<P, S, C, true>), dim3(grid), dim3(256), 0, s, L);
+    else hipLaunchKernelGGL((k_assemble_owner<P, S, C, false>), dim3(grid), dim3(256), 0, s, L);
+    return hipGetLastError();
+}
+
+static inline bool cfg_two_phase_generic(const LaunchCfg& cfg) { return cfg.pi_fused == 2; }
+
+template <int P, typename S>
+static hipError_t launch_pi_mfma(int accumulate, ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s,
+                                 int gcap) {
+    using C = typename Prec<S>::C;
+    // 1. assemble r into each problem's global-node array
+    hipError_t err = launch_assemble_owner<P, S>(ents, nprob, d_tab, s, gcap);
+    if (err != hipSuccess) return err;
+    int tiles = 0;
+    // 2. one wavefront per patch
+    for (int i = 0; i < nprob; ++i) {
+        const int npx = ents[i].n[0] - 1, npy = ents[i].n[1] - 1, npz = ents[i].n[2] - 1;
+        ents[i].tile_begin = tiles;
+        ents[i].ntiles = (npx > 0 && npy > 0 && npz > 0) ? npx * npy * npz : 0;
+        tiles += ents[i].ntiles;
+    }
+    LaunchTable L1{};
+    L1.nprob = nprob;
+    L1.total_tiles = tiles;
+    err = stage_table(L1, ents, nprob, d_tab, s);
+    if (err != hipSuccess) return err;
+    if (tiles > 0) {
+        const int grid = (tiles + 3) / 4;
+        if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_mfma<P, S, C, true>), dim3(grid), dim3(256), 0, s, L1);
+        else hipLaunchKernelGGL((k_pi_solve_mfma<P, S, C, false>), dim3(grid), dim3(256), 0, s, L1);
+        err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    // 3. combine into the cells
+    int tiles2 = 0;
+    for (int i = 0; i < nprob; ++i) {
+        ents[i].tile_begin = tiles2;
+        ents[i].ntiles = ents[i].nblk * (P + 1);
+        tiles2 += ents[i].ntiles;
+    }
+    LaunchTable L2{};
+    L2.nprob = nprob;
+    L2.total_tiles = tiles2;
+    err = stage_table(L2, ents, nprob, d_tab, s);
+    if (err != hipSuccess) return err;
+    const int grid2 = (tiles2 + 3) / 4;
+    if (nprob > 1) {
+        if (accumulate) hipLaunchKernelGGL((k_pi_combine_planes<P, S, 1, true>), dim3(grid2), dim3(256), 0, s, L2);
+        else hipLaunchKernelGGL((k_pi_combine_planes<P, S, 0, true>), dim3(grid2), dim3(256), 0, s, L2);
+    } else {
+        if (accumulate) hipLaunchKernelGGL((k_pi_combine_planes<P, S, 1, false>), dim3(grid2), dim3(256), 0, s, L2);
+        else hipLaunchKernelGGL((k_pi_combine_planes<P, S, 0, false>), dim3(grid2), dim3(256), 0, s, L2);
+    }
+    return hipGetLastError();
+}
+
 template <int P, typename S>
 static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s,
                               const LaunchCfg& cfg) {
@@ -829,6 +1343,9 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
         if (fused) return launch_pi_sweep<P, S>(accumulate, ents, nprob, d_tab, s);
     }
     const int gcap = cfg.grid_cap > 0 ? cfg.grid_cap : kMaxGrid;
+    if constexpr (P >= 4) {
+        if (!cfg_two_phase_generic(cfg)) return launch_pi_mfma<P, S>(accumulate, ents, nprob, d_tab, s, gcap);
+    }
     using C = typename Prec<S>::C;
     constexpr int CBP = pi_patches_per_tile<P, C>();
     LaunchTable L{};
@@ -844,7 +1361,31 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
     hipError_t err = stage_table(L, ents, nprob, d_tab, s);
     if (err != hipSuccess) return err;
     if (tiles > 0) {
-        if constexpr (P <= 4) {
+        if constexpr (P <= 3) {
+            const int grid = (tiles + 7) / 8 * 8;
+            if (g_restrict_from_cells) {
+                if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_r<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, L);
+                else hipLaunchKernelGGL((k_pi_solve_r<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, L);
+            } else {
+                // the table L is already staged; assemble first (it restages its own)
+                err = launch_assemble_owner<P, S>(ents, nprob, d_tab, s, gcap);
+                if (err != hipSuccess) return err;
+                int t1 = 0;
+                for (int i = 0; i < nprob; ++i) {
+                    const int npx = ents[i].n[0] - 1, npy = ents[i].n[1] - 1, npz = ents[i].n[2] - 1;
+                    ents[i].tile_begin = t1;
+                    ents[i].ntiles = (npx > 0 && npy > 0 && npz > 0) ? ((npx + CBP - 1) / CBP) * npy * npz : 0;
+                    t1 += ents[i].ntiles;
+                }
+                LaunchTable Lg{};
+                Lg.nprob = nprob;
+                Lg.total_tiles = t1;
+                err = stage_table(Lg, ents, nprob, d_tab, s);
+                if (err != hipSuccess) return err;
+                if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_g<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, Lg);
+                else hipLaunchKernelGGL((k_pi_solve_g<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, Lg);
+            }
+        } else if constexpr (P == 4) {
             const int grid = (tiles + 7) / 8 * 8;
             if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_r<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, L);
             else hipLaunchKernelGGL((k_pi_solve_r<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, L);
@@ -869,13 +1410,36 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
     err = stage_table(L2, ents, nprob, d_tab, s);
     if (err != hipSuccess) return err;
     if constexpr (P <= 3) {
-        const int grid = (tiles2 + 3) / 4;
+        if (g_combine_per_cell) {
+            const int grid = (tiles2 + 3) / 4;
+            if (nprob > 1) {
+                if (accumulate) hipLaunchKernelGGL((k_pi_combine_cell<P, S, 1, true>), dim3(grid), dim3(256), 0, s, L2);
+                else hipLaunchKernelGGL((k_pi_combine_cell<P, S, 0, true>), dim3(grid), dim3(256), 0, s, L2);
+            } else {
+                if (accumulate) hipLaunchKernelGGL((k_pi_combine_cell<P, S, 1, false>), dim3(grid), dim3(256), 0, s, L2);
+                else hipLaunchKernelGGL((k_pi_combine_cell<P, S, 0, false>), dim3(grid), dim3(256), 0, s, L2);
+            }
+            return hipGetLastError();
+        }
+        // one wavefront per (block, plane)
+        int t3 = 0;
+        for (int i = 0; i < nprob; ++i) {
+            ents[i].tile_begin = t3;
+            ents[i].ntiles = ents[i].nblk * (P + 1);
+            t3 += ents[i].ntiles;
+        }
+        LaunchTable L3{};
+        L3.nprob = nprob;
+        L3.total_tiles = t3;
+        err = stage_table(L3, ents, nprob, d_tab, s);
+        if (err != hipSuccess) return err;
+        const int grid = (t3 + 3) / 4;
         if (nprob > 1) {
-            if (accumulate) hipLaunchKernelGGL((k_pi_combine_cell<P, S, 1, true>), dim3(grid), dim3(256), 0, s, L2);
-            else hipLaunchKernelGGL((k_pi_combine_cell<P, S, 0, true>), dim3(grid), dim3(256), 0, s, L2);
+            if (accumulate) hipLaunchKernelGGL((k_pi_combine_planes<P, S, 1, true>), dim3(grid), dim3(256), 0, s, L3);
+            else hipLaunchKernelGGL((k_pi_combine_planes<P, S, 0, true>), dim3(grid), dim3(256), 0, s, L3);
         } else {
-            if (accumulate) hipLaunchKernelGGL((k_pi_combine_cell<P, S, 1, false>), dim3(grid), dim3(256), 0, s, L2);
-            else hipLaunchKernelGGL((k_pi_combine_cell<P, S, 0, false>), dim3(grid), dim3(256), 0, s, L2);
+            if (accumulate) hipLaunchKernelGGL((k_pi_combine_planes<P, S, 1, false>), dim3(grid), dim3(256), 0, s, L3);
+            else hipLaunchKernelGGL((k_pi_combine_planes<P, S, 0, false>), dim3(grid), dim3(256), 0, s, L3);
         }
         return hipGetLastError();
     }

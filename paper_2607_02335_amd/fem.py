@@ -164,6 +164,8 @@ def make_desc(p, n, widths=None, bc=DIRICHLET):
 
 
 OPT_PI_FUSED = 1
+OPT_COMBINE_PER_CELL = 2
+OPT_RESTRICT_FROM_CELLS = 3
 
 
 def set_option(option, value):
