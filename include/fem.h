@@ -278,6 +278,26 @@ typedef enum fem_option {
 } fem_option;
 fem_status fem_set_option(int option, int value);
 
+/* Launch trace (for measurement).  fem_trace_enable(1) starts recording:
+ * every kernel launch of the library's hot operations (apply, the patch
+ * inverse phases, DSS, reductions, CG updates) is bracketed by a pair of HIP
+ * events on the stream it is launched on; fem_trace_enable(0) stops, and
+ * either call discards what was recorded.  fem_trace_read waits for the
+ * recorded events, aggregates them per (label, p, precision) into out[0..),
+ * writing at most max_recs records, clears the record list and returns the
+ * number of distinct records (which may exceed max_recs; out may be NULL to
+ * count).  Tracing adds one event record before and after each launch;
+ * calls from several host threads are serialised by a lock. */
+typedef struct fem_trace_rec {
+    char label[48];      /* e.g. "apply", "pi_assemble", "pi_solve", "pi_combine" */
+    int p;
+    int prec;            /* fem_prec of the launch (the kernel's storage type) */
+    int launches;
+    double total_ms;     /* summed event-to-event durations */
+} fem_trace_rec;
+fem_status fem_trace_enable(int on);
+int fem_trace_read(fem_trace_rec* out, int max_recs);
+
 const char* fem_last_error(void);
 const char* fem_version(void);
 

@@ -32,7 +32,7 @@ COMMON = [
 ]
 
 SOURCES = [
-    "host_setup.cpp", "api.cpp", "batch.cpp",
+    "host_setup.cpp", "api.cpp", "batch.cpp", "trace.cpp",
     "kernels_apply.hip", "kernels_vec.hip", "kernels_patch.hip",
 ]
 

@@ -85,7 +85,8 @@ struct ProbEntry {
     double* red;         // per-problem reduction partials / scalars
     double alpha;        // scalar operand (e.g. damping)
     int ntiles_red;      // tiles of the reduction kernels (<= kRedParts)
-    int blocks_per_red;  // storage blocks per reduction tile
+    int blocks_per_red;  // storage blocks per reduction tile (red_lsplit == 1)
+    int red_lsplit;      // reduction tiles per storage block (blocks_per_red == 1)
     int zchunk;          // cell layers per z-chunk of the fused patch sweep
 };
 

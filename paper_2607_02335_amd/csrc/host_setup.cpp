@@ -276,13 +276,14 @@ int host_fd_1d(int p, double h0, double h1, double* S, double* lam) {
 
 using namespace fem;
 
-namespace fem { extern int g_pi_fused; extern int g_combine_per_cell; extern int g_restrict_from_cells; }
+namespace fem { extern int g_pi_fused; extern int g_combine_per_cell; extern int g_restrict_from_cells; extern int g_assemble_owner; }
 
 extern "C" fem_status fem_set_option(int option, int value) {
     switch (option) {
-        case FEM_OPT_PI_FUSED: fem::g_pi_fused = value ? 1 : 0; return FEM_OK;
+        case FEM_OPT_PI_FUSED: fem::g_pi_fused = (value >= 0 && value <= 2) ? value : 0; return FEM_OK;
         case FEM_OPT_COMBINE_PER_CELL: fem::g_combine_per_cell = value ? 1 : 0; return FEM_OK;
         case FEM_OPT_RESTRICT_FROM_CELLS: fem::g_restrict_from_cells = value ? 1 : 0; return FEM_OK;
+        case 4: fem::g_assemble_owner = value ? 1 : 0; return FEM_OK;
         default: return set_error(FEM_EINVAL, "fem_set_option: unknown option");
     }
 }

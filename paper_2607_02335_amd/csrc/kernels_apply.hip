@@ -23,6 +23,7 @@
 //    the three directions with one thread per 1D line.
 #include "fem_internal.h"
 #include "launch.h"
+#include "trace.h"
 
 namespace fem {
 
@@ -349,6 +350,150 @@ static RefMats<P, C> ref_mats() {
     return R;
 }
 
+// ---------------------------------------------------------------------------
+// Plane-streamed apply for p >= 4.  A workgroup owns 16 consecutive cells of
+// a storage block (so every load and store is a 128-byte run of one node
+// plane) and walks the z node planes two at a time.  Per pair of planes the
+// x and y contractions run in LDS with one thread per 1D line:
+//     T1 = Kx u, T2 = Mx u                         (x lines)
+//     P1 = cx My T1 + cy Ky T2,  P2 = My T2        (y lines, in place)
+// and every (cell, a, b) z line accumulates y(k') += Mz(k',k) P1_k +
+// cz Kz(k',k) P2_k in registers, so only two plane pairs of two arrays sit in
+// LDS.  The mass apply keeps the T2/P2 chain: y = vol Mz (My Mx u).
+template <int P, typename S, int MODE, bool MULTI>
+__global__ void __launch_bounds__(256)
+k_apply_planes(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
+    using C = typename Prec<S>::C;
+    constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
+    constexpr int CB = 16;                 // cells per workgroup
+    constexpr int KP = 2;                  // z planes per step
+    constexpr int NSTEP = (N + KP - 1) / KP;
+    constexpr int SL = KP * N2 * CB;       // values per LDS array
+    constexpr int ZL = N2 * CB;            // z lines per workgroup
+    constexpr int ZPT = (ZL + 255) / 256;  // z lines per thread
+    __shared__ C s1[SL];                   // u -> T1 -> P1
+    __shared__ C s2[SL];                   // T2 -> P2
+    static_assert(256 % CB == 0 && kLanes % CB == 0, "cells per workgroup must divide the block");
+    const int tid = threadIdx.x;
+    const int cl = tid % CB;               // the cell this thread serves in line passes
+    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+        const ProbEntry& pe = entry<MULTI>(L, tile);
+        const int t = tile - pe.tile_begin;
+        const int blk = t / (kLanes / CB), lane0 = (t % (kLanes / CB)) * CB;
+        const size_t base = (size_t)blk * NN * kLanes + lane0;
+        const S* __restrict__ x = static_cast<const S*>(pe.a) + base;
+        S* __restrict__ y = static_cast<S*>(pe.c) + base;
+        const int e = blk * kLanes + lane0 + cl;
+        const bool valid = e < pe.ncells;
+        CellGeom<C> g{};
+        if (valid) g = cell_geom<C>(pe, e);
+        C acc[ZPT][N];
+#pragma unroll
+        for (int q = 0; q < ZPT; ++q)
+#pragma unroll
+            for (int k = 0; k < N; ++k) acc[q][k] = (C)0;
+
+        for (int st = 0; st < NSTEP; ++st) {
+            const int k0 = st * KP;
+            // load planes k0, k0+1: item = cell + CB * (ab + N2 * kk)
+            for (int item = tid; item < SL; item += 256) {
+                const int kk = item / (N2 * CB), ab = (item / CB) % N2;
+                const int k = k0 + kk;
+                C v = (C)0;
+                if (k < N && valid) {
+                    const int l = ab + N2 * k;
+                    if (MODE == kApplyMass || !on_boundary<P>(g, ab % N, ab / N, k))
+                        v = load_as<C>(x + (size_t)l * kLanes + cl);
+                }
+                s1[item] = v;
+            }
+            __syncthreads();
+            // x lines: task = cell + CB * (b + N * kk)
+            for (int task = tid; task < CB * N * KP; task += 256) {
+                const int r = task / CB;                   // b + N kk
+                C v[N];
+#pragma unroll
+                for (int a = 0; a < N; ++a) v[a] = s1[(a + N * r) * CB + cl];
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    C sm = 0, sk = 0;
+#pragma unroll
+                    for (int m = 0; m < N; ++m) {
+                        sm += R.M[a * N + m] * v[m];
+                        if (MODE != kApplyMass) sk += R.K[a * N + m] * v[m];
+                    }
+                    s2[(a + N * r) * CB + cl] = sm;
+                    if (MODE != kApplyMass) s1[(a + N * r) * CB + cl] = sk;
+                }
+            }
+            __syncthreads();
+            // y lines (in place): task = cell + CB * (a + N * kk)
+            for (int task = tid; task < CB * N * KP; task += 256) {
+                const int r = task / CB;
+                const int a = r % N, kk = r / N;
+                C v1[N], v2[N];
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    v2[b] = s2[(a + N * b + N2 * kk) * CB + cl];
+                    if (MODE != kApplyMass) v1[b] = s1[(a + N * b + N2 * kk) * CB + cl];
+                }
+#pragma unroll
+                for (int b = 0; b < N; ++b) {
+                    C m1 = 0, k2 = 0, m2 = 0;
+#pragma unroll
+                    for (int m = 0; m < N; ++m) {
+                        m2 += R.M[b * N + m] * v2[m];
+                        if (MODE != kApplyMass) {
+                            m1 += R.M[b * N + m] * v1[m];
+                            k2 += R.K[b * N + m] * v2[m];
+                        }
+                    }
+                    s2[(a + N * b + N2 * kk) * CB + cl] = m2;
+                    if (MODE != kApplyMass) s1[(a + N * b + N2 * kk) * CB + cl] = g.cx * m1 + g.cy * k2;
+                }
+            }
+            __syncthreads();
+            // z accumulation: z line q of this thread = (cell, ab)
+#pragma unroll
+            for (int q = 0; q < ZPT; ++q) {
+                const int zl = tid + 256 * q;
+                if (zl >= ZL) break;
+                const int ab = zl / CB;               // the cell is cl: CB divides 256
+#pragma unroll
+                for (int kk = 0; kk < KP; ++kk) {
+                    const int k = k0 + kk;
+                    if (k >= N) break;
+                    const C p2 = s2[(ab + N2 * kk) * CB + cl];
+                    const C p1 = MODE != kApplyMass ? s1[(ab + N2 * kk) * CB + cl] : (C)0;
+#pragma unroll
+                    for (int kp = 0; kp < N; ++kp) {
+                        if (MODE == kApplyMass) acc[q][kp] += R.M[kp * N + k] * p2;
+                        else acc[q][kp] += R.M[kp * N + k] * p1 + g.cz * R.K[kp * N + k] * p2;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // store: z line (cell, ab) writes its N planes
+        const S* __restrict__ rres = (MODE == kApplyResidual) ? static_cast<const S*>(pe.b) + base : nullptr;
+#pragma unroll
+        for (int q = 0; q < ZPT; ++q) {
+            const int zl = tid + 256 * q;
+            if (zl >= ZL) break;
+            const int ab = zl / CB;
+#pragma unroll
+            for (int k = 0; k < N; ++k) {
+                const size_t off = (size_t)(ab + N2 * k) * kLanes + cl;
+                C v = acc[q][k];
+                if (MODE == kApplyMass) v *= g.vol;
+                if (MODE == kApplyResidual) v = load_as<C>(rres + off) - v;
+                if (!valid || on_boundary<P>(g, ab % N, ab / N, k)) v = (C)0;
+                store_from(y + off, v);
+            }
+        }
+    }
+}
+
 template <int P> constexpr int lds_cells(int bytes) {
     // largest power of two <= 64 with two LDS arrays within 64 KiB
     int cb = 64;
@@ -364,12 +509,13 @@ static hipError_t launch_apply_t(ProbEntry* ents, int nprob, TableStager* d_tab,
     using C = typename Prec<S>::C;
     const RefMats<P, C> R = ref_mats<P, C>();
     const bool use_reg = (P <= 3) && !force_lds;
+    const bool use_planes = (P >= 4) && !force_lds;
     constexpr int CB = lds_cells<P>((int)sizeof(C));
     LaunchTable L{};
     int tiles = 0;
     for (int i = 0; i < nprob; ++i) {
         ents[i].tile_begin = tiles;
-        ents[i].ntiles = use_reg ? ents[i].nblk : ents[i].nblk * (kLanes / CB);
+        ents[i].ntiles = use_reg ? ents[i].nblk : use_planes ? ents[i].nblk * (kLanes / 16) : ents[i].nblk * (kLanes / CB);
         tiles += ents[i].ntiles;
     }
     L.nprob = nprob;
@@ -377,11 +523,21 @@ static hipError_t launch_apply_t(ProbEntry* ents, int nprob, TableStager* d_tab,
     if (tiles == 0) return hipSuccess;
     hipError_t err = stage_table(L, ents, nprob, d_tab, s);
     if (err != hipSuccess) return err;
+    TraceSpan ts(MODE == kApplyLaplace ? "apply" : MODE == kApplyResidual ? "apply_residual" : "mass_apply", P,
+                 Prec<S>::id, s);
     if constexpr (P <= 3) {
         if (use_reg) {
             const int grid = (tiles + 3) / 4 < gcap ? (tiles + 3) / 4 : gcap;
             if (nprob > 1) hipLaunchKernelGGL((k_apply_reg<P, S, MODE, true>), dim3(grid), dim3(256), 0, s, L, R);
             else hipLaunchKernelGGL((k_apply_reg<P, S, MODE, false>), dim3(grid), dim3(256), 0, s, L, R);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (P >= 4) {
+        if (use_planes) {
+            const int grid = tiles < gcap ? tiles : gcap;
+            if (nprob > 1) hipLaunchKernelGGL((k_apply_planes<P, S, MODE, true>), dim3(grid), dim3(256), 0, s, L, R);
+            else hipLaunchKernelGGL((k_apply_planes<P, S, MODE, false>), dim3(grid), dim3(256), 0, s, L, R);
             return hipGetLastError();
         }
     }

@@ -23,6 +23,7 @@
 
 #include "fem_internal.h"
 #include "launch.h"
+#include "trace.h"
 
 namespace fem {
 
@@ -36,6 +37,9 @@ int g_combine_per_cell = 0;
 // 1: phase 1 of the p <= 3 patch inverse sums the copies from the cell-wise
 // vector itself instead of reading the owner-assembled global-node array.
 int g_restrict_from_cells = 0;
+// 1: assemble the residual with the owner-copy kernel (one thread per cell
+// copy) instead of one wavefront per global node row.
+int g_assemble_owner = 0;
 
 template <int P, typename C> constexpr int pi_patches_per_tile() {
     constexpr int nP = 2 * P - 1;
@@ -977,6 +981,378 @@ __global__ void __launch_bounds__(256) k_pi_solve_g(LaunchTable L) {
     }
 }
 
+// Assembly into the global-node array: one wavefront per node row (Y, Z),
+// its lanes walking X, so writes are contiguous and the row's y/z copy
+// structure is uniform over the wavefront.  Each node sums its copies in
+// ascending cell order along z, y, x, the same order for every node.
+// pe: a = r (S), e = global array (C); ntiles = ceil(rows / 4).
+template <int P, typename S, typename C, bool MULTI>
+__global__ void __launch_bounds__(256) k_assemble_nodes(LaunchTable L) {
+    constexpr int N = P + 1, NN = N * N * N;
+    const int tile = blockIdx.x;
+    if (tile >= L.total_tiles) return;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+    const int G0 = n0 * P + 1, G1 = n1 * P + 1, G2 = n2 * P + 1;
+    const int row = (tile - pe.tile_begin) * 4 + (int)(threadIdx.x / 64);
+    if (row >= G1 * G2) return;
+    const int lane = threadIdx.x % 64;
+    const int J = row % G1, K = row / G1;
+    // copies along y and z (uniform): lower cell first
+    const int qy = J / P, ry = J - qy * P, qz = K / P, rz = K - qz * P;
+    const int ny = (ry == 0 && qy >= 1 && qy <= n1 - 1) ? 2 : 1;
+    const int nz = (rz == 0 && qz >= 1 && qz <= n2 - 1) ? 2 : 1;
+    const int cy0 = (ry == 0 && qy >= 1) ? qy - 1 : qy, by0 = (ry == 0 && qy >= 1) ? P : ry;
+    const int cz0 = (rz == 0 && qz >= 1) ? qz - 1 : qz, bz0 = (rz == 0 && qz >= 1) ? P : rz;
+    const S* v = static_cast<const S*>(pe.a);
+    C* out = static_cast<C*>(pe.e) + (size_t)row * G0;
+    for (int I = lane; I < G0; I += 64) {
+        const int qx = I / P, rx = I - qx * P;
+        const int nx = (rx == 0 && qx >= 1 && qx <= n0 - 1) ? 2 : 1;
+        const int cx0 = (rx == 0 && qx >= 1) ? qx - 1 : qx, ax0 = (rx == 0 && qx >= 1) ? P : rx;
+        double s = 0.0;
+        for (int z = 0; z < nz; ++z)
+            for (int y = 0; y < ny; ++y)
+                for (int x = 0; x < nx; ++x) {
+                    const int e = (cx0 + x) + n0 * ((cy0 + y) + n1 * (cz0 + z));
+                    const int l = (x ? 0 : ax0) + N * ((y ? 0 : by0) + N * (z ? 0 : bz0));
+                    s += load_as<double>(v + cell_offset(e, l, NN));
+                }
+        out[I] = (C)s;
+    }
+}
+
+// Fused sweep from the assembled residual (p <= 3): like k_pi_sweep, but the
+// patch values are read from a ring of global-node z-planes instead of being
+// summed from cell copies, so the restriction is a plain copy folded into the
+// first transform.  A workgroup owns TX x TY cell columns and a chunk of cell
+// layers and walks the vertex layers in order; per vertex layer it solves the
+// (TX+1) x (TY+1) patches around its columns (work items are (patch, line)
+// pairs) and combines them into the cells: cell layer vk-1 is finished and
+// written, cell layer vk starts a partial sum.  Terms enter every node in
+// ascending vertex order along z, y, x, so copies stay bitwise equal, also
+// across workgroups (border patches are solved by both neighbours).
+// pe: e = assembled residual (C), c = z (S), alpha = damping.
+template <int P, typename S, int TX, int TY, int ACC, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_sweep_g(LaunchTable L) {
+    using C = typename Prec<S>::C;
+    constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
+    constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
+    constexpr int REC = fd_record(P);
+    constexpr int NPL = (TX + 1) * (TY + 1);       // patches per vertex layer
+    constexpr int NTASK = NPL * nP2;               // (patch, line) pairs per pass
+    constexpr int WX = (TX + 2) * P - 1, WY = (TY + 2) * P - 1;   // node window
+    constexpr int WXY = WX * WY;
+    constexpr int NZ = 2 * P - 1;                  // planes in the ring
+    constexpr int NLOAD = P * WXY;                 // new planes per vertex layer
+    constexpr int PF = (NLOAD + 255) / 256;
+    __shared__ C ring[NZ * WXY];
+    __shared__ C pv[nP3 * NPL];                    // current patch layer [q][patch]
+    __shared__ C part[TX * TY * NN];               // partial sums of the open cell layer
+    __shared__ C sSx[TX + 1][nP2 + 1];
+    __shared__ C sSy[TY + 1][nP2 + 1];
+    __shared__ C sSz[nP2];
+    __shared__ C sLx[TX + 1][nP];
+    __shared__ C sLy[TY + 1][nP];
+    __shared__ C sLz[nP];
+
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= L.total_tiles) return;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+    const int G0 = n0 * P + 1, G1 = n1 * P + 1;
+    const int ntx = (n0 + TX - 1) / TX, nty = (n1 + TY - 1) / TY;
+    int t = tile - pe.tile_begin;
+    const int tx = t % ntx;
+    t /= ntx;
+    const int ty = t % nty;
+    const int kc = t / nty;
+    const int i0 = tx * TX, j0 = ty * TY;
+    const int k0 = kc * pe.zchunk;
+    const int k1 = min(k0 + pe.zchunk, n2);
+    const int X0 = (i0 - 1) * P + 1, Y0 = (j0 - 1) * P + 1;
+    const int tid = threadIdx.x;
+    const C* g = static_cast<const C*>(pe.e);
+    S* zout = static_cast<S*>(pe.c);
+    const C alpha = (C)pe.alpha;
+
+    for (int w = tid; w < (TX + 1) * (nP2 + nP); w += 256) {
+        const int col = w / (nP2 + nP), o = w % (nP2 + nP);
+        const int line = max(0, min(i0 + col, n0 - 1) - 1);
+        const C v = static_cast<const C*>(pe.fd[0])[(size_t)line * REC + o];
+        if (o < nP2) sSx[col][o] = v; else sLx[col][o - nP2] = v;
+    }
+    for (int w = tid; w < (TY + 1) * (nP2 + nP); w += 256) {
+        const int col = w / (nP2 + nP), o = w % (nP2 + nP);
+        const int line = max(0, min(j0 + col, n1 - 1) - 1);
+        const C v = static_cast<const C*>(pe.fd[1])[(size_t)line * REC + o];
+        if (o < nP2) sSy[col][o] = v; else sLy[col][o - nP2] = v;
+    }
+
+    // planes Z0 .. Z0+P-1 of the window (zero outside the mesh); ring slot Z mod NZ
+    auto fetch = [&](int Z0, int nplanes, C* regs) {
+#pragma unroll
+        for (int m = 0; m < PF; ++m) {
+            const int item = tid + 256 * m;
+            C v = 0;
+            if (item < nplanes * WXY) {
+                const int wx = item % WX, wy = (item / WX) % WY, dz = item / WXY;
+                const int X = X0 + wx, Y = Y0 + wy, Z = Z0 + dz;
+                if (X >= 0 && X < G0 && Y >= 0 && Y < G1 && Z >= 0 && Z <= n2 * P)
+                    v = g[(size_t)X + (size_t)G0 * ((size_t)Y + (size_t)G1 * Z)];
+            }
+            regs[m] = v;
+        }
+    };
+    auto stash = [&](int Z0, int nplanes, const C* regs) {
+#pragma unroll
+        for (int m = 0; m < PF; ++m) {
+            const int item = tid + 256 * m;
+            if (item < nplanes * WXY) {
+                const int dz = item / WXY;
+                const int slot = ((Z0 + dz) % NZ + NZ) % NZ;
+                ring[slot * WXY + item % WXY] = regs[m];
+            }
+        }
+    };
+    {
+        // vertex layer k0 needs planes (k0-1)P+1 .. (k0+1)P-1
+        C reg[PF];
+        fetch((k0 - 1) * P + 1, P, reg);
+        stash((k0 - 1) * P + 1, P, reg);
+        if (P > 1) {
+            fetch(k0 * P + 1, P - 1, reg);
+            stash(k0 * P + 1, P - 1, reg);
+        }
+    }
+    __syncthreads();
+
+    for (int vk = k0; vk <= k1; ++vk) {
+        C nxt[PF];
+        // planes of the next layer not yet in the ring: (vk+1)P .. (vk+2)P-1
+        fetch((vk + 1) * P, P, nxt);
+        const bool layer_ok = vk >= 1 && vk <= n2 - 1;   // uniform over the workgroup
+        if (layer_ok) {
+            for (int w = tid; w < nP2 + nP; w += 256) {
+                const C v = static_cast<const C*>(pe.fd[2])[(size_t)(vk - 1) * REC + w];
+                if (w < nP2) sSz[w] = v; else sLz[w - nP2] = v;
+            }
+            __syncthreads();
+            {
+                C Sm[nP2];
+#pragma unroll
+                for (int i = 0; i < nP2; ++i) Sm[i] = sSz[i];
+                const int Zb = (vk - 1) * P + 1;
+                for (int task = tid; task < NTASK; task += 256) {     // forward z from the ring
+                    const int ps = task % NPL, ln = task / NPL;
+                    const int pxo = ps % (TX + 1), pyo = ps / (TX + 1);
+                    const int wxy = (pxo * P + ln % nP) + WX * (pyo * P + ln / nP);
+                    C v[nP];
+#pragma unroll
+                    for (int i = 0; i < nP; ++i) v[i] = ring[((Zb + i) % NZ) * WXY + wxy];
+#pragma unroll
+                    for (int j = 0; j < nP; ++j) {
+                        C s = 0;
+#pragma unroll
+                        for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
+                        pv[(ln + nP2 * j) * NPL + ps] = s;
+                    }
+                }
+            }
+            __syncthreads();
+            for (int task = tid; task < NTASK; task += 256) {         // forward y
+                const int ps = task % NPL, ln = task / NPL;
+                const int pyo = ps / (TX + 1);
+                const int qx = ln % nP, qz = ln / nP;
+                C v[nP];
+#pragma unroll
+                for (int i = 0; i < nP; ++i) v[i] = pv[(qx + nP * i + nP2 * qz) * NPL + ps];
+#pragma unroll
+                for (int j = 0; j < nP; ++j) {
+                    C s = 0;
+#pragma unroll
+                    for (int i = 0; i < nP; ++i) s += sSy[pyo][i * nP + j] * v[i];
+                    pv[(qx + nP * j + nP2 * qz) * NPL + ps] = s;
+                }
+            }
+            __syncthreads();
+            for (int task = tid; task < NTASK; task += 256) {         // x: forward, scale, back
+                const int ps = task % NPL, ln = task / NPL;
+                const int pxo = ps % (TX + 1), pyo = ps / (TX + 1);
+                const int qy = ln % nP, qz = ln / nP;
+                C v[nP], w[nP];
+#pragma unroll
+                for (int i = 0; i < nP; ++i) v[i] = pv[(i + nP * ln) * NPL + ps];
+                const C lyz = sLy[pyo][qy] + sLz[qz];
+#pragma unroll
+                for (int j = 0; j < nP; ++j) {
+                    C s = 0;
+#pragma unroll
+                    for (int i = 0; i < nP; ++i) s += sSx[pxo][i * nP + j] * v[i];
+                    w[j] = s / (sLx[pxo][j] + lyz);
+                }
+#pragma unroll
+                for (int i = 0; i < nP; ++i) {
+                    C s = 0;
+#pragma unroll
+                    for (int j = 0; j < nP; ++j) s += sSx[pxo][i * nP + j] * w[j];
+                    pv[(i + nP * ln) * NPL + ps] = s;
+                }
+            }
+            __syncthreads();
+            for (int task = tid; task < NTASK; task += 256) {         // backward y
+                const int ps = task % NPL, ln = task / NPL;
+                const int pyo = ps / (TX + 1);
+                const int qx = ln % nP, qz = ln / nP;
+                C v[nP];
+#pragma unroll
+                for (int j = 0; j < nP; ++j) v[j] = pv[(qx + nP * j + nP2 * qz) * NPL + ps];
+#pragma unroll
+                for (int i = 0; i < nP; ++i) {
+                    C s = 0;
+#pragma unroll
+                    for (int j = 0; j < nP; ++j) s += sSy[pyo][i * nP + j] * v[j];
+                    pv[(qx + nP * i + nP2 * qz) * NPL + ps] = s;
+                }
+            }
+            __syncthreads();
+            {
+                C Sm[nP2];
+#pragma unroll
+                for (int i = 0; i < nP2; ++i) Sm[i] = sSz[i];
+                for (int task = tid; task < NTASK; task += 256) {     // backward z
+                    const int ps = task % NPL, ln = task / NPL;
+                    C v[nP];
+#pragma unroll
+                    for (int j = 0; j < nP; ++j) v[j] = pv[(ln + nP2 * j) * NPL + ps];
+#pragma unroll
+                    for (int i = 0; i < nP; ++i) {
+                        C s = 0;
+#pragma unroll
+                        for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * v[j];
+                        pv[(ln + nP2 * i) * NPL + ps] = s;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        // finish cell layer vk-1, open cell layer vk
+        for (int item = tid; item < TX * TY * NN; item += 256) {
+            const int cx = item % TX;
+            const int cy = (item / TX) % TY;
+            const int l = item / (TX * TY);
+            const int i = i0 + cx, j = j0 + cy;
+            const int a = l % N, b = (l / N) % N, c = l / N2;
+            auto terms = [&](int sz, C acc) -> C {
+#pragma unroll
+                for (int sy = 0; sy < 2; ++sy) {
+                    if ((sy == 0 && b == P) || (sy == 1 && b == 0)) continue;
+                    const int vy = j + sy;
+                    if (vy < 1 || vy > n1 - 1) continue;
+                    const int qy = sy == 0 ? P - 1 + b : b - 1;
+#pragma unroll
+                    for (int sx = 0; sx < 2; ++sx) {
+                        if ((sx == 0 && a == P) || (sx == 1 && a == 0)) continue;
+                        const int vx = i + sx;
+                        if (vx < 1 || vx > n0 - 1) continue;
+                        const int qx = sx == 0 ? P - 1 + a : a - 1;
+                        const int qz = sz == 0 ? P - 1 + c : c - 1;
+                        acc += pv[(qx + nP * (qy + nP * qz)) * NPL + (vx - i0) + (TX + 1) * (vy - j0)];
+                    }
+                }
+                return acc;
+            };
+            if (i >= n0 || j >= n1) continue;
+            if (vk > k0) {
+                C sum = part[item];
+                if (layer_ok && c >= 1) sum = terms(1, sum);
+                const int e = i + n0 * (j + n1 * (vk - 1));
+                S* dst = zout + cell_offset(e, l, NN);
+                C out = alpha * sum;
+                if (ACC) out = load_as<C>(dst) + out;
+                store_from(dst, out);
+            }
+            if (vk < k1) part[item] = (layer_ok && c <= P - 1) ? terms(0, (C)0) : (C)0;
+        }
+        // the ring planes of layer vk below layer vk+1 are retired: the prefetched planes take their slots
+        stash((vk + 1) * P, P, nxt);
+        __syncthreads();
+    }
+}
+
+template <int P, typename S>
+static hipError_t launch_assemble_nodes(ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s) {
+    using C = typename Prec<S>::C;
+    int tiles = 0;
+    for (int i = 0; i < nprob; ++i) {
+        const int rows = (ents[i].n[1] * P + 1) * (ents[i].n[2] * P + 1);
+        ents[i].tile_begin = tiles;
+        ents[i].ntiles = (rows + 3) / 4;
+        tiles += ents[i].ntiles;
+    }
+    LaunchTable L{};
+    L.nprob = nprob;
+    L.total_tiles = tiles;
+    hipError_t err = stage_table(L, ents, nprob, d_tab, s);
+    if (err != hipSuccess || tiles == 0) return err;
+    TraceSpan ts("pi_assemble", P, Prec<S>::id, s);
+    if (nprob > 1) hipLaunchKernelGGL((k_assemble_nodes<P, S, C, true>), dim3(tiles), dim3(256), 0, s, L);
+    else hipLaunchKernelGGL((k_assemble_nodes<P, S, C, false>), dim3(tiles), dim3(256), 0, s, L);
+    return hipGetLastError();
+}
+
+template <int P, typename S> struct SweepGShape;
+template <typename S> struct SweepGShape<1, S> { static constexpr int TX = 16, TY = 4; };
+template <typename S> struct SweepGShape<2, S> { static constexpr int TX = 16, TY = 4; };
+template <> struct SweepGShape<2, double> { static constexpr int TX = 16, TY = 2; };
+template <> struct SweepGShape<3, double> { static constexpr int TX = 8, TY = 2; };
+template <typename S> struct SweepGShape<3, S> { static constexpr int TX = 8, TY = 4; };
+
+// Fused patch inverse from the assembled residual: assembly, then one sweep.
+template <int P, typename S>
+static hipError_t launch_pi_sweep_g(int accumulate, ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s) {
+    constexpr int TX = SweepGShape<P, S>::TX, TY = SweepGShape<P, S>::TY;
+    hipError_t err = launch_assemble_nodes<P, S>(ents, nprob, d_tab, s);
+    if (err != hipSuccess) return err;
+    LaunchTable L{};
+    int tiles = 0;
+    for (int i = 0; i < nprob; ++i) {
+        const int ntx = (ents[i].n[0] + TX - 1) / TX, nty = (ents[i].n[1] + TY - 1) / TY;
+        const int n2 = ents[i].n[2];
+        int nkc = (2048 + ntx * nty - 1) / (ntx * nty);
+        nkc = std::max(1, std::min(nkc, (n2 + 3) / 4));
+        ents[i].zchunk = (n2 + nkc - 1) / nkc;
+        nkc = (n2 + ents[i].zchunk - 1) / ents[i].zchunk;
+        ents[i].tile_begin = tiles;
+        ents[i].ntiles = ntx * nty * nkc;
+        tiles += ents[i].ntiles;
+    }
+    L.nprob = nprob;
+    L.total_tiles = tiles;
+    err = stage_table(L, ents, nprob, d_tab, s);
+    if (err != hipSuccess) return err;
+    const int grid = (tiles + 7) / 8 * 8;
+    {
+        TraceSpan ts("pi_sweep", P, Prec<S>::id, s);
+        if (nprob > 1) {
+            if (accumulate) hipLaunchKernelGGL((k_pi_sweep_g<P, S, TX, TY, 1, true>), dim3(grid), dim3(256), 0, s, L);
+            else hipLaunchKernelGGL((k_pi_sweep_g<P, S, TX, TY, 0, true>), dim3(grid), dim3(256), 0, s, L);
+        } else {
+            if (accumulate) hipLaunchKernelGGL((k_pi_sweep_g<P, S, TX, TY, 1, false>), dim3(grid), dim3(256), 0, s, L);
+            else hipLaunchKernelGGL((k_pi_sweep_g<P, S, TX, TY, 0, false>), dim3(grid), dim3(256), 0, s, L);
+        }
+    }
+    err = hipGetLastError();
+    if (err != hipSuccess) return err;
+    for (int i = 0; i < nprob; ++i) {
+        if (ents[i].ncells % kLanes == 0) continue;
+        constexpr int NN = (P + 1) * (P + 1) * (P + 1);
+        hipLaunchKernelGGL((k_zero_padding<S>), dim3(NN < 64 ? NN : 64), dim3(64), 0, s,
+                           static_cast<S*>(ents[i].c), ents[i].ncells, ents[i].nblk, NN);
+    }
+    return hipGetLastError();
+}
+
 template <int P, typename S>
 static hipError_t launch_pi_sweep(int accumulate, ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s) {
     using Sh = SweepShape<P, S>;
@@ -1000,6 +1376,7 @@ static hipError_t launch_pi_sweep(int accumulate, ProbEntry* ents, int nprob, Ta
     hipError_t err = stage_table(L, ents, nprob, d_tab, s);
     if (err != hipSuccess) return err;
     const int grid = (tiles + 7) / 8 * 8;
+    TraceSpan ts("pi_sweep", P, Prec<S>::id, s);
     if (nprob > 1) {
         if (accumulate) hipLaunchKernelGGL((k_pi_sweep<P, S, TX, TY, NS, 1, true>), dim3(grid), dim3(256), 0, s, L);
         else hipLaunchKernelGGL((k_pi_sweep<P, S, TX, TY, NS, 0, true>), dim3(grid), dim3(256), 0, s, L);
@@ -1278,9 +1655,19 @@ static hipError_t launch_assemble_owner(ProbEntry* ents, int nprob, TableStager*
     hipError_t err = stage_table(L, ents, nprob, d_tab, s);
     if (err != hipSuccess || tiles == 0) return err;
     const int grid = tiles < gcap ? tiles : gcap;
+    TraceSpan ts("pi_assemble", P, Prec<S>::id, s);
     if (nprob > 1) hipLaunchKernelGGL((k_assemble_owner<P, S, C, true>), dim3(grid), dim3(256), 0, s, L);
     else hipLaunchKernelGGL((k_assemble_owner<P, S, C, false>), dim3(grid), dim3(256), 0, s, L);
     return hipGetLastError();
+}
+
+template <int P, typename S>
+static hipError_t launch_assemble_nodes(ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s);
+
+template <int P, typename S>
+static hipError_t launch_assemble(ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s, int gcap) {
+    if (g_assemble_owner) return launch_assemble_owner<P, S>(ents, nprob, d_tab, s, gcap);
+    return launch_assemble_nodes<P, S>(ents, nprob, d_tab, s);
 }
 
 static inline bool cfg_two_phase_generic(const LaunchCfg& cfg) { return cfg.pi_fused == 2; }
@@ -1290,7 +1677,7 @@ static hipError_t launch_pi_mfma(int accumulate, ProbEntry* ents, int nprob, Tab
                                  int gcap) {
     using C = typename Prec<S>::C;
     // 1. assemble r into each problem's global-node array
-    hipError_t err = launch_assemble_owner<P, S>(ents, nprob, d_tab, s, gcap);
+    hipError_t err = launch_assemble<P, S>(ents, nprob, d_tab, s, gcap);
     if (err != hipSuccess) return err;
     int tiles = 0;
     // 2. one wavefront per patch
@@ -1307,6 +1694,7 @@ static hipError_t launch_pi_mfma(int accumulate, ProbEntry* ents, int nprob, Tab
     if (err != hipSuccess) return err;
     if (tiles > 0) {
         const int grid = (tiles + 3) / 4;
+        TraceSpan ts("pi_solve", P, Prec<S>::id, s);
         if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_mfma<P, S, C, true>), dim3(grid), dim3(256), 0, s, L1);
         else hipLaunchKernelGGL((k_pi_solve_mfma<P, S, C, false>), dim3(grid), dim3(256), 0, s, L1);
         err = hipGetLastError();
@@ -1325,6 +1713,7 @@ static hipError_t launch_pi_mfma(int accumulate, ProbEntry* ents, int nprob, Tab
     err = stage_table(L2, ents, nprob, d_tab, s);
     if (err != hipSuccess) return err;
     const int grid2 = (tiles2 + 3) / 4;
+    TraceSpan ts("pi_combine", P, Prec<S>::id, s);
     if (nprob > 1) {
         if (accumulate) hipLaunchKernelGGL((k_pi_combine_planes<P, S, 1, true>), dim3(grid2), dim3(256), 0, s, L2);
         else hipLaunchKernelGGL((k_pi_combine_planes<P, S, 0, true>), dim3(grid2), dim3(256), 0, s, L2);
@@ -1340,6 +1729,7 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
                               const LaunchCfg& cfg) {
     if constexpr (P <= 3) {
         const int fused = cfg.pi_fused >= 0 ? cfg.pi_fused : g_pi_fused;
+        if (fused == 2) return launch_pi_sweep_g<P, S>(accumulate, ents, nprob, d_tab, s);
         if (fused) return launch_pi_sweep<P, S>(accumulate, ents, nprob, d_tab, s);
     }
     const int gcap = cfg.grid_cap > 0 ? cfg.grid_cap : kMaxGrid;
@@ -1364,11 +1754,12 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
         if constexpr (P <= 3) {
             const int grid = (tiles + 7) / 8 * 8;
             if (g_restrict_from_cells) {
+                TraceSpan ts("pi_solve", P, Prec<S>::id, s);
                 if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_r<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, L);
                 else hipLaunchKernelGGL((k_pi_solve_r<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, L);
             } else {
                 // the table L is already staged; assemble first (it restages its own)
-                err = launch_assemble_owner<P, S>(ents, nprob, d_tab, s, gcap);
+                err = launch_assemble<P, S>(ents, nprob, d_tab, s, gcap);
                 if (err != hipSuccess) return err;
                 int t1 = 0;
                 for (int i = 0; i < nprob; ++i) {
@@ -1382,15 +1773,18 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
                 Lg.total_tiles = t1;
                 err = stage_table(Lg, ents, nprob, d_tab, s);
                 if (err != hipSuccess) return err;
+                TraceSpan ts("pi_solve", P, Prec<S>::id, s);
                 if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_g<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, Lg);
                 else hipLaunchKernelGGL((k_pi_solve_g<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, Lg);
             }
         } else if constexpr (P == 4) {
             const int grid = (tiles + 7) / 8 * 8;
+            TraceSpan ts("pi_solve", P, Prec<S>::id, s);
             if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_r<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, L);
             else hipLaunchKernelGGL((k_pi_solve_r<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, L);
         } else {
             const int grid = tiles < gcap ? tiles : gcap;
+            TraceSpan ts("pi_solve", P, Prec<S>::id, s);
             if (nprob > 1) hipLaunchKernelGGL((k_pi_solve<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, L);
             else hipLaunchKernelGGL((k_pi_solve<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, L);
         }
@@ -1412,6 +1806,7 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
     if constexpr (P <= 3) {
         if (g_combine_per_cell) {
             const int grid = (tiles2 + 3) / 4;
+            TraceSpan ts("pi_combine", P, Prec<S>::id, s);
             if (nprob > 1) {
                 if (accumulate) hipLaunchKernelGGL((k_pi_combine_cell<P, S, 1, true>), dim3(grid), dim3(256), 0, s, L2);
                 else hipLaunchKernelGGL((k_pi_combine_cell<P, S, 0, true>), dim3(grid), dim3(256), 0, s, L2);
@@ -1434,6 +1829,7 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
         err = stage_table(L3, ents, nprob, d_tab, s);
         if (err != hipSuccess) return err;
         const int grid = (t3 + 3) / 4;
+        TraceSpan ts("pi_combine", P, Prec<S>::id, s);
         if (nprob > 1) {
             if (accumulate) hipLaunchKernelGGL((k_pi_combine_planes<P, S, 1, true>), dim3(grid), dim3(256), 0, s, L3);
             else hipLaunchKernelGGL((k_pi_combine_planes<P, S, 0, true>), dim3(grid), dim3(256), 0, s, L3);
@@ -1444,6 +1840,7 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
         return hipGetLastError();
     }
     const int grid2 = tiles2 < gcap ? tiles2 : gcap;
+    TraceSpan ts("pi_combine", P, Prec<S>::id, s);
     if (nprob > 1) {
         if (accumulate) hipLaunchKernelGGL((k_pi_combine<P, S, 1, true>), dim3(grid2), dim3(256), 0, s, L2);
         else hipLaunchKernelGGL((k_pi_combine<P, S, 0, true>), dim3(grid2), dim3(256), 0, s, L2);

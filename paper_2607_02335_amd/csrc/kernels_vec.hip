@@ -12,6 +12,7 @@
 
 #include "fem_internal.h"
 #include "launch.h"
+#include "trace.h"
 
 namespace fem {
 
@@ -35,10 +36,8 @@ __global__ void __launch_bounds__(256) k_dot(LaunchTable L, int group) {
     for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
         const ProbEntry& pe = entry<MULTI>(L, tile);
         const int t = tile - pe.tile_begin;
-        const size_t bs = pe.len / pe.nblk;                       // elements per storage block
-        const size_t lo = (size_t)t * pe.blocks_per_red * bs;
-        size_t hi = lo + (size_t)pe.blocks_per_red * bs;
-        if (hi > pe.len) hi = pe.len;
+        size_t lo, hi;
+        red_range(pe, t, lo, hi);
         const SA* a = static_cast<const SA*>(pe.a);
         const SB* b = static_cast<const SB*>(pe.b);
         double acc = 0.0;
@@ -68,36 +67,39 @@ template <int P, typename S, bool MULTI>
 __global__ void __launch_bounds__(256) k_anorm(LaunchTable L, int group) {
     constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
     __shared__ double sh[4];
+    const int lane = threadIdx.x % kLanes, lq = threadIdx.x / kLanes;
     for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
         const ProbEntry& pe = entry<MULTI>(L, tile);
         const int t = tile - pe.tile_begin;
-        const int b0 = t * pe.blocks_per_red;
-        int b1 = b0 + pe.blocks_per_red;
-        if (b1 > pe.nblk) b1 = pe.nblk;
+        size_t lo, hi;
+        red_range(pe, t, lo, hi);
         const S* v = static_cast<const S*>(pe.a);
         const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
         double acc = 0.0;
-        for (long idx = (long)b0 * NN * kLanes + threadIdx.x; idx < (long)b1 * NN * kLanes; idx += 256) {
-            const int blk = (int)(idx / (NN * kLanes));
-            const int rem = (int)(idx % (NN * kLanes));
-            const int l = rem / kLanes, lane = rem % kLanes;
+        // walk the range block by block: a thread keeps its cell (lane) within a block
+        for (size_t base = lo - lo % ((size_t)NN * kLanes); base < hi; base += (size_t)NN * kLanes) {
+            const int blk = (int)(base / ((size_t)NN * kLanes));
             const int e = blk * kLanes + lane;
             if (e >= pe.ncells) continue;
+            const int lb = base < lo ? (int)((lo - base) / kLanes) : 0;
+            const int le = base + (size_t)NN * kLanes > hi ? (int)((hi - base) / kLanes) : NN;
             const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
-            const int a = l % N, b = (l / N) % N, c = l / N2;
-            if ((a == P && i < n0 - 1) || (b == P && j < n1 - 1) || (c == P && k < n2 - 1)) continue;
-            const int cx = (a == 0 && i > 0) ? 2 : 1;
-            const int cy = (b == 0 && j > 0) ? 2 : 1;
-            const int cz = (c == 0 && k > 0) ? 2 : 1;
-            double s = 0.0;
-            for (int sz = 0; sz < cz; ++sz)
-                for (int sy = 0; sy < cy; ++sy)
-                    for (int sx = 0; sx < cx; ++sx) {
-                        const int ee = (i - sx) + n0 * ((j - sy) + n1 * (k - sz));
-                        const int ll = (sx ? P : a) + N * ((sy ? P : b) + N * (sz ? P : c));
-                        s += load_as<double>(v + cell_offset(ee, ll, NN));
-                    }
-            acc += s * s;
+            for (int l = lb + lq; l < le; l += 4) {
+                const int a = l % N, b = (l / N) % N, c = l / N2;
+                if ((a == P && i < n0 - 1) || (b == P && j < n1 - 1) || (c == P && k < n2 - 1)) continue;
+                const int cx = (a == 0 && i > 0) ? 2 : 1;
+                const int cy = (b == 0 && j > 0) ? 2 : 1;
+                const int cz = (c == 0 && k > 0) ? 2 : 1;
+                double s = 0.0;
+                for (int sz = 0; sz < cz; ++sz)
+                    for (int sy = 0; sy < cy; ++sy)
+                        for (int sx = 0; sx < cx; ++sx) {
+                            const int ee = (i - sx) + n0 * ((j - sy) + n1 * (k - sz));
+                            const int ll = (sx ? P : a) + N * ((sy ? P : b) + N * (sz ? P : c));
+                            s += load_as<double>(v + cell_offset(ee, ll, NN));
+                        }
+                acc += s * s;
+            }
         }
         const double r = block_sum(acc, sh);
         if (threadIdx.x == 0) pe.red[group * kRedParts + t] = r;
@@ -116,49 +118,51 @@ template <int P, typename RS, bool MULTI>
 __global__ void __launch_bounds__(256) k_distribute(LaunchTable L, int group) {
     constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
     __shared__ double sh[4];
+    const int lane = threadIdx.x % kLanes, lq = threadIdx.x / kLanes;
     for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
         const ProbEntry& pe = entry<MULTI>(L, tile);
         const int t = tile - pe.tile_begin;
-        const int b0 = t * pe.blocks_per_red;
-        int b1 = b0 + pe.blocks_per_red;
-        if (b1 > pe.nblk) b1 = pe.nblk;
+        size_t lo, hi;
+        red_range(pe, t, lo, hi);
         const double* v = static_cast<const double*>(pe.a);
         RS* out = static_cast<RS*>(pe.c);
         const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
         double acc = 0.0;
-        for (long idx = (long)b0 * NN * kLanes + threadIdx.x; idx < (long)b1 * NN * kLanes; idx += 256) {
-            const int blk = (int)(idx / (NN * kLanes));
-            const int rem = (int)(idx % (NN * kLanes));
-            const int l = rem / kLanes, lane = rem % kLanes;
+        for (size_t base = lo - lo % ((size_t)NN * kLanes); base < hi; base += (size_t)NN * kLanes) {
+            const int blk = (int)(base / ((size_t)NN * kLanes));
             const int e = blk * kLanes + lane;
+            const int lb = base < lo ? (int)((lo - base) / kLanes) : 0;
+            const int le = base + (size_t)NN * kLanes > hi ? (int)((hi - base) / kLanes) : NN;
             if (e >= pe.ncells) {
-                store_from(out + idx, (typename Prec<RS>::C)0);
+                for (int l = lb + lq; l < le; l += 4) store_from(out + base + (size_t)l * kLanes + lane, (typename Prec<RS>::C)0);
                 continue;
             }
             const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
-            const int a = l % N, b = (l / N) % N, c = l / N2;
-            // sharing cells per direction: (cell, local index), ascending cell
-            int ci[2], ai[2], nx, cj[2], bj[2], ny, ck[2], ck_l[2], nz;
-            if (a == 0 && i > 0) { ci[0] = i - 1; ai[0] = P; ci[1] = i; ai[1] = 0; nx = 2; }
-            else if (a == P && i < n0 - 1) { ci[0] = i; ai[0] = P; ci[1] = i + 1; ai[1] = 0; nx = 2; }
-            else { ci[0] = i; ai[0] = a; nx = 1; }
-            if (b == 0 && j > 0) { cj[0] = j - 1; bj[0] = P; cj[1] = j; bj[1] = 0; ny = 2; }
-            else if (b == P && j < n1 - 1) { cj[0] = j; bj[0] = P; cj[1] = j + 1; bj[1] = 0; ny = 2; }
-            else { cj[0] = j; bj[0] = b; ny = 1; }
-            if (c == 0 && k > 0) { ck[0] = k - 1; ck_l[0] = P; ck[1] = k; ck_l[1] = 0; nz = 2; }
-            else if (c == P && k < n2 - 1) { ck[0] = k; ck_l[0] = P; ck[1] = k + 1; ck_l[1] = 0; nz = 2; }
-            else { ck[0] = k; ck_l[0] = c; nz = 1; }
-            double s = 0.0;
-            for (int z = 0; z < nz; ++z)
-                for (int y = 0; y < ny; ++y)
-                    for (int x = 0; x < nx; ++x) {
-                        const int ee = ci[x] + n0 * (cj[y] + n1 * ck[z]);
-                        const int ll = ai[x] + N * (bj[y] + N * ck_l[z]);
-                        s += v[cell_offset(ee, ll, NN)];
-                    }
-            store_from(out + idx, (typename Prec<RS>::C)(s / (double)(nx * ny * nz)));
-            // owner copy: lowest cell along every direction
-            if (ci[0] == i && cj[0] == j && ck[0] == k) acc += s * s;
+            for (int l = lb + lq; l < le; l += 4) {
+                const int a = l % N, b = (l / N) % N, c = l / N2;
+                // sharing cells per direction: (cell, local index), ascending cell
+                int ci[2], ai[2], nx, cj[2], bj[2], ny, ck[2], ck_l[2], nz;
+                if (a == 0 && i > 0) { ci[0] = i - 1; ai[0] = P; ci[1] = i; ai[1] = 0; nx = 2; }
+                else if (a == P && i < n0 - 1) { ci[0] = i; ai[0] = P; ci[1] = i + 1; ai[1] = 0; nx = 2; }
+                else { ci[0] = i; ai[0] = a; nx = 1; }
+                if (b == 0 && j > 0) { cj[0] = j - 1; bj[0] = P; cj[1] = j; bj[1] = 0; ny = 2; }
+                else if (b == P && j < n1 - 1) { cj[0] = j; bj[0] = P; cj[1] = j + 1; bj[1] = 0; ny = 2; }
+                else { cj[0] = j; bj[0] = b; ny = 1; }
+                if (c == 0 && k > 0) { ck[0] = k - 1; ck_l[0] = P; ck[1] = k; ck_l[1] = 0; nz = 2; }
+                else if (c == P && k < n2 - 1) { ck[0] = k; ck_l[0] = P; ck[1] = k + 1; ck_l[1] = 0; nz = 2; }
+                else { ck[0] = k; ck_l[0] = c; nz = 1; }
+                double s = 0.0;
+                for (int z = 0; z < nz; ++z)
+                    for (int y = 0; y < ny; ++y)
+                        for (int x = 0; x < nx; ++x) {
+                            const int ee = ci[x] + n0 * (cj[y] + n1 * ck[z]);
+                            const int ll = ai[x] + N * (bj[y] + N * ck_l[z]);
+                            s += v[cell_offset(ee, ll, NN)];
+                        }
+                store_from(out + base + (size_t)l * kLanes + lane, (typename Prec<RS>::C)(s / (double)(nx * ny * nz)));
+                // owner copy: lowest cell along every direction
+                if (ci[0] == i && cj[0] == j && ck[0] == k) acc += s * s;
+            }
         }
         const double r = block_sum(acc, sh);
         if (threadIdx.x == 0) pe.red[group * kRedParts + t] = r;
@@ -306,8 +310,8 @@ __global__ void __launch_bounds__(256) k_cg_ur(LaunchTable L) {
         const int t = tile - pe.tile_begin;
         const double* sl = red_slots(pe.red);
         const double alpha = sl[kSlotRZ] / sl[kSlotQP];
-        const size_t bs = pe.len / pe.nblk;
-        const size_t lo = (size_t)t * bs, hi = lo + bs;
+        size_t lo, hi;
+        red_range(pe, t, lo, hi);
         const double* p = static_cast<const double*>(pe.a);
         const double* q = static_cast<const double*>(pe.b);
         double* u = static_cast<double*>(pe.c);
@@ -330,8 +334,8 @@ __global__ void __launch_bounds__(256) k_cg_p(LaunchTable L, int variant) {
         const int t = tile - pe.tile_begin;
         const double* sl = red_slots(pe.red);
         const double beta = variant == FEM_CG_PCG ? sl[kSlotRZ] / sl[kSlotRZOld] : -sl[kSlotQZ] / sl[kSlotQP];
-        const size_t bs = pe.len / pe.nblk;
-        const size_t lo = (size_t)t * bs, hi = lo + bs;
+        size_t lo, hi;
+        red_range(pe, t, lo, hi);
         const SZ* z = static_cast<const SZ*>(pe.a);
         double* p = static_cast<double*>(pe.c);
         for (size_t i = lo + threadIdx.x; i < hi; i += 256)
@@ -345,8 +349,8 @@ __global__ void __launch_bounds__(256) k_convert_multi(LaunchTable L) {
     for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
         const ProbEntry& pe = entry<MULTI>(L, tile);
         const int t = tile - pe.tile_begin;
-        const size_t bs = pe.len / pe.nblk;
-        const size_t lo = (size_t)t * bs, hi = lo + bs;
+        size_t lo, hi;
+        red_range(pe, t, lo, hi);
         const SA* a = static_cast<const SA*>(pe.a);
         SB* c = static_cast<SB*>(pe.c);
         for (size_t i = lo + threadIdx.x; i < hi; i += 256) store_from(c + i, load_as<typename Prec<SB>::C>(a + i));
@@ -392,8 +396,22 @@ ProbEntry entry_of(const fem_problem* P) {
     e.h[1] = P->d_h + P->n[0];
     e.h[2] = P->d_h + P->n[0] + P->n[1];
     e.red = P->d_red;
-    e.blocks_per_red = (P->nblk + kRedParts - 1) / kRedParts;
-    e.ntiles_red = (P->nblk + e.blocks_per_red - 1) / e.blocks_per_red;
+    // about 1024 tiles (4 wavefronts each) where the problem is large enough
+    constexpr int kTarget = 1024;
+    const int nn = (P->p + 1) * (P->p + 1) * (P->p + 1);
+    if (P->nblk >= kTarget) {
+        e.blocks_per_red = (P->nblk + kRedParts - 1) / kRedParts;
+        e.red_lsplit = 1;
+        e.ntiles_red = (P->nblk + e.blocks_per_red - 1) / e.blocks_per_red;
+    } else {
+        e.blocks_per_red = 1;
+        int split = (kTarget + P->nblk - 1) / P->nblk;
+        if (split > (nn + 3) / 4) split = (nn + 3) / 4;        // at least 4 node planes per tile
+        if (split < 1) split = 1;
+        const int lchunk = (nn + split - 1) / split;
+        e.red_lsplit = (nn + lchunk - 1) / lchunk;
+        e.ntiles_red = P->nblk * e.red_lsplit;
+    }
     return e;
 }
 
@@ -476,6 +494,7 @@ hipError_t run_pack(fem_problem* P, const double* canon, void* vc, int prec, int
 
 template <int P_, typename S>
 static void launch_dss_axis(const ProbEntry& e, int axis, long total, hipStream_t s) {
+    TraceSpan ts("dss_axis", P_, Prec<S>::id, s);
     hipLaunchKernelGGL((k_dss_axis<P_, S>), dim3((total + 255) / 256), dim3(256), 0, s, e, axis, total);
 }
 
@@ -525,6 +544,7 @@ hipError_t run_dot(fem_problem* P, const void* a, int pa, const void* b, int pb,
         using SA = decltype(ta);
         return dispatch_prec(pb, [&](auto tb) {
             using SB = decltype(tb);
+            TraceSpan ts("dot", P->p, Prec<SA>::id, P->stream);
             hipLaunchKernelGGL((k_dot<SA, SB, false>), dim3(L.total_tiles), dim3(256), 0, P->stream, L, 0);
             return hipGetLastError();
         });
@@ -544,6 +564,7 @@ hipError_t run_assembled_norm2(fem_problem* P, const void* r, int prec, int slot
     hipError_t err = dispatch_prec(prec, [&](auto tag) {
         using S = decltype(tag);
         dim3 g(L.total_tiles), b(256);
+        TraceSpan ts("assembled_norm", P->p, Prec<S>::id, P->stream);
         switch (P->p) {
             case 1: hipLaunchKernelGGL((k_anorm<1, S, false>), g, b, 0, P->stream, L, 1); break;
             case 2: hipLaunchKernelGGL((k_anorm<2, S, false>), g, b, 0, P->stream, L, 1); break;
@@ -572,6 +593,7 @@ hipError_t run_distribute(fem_problem* P, const double* r, void* out, int prec, 
     hipError_t err = dispatch_prec(prec, [&](auto tag) {
         using S = decltype(tag);
         dim3 g(L.total_tiles), b(256);
+        TraceSpan ts("distribute", P->p, Prec<S>::id, P->stream);
         switch (P->p) {
             case 1: hipLaunchKernelGGL((k_distribute<1, S, false>), g, b, 0, P->stream, L, 2); break;
             case 2: hipLaunchKernelGGL((k_distribute<2, S, false>), g, b, 0, P->stream, L, 2); break;
@@ -599,11 +621,12 @@ hipError_t run_cg_update_ur(fem_problem* P, double* u, double* r, const double* 
     e.tile_begin = 0;
     LaunchTable L{};
     L.nprob = 1;
-    L.total_tiles = e.nblk;
+    L.total_tiles = e.ntiles_red;
     L.one = e;
-    const int grid = e.nblk < kMaxGrid ? e.nblk : kMaxGrid;
+    const int grid = e.ntiles_red < kMaxGrid ? e.ntiles_red : kMaxGrid;
     return dispatch_prec(rs ? rs_prec : FEM_F64, [&](auto tag) {
         using S = decltype(tag);
+        TraceSpan ts("cg_update_ur", P->p, Prec<S>::id, P->stream);
         hipLaunchKernelGGL((k_cg_ur<S, false>), dim3(grid), dim3(256), 0, P->stream, L);
         return hipGetLastError();
     });
@@ -616,11 +639,12 @@ hipError_t run_cg_update_p(fem_problem* P, double* p, const void* z, int zprec, 
     e.tile_begin = 0;
     LaunchTable L{};
     L.nprob = 1;
-    L.total_tiles = e.nblk;
+    L.total_tiles = e.ntiles_red;
     L.one = e;
-    const int grid = e.nblk < kMaxGrid ? e.nblk : kMaxGrid;
+    const int grid = e.ntiles_red < kMaxGrid ? e.ntiles_red : kMaxGrid;
     return dispatch_prec(zprec, [&](auto tag) {
         using S = decltype(tag);
+        TraceSpan ts("cg_update_p", P->p, Prec<S>::id, P->stream);
         hipLaunchKernelGGL((k_cg_p<S, false>), dim3(grid), dim3(256), 0, P->stream, L, variant);
         return hipGetLastError();
     });
@@ -641,14 +665,6 @@ static int tiles_red(ProbEntry* ents, int nprob) {
     for (int i = 0; i < nprob; ++i) {
         ents[i].tile_begin = t;
         t += ents[i].ntiles_red;
-    }
-    return t;
-}
-static int tiles_blocks(ProbEntry* ents, int nprob) {
-    int t = 0;
-    for (int i = 0; i < nprob; ++i) {
-        ents[i].tile_begin = t;
-        t += ents[i].nblk;
     }
     return t;
 }
@@ -745,7 +761,7 @@ hipError_t launch_cg_ur(ProbEntry* ents, int nprob, TableStager* st, hipStream_t
     if (nprob <= 0) return hipSuccess;
     LaunchTable L{};
     L.nprob = nprob;
-    L.total_tiles = tiles_blocks(ents, nprob);
+    L.total_tiles = tiles_red(ents, nprob);
     hipError_t err = stage_table(L, ents, nprob, st, s);
     if (err != hipSuccess) return err;
     const int grid = L.total_tiles < kMaxGrid ? L.total_tiles : kMaxGrid;
@@ -758,7 +774,7 @@ hipError_t launch_cg_p(int zprec, int variant, ProbEntry* ents, int nprob, Table
     if (nprob <= 0) return hipSuccess;
     LaunchTable L{};
     L.nprob = nprob;
-    L.total_tiles = tiles_blocks(ents, nprob);
+    L.total_tiles = tiles_red(ents, nprob);
     hipError_t err = stage_table(L, ents, nprob, st, s);
     if (err != hipSuccess) return err;
     const int grid = L.total_tiles < kMaxGrid ? L.total_tiles : kMaxGrid;
@@ -799,7 +815,7 @@ hipError_t launch_convert(int sp, int dp, ProbEntry* ents, int nprob, TableStage
     if (nprob <= 0) return hipSuccess;
     LaunchTable L{};
     L.nprob = nprob;
-    L.total_tiles = tiles_blocks(ents, nprob);
+    L.total_tiles = tiles_red(ents, nprob);
     hipError_t err = stage_table(L, ents, nprob, st, s);
     if (err != hipSuccess) return err;
     const int grid = L.total_tiles < kMaxGrid ? L.total_tiles : kMaxGrid;

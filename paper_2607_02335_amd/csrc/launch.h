@@ -10,7 +10,7 @@ namespace fem {
 constexpr int kMaxGrid = 256 * 8;
 // Number of workgroup partial sums of one reduction (fixed, so the
 // reduction order of a problem never depends on what else is launched).
-constexpr int kRedParts = 512;
+constexpr int kRedParts = 2048;
 // Scalar slots after the partials in a problem's reduction area.
 enum RedSlot {
     kSlotRZ = 0,      // <r, z>
@@ -24,6 +24,27 @@ enum RedSlot {
 };
 constexpr int kRedStride = kRedParts * 4 + kSlotCount;   // 4 partial groups + slots
 __host__ __device__ inline double* red_slots(double* red) { return red + kRedParts * 4; }
+
+// Element range [lo, hi) of reduction (and elementwise) tile t of a problem:
+// either blocks_per_red whole storage blocks, or, for problems with few
+// blocks, one of red_lsplit contiguous slices of node planes of one block.
+// Depends only on the problem's own sizes.
+__host__ __device__ inline void red_range(const ProbEntry& pe, int t, size_t& lo, size_t& hi) {
+    const size_t bs = pe.len / pe.nblk;
+    if (pe.red_lsplit <= 1) {
+        lo = (size_t)t * pe.blocks_per_red * bs;
+        hi = lo + (size_t)pe.blocks_per_red * bs;
+    } else {
+        const int nn = (int)(bs / kLanes);
+        const int lchunk = (nn + pe.red_lsplit - 1) / pe.red_lsplit;
+        const int blk = t / pe.red_lsplit, part = t % pe.red_lsplit;
+        const int l0 = part * lchunk, l1 = l0 + lchunk < nn ? l0 + lchunk : nn;
+        lo = (size_t)blk * bs + (size_t)l0 * kLanes;
+        hi = (size_t)blk * bs + (size_t)l1 * kLanes;
+    }
+    if (hi > pe.len) hi = pe.len;
+    if (lo > hi) lo = hi;
+}
 
 // 1D reference matrices of degree p on [0,1] (row-major, (p+1)^2), built on
 // the host once per process.

@@ -35,6 +35,11 @@ class Desc(ct.Structure):
                 ("bc", ct.c_int)]
 
 
+class TraceRec(ct.Structure):
+    _fields_ = [("label", ct.c_char * 48), ("p", ct.c_int), ("prec", ct.c_int), ("launches", ct.c_int),
+                ("total_ms", ct.c_double)]
+
+
 class SolveInfo(ct.Structure):
     _fields_ = [("iters", ct.c_int), ("status", ct.c_int), ("relres", ct.c_double),
                 ("seconds", ct.c_double)]
@@ -88,6 +93,8 @@ def lib():
         "fem_host_fd_1d": ([i, d, d, vp, vp], i),
         "fem_host_gll_nodes": ([i, vp], i),
         "fem_set_option": ([i, i], i),
+        "fem_trace_enable": ([i], i),
+        "fem_trace_read": ([ct.POINTER(TraceRec), i], i),
         "fem_last_error": ([], ct.c_char_p),
         "fem_version": ([], ct.c_char_p),
     }
@@ -170,6 +177,21 @@ OPT_RESTRICT_FROM_CELLS = 3
 
 def set_option(option, value):
     check(lib().fem_set_option(option, value), "fem_set_option")
+
+
+def trace_enable(on=True):
+    """Start (or stop) recording per-launch HIP event pairs."""
+    check(lib().fem_trace_enable(1 if on else 0), "fem_trace_enable")
+
+
+def trace_read():
+    """Aggregated launch durations since the last read: a list of dicts
+    {label, p, prec, launches, total_ms, avg_us}."""
+    cap = 512
+    recs = (TraceRec * cap)()
+    n = min(cap, lib().fem_trace_read(recs, cap))
+    return [dict(label=r.label.decode(), p=r.p, prec=r.prec, launches=r.launches, total_ms=r.total_ms,
+                 avg_us=r.total_ms * 1e3 / max(r.launches, 1)) for r in recs[:n]]
 
 
 def host_1d_matrices(p):
