@@ -1400,22 +1400,30 @@ static hipError_t launch_pi_sweep(int accumulate, ProbEntry* ents, int nprob, Ta
 // c), so even small meshes give N times as many wavefronts as blocks; the
 // eight corner-patch addresses are formed once per cell, (a, b) loops are
 // unrolled.
+template <int P> constexpr int combine_brows() { return P <= 3 ? P + 1 : 2; }
+
 template <int P, typename S, int ACC, bool MULTI>
 __global__ void __launch_bounds__(256) k_pi_combine_planes(LaunchTable L) {
     using C = typename Prec<S>::C;
     constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
     constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
+    constexpr int BS = combine_brows<P>();          // b rows per wavefront
+    constexpr int NBG = (N + BS - 1) / BS;          // row groups per plane
     const int lane = threadIdx.x & 63;
     const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (tile >= L.total_tiles) return;
     const ProbEntry& pe = entry<MULTI>(L, tile);
-    const int blk = (tile - pe.tile_begin) / N;
-    const int c = (tile - pe.tile_begin) % N;
+    const int blk = (tile - pe.tile_begin) / (N * NBG);
+    const int c = ((tile - pe.tile_begin) / NBG) % N;
+    const int b0 = ((tile - pe.tile_begin) % NBG) * BS;
     const int e = blk * kLanes + lane;
     S* z = static_cast<S*>(pe.c) + (size_t)blk * NN * kLanes + (size_t)c * N2 * kLanes + lane;
     if (e >= pe.ncells) {
 #pragma unroll
-        for (int l = 0; l < N2; ++l) store_from(z + l * kLanes, (C)0);
+        for (int bb = 0; bb < BS; ++bb)
+#pragma unroll
+            for (int a = 0; a < N; ++a)
+                if (b0 + bb < N) store_from(z + (a + N * (b0 + bb)) * kLanes, (C)0);
         return;
     }
     const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
@@ -1445,9 +1453,11 @@ __global__ void __launch_bounds__(256) k_pi_combine_planes(LaunchTable L) {
                 }
             }
 #pragma unroll
-    for (int b = 0; b < N; ++b)
+    for (int bb = 0; bb < BS; ++bb)
 #pragma unroll
         for (int a = 0; a < N; ++a) {
+            const int b = b0 + bb;
+            if (b >= N) break;
             C sum = 0;
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
@@ -1514,10 +1524,11 @@ __device__ __forceinline__ void wave_sync() {
 }
 
 // out(j, line) = sum_i Op(j, i) v(i, line) in place over all lines of the
-// wave's patch; Op's 16x4 slices for the four k-steps are in `a`.  MODE 1
+// patch; Op's 16x4 slices for the four k-steps are in `a`.  The patch's WPP
+// wavefronts (sub = this one's index) take every WPP-th 16-line tile.  MODE 1
 // additionally divides by lambda_x(j) + lambda_y(y) + lambda_z(z) (x pass).
-template <typename C, int nP, int DIR, int MODE>
-__device__ __forceinline__ void mfma_pass(C* pv, const C (&a)[4], int lane, const C* lx, const C* ly,
+template <typename C, int nP, int DIR, int MODE, int WPP>
+__device__ __forceinline__ void mfma_pass(C* pv, const C (&a)[4], int lane, int sub, const C* lx, const C* ly,
                                           const C* lz) {
     using M = Mfma<C>;
     constexpr int NL = nP * nP, NT = (NL + 15) / 16;
@@ -1527,7 +1538,7 @@ __device__ __forceinline__ void mfma_pass(C* pv, const C (&a)[4], int lane, cons
         return i + nP * line;                                               // x lines: line = qy + nP qz
     };
     const int col = lane % 16;
-    for (int t = 0; t < NT; ++t) {
+    for (int t = sub; t < NT; t += WPP) {
         const int line = 16 * t + col;
         typename M::V acc = {0, 0, 0, 0};
 #pragma unroll
@@ -1548,18 +1559,99 @@ __device__ __forceinline__ void mfma_pass(C* pv, const C (&a)[4], int lane, cons
             }
         }
     }
-    wave_sync();
+    if (WPP == 1) wave_sync();
+    else __syncthreads();
 }
+
+// Combine from a patch-major buffer (p >= 4): a workgroup takes one storage
+// block (64 cells) at one node plane c.  Each wavefront walks 16 of the
+// cells; its lanes are the (a, b) nodes of the plane, so the reads of a
+// corner patch are rows of contiguous values.  The sums go through LDS
+// (padded rows) and leave as coalesced cell-wise stores.  Terms are added in
+// ascending vertex order along z, y, x for every copy of a node.
+template <int P, typename S, int ACC, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_combine_pm(LaunchTable L) {
+    using C = typename Prec<S>::C;
+    constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
+    constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
+    constexpr int RS = kLanes + 1;                  // padded LDS row
+    __shared__ C sz[N2 * RS];
+    const int tile = blockIdx.x;
+    if (tile >= L.total_tiles) return;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int blk = (tile - pe.tile_begin) / N;
+    const int c = (tile - pe.tile_begin) % N;
+    const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+    const int npx = n0 - 1, npy = n1 - 1;
+    const C* pbuf = static_cast<const C*>(pe.d);
+    const C alpha = (C)pe.alpha;
+    const int ab = threadIdx.x % 64, wv = threadIdx.x / 64;
+    const int a = ab % N, b = ab / N;
+    // the z-plane c selects the vertex layers (and their patch-local qz)
+    int nz = 0, szs[2], qzs[2];
+    if (c != P) { szs[nz] = 0; qzs[nz] = P - 1 + c; ++nz; }
+    if (c != 0) { szs[nz] = 1; qzs[nz] = c - 1; ++nz; }
+    if (ab < N2) {
+        for (int cl = wv; cl < kLanes; cl += 4) {
+            const int e = blk * kLanes + cl;
+            C sum = 0;
+            if (e < pe.ncells) {
+                const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    if (t >= nz) break;
+                    const int vz = k + szs[t];
+                    if (vz < 1 || vz > n2 - 1) continue;
+#pragma unroll
+                    for (int sy = 0; sy < 2; ++sy) {
+                        if ((sy == 0 && b == P) || (sy == 1 && b == 0)) continue;
+                        const int vy = j + sy;
+                        if (vy < 1 || vy > npy) continue;
+                        const int qy = sy == 0 ? P - 1 + b : b - 1;
+#pragma unroll
+                        for (int sx = 0; sx < 2; ++sx) {
+                            if ((sx == 0 && a == P) || (sx == 1 && a == 0)) continue;
+                            const int vx = i + sx;
+                            if (vx < 1 || vx > npx) continue;
+                            const int qx = sx == 0 ? P - 1 + a : a - 1;
+                            const int pidx = (vx - 1) + npx * ((vy - 1) + npy * (vz - 1));
+                            sum += pbuf[(size_t)pidx * nP3 + qx + nP * qy + nP2 * qzs[t]];
+                        }
+                    }
+                }
+            }
+            sz[ab * RS + cl] = sum;
+        }
+    }
+    __syncthreads();
+    S* z = static_cast<S*>(pe.c) + (size_t)blk * NN * kLanes + (size_t)c * N2 * kLanes;
+    for (int idx = threadIdx.x; idx < N2 * kLanes; idx += 256) {
+        const int l = idx / kLanes, cl = idx % kLanes;
+        const int e = blk * kLanes + cl;
+        C out = e < pe.ncells ? alpha * sz[l * RS + cl] : (C)0;
+        if (ACC && e < pe.ncells) out = load_as<C>(z + idx) + out;
+        store_from(z + idx, out);
+    }
+}
+
+// Wavefronts that share one patch: the larger patches split their 16-line
+// tiles over the whole workgroup for more waves in flight per LDS byte.
+template <int P> constexpr int mfma_waves_per_patch() { return P >= 6 ? 2 : 1; }
 
 // pe: e = assembled global residual (C), d = patch buffer (C), fd = FD data (C)
 template <int P, typename S, typename C, bool MULTI>
 __global__ void __launch_bounds__(256) k_pi_solve_mfma(LaunchTable L) {
     constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
     constexpr int REC = fd_record(P);
+    constexpr int WPP = mfma_waves_per_patch<P>();   // wavefronts per patch
+    constexpr int PPW = 4 / WPP;                      // patches per workgroup
     static_assert(nP <= 16, "one MFMA tile per contraction");
-    __shared__ C spv[4][nP3];
+    __shared__ C spv[PPW][nP3];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int tile = blockIdx.x * 4 + wv;
+    const int slot = wv / WPP, sub = wv % WPP;
+    const int tile = blockIdx.x * PPW + slot;
+    // a workgroup's patches are consecutive tiles; with WPP > 1 the whole
+    // workgroup serves one patch, so this exit is uniform over it
     if (tile >= L.total_tiles) return;
     const ProbEntry& pe = entry<MULTI>(L, tile);
     const int pidx = tile - pe.tile_begin;
@@ -1581,29 +1673,32 @@ __global__ void __launch_bounds__(256) k_pi_solve_mfma(LaunchTable L) {
         aby[ks] = ok ? fy[rr * nP + kk] : (C)0;
         abz[ks] = ok ? fz[rr * nP + kk] : (C)0;
     }
-    C* pv = spv[wv];
+    C* pv = spv[slot];
+    const int t64 = sub * 64 + lane;                  // thread index within the patch's wavefronts
     // restrict: the patch's box of the assembled residual
     {
         const C* g = static_cast<const C*>(pe.e);
         const size_t G0 = (size_t)pe.n[0] * P + 1, G1 = (size_t)pe.n[1] * P + 1;
         const size_t I0 = (size_t)(vi - 1) * P + 1, J0 = (size_t)(vj - 1) * P + 1, K0 = (size_t)(vk - 1) * P + 1;
-        for (int q = lane; q < nP3; q += 64) {
+        for (int q = t64; q < nP3; q += 64 * WPP) {
             const int qx = q % nP, qy = (q / nP) % nP, qz = q / nP2;
             pv[q] = g[(I0 + qx) + G0 * ((J0 + qy) + G1 * (K0 + qz))];
         }
     }
-    wave_sync();
+    if (WPP == 1) wave_sync();
+    else __syncthreads();
     const C* lx = fx + nP2;
     const C* ly = fy + nP2;
     const C* lz = fz + nP2;
-    mfma_pass<C, nP, 2, 0>(pv, afz, lane, lx, ly, lz);
-    mfma_pass<C, nP, 1, 0>(pv, afy, lane, lx, ly, lz);
-    mfma_pass<C, nP, 0, 1>(pv, afx, lane, lx, ly, lz);
-    mfma_pass<C, nP, 0, 0>(pv, abx, lane, lx, ly, lz);
-    mfma_pass<C, nP, 1, 0>(pv, aby, lane, lx, ly, lz);
-    mfma_pass<C, nP, 2, 0>(pv, abz, lane, lx, ly, lz);
-    C* out = static_cast<C*>(pe.d) + (size_t)(pidx / kLanes) * nP3 * kLanes + (pidx % kLanes);
-    for (int q = lane; q < nP3; q += 64) out[(size_t)q * kLanes] = pv[q];
+    mfma_pass<C, nP, 2, 0, WPP>(pv, afz, lane, sub, lx, ly, lz);
+    mfma_pass<C, nP, 1, 0, WPP>(pv, afy, lane, sub, lx, ly, lz);
+    mfma_pass<C, nP, 0, 1, WPP>(pv, afx, lane, sub, lx, ly, lz);
+    mfma_pass<C, nP, 0, 0, WPP>(pv, abx, lane, sub, lx, ly, lz);
+    mfma_pass<C, nP, 1, 0, WPP>(pv, aby, lane, sub, lx, ly, lz);
+    mfma_pass<C, nP, 2, 0, WPP>(pv, abz, lane, sub, lx, ly, lz);
+    // patch-major buffer: each patch's values are one contiguous run
+    C* out = static_cast<C*>(pe.d) + (size_t)pidx * nP3;
+    for (int q = t64; q < nP3; q += 64 * WPP) out[q] = pv[q];
 }
 
 // Assemble a dual cell-wise vector into the global-node array (sum of all
@@ -1693,7 +1788,8 @@ static hipError_t launch_pi_mfma(int accumulate, ProbEntry* ents, int nprob, Tab
     err = stage_table(L1, ents, nprob, d_tab, s);
     if (err != hipSuccess) return err;
     if (tiles > 0) {
-        const int grid = (tiles + 3) / 4;
+        constexpr int PPW = 4 / mfma_waves_per_patch<P>();
+        const int grid = (tiles + PPW - 1) / PPW;
         TraceSpan ts("pi_solve", P, Prec<S>::id, s);
         if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_mfma<P, S, C, true>), dim3(grid), dim3(256), 0, s, L1);
         else hipLaunchKernelGGL((k_pi_solve_mfma<P, S, C, false>), dim3(grid), dim3(256), 0, s, L1);
@@ -1712,14 +1808,14 @@ static hipError_t launch_pi_mfma(int accumulate, ProbEntry* ents, int nprob, Tab
     L2.total_tiles = tiles2;
     err = stage_table(L2, ents, nprob, d_tab, s);
     if (err != hipSuccess) return err;
-    const int grid2 = (tiles2 + 3) / 4;
+    const int grid2 = tiles2;
     TraceSpan ts("pi_combine", P, Prec<S>::id, s);
     if (nprob > 1) {
-        if (accumulate) hipLaunchKernelGGL((k_pi_combine_planes<P, S, 1, true>), dim3(grid2), dim3(256), 0, s, L2);
-        else hipLaunchKernelGGL((k_pi_combine_planes<P, S, 0, true>), dim3(grid2), dim3(256), 0, s, L2);
+        if (accumulate) hipLaunchKernelGGL((k_pi_combine_pm<P, S, 1, true>), dim3(grid2), dim3(256), 0, s, L2);
+        else hipLaunchKernelGGL((k_pi_combine_pm<P, S, 0, true>), dim3(grid2), dim3(256), 0, s, L2);
     } else {
-        if (accumulate) hipLaunchKernelGGL((k_pi_combine_planes<P, S, 1, false>), dim3(grid2), dim3(256), 0, s, L2);
-        else hipLaunchKernelGGL((k_pi_combine_planes<P, S, 0, false>), dim3(grid2), dim3(256), 0, s, L2);
+        if (accumulate) hipLaunchKernelGGL((k_pi_combine_pm<P, S, 1, false>), dim3(grid2), dim3(256), 0, s, L2);
+        else hipLaunchKernelGGL((k_pi_combine_pm<P, S, 0, false>), dim3(grid2), dim3(256), 0, s, L2);
     }
     return hipGetLastError();
 }
@@ -1820,7 +1916,7 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
         int t3 = 0;
         for (int i = 0; i < nprob; ++i) {
             ents[i].tile_begin = t3;
-            ents[i].ntiles = ents[i].nblk * (P + 1);
+            ents[i].ntiles = ents[i].nblk * (P + 1) * ((P + 1 + combine_brows<P>() - 1) / combine_brows<P>());
             t3 += ents[i].ntiles;
         }
         LaunchTable L3{};
