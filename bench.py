@@ -123,6 +123,7 @@ def measure_workload(fem, torch, p, n, seed, steps, warmup):
                apply_cell_gdofs=c / t_apply / 1e9, pi_cell_gdofs=c / t_pi / 1e9,
                step_unique_gdofs=u / wall / 1e9,
                apply_gbs=16 * c / t_apply / 1e9, pi_gbs=16 * c / t_pi / 1e9)
+    res["roofline_by_kernel"] = kernel_table(res)
     del sets
     P.close()
     torch.cuda.empty_cache()
@@ -154,7 +155,37 @@ def kernel_flops(label, p, n):
     return None
 
 
-def roofline(rec):
+def measured_traffic(workload, label):
+    """HBM bytes per launch of a traced kernel from the committed counter
+    summary of the workload, or None when there is none or the kernel
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    from paper_2607_02335_amd import profiling
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("sources_sha256") != profiling.sources_hash():
+        return None
+    k = rec.get("kernels", {}).get(label)
+    return None if k is None else int(round(k["bytes"]))
+
+
+def kernel_table(rec):
+    """Every traced kernel of a workload against the HBM roofline."""
+    p, n = rec["p"], rec["n"]
+    out = []
+    for k in rec["kernels"]:
+        b = kernel_bytes(k["label"], p, n)
+        if b is None:
+            continue
+        gbs = b / (k["avg_us"] * 1e-6) / 1e9
+        out.append({"kernel": k["label"], "avg_us": round(k["avg_us"], 2), "algorithmic_bytes": b,
+                    "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+    return out
+
+
+def roofline(rec, workload="q3_64"):
     """Roofline record of the kernel with the largest share of the step."""
     p, n = rec["p"], rec["n"]
     ks = [k for k in rec["kernels"] if kernel_bytes(k["label"], p, n) is not None]
@@ -164,13 +195,49 @@ def roofline(rec):
     gbs = byts / t / 1e9
     fl = kernel_flops(dom["label"], p, n)
     out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload, dom["label"]),
            "kernel": dom["label"], "launch_avg_us": round(dom["avg_us"], 2), "launches": dom["launches"],
            "algorithmic_bytes_per_launch": byts}
     if fl is not None:
         tf = fl / t / 1e12
         out["fp64_tflops"] = round(tf, 2)
         out["fp64_frac"] = round(tf / FP64_PEAK_TFLOPS, 4)
+    return out
+
+
+def batch_times(fem, torch, steps, warmup, count=256, seed=3):
+    """256 independent problems (p uniform in {2,3,7}, n uniform in [4,32],
+    seed 3): FP32 apply + patch inverse of all of them, one launch per degree
+    and operation, with the autotuned kernel shapes.  Rate = unique DoFs of
+    the whole batch per second of one pass."""
+    import synth
+    wls = synth.batch_problems(count=count, seed=seed)
+    B = fem.Batch([(w.p, w.n, None) for w in wls])
+    xs = [P.gather(torch.as_tensor(w.x, device="cuda"), fem.F32) for P, w in zip(B.problems, wls)]
+    ys = [P.cell_vector(fem.F32) for P in B.problems]
+    zs = [P.cell_vector(fem.F32) for P in B.problems]
+    choice = B.autotune(fem.F32)
+
+    def step(i):
+        B.apply(xs, ys)
+        B.patch_inverse(ys, zs)
+
+    for i in range(warmup):
+        step(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(i)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / steps
+    uniq = sum(unique_dofs(w.p, w.n[0]) for w in wls)
+    cell = sum(cell_dofs(w.p, w.n[0]) for w in wls)
+    out = dict(problems=count, unique_dofs=uniq, cell_dofs=cell, s_per_pass=t,
+               unique_gdofs=uniq / t / 1e9, cell_gdofs=cell / t / 1e9,
+               autotuned={str(k): v for k, v in choice.items()})
+    del xs, ys, zs
+    B.close()
+    torch.cuda.empty_cache()
     return out
 
 
@@ -242,7 +309,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="bench", choices=["bench", "calib", "serve"])
     ap.add_argument("--quick", action="store_true", help="headline workload only")
-    ap.add_argument("--only", choices=["q2_96", "q7_24", "q7_solve"], default=None,
+    ap.add_argument("--only", choices=["q2_96", "q7_24", "q7_solve", "batch_256"], default=None,
                     help="run one secondary workload alone (for profiling) and print its record")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--solve-reps", type=int, default=5)
@@ -275,6 +342,8 @@ def main():
         log(f"{a.only} alone")
         if a.only == "q7_solve":
             rec = solve_times(fem, torch, a.solve_reps)
+        elif a.only == "batch_256":
+            rec = batch_times(fem, torch, a.steps, a.warmup)
         else:
             p, n = (2, 96) if a.only == "q2_96" else (7, 24)
             rec = measure_workload(fem, torch, p, n, 1, a.steps, a.warmup)
@@ -290,6 +359,8 @@ def main():
         extra["q7_24"] = measure_workload(fem, torch, 7, 24, 1, a.steps, a.warmup)
         log("Q7 24^3 solves")
         extra["q7_solve"] = solve_times(fem, torch, a.solve_reps)
+        log("batch of 256 problems")
+        extra["batch_256"] = batch_times(fem, torch, a.steps, a.warmup)
 
     roof = roofline(head)
     cpu = None

@@ -276,7 +276,7 @@ int host_fd_1d(int p, double h0, double h1, double* S, double* lam) {
 
 using namespace fem;
 
-namespace fem { extern int g_pi_fused; extern int g_combine_per_cell; extern int g_restrict_from_cells; extern int g_assemble_owner; }
+namespace fem { extern int g_pi_fused; extern int g_combine_per_cell; extern int g_restrict_from_cells; extern int g_assemble_owner; extern int g_pi_xcombine; }
 
 extern "C" fem_status fem_set_option(int option, int value) {
     switch (option) {
@@ -284,6 +284,7 @@ extern "C" fem_status fem_set_option(int option, int value) {
         case FEM_OPT_COMBINE_PER_CELL: fem::g_combine_per_cell = value ? 1 : 0; return FEM_OK;
         case FEM_OPT_RESTRICT_FROM_CELLS: fem::g_restrict_from_cells = value ? 1 : 0; return FEM_OK;
         case 4: fem::g_assemble_owner = value ? 1 : 0; return FEM_OK;
+        case 5: fem::g_pi_xcombine = value ? 1 : 0; return FEM_OK;
         default: return set_error(FEM_EINVAL, "fem_set_option: unknown option");
     }
 }

@@ -258,7 +258,8 @@ def test_distribute_assembled_before_demotion(F, prec):
     np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(d), prec))), to_np(P.unpack(d)))
 
 
-@pytest.mark.parametrize("p,n", [(2, (17, 5, 9)), (3, (10, 3, 7)), (1, (33, 6, 5)), (3, (19, 9, 13))])
+@pytest.mark.parametrize("p,n", [(2, (17, 5, 9)), (3, (10, 3, 7)), (1, (33, 6, 5)), (3, (19, 9, 13)),
+                                 (3, (40, 4, 3)), (2, (70, 3, 3))])
 @pytest.mark.parametrize("prec", [0, 1])
 @pytest.mark.parametrize("mode", [1, 2])
 def test_fused_sweep_matches_two_phase(F, p, n, prec, mode):
