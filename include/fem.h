@@ -248,6 +248,10 @@ fem_status fem_server_step(fem_server* S, int* n_active, int* n_queued, int* n_d
 fem_status fem_server_poll(fem_server* S, uint64_t ticket, double* u_glob, fem_solve_info* info);
 /* Device bytes currently held by admitted solves, and the high-water mark. */
 fem_status fem_server_memory(fem_server* S, size_t* in_use, size_t* high_water);
+/* Tickets whose solves have finished and are not collected yet, in
+ * ascending order: writes at most max_tickets into out (may be NULL to
+ * count) and returns how many there are. */
+int fem_server_finished(fem_server* S, uint64_t* out, int max_tickets);
 
 /* ------------------------------------------------------- host utilities */
 

@@ -76,12 +76,18 @@ extern "C" size_t fem_prec_bytes(int prec) { return prec_bytes(prec); }
 
 extern "C" size_t fem_footprint_bytes(const fem_desc* d, int smoother_prec) {
     if (check_desc(d) != FEM_OK) return 0;
-    // the solve also holds b and u (FP64)
-    return workspace_bytes(d) + solve_vector_bytes(d, smoother_prec) + align256(2 * 8 * desc_cell_len(d));
+    // workspace, then u, b, r, p, q (FP64) and z, rs (smoother precision):
+    // exactly the block the solve server carves for a request
+    const size_t len = desc_cell_len(d);
+    return workspace_bytes(d) + 5 * align256(8 * len) + 2 * align256(prec_bytes(smoother_prec) * len);
 }
 
 static void free_problem(fem_problem* P) {
     if (!P) return;
+    if (P->external_mem) {
+        delete P;
+        return;
+    }
     hipFree(P->d_h);
     hipFree(P->d_fd64);
     hipFree(P->d_fd32);
@@ -95,7 +101,12 @@ static void free_problem(fem_problem* P) {
 }
 
 namespace fem {
-fem_status create_problem(const fem_desc* d, hipStream_t stream, fem_problem** out) {
+size_t problem_stage_bytes(const fem_desc* d) {
+    return align256(sizeof(double) * (d->n[0] + d->n[1] + d->n[2])) + align256(sizeof(double) * 3 * fd_stride(d)) +
+           align256(sizeof(float) * 3 * fd_stride(d));
+}
+
+fem_status create_problem(const fem_desc* d, hipStream_t stream, fem_problem** out, const ProblemMem* mem) {
     if (!out) return set_error(FEM_EINVAL, "out is NULL");
     *out = nullptr;
     fem_status st = check_desc(d);
@@ -140,6 +151,44 @@ fem_status create_problem(const fem_desc* d, hipStream_t stream, fem_problem** o
     for (size_t i = 0; i < fd.size(); ++i) fd32[i] = (float)fd[i];
 
     hipError_t e;
+    if (mem) {
+        // carve the workspace from the caller's block, in workspace_bytes order
+        if (mem->dev_bytes < workspace_bytes(d) || mem->stage_bytes < problem_stage_bytes(d)) {
+            free_problem(P);
+            return set_error(FEM_EINVAL, "create_problem: caller memory too small");
+        }
+        P->external_mem = true;
+        size_t off = 0;
+        auto take = [&](size_t bytes) {
+            char* q = mem->dev + off;
+            off += align256(bytes);
+            return q;
+        };
+        P->d_h = reinterpret_cast<double*>(take(sizeof(double) * h.size()));
+        P->d_fd64 = reinterpret_cast<double*>(take(sizeof(double) * fd.size()));
+        P->d_fd32 = reinterpret_cast<float*>(take(sizeof(float) * fd32.size()));
+        P->d_red = reinterpret_cast<double*>(take(sizeof(double) * kRedStride));
+        P->d_patch = take(sizeof(double) * std::max<size_t>(P->patch_len, 1));
+        P->d_tmp = take(sizeof(double) * P->cell_len);
+        P->d_glob = take(sizeof(double) * P->global_len);
+        char* hs = mem->stage;
+        std::memcpy(hs, h.data(), sizeof(double) * h.size());
+        char* hf = hs + align256(sizeof(double) * h.size());
+        std::memcpy(hf, fd.data(), sizeof(double) * fd.size());
+        char* hf32 = hf + align256(sizeof(double) * fd.size());
+        std::memcpy(hf32, fd32.data(), sizeof(float) * fd32.size());
+        e = hipMemcpyAsync(P->d_h, hs, sizeof(double) * h.size(), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(P->d_fd64, hf, sizeof(double) * fd.size(), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(P->d_fd32, hf32, sizeof(float) * fd32.size(), hipMemcpyHostToDevice, stream);
+        if (e != hipSuccess) {
+            free_problem(P);
+            return hip_error(e, "create_problem upload");
+        }
+        *out = P;
+        return FEM_OK;
+    }
 #define ALLOC(ptr, bytes)                                                    \
     e = hipMalloc((void**)&(ptr), (bytes));                                  \
     if (e != hipSuccess) {                                                   \
@@ -175,7 +224,7 @@ fem_status create_problem(const fem_desc* d, hipStream_t stream, fem_problem** o
 }  // namespace fem
 
 extern "C" fem_status fem_problem_create(const fem_desc* d, void* stream, fem_problem** out) {
-    return create_problem(d, static_cast<hipStream_t>(stream), out);
+    return create_problem(d, static_cast<hipStream_t>(stream), out, nullptr);
 }
 
 extern "C" fem_status fem_problem_destroy(fem_problem* P) {

@@ -12,6 +12,7 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <new>
 #include <unordered_map>
 #include <vector>
@@ -21,10 +22,6 @@
 #include "launch.h"
 
 using namespace fem;
-
-namespace fem {
-fem_status create_problem(const fem_desc* d, hipStream_t stream, fem_problem** out);
-}
 
 static void destroy_problem_internal(fem_problem* P) {
     if (!P) return;
@@ -254,7 +251,9 @@ struct Request {
 struct Active {
     Request req;
     fem_problem* P = nullptr;
-    char* mem = nullptr;
+    char* mem = nullptr;        // solve vectors, after the problem workspace in the block
+    size_t block_off = 0;       // the solve's block in the server arena
+    size_t block_bytes = 0;
     double *u = nullptr, *b = nullptr, *r = nullptr, *p = nullptr, *q = nullptr;
     void* z = nullptr;
     void* rs = nullptr;
@@ -285,7 +284,72 @@ struct fem_server {
     TableStager st;
     double* d_collect = nullptr;
     double* h_collect = nullptr;
+    // device arena (one allocation of the budget) with a first-fit free list
+    // of (offset -> bytes), coalesced on release
+    char* arena = nullptr;
+    std::map<size_t, size_t> free_blocks;
+    // pinned staging for uploads at admission and downloads at retirement;
+    // a bump region reset at the start of every step (the previous step ended
+    // with a stream synchronisation, so nothing still reads it)
+    char* stage = nullptr;
+    size_t stage_cap = 0, stage_used = 0;
+    // solves whose solutions are being copied out (event ev_retire)
+    std::vector<Active*> retiring;
+    std::vector<char*> retiring_at;
+    hipEvent_t ev_retire = nullptr, ev_scalars = nullptr;
 };
+
+static bool arena_alloc(fem_server* S, size_t bytes, size_t* off) {
+    for (auto it = S->free_blocks.begin(); it != S->free_blocks.end(); ++it) {
+        if (it->second < bytes) continue;
+        *off = it->first;
+        const size_t rest = it->second - bytes;
+        const size_t at = it->first + bytes;
+        S->free_blocks.erase(it);
+        if (rest) S->free_blocks[at] = rest;
+        return true;
+    }
+    return false;
+}
+
+static void arena_free(fem_server* S, size_t off, size_t bytes) {
+    auto it = S->free_blocks.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != S->free_blocks.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        S->free_blocks.erase(nx);
+    }
+    if (it != S->free_blocks.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            S->free_blocks.erase(it);
+        }
+    }
+}
+
+// Reserve pinned staging bytes for this step; grows the staging (after a
+// stream synchronisation, so no copy still reads the old one).
+static char* stage_take(fem_server* S, size_t bytes) {
+    bytes = align256(bytes);
+    if (S->stage_used + bytes > S->stage_cap) {
+        if (S->stage_used > 0) return nullptr;          // caller retries next step
+        if (hipStreamSynchronize(S->stream) != hipSuccess) return nullptr;
+        if (S->stage) hipHostFree(S->stage);
+        S->stage = nullptr;
+        S->stage_cap = 0;
+        size_t cap = std::max<size_t>(bytes, 64u << 20);
+        if (hipHostMalloc((void**)&S->stage, cap, hipHostMallocDefault) != hipSuccess) return nullptr;
+        S->stage_cap = cap;
+    }
+    char* q = S->stage + S->stage_used;
+    S->stage_used += bytes;
+    return q;
+}
+
+// Bytes of one solve's block: problem workspace, then u, b, r, p, q (FP64)
+// and z, rs (smoother precision).
+static size_t solve_block_bytes(const fem_desc* d, int sp) { return fem_footprint_bytes(d, sp); }
 
 extern "C" fem_status fem_server_create(size_t hbm_budget, int max_active, int smoother_prec, int sweeps,
                                         double omega, void* stream, fem_server** out) {
@@ -304,21 +368,28 @@ extern "C" fem_status fem_server_create(size_t hbm_budget, int max_active, int s
     S->stream = static_cast<hipStream_t>(stream);
     if (S->st.init(2 * max_active) != hipSuccess ||
         hipMalloc((void**)&S->d_collect, sizeof(double) * 4 * max_active) != hipSuccess ||
-        hipHostMalloc((void**)&S->h_collect, sizeof(double) * 4 * max_active, hipHostMallocDefault) != hipSuccess) {
+        hipHostMalloc((void**)&S->h_collect, sizeof(double) * 4 * max_active, hipHostMallocDefault) != hipSuccess ||
+        hipMalloc((void**)&S->arena, hbm_budget) != hipSuccess ||
+        hipEventCreateWithFlags(&S->ev_retire, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&S->ev_scalars, hipEventDisableTiming) != hipSuccess) {
         S->st.destroy();
         hipFree(S->d_collect);
         if (S->h_collect) hipHostFree(S->h_collect);
+        if (S->arena) hipFree(S->arena);
+        if (S->ev_retire) hipEventDestroy(S->ev_retire);
+        if (S->ev_scalars) hipEventDestroy(S->ev_scalars);
         delete S;
         return set_error(FEM_ENOMEM, "fem_server_create: allocation failed");
     }
+    S->free_blocks[0] = hbm_budget;
     *out = S;
     return FEM_OK;
 }
 
 static void release_active(fem_server* S, Active* A) {
-    hipFree(A->mem);
     destroy_problem_internal(A->P);
-    S->in_use -= A->req.footprint;
+    arena_free(S, A->block_off, A->block_bytes);
+    S->in_use -= A->block_bytes;
     delete A;
 }
 
@@ -329,6 +400,11 @@ extern "C" fem_status fem_server_destroy(fem_server* S) {
     S->st.destroy();
     hipFree(S->d_collect);
     hipHostFree(S->h_collect);
+    for (Active* A : S->retiring) release_active(S, A);
+    hipFree(S->arena);
+    if (S->stage) hipHostFree(S->stage);
+    hipEventDestroy(S->ev_retire);
+    hipEventDestroy(S->ev_scalars);
     delete S;
     return FEM_OK;
 }
@@ -361,17 +437,36 @@ extern "C" fem_status fem_server_submit(fem_server* S, const fem_desc* desc, con
     return FEM_OK;
 }
 
-// Admission: allocate the solve's vectors, form b = P_I M f, and run the
-// iteration's start (r = b, z = P(r), p = z, <r,z>) with single-problem
-// launches on the server stream.
-static fem_status admit(fem_server* S, Request&& R) {
+// Admission: carve the solve's block from the arena, form b = P_I M f, and
+// run the iteration's start (r = b, z = P(r), p = z, <r,z>) with
+// single-problem launches on the server stream.  Returns FEM_EAGAIN (and
+// leaves R untouched) when the arena has no free block of the size yet or
+// this step's pinned staging is used up.
+static fem_status admit(fem_server* S, Request& R) {
+    fem_desc d = R.desc;
+    for (int k = 0; k < 3; ++k) d.widths[k] = R.widths[k].empty() ? nullptr : R.widths[k].data();
+    const size_t need = solve_block_bytes(&d, S->sp);
+    size_t off = 0;
+    if (S->in_use + need > S->budget || !arena_alloc(S, need, &off)) return FEM_EAGAIN;
+    char* hs = stage_take(S, problem_stage_bytes(&d) + sizeof(double) * R.f.size());
+    if (!hs) {
+        arena_free(S, off, need);
+        return FEM_EAGAIN;
+    }
     Active* A = new (std::nothrow) Active();
-    if (!A) return set_error(FEM_ENOMEM, "host allocation failed");
+    if (!A) {
+        arena_free(S, off, need);
+        return set_error(FEM_ENOMEM, "host allocation failed");
+    }
     A->req = std::move(R);
-    fem_desc d = A->req.desc;
+    A->block_off = off;
+    A->block_bytes = need;
     for (int k = 0; k < 3; ++k) d.widths[k] = A->req.widths[k].empty() ? nullptr : A->req.widths[k].data();
-    fem_status st = create_problem(&d, S->stream, &A->P);
+    const size_t wsb = workspace_bytes(&d);
+    ProblemMem pm{S->arena + off, wsb, hs, problem_stage_bytes(&d)};
+    fem_status st = create_problem(&d, S->stream, &A->P, &pm);
     if (st != FEM_OK) {
+        arena_free(S, off, need);
         delete A;
         return st;
     }
@@ -379,11 +474,7 @@ static fem_status admit(fem_server* S, Request&& R) {
     fem_problem* P = A->P;
     const size_t len = P->cell_len;
     const size_t v64 = align256(8 * len), vs = align256(pbytes(S->sp) * len);
-    if (hipMalloc((void**)&A->mem, 5 * v64 + 2 * vs) != hipSuccess) {
-        destroy_problem_internal(P);
-        delete A;
-        return set_error(FEM_ENOMEM, "server admission: device allocation failed");
-    }
+    A->mem = S->arena + off + wsb;
     A->u = reinterpret_cast<double*>(A->mem);
     A->b = reinterpret_cast<double*>(A->mem + v64);
     A->r = reinterpret_cast<double*>(A->mem + 2 * v64);
@@ -391,14 +482,17 @@ static fem_status admit(fem_server* S, Request&& R) {
     A->q = reinterpret_cast<double*>(A->mem + 4 * v64);
     A->z = A->mem + 5 * v64;
     A->rs = S->sp == FEM_F64 ? (void*)A->r : (void*)(A->mem + 5 * v64 + vs);
-    S->in_use += A->req.footprint;
+    S->in_use += need;
     S->high_water = std::max(S->high_water, S->in_use);
     A->req.t_admit = std::chrono::steady_clock::now();
+    char* hf = hs + align256(problem_stage_bytes(&d));
+    std::memcpy(hf, A->req.f.data(), sizeof(double) * A->req.f.size());
+    A->req.f.clear();
+    A->req.f.shrink_to_fit();
 
     hipStream_t s = S->stream;
     // f (global) staged in q, gathered into p, b = P_I M f
-    FEM_HIP(hipMemcpyAsync(A->q, A->req.f.data(), sizeof(double) * A->req.f.size(), hipMemcpyHostToDevice, s),
-            "server upload");
+    FEM_HIP(hipMemcpyAsync(A->q, hf, sizeof(double) * P->global_len, hipMemcpyHostToDevice, s), "server upload");
     FEM_HIP(run_gather(P, A->q, A->p, FEM_F64), "server gather");
     {
         ProbEntry e = entry_of(P);
@@ -419,34 +513,71 @@ static fem_status admit(fem_server* S, Request&& R) {
     return FEM_OK;
 }
 
-static fem_status retire(fem_server* S, Active* A) {
-    fem_problem* P = A->P;
-    Done D;
-    D.u.resize(P->global_len);
-    // u (FP64) to global order, staged in q
-    FEM_HIP(run_extract(P, A->u, A->q, FEM_F64), "server extract");
-    FEM_HIP(hipMemcpyAsync(D.u.data(), A->q, sizeof(double) * P->global_len, hipMemcpyDeviceToHost, S->stream),
-            "server download");
-    FEM_HIP(hipStreamSynchronize(S->stream), "server download");
-    D.info.iters = A->iters;
-    D.info.status = A->status;
-    D.info.relres = A->relres;
-    D.info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - A->req.t_admit).count();
-    S->done[A->req.ticket] = std::move(D);
-    S->state[A->req.ticket] = 2;
-    release_active(S, A);
+// Retire finished solves in two halves.  start: every solution goes to
+// global order and into the pinned staging with asynchronous copies, and an
+// event marks their end; finish (next step, or destroy): wait for the event,
+// hand the solutions to the host and free the solves' arena blocks.
+static fem_status retire_finish(fem_server* S) {
+    if (S->retiring.empty()) return FEM_OK;
+    FEM_HIP(hipEventSynchronize(S->ev_retire), "server retire");
+    for (size_t i = 0; i < S->retiring.size(); ++i) {
+        Active* A = S->retiring[i];
+        Done D;
+        const double* src = reinterpret_cast<const double*>(S->retiring_at[i]);
+        D.u.assign(src, src + A->P->global_len);
+        D.info.iters = A->iters;
+        D.info.status = A->status;
+        D.info.relres = A->relres;
+        D.info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - A->req.t_admit).count();
+        S->done[A->req.ticket] = std::move(D);
+        S->state[A->req.ticket] = 2;
+        release_active(S, A);
+    }
+    S->retiring.clear();
+    S->retiring_at.clear();
+    return FEM_OK;
+}
+
+static fem_status retire_start(fem_server* S, std::vector<Active*>& fin) {
+    if (fin.empty()) return FEM_OK;
+    size_t bytes = 0;
+    for (Active* A : fin) bytes += align256(sizeof(double) * A->P->global_len);
+    char* hs = stage_take(S, bytes);
+    if (!hs) {
+        // this step's staging is taken by admissions: let their copies finish
+        FEM_HIP(hipStreamSynchronize(S->stream), "server retire");
+        S->stage_used = 0;
+        hs = stage_take(S, bytes);
+        if (!hs) return set_error(FEM_ENOMEM, "server retire: pinned staging allocation failed");
+    }
+    char* q = hs;
+    for (Active* A : fin) {
+        fem_problem* P = A->P;
+        S->retiring.push_back(A);
+        S->retiring_at.push_back(q);
+        // u (FP64) to global order, staged in q
+        FEM_HIP(run_extract(P, A->u, A->q, FEM_F64), "server extract");
+        FEM_HIP(hipMemcpyAsync(q, A->q, sizeof(double) * P->global_len, hipMemcpyDeviceToHost, S->stream),
+                "server download");
+        q += align256(sizeof(double) * P->global_len);
+    }
+    FEM_HIP(hipEventRecord(S->ev_retire, S->stream), "server retire");
     return FEM_OK;
 }
 
 extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queued, int* n_done) {
     if (!S) return set_error(FEM_EINVAL, "fem_server_step: NULL server");
+    // 0. solutions copied out by the previous step reach the host; after
+    //    that wait nothing on the stream reads the pinned staging any more
+    fem_status st0 = retire_finish(S);
+    if (st0 != FEM_OK) return st0;
     // 1. admission in arrival order
-    while (!S->queue.empty() && (int)S->active.size() < S->max_active &&
-           S->in_use + S->queue.front().footprint <= S->budget) {
-        Request R = std::move(S->queue.front());
-        S->queue.pop_front();
-        fem_status st = admit(S, std::move(R));
+    S->stage_used = 0;
+    while (!S->queue.empty() && (int)S->active.size() < S->max_active) {
+        fem_status st = admit(S, S->queue.front());
+        if (st == FEM_EAGAIN) break;
         if (st != FEM_OK) return st;
+        S->queue.pop_front();
     }
     hipStream_t s = S->stream;
     const int na = (int)S->active.size();
@@ -493,7 +624,9 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
             if (S->sp == FEM_F64) FEM_HIP(launch_anorm(p, ents.data(), n, &S->st, s, kSlotRN), "server norm");
             else FEM_HIP(launch_distribute(p, S->sp, ents.data(), n, &S->st, s, kSlotRN), "server norm");
         }
-        // 3. one read-back of every solve's scalars
+        // 3. one read-back of every solve's scalars, waited for only after the
+        //    smoother of this iteration is queued (a solve that has just
+        //    converged runs it once more in vain; its u is final already)
         ents.resize(na);
         for (int i = 0; i < na; ++i) ents[i] = entry_of(S->active[i]->P);
         FEM_HIP(launch_collect_slots(ents.data(), na, &S->st, s, kSlotRN, kSlotQP, S->d_collect), "server collect");
@@ -501,23 +634,7 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
                 "server collect");
         FEM_HIP(hipMemcpyAsync(S->h_collect, S->d_collect, sizeof(double) * 4 * na, hipMemcpyDeviceToHost, s),
                 "server read-back");
-        FEM_HIP(hipStreamSynchronize(s), "server read-back");
-        for (int i = 0; i < na; ++i) {
-            Active* A = S->active[i];
-            const double rn = S->h_collect[2 * i], qp = S->h_collect[2 * i + 1], b2 = S->h_collect[2 * na + 2 * i];
-            A->iters += 1;
-            A->relres = b2 > 0 ? std::sqrt(rn / b2) : 0.0;
-            if (!(qp > 0) || !std::isfinite(qp) || !std::isfinite(A->relres)) {
-                A->finished = true;
-                A->status = FEM_EBREAKDOWN;
-            } else if (A->relres <= A->req.rtol) {
-                A->finished = true;
-                A->status = FEM_OK;
-            } else if (A->iters >= A->req.maxit) {
-                A->finished = true;
-                A->status = FEM_ENOTCONV;
-            }
-        }
+        FEM_HIP(hipEventRecord(S->ev_scalars, s), "server read-back");
         // 4. smoother, pairings and the new direction for the unfinished solves
         for (int p = 1; p <= kMaxP; ++p) {
             std::vector<Active*> g = group_of(p);
@@ -561,17 +678,29 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
             }
             FEM_HIP(launch_cg_p(S->sp, S->variant, ents.data(), n, &S->st, s), "server direction");
         }
-        // 5. retire finished solves (frees their memory for the next admissions)
-        std::vector<Active*> keep;
-        for (Active* A : S->active) {
-            if (A->finished) {
-                fem_status st = retire(S, A);
-                if (st != FEM_OK) return st;
-            } else {
-                keep.push_back(A);
+        FEM_HIP(hipEventSynchronize(S->ev_scalars), "server read-back");
+        for (int i = 0; i < na; ++i) {
+            Active* A = S->active[i];
+            const double rn = S->h_collect[2 * i], qp = S->h_collect[2 * i + 1], b2 = S->h_collect[2 * na + 2 * i];
+            A->iters += 1;
+            A->relres = b2 > 0 ? std::sqrt(rn / b2) : 0.0;
+            if (!(qp > 0) || !std::isfinite(qp) || !std::isfinite(A->relres)) {
+                A->finished = true;
+                A->status = FEM_EBREAKDOWN;
+            } else if (A->relres <= A->req.rtol) {
+                A->finished = true;
+                A->status = FEM_OK;
+            } else if (A->iters >= A->req.maxit) {
+                A->finished = true;
+                A->status = FEM_ENOTCONV;
             }
         }
+        // 5. retire finished solves (frees their memory for the next admissions)
+        std::vector<Active*> keep, fin;
+        for (Active* A : S->active) (A->finished ? fin : keep).push_back(A);
         S->active.swap(keep);
+        fem_status st = retire_start(S, fin);
+        if (st != FEM_OK) return st;
     }
     if (n_active) *n_active = (int)S->active.size();
     if (n_queued) *n_queued = (int)S->queue.size();
@@ -590,6 +719,17 @@ extern "C" fem_status fem_server_poll(fem_server* S, uint64_t ticket, double* u_
     S->done.erase(ticket);
     S->state.erase(it);
     return FEM_OK;
+}
+
+extern "C" int fem_server_finished(fem_server* S, uint64_t* out, int max_tickets) {
+    if (!S) return 0;
+    std::vector<uint64_t> t;
+    t.reserve(S->done.size());
+    for (const auto& kv : S->done) t.push_back(kv.first);
+    std::sort(t.begin(), t.end());
+    if (out)
+        for (int i = 0; i < (int)t.size() && i < max_tickets; ++i) out[i] = t[i];
+    return (int)t.size();
 }
 
 extern "C" fem_status fem_server_memory(fem_server* S, size_t* in_use, size_t* high_water) {

@@ -164,5 +164,18 @@ struct fem_problem {
     void* d_glob;          // assembled residual in global-node order (FP64 size; p >= 4 patch solves)
     void* d_solve;         // pcg_solve vectors, allocated on first use
     size_t solve_bytes;
-    double* h_red;         // pinned host mirror of the scalar slots
+    double* h_red;         // pinned host mirror of the scalar slots (null for arena problems)
+    bool external_mem;     // buffers carved from caller memory (freed with it)
+};
+
+// Caller-provided memory for a problem (the solve server's arena): device
+// bytes for the workspace (at least workspace_bytes) and pinned host bytes
+// (at least problem_stage_bytes) from which the set-up data is uploaded
+// asynchronously; the caller keeps the staging alive until the stream has
+// passed the uploads.
+struct ProblemMem {
+    char* dev;
+    size_t dev_bytes;
+    char* stage;
+    size_t stage_bytes;
 };

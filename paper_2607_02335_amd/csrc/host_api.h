@@ -25,6 +25,11 @@ size_t workspace_bytes(const fem_desc* d);
 // Bytes of pcg_solve's own vectors for a smoother precision.
 size_t solve_vector_bytes(const fem_desc* d, int smoother_prec);
 size_t desc_cell_len(const fem_desc* d);
+// Create a problem; with mem, its workspace is carved from caller memory and
+// its set-up data uploaded asynchronously from the caller's pinned staging.
+fem_status create_problem(const fem_desc* d, hipStream_t stream, fem_problem** out, const ProblemMem* mem = nullptr);
+// Pinned staging bytes create_problem needs with caller memory.
+size_t problem_stage_bytes(const fem_desc* d);
 
 // Solver pieces reused by the server (all asynchronous on P->stream).
 fem_status smoother_run(fem_problem* P, const void* r, void* z, int prec, int sweeps, double omega);

@@ -396,16 +396,20 @@ ProbEntry entry_of(const fem_problem* P) {
     e.h[1] = P->d_h + P->n[0];
     e.h[2] = P->d_h + P->n[0] + P->n[1];
     e.red = P->d_red;
-    // about 1024 tiles (4 wavefronts each) where the problem is large enough
-    constexpr int kTarget = 1024;
+    // tiles of about 8192 elements (a few per thread of a 256-thread
+    // workgroup), at most kRedParts; fixed by the problem's own sizes
+    constexpr size_t kTileElems = 8192;
     const int nn = (P->p + 1) * (P->p + 1) * (P->p + 1);
-    if (P->nblk >= kTarget) {
-        e.blocks_per_red = (P->nblk + kRedParts - 1) / kRedParts;
+    size_t want = (P->cell_len + kTileElems - 1) / kTileElems;
+    if (want < 1) want = 1;
+    if (want > (size_t)kRedParts) want = kRedParts;
+    if ((int)want <= P->nblk) {
+        e.blocks_per_red = (int)((P->nblk + want - 1) / want);
         e.red_lsplit = 1;
         e.ntiles_red = (P->nblk + e.blocks_per_red - 1) / e.blocks_per_red;
     } else {
         e.blocks_per_red = 1;
-        int split = (kTarget + P->nblk - 1) / P->nblk;
+        int split = (int)((want + P->nblk - 1) / P->nblk);
         if (split > (nn + 3) / 4) split = (nn + 3) / 4;        // at least 4 node planes per tile
         if (split < 1) split = 1;
         const int lchunk = (nn + split - 1) / split;

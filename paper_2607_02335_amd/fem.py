@@ -89,6 +89,7 @@ def lib():
         "fem_server_step": ([vp, ct.POINTER(i), ct.POINTER(i), ct.POINTER(i)], i),
         "fem_server_poll": ([vp, ct.c_uint64, vp, ct.POINTER(SolveInfo)], i),
         "fem_server_memory": ([vp, ct.POINTER(sz), ct.POINTER(sz)], i),
+        "fem_server_finished": ([vp, ct.POINTER(ct.c_uint64), i], i),
         "fem_host_1d_matrices": ([i, vp, vp], i),
         "fem_host_fd_1d": ([i, d, d, vp, vp], i),
         "fem_host_gll_nodes": ([i, vp], i),
@@ -480,6 +481,16 @@ class Server:
         check(st, "fem_server_poll")
         self.glen.pop(ticket, None)
         return u, dict(iters=info.iters, status=info.status, relres=info.relres, seconds=info.seconds)
+
+    def finished(self):
+        """Tickets of finished, not yet collected solves (ascending)."""
+        L = lib()
+        n = L.fem_server_finished(self.h, None, 0)
+        if n <= 0:
+            return []
+        out = (ct.c_uint64 * n)()
+        n = min(n, L.fem_server_finished(self.h, out, n))
+        return [int(out[k]) for k in range(n)]
 
     def memory(self):
         a, b = ct.c_size_t(), ct.c_size_t()

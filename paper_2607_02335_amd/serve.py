@@ -39,7 +39,7 @@ def run_stream(requests, hbm_budget=64 << 30, max_active=256, smoother_prec=fem.
         steps += 1
         peak_active = max(peak_active, a)
         tnow = time.perf_counter() - t0
-        for tk in list(pending):
+        for tk in (S.finished() if d else []):
             res = S.poll(tk, want_u=False)
             if res is None:
                 continue

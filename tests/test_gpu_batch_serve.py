@@ -123,8 +123,11 @@ def test_server_admission_by_memory(F):
         max_active = max(max_active, a)
         in_use, hw = S.memory()
         assert in_use <= budget
+        fin = S.finished()
+        assert fin == sorted(fin) and set(fin) <= pending
         for t in list(pending):
             r = S.poll(t, want_u=False)
+            assert (r is not None) == (t in fin)
             if r is not None:
                 assert r[1]["status"] == 0
                 pending.discard(t)
