@@ -214,11 +214,15 @@ fem_status fem_batch_apply(fem_batch* B, void* const* x, void* const* y, int pre
 /* z[i] = P_AS r[i] for every problem i. */
 fem_status fem_batch_patch_inverse(fem_batch* B, void* const* r, void* const* z, int prec);
 /* Tile-shape autotuner: for each degree present in the batch, time the
- * candidate kernel shapes on the batch's own problems (apply: register or
- * LDS kernel x persistent grid cap; patch inverse: two-phase or fused sweep
- * x grid cap) and keep the fastest for later batched calls.  choice (may be
- * NULL): int[14], choice[2(p-1)] = apply candidate, choice[2(p-1)+1] =
- * patch-inverse candidate of degree p (untouched for absent degrees).
+ * candidate kernel shapes on the batch's own problems (apply: register
+ * (p <= 3) or plane-streamed (p >= 4) kernel, or the LDS line kernel, each x
+ * two persistent grid caps; patch inverse for p <= 3: two launches through
+ * the patch buffer, fused sweep from the cell copies, or fused sweep from
+ * the assembled residual; for p >= 4: MFMA or line patch solves; each x two
+ * grid caps) and keep the fastest for later batched calls.  choice (may be
+ * NULL): int[14], choice[2(p-1)] = apply candidate index, choice[2(p-1)+1]
+ * = patch-inverse candidate index of degree p, candidates in the order
+ * listed with the grid cap varying fastest (untouched for absent degrees).
  * Synchronises the stream; allocates and frees its own scratch vectors. */
 fem_status fem_batch_autotune(fem_batch* B, int prec, int* choice);
 

@@ -177,10 +177,15 @@ extern "C" fem_status fem_batch_autotune(fem_batch* B, int prec, int* choice) {
     for (int p = 1; p <= kMaxP && result == FEM_OK; ++p) {
         if (B->group[p].empty()) continue;
         for (int which = 0; which < 2 && result == FEM_OK; ++which) {
+            // apply: 0 = register (p <= 3) / plane-streamed (p >= 4) kernel,
+            //        1 = LDS line kernel;
+            // patch inverse, p <= 3: 0 = two launches through the patch buffer,
+            //        1 = fused sweep summing cell copies, 2 = fused sweep from the
+            //        assembled residual; p >= 4: 0 = MFMA solves, 2 = line solves
+            std::vector<int> kinds = which == 0 ? std::vector<int>{0, 1}
+                                   : (p <= 3 ? std::vector<int>{0, 1, 2} : std::vector<int>{0, 2});
             std::vector<LaunchCfg> cand;
-            for (int kind = 0; kind < 2; ++kind) {
-                if (which == 0 && kind == 1 && p > 3) continue;      // above p = 3 the LDS kernel is the only one
-                if (which == 1 && kind == 1 && p > 3) continue;      // no fused sweep above p = 3
+            for (int kind : kinds) {
                 for (int c : caps) {
                     LaunchCfg cfg;
                     cfg.grid_cap = c;
