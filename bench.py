@@ -63,24 +63,24 @@ class Timer:
         return s.elapsed_time(e) / reps * 1e-3      # seconds per call
 
 
-def setup(fem, torch, p, n, seed, rotate_bytes=768 << 20):
-    """Problem plus enough (x, y, z) FP64 sets to exceed the Infinity Cache."""
+def setup(fem, torch, p, n, seed, prec=0, rotate_bytes=768 << 20):
+    """Problem plus enough (x, y, z) sets to exceed the Infinity Cache."""
     import synth
     wl = synth._graded(f"q{p}_{n}", p, n, seed)
     P = fem.Problem(p, n, wl.widths)
     xg = torch.as_tensor(wl.x, device="cuda")
-    x0 = P.gather(xg)
-    per_set = 3 * P.cell_len * 8
+    x0 = P.gather(xg, prec)
+    per_set = 3 * P.cell_len * fem.lib().fem_prec_bytes(prec)
     nsets = max(1, min(6, -(-rotate_bytes // per_set)))
     sets = []
     for _ in range(nsets):
-        sets.append((x0.clone(), P.cell_vector(fem.F64), P.cell_vector(fem.F64)))
+        sets.append((x0.clone(), P.cell_vector(prec), P.cell_vector(prec)))
     torch.cuda.synchronize()
     return P, sets, wl
 
 
-def measure_workload(fem, torch, p, n, seed, steps, warmup):
-    P, sets, wl = setup(fem, torch, p, n, seed)
+def measure_workload(fem, torch, p, n, seed, steps, warmup, prec=0):
+    P, sets, wl = setup(fem, torch, p, n, seed, prec)
     ns = len(sets)
 
     def step(i):
@@ -117,12 +117,14 @@ def measure_workload(fem, torch, p, n, seed, steps, warmup):
     fem.trace_enable(False)
     u = unique_dofs(p, n)
     c = cell_dofs(p, n)
-    res = dict(p=p, n=n, unique_dofs=u, cell_dofs=c, s_per_step=wall, kernels=kernels,
+    es = {0: 8, 1: 4, 2: 2}[prec]
+    cs = 8 if prec == 0 else 4
+    res = dict(p=p, n=n, unique_dofs=u, cell_dofs=c, s_per_step=wall, kernels=kernels, esize=es, csize=cs,
                apply_s=t_apply, pi_s=t_pi,
                apply_unique_gdofs=u / t_apply / 1e9, pi_unique_gdofs=u / t_pi / 1e9,
                apply_cell_gdofs=c / t_apply / 1e9, pi_cell_gdofs=c / t_pi / 1e9,
                step_unique_gdofs=u / wall / 1e9,
-               apply_gbs=16 * c / t_apply / 1e9, pi_gbs=16 * c / t_pi / 1e9)
+               apply_gbs=2 * es * c / t_apply / 1e9, pi_gbs=2 * es * c / t_pi / 1e9)
     res["roofline_by_kernel"] = kernel_table(res)
     del sets
     P.close()
@@ -130,15 +132,16 @@ def measure_workload(fem, torch, p, n, seed, steps, warmup):
     return res
 
 
-def kernel_bytes(label, p, n, esize=8):
+def kernel_bytes(label, p, n, esize=8, csize=8):
     """Algorithmic HBM bytes of one launch of a traced kernel: each array it
-    must read or write, once.  cell = cell-wise vector, uniq = assembled
-    global-node array, patch = patch-result buffer ((2p-1)^3 per patch)."""
+    must read or write, once.  cell = cell-wise vector (storage precision,
+    esize bytes), uniq = assembled global-node array, patch = patch-result
+    buffer ((2p-1)^3 per patch), both in the compute precision (csize)."""
     cell = cell_dofs(p, n) * esize
-    uniq = unique_dofs(p, n) * esize
-    patch = (n - 1) ** 3 * (2 * p - 1) ** 3 * esize
+    uniq = unique_dofs(p, n) * csize
+    patch = (n - 1) ** 3 * (2 * p - 1) ** 3 * csize
     return {"apply": 2 * cell, "pi_assemble": cell + uniq, "pi_solve": uniq + patch,
-            "pi_combine": patch + cell, "pi_sweep": 2 * cell}.get(label)
+            "pi_combine": patch + cell, "pi_sweep": 2 * cell + uniq}.get(label)
 
 
 def kernel_flops(label, p, n):
@@ -176,22 +179,29 @@ def kernel_table(rec):
     p, n = rec["p"], rec["n"]
     out = []
     for k in rec["kernels"]:
-        b = kernel_bytes(k["label"], p, n)
+        b = kernel_bytes(k["label"], p, n, rec.get("esize", 8), rec.get("csize", 8))
         if b is None:
             continue
         gbs = b / (k["avg_us"] * 1e-6) / 1e9
-        out.append({"kernel": k["label"], "avg_us": round(k["avg_us"], 2), "algorithmic_bytes": b,
-                    "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)})
+        row = {"kernel": k["label"], "avg_us": round(k["avg_us"], 2), "algorithmic_bytes": b,
+               "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        fl = kernel_flops(k["label"], p, n)
+        if fl is not None:
+            peak = FP64_PEAK_TFLOPS if rec.get("csize", 8) == 8 else FP32_PEAK_TFLOPS
+            tf = fl / (k["avg_us"] * 1e-6) / 1e12
+            row.update({"algorithmic_flops": fl, "TFLOP/s": round(tf, 2), "flop_frac": round(tf / peak, 4)})
+        out.append(row)
     return out
 
 
 def roofline(rec, workload="q3_64"):
     """Roofline record of the kernel with the largest share of the step."""
     p, n = rec["p"], rec["n"]
-    ks = [k for k in rec["kernels"] if kernel_bytes(k["label"], p, n) is not None]
+    es, cs = rec.get("esize", 8), rec.get("csize", 8)
+    ks = [k for k in rec["kernels"] if kernel_bytes(k["label"], p, n, es, cs) is not None]
     dom = max(ks, key=lambda k: k["total_ms"])
     t = dom["avg_us"] * 1e-6
-    byts = kernel_bytes(dom["label"], p, n)
+    byts = kernel_bytes(dom["label"], p, n, es, cs)
     gbs = byts / t / 1e9
     fl = kernel_flops(dom["label"], p, n)
     out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -314,6 +324,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--solve-reps", type=int, default=5)
     ap.add_argument("--requests", type=int, default=10000, help="serving mode: stream length")
+    ap.add_argument("--prec", choices=["f64", "f32", "bf16"], default="f64",
+                    help="storage precision of --only q2_96 / q7_24")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only (the hot path is single-device; "
@@ -346,7 +358,9 @@ def main():
             rec = batch_times(fem, torch, a.steps, a.warmup)
         else:
             p, n = (2, 96) if a.only == "q2_96" else (7, 24)
-            rec = measure_workload(fem, torch, p, n, 1, a.steps, a.warmup)
+            prec = {"f64": fem.F64, "f32": fem.F32, "bf16": fem.BF16}[a.prec]
+            rec = measure_workload(fem, torch, p, n, 1, a.steps, a.warmup, prec)
+            rec["prec"] = a.prec
         print(json.dumps({a.only: rec}))
         return
     log("headline workload Q3 64^3 graded FP64")

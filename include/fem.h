@@ -256,6 +256,11 @@ fem_status fem_server_memory(fem_server* S, size_t* in_use, size_t* high_water);
  * ascending order: writes at most max_tickets into out (may be NULL to
  * count) and returns how many there are. */
 int fem_server_finished(fem_server* S, uint64_t* out, int max_tickets);
+/* Host-side accounting of fem_server_step (for tuning): out[0..n) receives,
+ * as far as n reaches, the seconds spent in admission, in queuing the
+ * iteration's launches, waiting for the solves' scalars, handing finished
+ * solutions over, starting retirements, and the number of steps. */
+fem_status fem_server_stats(fem_server* S, double* out, int n);
 
 /* ------------------------------------------------------- host utilities */
 
@@ -270,15 +275,18 @@ fem_status fem_host_1d_matrices(int p, double* mass, double* stiff);
 fem_status fem_host_gll_nodes(int p, double* nodes);
 fem_status fem_host_fd_1d(int p, double h0, double h1, double* S, double* lambda);
 
-/* Process-wide tuning switches (for comparisons and the autotuner).
- * FEM_OPT_PI_FUSED = 1 runs patch_inverse for p <= 3 as one fused sweep that
- * keeps patch results on chip; 0 (default) solves patches into a buffer and
- * combines them in a second launch.  FEM_OPT_COMBINE_PER_CELL = 1 makes that
- * second launch use one wavefront per 64-cell block (all node planes)
- * instead of one per (block, plane) for p <= 3.  FEM_OPT_RESTRICT_FROM_CELLS
- * = 1 makes the p <= 3 patch solves sum the residual copies from the cell
- * vector instead of reading the owner-assembled global-node array.  Unknown
- * options are FEM_EINVAL. */
+/* Process-wide kernel-variant switches (for comparisons; the batch
+ * autotuner picks per batch instead).  FEM_OPT_PI_FUSED: patch_inverse for
+ * p <= 3 as 0 (default) two launches through the patch buffer, 1 one fused
+ * sweep summing the residual's cell copies on chip, 2 assembly plus one
+ * fused sweep reading the assembled residual; for p >= 4, 2 selects line
+ * (VALU) patch solves instead of MFMA.  FEM_OPT_COMBINE_PER_CELL = 1 makes
+ * the p <= 3 combine use one wavefront per 64-cell block (all node planes)
+ * instead of one per (block, plane).  FEM_OPT_RESTRICT_FROM_CELLS = 1 makes
+ * the p <= 3 patch solves sum the residual copies from the cell vector
+ * instead of reading the assembled global-node array.  Every variant gives
+ * the same result up to the rounding of the summation order (bitwise
+ * continuous in all cases).  Unknown options or values are FEM_EINVAL. */
 typedef enum fem_option {
     FEM_OPT_PI_FUSED = 1,
     FEM_OPT_COMBINE_PER_CELL = 2,

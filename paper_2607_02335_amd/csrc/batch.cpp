@@ -293,16 +293,37 @@ struct fem_server {
     // of (offset -> bytes), coalesced on release
     char* arena = nullptr;
     std::map<size_t, size_t> free_blocks;
-    // pinned staging for uploads at admission and downloads at retirement;
-    // a bump region reset at the start of every step (the previous step ended
-    // with a stream synchronisation, so nothing still reads it)
+    // pinned staging for uploads at admission and downloads at retirement:
+    // two bump regions used by alternate steps.  A step's region is free again
+    // two steps later: its uploads were consumed before the step's scalar
+    // read-back completed, and its downloads are handed over (retire_finish)
+    // during the next step.
+    char* stage_buf[2] = {nullptr, nullptr};
+    size_t stage_capv[2] = {0, 0};
+    int cur = 0;
     char* stage = nullptr;
     size_t stage_cap = 0, stage_used = 0;
     // solves whose solutions are being copied out (event ev_retire)
     std::vector<Active*> retiring;
     std::vector<char*> retiring_at;
     hipEvent_t ev_retire = nullptr, ev_scalars = nullptr;
+    // host seconds per step phase: admission, launches, waits for the
+    // scalars, retirement hand-over, retirement start; and steps taken
+    double t_phase[5] = {0, 0, 0, 0, 0};
+    long steps = 0;
 };
+
+namespace {
+struct PhaseClock {
+    std::chrono::steady_clock::time_point t = std::chrono::steady_clock::now();
+    double lap() {
+        const auto n = std::chrono::steady_clock::now();
+        const double d = std::chrono::duration<double>(n - t).count();
+        t = n;
+        return d;
+    }
+};
+}  // namespace
 
 static bool arena_alloc(fem_server* S, size_t bytes, size_t* off) {
     for (auto it = S->free_blocks.begin(); it != S->free_blocks.end(); ++it) {
@@ -344,8 +365,14 @@ static char* stage_take(fem_server* S, size_t bytes) {
         S->stage = nullptr;
         S->stage_cap = 0;
         size_t cap = std::max<size_t>(bytes, 64u << 20);
-        if (hipHostMalloc((void**)&S->stage, cap, hipHostMallocDefault) != hipSuccess) return nullptr;
+        if (hipHostMalloc((void**)&S->stage, cap, hipHostMallocDefault) != hipSuccess) {
+            S->stage_buf[S->cur] = nullptr;
+            S->stage_capv[S->cur] = 0;
+            return nullptr;
+        }
         S->stage_cap = cap;
+        S->stage_buf[S->cur] = S->stage;
+        S->stage_capv[S->cur] = cap;
     }
     char* q = S->stage + S->stage_used;
     S->stage_used += bytes;
@@ -407,7 +434,8 @@ extern "C" fem_status fem_server_destroy(fem_server* S) {
     hipHostFree(S->h_collect);
     for (Active* A : S->retiring) release_active(S, A);
     hipFree(S->arena);
-    if (S->stage) hipHostFree(S->stage);
+    for (int k = 0; k < 2; ++k)
+        if (S->stage_buf[k]) hipHostFree(S->stage_buf[k]);
     hipEventDestroy(S->ev_retire);
     hipEventDestroy(S->ev_scalars);
     delete S;
@@ -572,11 +600,12 @@ static fem_status retire_start(fem_server* S, std::vector<Active*>& fin) {
 
 extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queued, int* n_done) {
     if (!S) return set_error(FEM_EINVAL, "fem_server_step: NULL server");
-    // 0. solutions copied out by the previous step reach the host; after
-    //    that wait nothing on the stream reads the pinned staging any more
-    fem_status st0 = retire_finish(S);
-    if (st0 != FEM_OK) return st0;
-    // 1. admission in arrival order
+    PhaseClock clk;
+    S->steps += 1;
+    // 1. admission in arrival order, staged in this step's region
+    S->cur ^= 1;
+    S->stage = S->stage_buf[S->cur];
+    S->stage_cap = S->stage_capv[S->cur];
     S->stage_used = 0;
     while (!S->queue.empty() && (int)S->active.size() < S->max_active) {
         fem_status st = admit(S, S->queue.front());
@@ -586,6 +615,7 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
     }
     hipStream_t s = S->stream;
     const int na = (int)S->active.size();
+    S->t_phase[0] += clk.lap();
     if (na > 0) {
         std::vector<ProbEntry> ents;
         auto group_of = [&](int p) {
@@ -683,7 +713,14 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
             }
             FEM_HIP(launch_cg_p(S->sp, S->variant, ents.data(), n, &S->st, s), "server direction");
         }
+        S->t_phase[1] += clk.lap();
+        // the previous step's retirements reach the host while the GPU runs
+        // this step's work
+        fem_status stf = retire_finish(S);
+        if (stf != FEM_OK) return stf;
+        S->t_phase[3] += clk.lap();
         FEM_HIP(hipEventSynchronize(S->ev_scalars), "server read-back");
+        S->t_phase[2] += clk.lap();
         for (int i = 0; i < na; ++i) {
             Active* A = S->active[i];
             const double rn = S->h_collect[2 * i], qp = S->h_collect[2 * i + 1], b2 = S->h_collect[2 * na + 2 * i];
@@ -706,6 +743,12 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
         S->active.swap(keep);
         fem_status st = retire_start(S, fin);
         if (st != FEM_OK) return st;
+        S->t_phase[4] += clk.lap();
+    }
+    if (na == 0) {
+        // nothing ran this step: hand over the previous step's retirements now
+        fem_status stf = retire_finish(S);
+        if (stf != FEM_OK) return stf;
     }
     if (n_active) *n_active = (int)S->active.size();
     if (n_queued) *n_queued = (int)S->queue.size();
@@ -723,6 +766,14 @@ extern "C" fem_status fem_server_poll(fem_server* S, uint64_t ticket, double* u_
     if (info) *info = D.info;
     S->done.erase(ticket);
     S->state.erase(it);
+    return FEM_OK;
+}
+
+extern "C" fem_status fem_server_stats(fem_server* S, double* out, int n) {
+    if (!S || !out) return set_error(FEM_EINVAL, "fem_server_stats: NULL argument");
+    const double v[6] = {S->t_phase[0], S->t_phase[1], S->t_phase[2], S->t_phase[3], S->t_phase[4],
+                         (double)S->steps};
+    for (int i = 0; i < n && i < 6; ++i) out[i] = v[i];
     return FEM_OK;
 }
 

@@ -18,6 +18,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdint>
+#include <unordered_map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -208,7 +210,47 @@ void host_patch_1d(int p, double h0, double h1, std::vector<double>& M, std::vec
     }
 }
 
+static int host_fd_1d_compute(int p, double h0, double h1, double* S, double* lam);
+
+// The 1D data depend only on (p, h0, h1); uniform meshes and repeated
+// requests reuse them, so results are memoised (bounded, process-wide).
 int host_fd_1d(int p, double h0, double h1, double* S, double* lam) {
+    struct Key {
+        int p;
+        uint64_t a, b;
+        bool operator==(const Key& o) const { return p == o.p && a == o.a && b == o.b; }
+    };
+    struct KeyHash {
+        size_t operator()(const Key& k) const {
+            return std::hash<uint64_t>()(k.a * 0x9E3779B97F4A7C15ull ^ (k.b + (uint64_t)k.p * 0x632BE59BD9B4E019ull));
+        }
+    };
+    static std::mutex mu;
+    static std::unordered_map<Key, std::vector<double>, KeyHash> cache;
+    const int n = 2 * p - 1;
+    Key key{p, 0, 0};
+    std::memcpy(&key.a, &h0, 8);
+    std::memcpy(&key.b, &h1, 8);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            std::memcpy(S, it->second.data(), sizeof(double) * n * n);
+            std::memcpy(lam, it->second.data() + n * n, sizeof(double) * n);
+            return 0;
+        }
+    }
+    const int rc = host_fd_1d_compute(p, h0, h1, S, lam);
+    if (rc != 0) return rc;
+    std::vector<double> v(S, S + n * n);
+    v.insert(v.end(), lam, lam + n);
+    std::lock_guard<std::mutex> lk(mu);
+    if (cache.size() >= 16384) cache.clear();
+    cache.emplace(key, std::move(v));
+    return 0;
+}
+
+static int host_fd_1d_compute(int p, double h0, double h1, double* S, double* lam) {
     const int n = 2 * p - 1;
     std::vector<double> M, K;
     host_patch_1d(p, h0, h1, M, K);
@@ -276,15 +318,16 @@ int host_fd_1d(int p, double h0, double h1, double* S, double* lam) {
 
 using namespace fem;
 
-namespace fem { extern int g_pi_fused; extern int g_combine_per_cell; extern int g_restrict_from_cells; extern int g_assemble_owner; extern int g_pi_xcombine; }
+namespace fem { extern int g_pi_fused; extern int g_combine_per_cell; extern int g_restrict_from_cells; }
 
 extern "C" fem_status fem_set_option(int option, int value) {
     switch (option) {
-        case FEM_OPT_PI_FUSED: fem::g_pi_fused = (value >= 0 && value <= 2) ? value : 0; return FEM_OK;
+        case FEM_OPT_PI_FUSED:
+            if (value < 0 || value > 2) return set_error(FEM_EINVAL, "fem_set_option: FEM_OPT_PI_FUSED is 0, 1 or 2");
+            fem::g_pi_fused = value;
+            return FEM_OK;
         case FEM_OPT_COMBINE_PER_CELL: fem::g_combine_per_cell = value ? 1 : 0; return FEM_OK;
         case FEM_OPT_RESTRICT_FROM_CELLS: fem::g_restrict_from_cells = value ? 1 : 0; return FEM_OK;
-        case 4: fem::g_assemble_owner = value ? 1 : 0; return FEM_OK;
-        case 5: fem::g_pi_xcombine = value ? 1 : 0; return FEM_OK;
         default: return set_error(FEM_EINVAL, "fem_set_option: unknown option");
     }
 }

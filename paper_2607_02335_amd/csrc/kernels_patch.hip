@@ -37,12 +37,6 @@ int g_combine_per_cell = 0;
 // 1: phase 1 of the p <= 3 patch inverse sums the copies from the cell-wise
 // vector itself instead of reading the owner-assembled global-node array.
 int g_restrict_from_cells = 0;
-// 1: assemble the residual with the owner-copy kernel (one thread per cell
-// copy) instead of one wavefront per global node row.
-int g_assemble_owner = 0;
-// 1: the p <= 3 patch solves sum the x-overlap on chip and the combine reads
-// x-combined node rows; 0: full patch results go through the patch buffer.
-int g_pi_xcombine = 0;
 
 template <int P, typename C> constexpr int pi_patches_per_tile() {
     constexpr int nP = 2 * P - 1;
@@ -793,43 +787,6 @@ template <> struct SweepShape<3, double> { static constexpr int TX = 8, TY = 2, 
 template <> struct SweepShape<3, float> { static constexpr int TX = 8, TY = 4, NS = 64; };
 template <> struct SweepShape<3, bf16_t> { static constexpr int TX = 8, TY = 4, NS = 64; };
 
-// Owner-copy assembly: each global node is written once, by its copy in the
-// lowest-numbered cell along every direction, as the sum of all its copies
-// (ascending cell order).  Threads walk the cell-wise vector (coalesced reads
-// of their own copies); pe: a = r (S), e = global-node array (C).
-template <int P, typename S, typename C, bool MULTI>
-__global__ void __launch_bounds__(256) k_assemble_owner(LaunchTable L) {
-    constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
-    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
-        const ProbEntry& pe = entry<MULTI>(L, tile);
-        const int blk = tile - pe.tile_begin;
-        const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
-        const size_t G0 = (size_t)n0 * P + 1, G1 = (size_t)n1 * P + 1;
-        const S* v = static_cast<const S*>(pe.a);
-        C* out = static_cast<C*>(pe.e);
-        for (int idx = threadIdx.x; idx < NN * kLanes; idx += 256) {
-            const int l = idx / kLanes, lane = idx % kLanes;
-            const int e = blk * kLanes + lane;
-            if (e >= pe.ncells) continue;
-            const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
-            const int a = l % N, b = (l / N) % N, c = l / N2;
-            if ((a == P && i < n0 - 1) || (b == P && j < n1 - 1) || (c == P && k < n2 - 1)) continue;
-            const int cx = (a == 0 && i > 0) ? 2 : 1;
-            const int cy = (b == 0 && j > 0) ? 2 : 1;
-            const int cz = (c == 0 && k > 0) ? 2 : 1;
-            double s = 0.0;
-            for (int sz = cz - 1; sz >= 0; --sz)
-                for (int sy = cy - 1; sy >= 0; --sy)
-                    for (int sx = cx - 1; sx >= 0; --sx) {
-                        const int ee = (i - sx) + n0 * ((j - sy) + n1 * (k - sz));
-                        const int ll = (sx ? P : a) + N * ((sy ? P : b) + N * (sz ? P : c));
-                        s += load_as<double>(v + cell_offset(ee, ll, NN));
-                    }
-            out[(size_t)(i * P + a) + G0 * ((size_t)(j * P + b) + G1 * (size_t)(k * P + c))] = (C)s;
-        }
-    }
-}
-
 // Phase 1 for p <= 3 reading the assembled residual: the tile's CBP patches
 // along x cover, for each of their (2p-1)^2 (y, z) rows, one contiguous run
 // of CBP*p + p - 1 global nodes; each node is loaded once (coalesced) and
@@ -1283,242 +1240,6 @@ __global__ void __launch_bounds__(256) k_pi_sweep_g(LaunchTable L) {
     }
 }
 
-// Patch solves with the x-overlap summed on chip (p <= 3).  A workgroup
-// solves CBP consecutive patches of one vertex row (vj, vk): slot 0 is the
-// left neighbour of its OP = CBP-1 own patches (solved again, as a halo) so
-// that every global x node of the row in the workgroup's range
-// [(vi0-1)P+1, (vi0+OP-1)P] gets the sum of its one or two covering patches
-// (ascending).  Output: the x-combined row buffer
-//     T[((row * nP^2 + qy + nP qz) * (G0-2)) + X-1],  row = (vj-1) + npy (vk-1),
-// one contiguous run of x nodes per (qy, qz), so the combine only adds the
-// (at most four) y/z neighbours.  pe: e = assembled residual, d = T.
-template <int P, typename S, int CBP, bool MULTI>
-__global__ void __launch_bounds__(256) k_pi_solve_gx(LaunchTable L) {
-    using C = typename Prec<S>::C;
-    constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
-    constexpr int REC = fd_record(P);
-    constexpr int NT = 256, LPT = NT / CBP;
-    constexpr int OP = CBP - 1;
-    constexpr int RUN = CBP * P + P - 1;
-    static_assert(NT % CBP == 0, "patch slots must divide the workgroup");
-    __shared__ C sv[nP3 * CBP];
-    __shared__ C sSx[CBP][nP2 + 1];
-    __shared__ C sLx[CBP][nP];
-    __shared__ C sSyz[2][nP2];
-    __shared__ C sLyz[2][nP];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
-    if (tile >= L.total_tiles) return;
-    const int tid = threadIdx.x;
-    const int pc = tid % CBP;
-    const ProbEntry& pe = entry<MULTI>(L, tile);
-    const int t = tile - pe.tile_begin;
-    const int npx = pe.n[0] - 1, npy = pe.n[1] - 1;
-    const int tpr = (npx + OP - 1) / OP;
-    const int row = t / tpr, xt = t % tpr;
-    const int vj = 1 + row % npy, vk = 1 + row / npy;
-    const int vi0 = 1 + xt * OP;                     // first own patch; slot s holds patch vi0 - 1 + s
-    const int vi = vi0 - 1 + pc;
-    {
-        const int line = vi < 1 ? 0 : (vi > npx ? npx - 1 : vi - 1);
-        const C* fx = static_cast<const C*>(pe.fd[0]) + (size_t)line * REC;
-        for (int w = tid / CBP; w < nP2 + nP; w += LPT) {
-            const C v = fx[w];
-            if (w < nP2) sSx[pc][w] = v; else sLx[pc][w - nP2] = v;
-        }
-        for (int w = tid; w < 2 * (nP2 + nP); w += NT) {
-            const int d = w / (nP2 + nP), o = w % (nP2 + nP);
-            const C v = static_cast<const C*>(pe.fd[1 + d])[(size_t)((d == 0 ? vj : vk) - 1) * REC + o];
-            if (o < nP2) sSyz[d][o] = v; else sLyz[d][o - nP2] = v;
-        }
-    }
-    const int G0 = pe.n[0] * P + 1, G1 = pe.n[1] * P + 1;
-    {
-        const C* g = static_cast<const C*>(pe.e);
-        const int Ibase = (vi0 - 2) * P + 1;        // first node of slot 0
-        for (int item = tid; item < RUN * nP2; item += NT) {
-            const int x = item % RUN, yz = item / RUN;
-            const int qy = yz % nP, qz = yz / nP;
-            const int X = Ibase + x;
-            C v = 0;
-            if (X >= 1 && X <= G0 - 2)
-                v = g[(size_t)X + (size_t)G0 * ((size_t)((vj - 1) * P + 1 + qy) + (size_t)G1 * ((vk - 1) * P + 1 + qz))];
-            const int p1 = x / P;
-#pragma unroll
-            for (int d = 0; d < 2; ++d) {
-                const int pp = p1 - d;
-                const int qx = x - pp * P;
-                if (pp >= 0 && pp < CBP && qx >= 0 && qx < nP) sv[(qx + nP * (qy + nP * qz)) * CBP + pp] = v;
-            }
-        }
-    }
-    __syncthreads();
-    C Sm[nP2];
-#pragma unroll
-    for (int i = 0; i < nP2; ++i) Sm[i] = sSyz[1][i];
-    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // forward z
-        C v[nP];
-#pragma unroll
-        for (int i = 0; i < nP; ++i) v[i] = sv[(ln + nP2 * i) * CBP + pc];
-#pragma unroll
-        for (int j = 0; j < nP; ++j) {
-            C s = 0;
-#pragma unroll
-            for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
-            sv[(ln + nP2 * j) * CBP + pc] = s;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < nP2; ++i) Sm[i] = sSyz[0][i];
-    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // forward y
-        const int qx = ln % nP, qz = ln / nP;
-        C v[nP];
-#pragma unroll
-        for (int i = 0; i < nP; ++i) v[i] = sv[(qx + nP * i + nP2 * qz) * CBP + pc];
-#pragma unroll
-        for (int j = 0; j < nP; ++j) {
-            C s = 0;
-#pragma unroll
-            for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
-            sv[(qx + nP * j + nP2 * qz) * CBP + pc] = s;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < nP2; ++i) Sm[i] = sSx[pc][i];
-    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // x: forward, scale, backward
-        const int qy = ln % nP, qz = ln / nP;
-        C v[nP], w[nP];
-#pragma unroll
-        for (int i = 0; i < nP; ++i) v[i] = sv[(i + nP * ln) * CBP + pc];
-        const C lyz = sLyz[0][qy] + sLyz[1][qz];
-#pragma unroll
-        for (int j = 0; j < nP; ++j) {
-            C s = 0;
-#pragma unroll
-            for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
-            w[j] = s / (sLx[pc][j] + lyz);
-        }
-#pragma unroll
-        for (int i = 0; i < nP; ++i) {
-            C s = 0;
-#pragma unroll
-            for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * w[j];
-            sv[(i + nP * ln) * CBP + pc] = s;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < nP2; ++i) Sm[i] = sSyz[0][i];
-    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // backward y
-        const int qx = ln % nP, qz = ln / nP;
-        C v[nP];
-#pragma unroll
-        for (int j = 0; j < nP; ++j) v[j] = sv[(qx + nP * j + nP2 * qz) * CBP + pc];
-#pragma unroll
-        for (int i = 0; i < nP; ++i) {
-            C s = 0;
-#pragma unroll
-            for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * v[j];
-            sv[(qx + nP * i + nP2 * qz) * CBP + pc] = s;
-        }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < nP2; ++i) Sm[i] = sSyz[1][i];
-    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // backward z
-        C v[nP];
-#pragma unroll
-        for (int j = 0; j < nP; ++j) v[j] = sv[(ln + nP2 * j) * CBP + pc];
-#pragma unroll
-        for (int i = 0; i < nP; ++i) {
-            C s = 0;
-#pragma unroll
-            for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * v[j];
-            sv[(ln + nP2 * i) * CBP + pc] = s;
-        }
-    }
-    __syncthreads();
-    // x-combine of the own node range and store
-    {
-        const int Xlo = (vi0 - 1) * P + 1;
-        // the row's last tile also takes the nodes beyond its last patch's vertex plane
-        const int Xhi = (xt == tpr - 1) ? G0 - 2 : (vi0 + OP - 1) * P;
-        const int len = Xhi - Xlo + 1;
-        const int rowi = (vj - 1) + npy * (vk - 1);
-        C* T = static_cast<C*>(pe.d);
-        for (int item = tid; item < len * nP2; item += NT) {
-            const int X = Xlo + item % len, yz = item / len;
-            const int v = X / P, r = X - v * P;
-            C sum;
-            if (r == 0) {
-                sum = sv[(P - 1 + nP * yz) * CBP + (v - (vi0 - 1))];
-            } else {
-                sum = 0;
-                if (v >= 1) sum += sv[(P - 1 + r + nP * yz) * CBP + (v - (vi0 - 1))];
-                if (v + 1 <= npx) sum += sv[(r - 1 + nP * yz) * CBP + (v + 1 - (vi0 - 1))];
-            }
-            T[((size_t)rowi * nP2 + yz) * (size_t)(G0 - 2) + (X - 1)] = sum;
-        }
-    }
-}
-
-// Combine from the x-combined row buffer (p <= 3): one wavefront per
-// (storage block, node plane c), lanes = cells.  A node receives the row
-// values of its (at most two) covering vertex layers times (at most two)
-// covering vertex rows, added in ascending (z, y) order.
-template <int P, typename S, int ACC, bool MULTI>
-__global__ void __launch_bounds__(256) k_pi_combine_x(LaunchTable L) {
-    using C = typename Prec<S>::C;
-    constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
-    constexpr int nP = 2 * P - 1, nP2 = nP * nP;
-    const int lane = threadIdx.x & 63;
-    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= L.total_tiles) return;
-    const ProbEntry& pe = entry<MULTI>(L, tile);
-    const int blk = (tile - pe.tile_begin) / N;
-    const int c = (tile - pe.tile_begin) % N;
-    const int e = blk * kLanes + lane;
-    S* z = static_cast<S*>(pe.c) + (size_t)blk * NN * kLanes + (size_t)c * N2 * kLanes + lane;
-    if (e >= pe.ncells) {
-#pragma unroll
-        for (int l = 0; l < N2; ++l) store_from(z + l * kLanes, (C)0);
-        return;
-    }
-    const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
-    const int npy = n1 - 1;
-    const int G0 = n0 * P + 1;
-    const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
-    const C* T = static_cast<const C*>(pe.d);
-    const C alpha = (C)pe.alpha;
-    // covering vertex layers of plane c: (vz, qz), ascending
-    int nz = 0, vzs[2], qzs[2];
-    if (c != P && k >= 1) { vzs[nz] = k; qzs[nz] = P - 1 + c; ++nz; }
-    if (c != 0 && k + 1 <= n2 - 1) { vzs[nz] = k + 1; qzs[nz] = c - 1; ++nz; }
-#pragma unroll
-    for (int b = 0; b < N; ++b) {
-        int ny = 0, vys[2], qys[2];
-        if (b != P && j >= 1) { vys[ny] = j; qys[ny] = P - 1 + b; ++ny; }
-        if (b != 0 && j + 1 <= npy) { vys[ny] = j + 1; qys[ny] = b - 1; ++ny; }
-#pragma unroll
-        for (int a = 0; a < N; ++a) {
-            const int X = i * P + a;
-            C sum = 0;
-            if (X >= 1 && X <= G0 - 2) {
-                for (int tz = 0; tz < nz; ++tz)
-                    for (int ty = 0; ty < ny; ++ty) {
-                        const int rowi = (vys[ty] - 1) + npy * (vzs[tz] - 1);
-                        sum += T[((size_t)rowi * nP2 + qys[ty] + nP * qzs[tz]) * (size_t)(G0 - 2) + (X - 1)];
-                    }
-            }
-            const int l = a + N * b;
-            C out = alpha * sum;
-            if (ACC) out = load_as<C>(z + l * kLanes) + out;
-            store_from(z + l * kLanes, out);
-        }
-    }
-}
-
 template <int P, typename S>
 static hipError_t launch_assemble_nodes(ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s) {
     using C = typename Prec<S>::C;
@@ -1726,9 +1447,10 @@ __global__ void __launch_bounds__(256) k_pi_combine_planes(LaunchTable L) {
 // matrix of the patch's lines, so they run on the matrix cores: 16x16x4
 // MFMA tiles (FP64 or FP32), the basis zero-padded to 16x16 as the register
 // A operand and 16 patch lines per tile as the B operand read from LDS.
-// One wavefront owns one patch; four per workgroup, no workgroup barriers.
-// The residual is first assembled into a global-node array (k_assemble), so
-// a patch reads its (2p-1)^3 box without summing copies.
+// One or two wavefronts own one patch (mfma_waves_per_patch); the residual
+// is first assembled into a global-node array (k_assemble_nodes), so a patch
+// reads its (2p-1)^3 box without summing copies, and the results go to a
+// patch-major buffer (one contiguous run per patch) for k_pi_combine_pm.
 typedef double v4d_t __attribute__((ext_vector_type(4)));
 typedef float v4f_t __attribute__((ext_vector_type(4)));
 
@@ -1771,29 +1493,31 @@ __device__ __forceinline__ void mfma_pass(C* pv, const C (&a)[4], int lane, int 
                                           const C* lz) {
     using M = Mfma<C>;
     constexpr int NL = nP * nP, NT = (NL + 15) / 16;
-    auto addr = [](int i, int line) -> int {
-        if (DIR == 2) return line + NL * i;                                 // z lines: line = qx + nP qy
-        if (DIR == 1) return (line % nP) + nP * i + NL * (line / nP);       // y lines: line = qx + nP qz
-        return i + nP * line;                                               // x lines: line = qy + nP qz
-    };
-    const int col = lane % 16;
+    // element (i, line) of the pass's lines sits at base(line) + STRIDE * i
+    constexpr int STRIDE = DIR == 2 ? NL : DIR == 1 ? nP : 1;
+    const int col = lane % 16, g = lane / 16;
     for (int t = sub; t < NT; t += WPP) {
         const int line = 16 * t + col;
+        const bool lok = line < NL;
+        const int base = DIR == 2 ? line : DIR == 1 ? (line % nP) + NL * (line / nP) : nP * line;
+        const C* src = pv + base + STRIDE * g;
         typename M::V acc = {0, 0, 0, 0};
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
-            const int k = 4 * ks + lane / 16;
-            const C b = (k < nP && line < NL) ? pv[addr(k, line)] : (C)0;
+            const int k = 4 * ks + g;
+            const C b = (k < nP && lok) ? src[4 * STRIDE * ks] : (C)0;
             acc = M::mma(a[ks], b, acc);
         }
-        if (line < NL) {
+        if (lok) {
+            C lyz = 0;
+            if (MODE == 1) lyz = ly[line % nP] + lz[line / nP];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int j = M::row(lane, r);
                 if (j < nP) {
                     C v = acc[r];
-                    if (MODE == 1) v = v * recip(lx[j] + ly[line % nP] + lz[line / nP]);
-                    pv[addr(j, line)] = v;
+                    if (MODE == 1) v = v * recip(lx[j] + lyz);
+                    pv[base + STRIDE * j] = v;
                 }
             }
         }
@@ -1940,67 +1664,12 @@ __global__ void __launch_bounds__(256) k_pi_solve_mfma(LaunchTable L) {
     for (int q = t64; q < nP3; q += 64 * WPP) out[q] = pv[q];
 }
 
-// Assemble a dual cell-wise vector into the global-node array (sum of all
-// copies, fixed order), in the compute precision C.  pe: a = r (S), e = out.
-template <typename S, typename C, bool MULTI>
-__global__ void __launch_bounds__(256) k_assemble(LaunchTable L) {
-    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
-        const ProbEntry& pe = entry<MULTI>(L, tile);
-        const int p = pe.p, N = p + 1, NN = N * N * N;
-        const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
-        const size_t G0 = (size_t)n0 * p + 1, G1 = (size_t)n1 * p + 1, G2 = (size_t)n2 * p + 1;
-        const size_t g = (size_t)(tile - pe.tile_begin) * 256 + threadIdx.x;
-        if (g >= G0 * G1 * G2) continue;
-        const int I = g % G0, J = (g / G0) % G1, K = g / (G0 * G1);
-        int ci[3][2], li[3][2], cnt[3];
-        const int idx[3] = {I, J, K};
-        const int nn[3] = {n0, n1, n2};
-        for (int d = 0; d < 3; ++d) {
-            cnt[d] = 0;
-            const int q = idx[d] / p, rr = idx[d] % p;
-            if (rr == 0 && q >= 1) { ci[d][cnt[d]] = q - 1; li[d][cnt[d]] = p; ++cnt[d]; }
-            if (q <= nn[d] - 1) { ci[d][cnt[d]] = q; li[d][cnt[d]] = rr; ++cnt[d]; }
-        }
-        const S* v = static_cast<const S*>(pe.a);
-        double s = 0.0;
-        for (int z = 0; z < cnt[2]; ++z)
-            for (int y = 0; y < cnt[1]; ++y)
-                for (int x = 0; x < cnt[0]; ++x) {
-                    const int e = ci[0][x] + n0 * (ci[1][y] + n1 * ci[2][z]);
-                    const int l = li[0][x] + N * (li[1][y] + N * li[2][z]);
-                    s += load_as<double>(v + cell_offset(e, l, NN));
-                }
-        static_cast<C*>(pe.e)[g] = (C)s;
-    }
-}
-
-template <int P, typename S>
-static hipError_t launch_assemble_owner(ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s, int gcap) {
-    using C = typename Prec<S>::C;
-    int tiles = 0;
-    for (int i = 0; i < nprob; ++i) {
-        ents[i].tile_begin = tiles;
-        ents[i].ntiles = ents[i].nblk;
-        tiles += ents[i].nblk;
-    }
-    LaunchTable L{};
-    L.nprob = nprob;
-    L.total_tiles = tiles;
-    hipError_t err = stage_table(L, ents, nprob, d_tab, s);
-    if (err != hipSuccess || tiles == 0) return err;
-    const int grid = tiles < gcap ? tiles : gcap;
-    TraceSpan ts("pi_assemble", P, Prec<S>::id, s);
-    if (nprob > 1) hipLaunchKernelGGL((k_assemble_owner<P, S, C, true>), dim3(grid), dim3(256), 0, s, L);
-    else hipLaunchKernelGGL((k_assemble_owner<P, S, C, false>), dim3(grid), dim3(256), 0, s, L);
-    return hipGetLastError();
-}
-
 template <int P, typename S>
 static hipError_t launch_assemble_nodes(ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s);
 
 template <int P, typename S>
 static hipError_t launch_assemble(ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s, int gcap) {
-    if (g_assemble_owner) return launch_assemble_owner<P, S>(ents, nprob, d_tab, s, gcap);
+    (void)gcap;
     return launch_assemble_nodes<P, S>(ents, nprob, d_tab, s);
 }
 
@@ -2083,7 +1752,9 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
     }
     L.nprob = nprob;
     L.total_tiles = tiles;
-    hipError_t err = stage_table(L, ents, nprob, d_tab, s);
+    // the default p <= 3 path stages its own tables (assembly, solves)
+    const bool own_tables = (P <= 3) && !g_restrict_from_cells;
+    hipError_t err = own_tables ? hipSuccess : stage_table(L, ents, nprob, d_tab, s);
     if (err != hipSuccess) return err;
     if (tiles > 0) {
         if constexpr (P <= 3) {
@@ -2092,53 +1763,7 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
                 TraceSpan ts("pi_solve", P, Prec<S>::id, s);
                 if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_r<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, L);
                 else hipLaunchKernelGGL((k_pi_solve_r<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, L);
-            } else if (g_pi_xcombine) {
-                err = launch_assemble<P, S>(ents, nprob, d_tab, s, gcap);
-                if (err != hipSuccess) return err;
-                constexpr int OP = CBP - 1;
-                int t1 = 0;
-                for (int i = 0; i < nprob; ++i) {
-                    const int npx = ents[i].n[0] - 1, npy = ents[i].n[1] - 1, npz = ents[i].n[2] - 1;
-                    ents[i].tile_begin = t1;
-                    ents[i].ntiles = (npx > 0 && npy > 0 && npz > 0) ? ((npx + OP - 1) / OP) * npy * npz : 0;
-                    t1 += ents[i].ntiles;
-                }
-                LaunchTable Lg{};
-                Lg.nprob = nprob;
-                Lg.total_tiles = t1;
-                err = stage_table(Lg, ents, nprob, d_tab, s);
-                if (err != hipSuccess) return err;
-                const int gridx = (t1 + 7) / 8 * 8;
-                {
-                    TraceSpan ts("pi_solve", P, Prec<S>::id, s);
-                    if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_gx<P, S, CBP, true>), dim3(gridx), dim3(256), 0, s, Lg);
-                    else hipLaunchKernelGGL((k_pi_solve_gx<P, S, CBP, false>), dim3(gridx), dim3(256), 0, s, Lg);
-                }
-                err = hipGetLastError();
-                if (err != hipSuccess) return err;
-                int t3 = 0;
-                for (int i = 0; i < nprob; ++i) {
-                    ents[i].tile_begin = t3;
-                    ents[i].ntiles = ents[i].nblk * (P + 1);
-                    t3 += ents[i].ntiles;
-                }
-                LaunchTable L3{};
-                L3.nprob = nprob;
-                L3.total_tiles = t3;
-                err = stage_table(L3, ents, nprob, d_tab, s);
-                if (err != hipSuccess) return err;
-                const int grid3 = (t3 + 3) / 4;
-                TraceSpan ts("pi_combine", P, Prec<S>::id, s);
-                if (nprob > 1) {
-                    if (accumulate) hipLaunchKernelGGL((k_pi_combine_x<P, S, 1, true>), dim3(grid3), dim3(256), 0, s, L3);
-                    else hipLaunchKernelGGL((k_pi_combine_x<P, S, 0, true>), dim3(grid3), dim3(256), 0, s, L3);
-                } else {
-                    if (accumulate) hipLaunchKernelGGL((k_pi_combine_x<P, S, 1, false>), dim3(grid3), dim3(256), 0, s, L3);
-                    else hipLaunchKernelGGL((k_pi_combine_x<P, S, 0, false>), dim3(grid3), dim3(256), 0, s, L3);
-                }
-                return hipGetLastError();
             } else {
-                // the table L is already staged; assemble first (it restages its own)
                 err = launch_assemble<P, S>(ents, nprob, d_tab, s, gcap);
                 if (err != hipSuccess) return err;
                 int t1 = 0;

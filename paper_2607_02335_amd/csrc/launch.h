@@ -56,7 +56,7 @@ const double* ref_stiff(int p);
 // only after the copy that read it has run (event), and the device side only
 // by work later on the same stream.
 struct TableStager {
-    static constexpr int kSlots = 16;
+    static constexpr int kSlots = 64;
     int cap = 0;
     ProbEntry* host[kSlots] = {};
     ProbEntry* dev[kSlots] = {};

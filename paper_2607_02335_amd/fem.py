@@ -90,6 +90,7 @@ def lib():
         "fem_server_poll": ([vp, ct.c_uint64, vp, ct.POINTER(SolveInfo)], i),
         "fem_server_memory": ([vp, ct.POINTER(sz), ct.POINTER(sz)], i),
         "fem_server_finished": ([vp, ct.POINTER(ct.c_uint64), i], i),
+        "fem_server_stats": ([vp, ct.POINTER(d), i], i),
         "fem_host_1d_matrices": ([i, vp, vp], i),
         "fem_host_fd_1d": ([i, d, d, vp, vp], i),
         "fem_host_gll_nodes": ([i, vp], i),
@@ -491,6 +492,13 @@ class Server:
         out = (ct.c_uint64 * n)()
         n = min(n, L.fem_server_finished(self.h, out, n))
         return [int(out[k]) for k in range(n)]
+
+    def stats(self):
+        """Host seconds per server-step phase and the step count."""
+        out = (ct.c_double * 6)()
+        check(lib().fem_server_stats(self.h, out, 6), "fem_server_stats")
+        keys = ("admit", "launch", "wait_scalars", "retire_finish", "retire_start", "steps")
+        return dict(zip(keys, list(out)))
 
     def memory(self):
         a, b = ct.c_size_t(), ct.c_size_t()

@@ -1,6 +1,7 @@
 """Turn rocprofv3 output into the short summaries kept under profiles/.
 
     python -m paper_2607_02335_amd.profiling stats  STATS_CSV  --workload W --command C -o OUT.md
+    python -m paper_2607_02335_amd.profiling counters RUN_DIR [RUN_DIR ...] --workload W --command C -o OUT.md
     python -m paper_2607_02335_amd.profiling traffic --workload W --command C \\
         --fetch FETCH_DIR --write WRITE_DIR --calib-fetch DIR --calib-write DIR \\
         --calib-bytes N -o OUT.md
@@ -82,6 +83,32 @@ def stats(args) -> None:
         f.write("\n".join(lines) + "\n")
 
 
+def counters(args) -> None:
+    """Per-kernel averages of any --pmc counters (one or more runs)."""
+    table = collections.defaultdict(dict)
+    for d in args.runs:
+        paths = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        vals = collections.defaultdict(list)
+        for p in paths:
+            for r in csv.DictReader(open(p)):
+                vals[(r["Kernel_Name"], r["Counter_Name"])].append(float(r["Counter_Value"]))
+        for (k, c), v in vals.items():
+            if args.match and not any(m in k for m in args.match):
+                continue
+            table[_short(k)][c] = sum(v) / len(v)
+    names = sorted({c for row in table.values() for c in row})
+    lines = [f"# Counters per dispatch: {args.workload}", "",
+             "Commands (from the repository root, with `cd /tmp && export TMPDIR=/tmp` first):", "",
+             f"    {args.command}", "",
+             "| kernel | " + " | ".join(names) + " |", "|---|" + "---|" * len(names)]
+    for k, row in table.items():
+        lines.append(f"| `{k}` | " + " | ".join(
+            (f"{row[c]:.1f}" if c in row and abs(row[c]) < 1000 else f"{row[c]:.4g}" if c in row else "")
+            for c in names) + " |")
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def _counter_means(run_dir: str):
     paths = glob.glob(os.path.join(run_dir, "**", "*counter_collection.csv"), recursive=True)
     if not paths:
@@ -136,13 +163,19 @@ def main(argv=None):
     s.add_argument("--workload", required=True)
     s.add_argument("--command", required=True)
     s.add_argument("-o", "--out", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("runs", nargs="+")
+    c.add_argument("--workload", required=True)
+    c.add_argument("--command", required=True)
+    c.add_argument("--match", action="append", default=[], help="keep kernels whose name contains this")
+    c.add_argument("-o", "--out", required=True)
     t = sub.add_parser("traffic")
     for a in ("--fetch", "--write", "--calib-fetch", "--calib-write", "--workload", "--command"):
         t.add_argument(a, required=True)
     t.add_argument("--calib-bytes", type=float, default=float(1 << 30))
     t.add_argument("-o", "--out", required=True)
     a = ap.parse_args(argv)
-    stats(a) if a.cmd == "stats" else traffic(a)
+    {"stats": stats, "counters": counters, "traffic": traffic}[a.cmd](a)
 
 
 if __name__ == "__main__":

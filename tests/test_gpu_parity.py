@@ -282,3 +282,28 @@ def test_fused_sweep_matches_two_phase(F, p, n, prec, mode):
     np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(zc), prec))), to_np(P.unpack(zc)))
     zref = patches.SchwarzFactors(m)(operators.scatter(m, to_np(P.unpack(rd)).astype(np.float64)))
     assert rel_err(to_np(P.unpack(zc)), zref[m.dofs]) <= {0: 1e-12, 1: 5e-5}[prec]
+
+
+@pytest.mark.parametrize("p,n", [(2, (9, 5, 4)), (3, (7, 4, 5)), (7, (3, 4, 2))])
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("opt,val", [("PI_FUSED", 1), ("PI_FUSED", 2), ("COMBINE_PER_CELL", 1),
+                                     ("RESTRICT_FROM_CELLS", 1)])
+def test_patch_inverse_variants_agree(F, p, n, prec, opt, val):
+    """Every kernel-variant switch gives the default path's patch inverse up
+    to summation-order rounding, continuous bit for bit."""
+    if p > 3 and opt != "PI_FUSED":
+        pytest.skip("switch only affects p <= 3")
+    note(f"variant {opt}={val} p={p} n={n} prec={prec}")
+    m, w, rng = graded(p, n, 50 + p)
+    P = make(F, m)
+    rd = P.pack(to_dev(rng.uniform(-1, 1, m.ncells * m.n1 ** 3)), prec)
+    z0 = to_np(P.unpack(P.patch_inverse(rd)))
+    code = getattr(F, "OPT_" + opt)
+    F.set_option(code, val)
+    try:
+        zc = P.patch_inverse(rd)
+    finally:
+        F.set_option(code, 0)
+    z1 = to_np(P.unpack(zc))
+    assert rel_err(z1, z0) <= {0: 1e-13, 1: 1e-6}[prec]
+    np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(zc), prec))), z1)
