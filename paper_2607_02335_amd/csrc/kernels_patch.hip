@@ -30,7 +30,7 @@ namespace fem {
 // 1: use the fused sweep (no patch buffer) for p <= 3; selected by
 // fem_set_option.  The two-phase path is the default: on MI355X it is faster
 // for every measured workload (the sweep's per-layer chain is latency-bound).
-int g_pi_fused = 0;
+int g_pi_fused = -1;
 // 1: combine the two-phase patch results with one wavefront per storage
 // block (all planes) instead of one per (block, plane).
 int g_combine_per_cell = 0;
@@ -1673,7 +1673,6 @@ static hipError_t launch_assemble(ProbEntry* ents, int nprob, TableStager* d_tab
     return launch_assemble_nodes<P, S>(ents, nprob, d_tab, s);
 }
 
-static inline bool cfg_two_phase_generic(const LaunchCfg& cfg) { return cfg.pi_fused == 2; }
 
 template <int P, typename S>
 static hipError_t launch_pi_mfma(int accumulate, ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s,
@@ -1732,13 +1731,19 @@ template <int P, typename S>
 static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s,
                               const LaunchCfg& cfg) {
     if constexpr (P <= 3) {
-        const int fused = cfg.pi_fused >= 0 ? cfg.pi_fused : g_pi_fused;
+        // default by degree and precision only (never by size or launch mix, so
+        // a problem gets the same variant alone and batched): the fused sweep
+        // from the assembled residual for p = 2 in FP64/FP32 (measured faster
+        // there), the two launches through the patch buffer otherwise
+        const int dflt = (P == 2 && Prec<S>::id != FEM_BF16) ? 2 : 0;
+        const int fused = cfg.pi_fused >= 0 ? cfg.pi_fused : g_pi_fused >= 0 ? g_pi_fused : dflt;
         if (fused == 2) return launch_pi_sweep_g<P, S>(accumulate, ents, nprob, d_tab, s);
         if (fused) return launch_pi_sweep<P, S>(accumulate, ents, nprob, d_tab, s);
     }
     const int gcap = cfg.grid_cap > 0 ? cfg.grid_cap : kMaxGrid;
     if constexpr (P >= 4) {
-        if (!cfg_two_phase_generic(cfg)) return launch_pi_mfma<P, S>(accumulate, ents, nprob, d_tab, s, gcap);
+        const int mode = cfg.pi_fused >= 0 ? cfg.pi_fused : g_pi_fused >= 0 ? g_pi_fused : 0;
+        if (mode != 2) return launch_pi_mfma<P, S>(accumulate, ents, nprob, d_tab, s, gcap);
     }
     using C = typename Prec<S>::C;
     constexpr int CBP = pi_patches_per_tile<P, C>();

@@ -271,13 +271,14 @@ def test_fused_sweep_matches_two_phase(F, p, n, prec, mode):
     m, w, rng = graded(p, n, 90 + p)
     P = make(F, m)
     rd = P.pack(to_dev(rng.uniform(-1, 1, m.ncells * m.n1 ** 3)), prec)
-    z1 = to_np(P.unpack(P.smoother_step(rd, sweeps=2, omega=0.3)))
-    F.set_option(F.OPT_PI_FUSED, mode)
     try:
+        F.set_option(F.OPT_PI_FUSED, 0)
+        z1 = to_np(P.unpack(P.smoother_step(rd, sweeps=2, omega=0.3)))
+        F.set_option(F.OPT_PI_FUSED, mode)
         z2 = to_np(P.unpack(P.smoother_step(rd, sweeps=2, omega=0.3)))
         zc = P.patch_inverse(rd)
     finally:
-        F.set_option(F.OPT_PI_FUSED, 0)
+        F.set_option(F.OPT_PI_FUSED, -1)
     assert rel_err(z1, z2) <= {0: 1e-14, 1: 1e-6}[prec]
     np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(zc), prec))), to_np(P.unpack(zc)))
     zref = patches.SchwarzFactors(m)(operators.scatter(m, to_np(P.unpack(rd)).astype(np.float64)))
@@ -286,7 +287,7 @@ def test_fused_sweep_matches_two_phase(F, p, n, prec, mode):
 
 @pytest.mark.parametrize("p,n", [(2, (9, 5, 4)), (3, (7, 4, 5)), (7, (3, 4, 2))])
 @pytest.mark.parametrize("prec", [0, 1])
-@pytest.mark.parametrize("opt,val", [("PI_FUSED", 1), ("PI_FUSED", 2), ("COMBINE_PER_CELL", 1),
+@pytest.mark.parametrize("opt,val", [("PI_FUSED", 0), ("PI_FUSED", 1), ("PI_FUSED", 2), ("COMBINE_PER_CELL", 1),
                                      ("RESTRICT_FROM_CELLS", 1)])
 def test_patch_inverse_variants_agree(F, p, n, prec, opt, val):
     """Every kernel-variant switch gives the default path's patch inverse up
@@ -303,7 +304,7 @@ def test_patch_inverse_variants_agree(F, p, n, prec, opt, val):
     try:
         zc = P.patch_inverse(rd)
     finally:
-        F.set_option(code, 0)
+        F.set_option(code, -1 if opt == "PI_FUSED" else 0)
     z1 = to_np(P.unpack(zc))
     assert rel_err(z1, z0) <= {0: 1e-13, 1: 1e-6}[prec]
     np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(zc), prec))), z1)
