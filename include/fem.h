@@ -285,13 +285,18 @@ fem_status fem_host_fd_1d(int p, double h0, double h1, double* S, double* lambda
  * the p <= 3 combine use one wavefront per 64-cell block (all node planes)
  * instead of one per (block, plane).  FEM_OPT_RESTRICT_FROM_CELLS = 1 makes
  * the p <= 3 patch solves sum the residual copies from the cell vector
- * instead of reading the assembled global-node array.  Every variant gives
+ * instead of reading the assembled global-node array.  FEM_OPT_PI_SLAB_MB =
+ * m > 0 runs the p <= 3 two-launch patch inverse of a single problem in
+ * z-slabs of about m MB of patch results each (solve, then combine what is
+ * complete), so the results are re-read from the Infinity Cache; 0 (default)
+ * launches each phase once.  Every variant gives
  * the same result up to the rounding of the summation order (bitwise
  * continuous in all cases).  Unknown options or values are FEM_EINVAL. */
 typedef enum fem_option {
     FEM_OPT_PI_FUSED = 1,
     FEM_OPT_COMBINE_PER_CELL = 2,
-    FEM_OPT_RESTRICT_FROM_CELLS = 3
+    FEM_OPT_RESTRICT_FROM_CELLS = 3,
+    FEM_OPT_PI_SLAB_MB = 4
 } fem_option;
 fem_status fem_set_option(int option, int value);
 

@@ -318,7 +318,7 @@ static int host_fd_1d_compute(int p, double h0, double h1, double* S, double* la
 
 using namespace fem;
 
-namespace fem { extern int g_pi_fused; extern int g_combine_per_cell; extern int g_restrict_from_cells; }
+namespace fem { extern int g_pi_fused; extern int g_combine_per_cell; extern int g_restrict_from_cells; extern int g_pi_slab_mb; }
 
 extern "C" fem_status fem_set_option(int option, int value) {
     switch (option) {
@@ -328,6 +328,10 @@ extern "C" fem_status fem_set_option(int option, int value) {
             return FEM_OK;
         case FEM_OPT_COMBINE_PER_CELL: fem::g_combine_per_cell = value ? 1 : 0; return FEM_OK;
         case FEM_OPT_RESTRICT_FROM_CELLS: fem::g_restrict_from_cells = value ? 1 : 0; return FEM_OK;
+        case FEM_OPT_PI_SLAB_MB:
+            if (value < 0) return set_error(FEM_EINVAL, "fem_set_option: FEM_OPT_PI_SLAB_MB >= 0");
+            fem::g_pi_slab_mb = value;
+            return FEM_OK;
         default: return set_error(FEM_EINVAL, "fem_set_option: unknown option");
     }
 }

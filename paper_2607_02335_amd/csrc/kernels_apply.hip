@@ -360,20 +360,25 @@ static RefMats<P, C> ref_mats() {
 // and every (cell, a, b) z line accumulates y(k') += Mz(k',k) P1_k +
 // cz Kz(k',k) P2_k in registers, so only two plane pairs of two arrays sit in
 // LDS.  The mass apply keeps the T2/P2 chain: y = vol Mz (My Mx u).
+// Workgroup shape of the plane-streamed apply (threads, z planes per step).
+// A 512-thread, four-plane shape for 8-byte values measured slower.
+template <int P, typename C> struct PlanesShape { static constexpr int NT = 256, KP = 2; };
+
 template <int P, typename S, int MODE, bool MULTI>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__((PlanesShape<P, typename Prec<S>::C>::NT))
 k_apply_planes(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
     using C = typename Prec<S>::C;
     constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
+    constexpr int NT = PlanesShape<P, C>::NT;
     constexpr int CB = 16;                 // cells per workgroup
-    constexpr int KP = 2;                  // z planes per step
+    constexpr int KP = PlanesShape<P, C>::KP;   // z planes per step
     constexpr int NSTEP = (N + KP - 1) / KP;
     constexpr int SL = KP * N2 * CB;       // values per LDS array
     constexpr int ZL = N2 * CB;            // z lines per workgroup
-    constexpr int ZPT = (ZL + 255) / 256;  // z lines per thread
+    constexpr int ZPT = (ZL + NT - 1) / NT;  // z lines per thread
     __shared__ C s1[SL];                   // u -> T1 -> P1
     __shared__ C s2[SL];                   // T2 -> P2
-    static_assert(256 % CB == 0 && kLanes % CB == 0, "cells per workgroup must divide the block");
+    static_assert(NT % CB == 0 && kLanes % CB == 0, "cells per workgroup must divide the block");
     const int tid = threadIdx.x;
     const int cl = tid % CB;               // the cell this thread serves in line passes
     for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
@@ -396,7 +401,7 @@ k_apply_planes(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
         for (int st = 0; st < NSTEP; ++st) {
             const int k0 = st * KP;
             // load planes k0, k0+1: item = cell + CB * (ab + N2 * kk)
-            for (int item = tid; item < SL; item += 256) {
+            for (int item = tid; item < SL; item += NT) {
                 const int kk = item / (N2 * CB), ab = (item / CB) % N2;
                 const int k = k0 + kk;
                 C v = (C)0;
@@ -409,7 +414,7 @@ k_apply_planes(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
             }
             __syncthreads();
             // x lines: task = cell + CB * (b + N * kk)
-            for (int task = tid; task < CB * N * KP; task += 256) {
+            for (int task = tid; task < CB * N * KP; task += NT) {
                 const int r = task / CB;                   // b + N kk
                 C v[N];
 #pragma unroll
@@ -428,7 +433,7 @@ k_apply_planes(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
             }
             __syncthreads();
             // y lines (in place): task = cell + CB * (a + N * kk)
-            for (int task = tid; task < CB * N * KP; task += 256) {
+            for (int task = tid; task < CB * N * KP; task += NT) {
                 const int r = task / CB;
                 const int a = r % N, kk = r / N;
                 C v1[N], v2[N];
@@ -456,9 +461,9 @@ k_apply_planes(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
             // z accumulation: z line q of this thread = (cell, ab)
 #pragma unroll
             for (int q = 0; q < ZPT; ++q) {
-                const int zl = tid + 256 * q;
+                const int zl = tid + NT * q;
                 if (zl >= ZL) break;
-                const int ab = zl / CB;               // the cell is cl: CB divides 256
+                const int ab = zl / CB;               // the cell is cl: CB divides NT
 #pragma unroll
                 for (int kk = 0; kk < KP; ++kk) {
                     const int k = k0 + kk;
@@ -478,7 +483,7 @@ k_apply_planes(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
         const S* __restrict__ rres = (MODE == kApplyResidual) ? static_cast<const S*>(pe.b) + base : nullptr;
 #pragma unroll
         for (int q = 0; q < ZPT; ++q) {
-            const int zl = tid + 256 * q;
+            const int zl = tid + NT * q;
             if (zl >= ZL) break;
             const int ab = zl / CB;
 #pragma unroll
@@ -536,8 +541,9 @@ static hipError_t launch_apply_t(ProbEntry* ents, int nprob, TableStager* d_tab,
     if constexpr (P >= 4) {
         if (use_planes) {
             const int grid = tiles < gcap ? tiles : gcap;
-            if (nprob > 1) hipLaunchKernelGGL((k_apply_planes<P, S, MODE, true>), dim3(grid), dim3(256), 0, s, L, R);
-            else hipLaunchKernelGGL((k_apply_planes<P, S, MODE, false>), dim3(grid), dim3(256), 0, s, L, R);
+            constexpr int NT = PlanesShape<P, C>::NT;
+            if (nprob > 1) hipLaunchKernelGGL((k_apply_planes<P, S, MODE, true>), dim3(grid), dim3(NT), 0, s, L, R);
+            else hipLaunchKernelGGL((k_apply_planes<P, S, MODE, false>), dim3(grid), dim3(NT), 0, s, L, R);
             return hipGetLastError();
         }
     }

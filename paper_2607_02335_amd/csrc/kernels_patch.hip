@@ -37,6 +37,9 @@ int g_combine_per_cell = 0;
 // 1: phase 1 of the p <= 3 patch inverse sums the copies from the cell-wise
 // vector itself instead of reading the owner-assembled global-node array.
 int g_restrict_from_cells = 0;
+// Patch results per z-slab (MB) of the single-problem two-phase patch
+// inverse for p <= 3; 0 runs one solve and one combine launch.
+int g_pi_slab_mb = 0;
 
 template <int P, typename C> constexpr int pi_patches_per_tile() {
     constexpr int nP = 2 * P - 1;
@@ -1537,7 +1540,10 @@ __global__ void __launch_bounds__(256) k_pi_combine_pm(LaunchTable L) {
     using C = typename Prec<S>::C;
     constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
     constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
-    constexpr int RS = kLanes + 1;                  // padded LDS row
+    // cells per LDS pass: half a block for 8-byte values keeps the LDS at
+    // about 16 KB per workgroup
+    constexpr int CH = sizeof(C) >= 8 ? kLanes / 2 : kLanes;
+    constexpr int RS = CH + 1;                      // padded LDS row
     __shared__ C sz[N2 * RS];
     const int tile = blockIdx.x;
     if (tile >= L.total_tiles) return;
@@ -1554,46 +1560,50 @@ __global__ void __launch_bounds__(256) k_pi_combine_pm(LaunchTable L) {
     int nz = 0, szs[2], qzs[2];
     if (c != P) { szs[nz] = 0; qzs[nz] = P - 1 + c; ++nz; }
     if (c != 0) { szs[nz] = 1; qzs[nz] = c - 1; ++nz; }
-    if (ab < N2) {
-        for (int cl = wv; cl < kLanes; cl += 4) {
-            const int e = blk * kLanes + cl;
-            C sum = 0;
-            if (e < pe.ncells) {
-                const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
+    S* z = static_cast<S*>(pe.c) + (size_t)blk * NN * kLanes + (size_t)c * N2 * kLanes;
+    for (int h = 0; h < kLanes; h += CH) {
+        if (ab < N2) {
+            for (int cl = wv; cl < CH; cl += 4) {
+                const int e = blk * kLanes + h + cl;
+                C sum = 0;
+                if (e < pe.ncells) {
+                    const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
 #pragma unroll
-                for (int t = 0; t < 2; ++t) {
-                    if (t >= nz) break;
-                    const int vz = k + szs[t];
-                    if (vz < 1 || vz > n2 - 1) continue;
+                    for (int t = 0; t < 2; ++t) {
+                        if (t >= nz) break;
+                        const int vz = k + szs[t];
+                        if (vz < 1 || vz > n2 - 1) continue;
 #pragma unroll
-                    for (int sy = 0; sy < 2; ++sy) {
-                        if ((sy == 0 && b == P) || (sy == 1 && b == 0)) continue;
-                        const int vy = j + sy;
-                        if (vy < 1 || vy > npy) continue;
-                        const int qy = sy == 0 ? P - 1 + b : b - 1;
+                        for (int sy = 0; sy < 2; ++sy) {
+                            if ((sy == 0 && b == P) || (sy == 1 && b == 0)) continue;
+                            const int vy = j + sy;
+                            if (vy < 1 || vy > npy) continue;
+                            const int qy = sy == 0 ? P - 1 + b : b - 1;
 #pragma unroll
-                        for (int sx = 0; sx < 2; ++sx) {
-                            if ((sx == 0 && a == P) || (sx == 1 && a == 0)) continue;
-                            const int vx = i + sx;
-                            if (vx < 1 || vx > npx) continue;
-                            const int qx = sx == 0 ? P - 1 + a : a - 1;
-                            const int pidx = (vx - 1) + npx * ((vy - 1) + npy * (vz - 1));
-                            sum += pbuf[(size_t)pidx * nP3 + qx + nP * qy + nP2 * qzs[t]];
+                            for (int sx = 0; sx < 2; ++sx) {
+                                if ((sx == 0 && a == P) || (sx == 1 && a == 0)) continue;
+                                const int vx = i + sx;
+                                if (vx < 1 || vx > npx) continue;
+                                const int qx = sx == 0 ? P - 1 + a : a - 1;
+                                const int pidx = (vx - 1) + npx * ((vy - 1) + npy * (vz - 1));
+                                sum += pbuf[(size_t)pidx * nP3 + qx + nP * qy + nP2 * qzs[t]];
+                            }
                         }
                     }
                 }
+                sz[ab * RS + cl] = sum;
             }
-            sz[ab * RS + cl] = sum;
         }
-    }
-    __syncthreads();
-    S* z = static_cast<S*>(pe.c) + (size_t)blk * NN * kLanes + (size_t)c * N2 * kLanes;
-    for (int idx = threadIdx.x; idx < N2 * kLanes; idx += 256) {
-        const int l = idx / kLanes, cl = idx % kLanes;
-        const int e = blk * kLanes + cl;
-        C out = e < pe.ncells ? alpha * sz[l * RS + cl] : (C)0;
-        if (ACC && e < pe.ncells) out = load_as<C>(z + idx) + out;
-        store_from(z + idx, out);
+        __syncthreads();
+        for (int idx = threadIdx.x; idx < N2 * CH; idx += 256) {
+            const int l = idx / CH, cl = idx % CH;
+            const int e = blk * kLanes + h + cl;
+            S* dst = z + (size_t)l * kLanes + h + cl;
+            C out = e < pe.ncells ? alpha * sz[l * RS + cl] : (C)0;
+            if (ACC && e < pe.ncells) out = load_as<C>(dst) + out;
+            store_from(dst, out);
+        }
+        __syncthreads();
     }
 }
 
@@ -1727,6 +1737,56 @@ static hipError_t launch_pi_mfma(int accumulate, ProbEntry* ents, int nprob, Tab
     return hipGetLastError();
 }
 
+// Two-phase patch inverse of one problem in z-slabs of vertex layers: the
+// solves of a slab are followed at once by the combine of every cell block
+// whose patches are now all solved, so a slab's patch results are read back
+// while they still sit in the Infinity Cache.  Same kernels and the same
+// arithmetic as one launch of each (the results are identical); tiles are
+// offset through the entry's tile_begin.
+template <int P, typename S>
+static hipError_t launch_pi_slabs(int accumulate, ProbEntry e, hipStream_t s, int nslab, int gcap) {
+    using C = typename Prec<S>::C;
+    constexpr int CBP = pi_patches_per_tile<P, C>();
+    constexpr int N = P + 1;
+    hipError_t err = launch_assemble<P, S>(&e, 1, nullptr, s, gcap);
+    if (err != hipSuccess) return err;
+    const int npx = e.n[0] - 1, npy = e.n[1] - 1, npz = e.n[2] - 1;
+    const int tpr = (npx + CBP - 1) / CBP;
+    const long layer_cells = (long)e.n[0] * e.n[1];
+    int kdone = 0, bdone = 0;                       // cell layers / blocks combined so far
+    for (int c = 0; c < nslab; ++c) {
+        const int va = 1 + (int)((long)npz * c / nslab), vb = (int)((long)npz * (c + 1) / nslab);
+        if (vb >= va && npx > 0 && npy > 0) {
+            LaunchTable L{};
+            L.nprob = 1;
+            const int t0 = (va - 1) * npy * tpr, t1 = vb * npy * tpr;
+            L.one = e;
+            L.one.tile_begin = -t0;
+            L.total_tiles = t1 - t0;
+            TraceSpan ts("pi_solve", P, Prec<S>::id, s);
+            hipLaunchKernelGGL((k_pi_solve_g<P, S, CBP, false>), dim3((t1 - t0 + 7) / 8 * 8), dim3(256), 0, s, L);
+        }
+        // cell layers whose covering vertex layers (k and k+1 within 1..npz) are solved
+        const int kb = (c == nslab - 1) ? e.n[2] : vb;       // layers [kdone, kb) are complete
+        int bb = (c == nslab - 1) ? e.nblk : (int)((kb * layer_cells) / kLanes);
+        if (bb > bdone) {
+            LaunchTable L{};
+            L.nprob = 1;
+            L.one = e;
+            L.one.tile_begin = -bdone * N;
+            L.total_tiles = (bb - bdone) * N;
+            TraceSpan ts("pi_combine", P, Prec<S>::id, s);
+            const int grid = (L.total_tiles + 3) / 4;
+            if (accumulate) hipLaunchKernelGGL((k_pi_combine_planes<P, S, 1, false>), dim3(grid), dim3(256), 0, s, L);
+            else hipLaunchKernelGGL((k_pi_combine_planes<P, S, 0, false>), dim3(grid), dim3(256), 0, s, L);
+            bdone = bb;
+        }
+        kdone = kb;
+    }
+    (void)kdone;
+    return hipGetLastError();
+}
+
 template <int P, typename S>
 static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s,
                               const LaunchCfg& cfg) {
@@ -1747,6 +1807,16 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
     }
     using C = typename Prec<S>::C;
     constexpr int CBP = pi_patches_per_tile<P, C>();
+    if constexpr (P <= 3) {
+        if (nprob == 1 && !g_restrict_from_cells && !g_combine_per_cell) {
+            // slabs of at most ~pi_slab_bytes of patch results (one slab: plain two launches)
+            const size_t pbytes = (size_t)(ents[0].n[0] - 1) * (ents[0].n[1] - 1) * (ents[0].n[2] - 1) *
+                                  (2 * P - 1) * (2 * P - 1) * (2 * P - 1) * sizeof(C);
+            int nslab = g_pi_slab_mb > 0 ? (int)((pbytes + ((size_t)g_pi_slab_mb << 20) - 1) / ((size_t)g_pi_slab_mb << 20)) : 1;
+            nslab = std::max(1, std::min(nslab, std::max(1, ents[0].n[2] - 1)));
+            if (nslab > 1) return launch_pi_slabs<P, S>(accumulate, ents[0], s, nslab, gcap);
+        }
+    }
     LaunchTable L{};
     int tiles = 0;
     for (int i = 0; i < nprob; ++i) {

@@ -175,6 +175,7 @@ def make_desc(p, n, widths=None, bc=DIRICHLET):
 OPT_PI_FUSED = 1
 OPT_COMBINE_PER_CELL = 2
 OPT_RESTRICT_FROM_CELLS = 3
+OPT_PI_SLAB_MB = 4
 
 
 def set_option(option, value):

@@ -308,3 +308,26 @@ def test_patch_inverse_variants_agree(F, p, n, prec, opt, val):
     z1 = to_np(P.unpack(zc))
     assert rel_err(z1, z0) <= {0: 1e-13, 1: 1e-6}[prec]
     np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(zc), prec))), z1)
+
+
+@pytest.mark.parametrize("p,n,prec", [(3, (12, 10, 20), 0), (3, (9, 11, 30), 1), (2, (20, 9, 17), 0)])
+def test_patch_inverse_slabs_identical(F, p, n, prec):
+    """The z-slab schedule runs the same kernels on the same data: results are
+    identical to one solve and one combine launch, for the plain and the
+    accumulating (smoother) form."""
+    note(f"slabs p={p} n={n} prec={prec}")
+    m, w, rng = graded(p, n, 70 + p)
+    P = make(F, m)
+    rd = P.pack(to_dev(rng.uniform(-1, 1, m.ncells * m.n1 ** 3)), prec)
+    F.set_option(F.OPT_PI_FUSED, 0)
+    try:
+        z0 = to_np(P.unpack(P.patch_inverse(rd)))
+        s0 = to_np(P.unpack(P.smoother_step(rd, sweeps=2, omega=0.3)))
+        F.set_option(F.OPT_PI_SLAB_MB, 1)
+        z1 = to_np(P.unpack(P.patch_inverse(rd)))
+        s1 = to_np(P.unpack(P.smoother_step(rd, sweeps=2, omega=0.3)))
+    finally:
+        F.set_option(F.OPT_PI_SLAB_MB, 0)
+        F.set_option(F.OPT_PI_FUSED, -1)
+    np.testing.assert_array_equal(z1, z0)
+    np.testing.assert_array_equal(s1, s0)
