@@ -1607,6 +1607,50 @@ __global__ void __launch_bounds__(256) k_pi_combine_pm(LaunchTable L) {
     }
 }
 
+// The x pair (forward product, scaling by 1/(lambda_x+lambda_y+lambda_z),
+// backward product) of every 16-line tile chained in registers: the
+// forward product's accumulators are the backward product's B operand.  A
+// lane holds accumulator rows row(lane, 0..3), so the backward k-steps take
+// k = row(lane, ks) for lane group g = lane/16; `ab` holds the backward
+// basis slices in that order (A[m][row(16 g + m, ks)]).
+template <typename C, int nP, int WPP>
+__device__ __forceinline__ void mfma_pass_x2(C* pv, const C (&af)[4], const C (&ab)[4], int lane, int sub,
+                                             const C* lx, const C* ly, const C* lz) {
+    using M = Mfma<C>;
+    constexpr int NL = nP * nP, NT = (NL + 15) / 16;
+    const int col = lane % 16, g = lane / 16;
+    for (int t = sub; t < NT; t += WPP) {
+        const int line = 16 * t + col;
+        const bool lok = line < NL;
+        const C* src = pv + nP * line + g;
+        typename M::V acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int k = 4 * ks + g;
+            const C b = (k < nP && lok) ? src[4 * ks] : (C)0;
+            acc = M::mma(af[ks], b, acc);
+        }
+        const C lyz = lok ? ly[line % nP] + lz[line / nP] : (C)1;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int j = M::row(lane, r);
+            acc[r] = j < nP ? acc[r] * recip(lx[j] + lyz) : (C)0;
+        }
+        typename M::V out = {0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) out = M::mma(ab[ks], acc[ks], out);
+        if (lok) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int j = M::row(lane, r);
+                if (j < nP) pv[nP * line + j] = out[r];
+            }
+        }
+    }
+    if (WPP == 1) wave_sync();
+    else __syncthreads();
+}
+
 // Wavefronts that share one patch: the larger patches split their 16-line
 // tiles over the whole workgroup for more waves in flight per LDS byte.
 template <int P> constexpr int mfma_waves_per_patch() { return P >= 6 ? 2 : 1; }
@@ -1665,8 +1709,16 @@ __global__ void __launch_bounds__(256) k_pi_solve_mfma(LaunchTable L) {
     const C* lz = fz + nP2;
     mfma_pass<C, nP, 2, 0, WPP>(pv, afz, lane, sub, lx, ly, lz);
     mfma_pass<C, nP, 1, 0, WPP>(pv, afy, lane, sub, lx, ly, lz);
-    mfma_pass<C, nP, 0, 1, WPP>(pv, afx, lane, sub, lx, ly, lz);
-    mfma_pass<C, nP, 0, 0, WPP>(pv, abx, lane, sub, lx, ly, lz);
+    {
+        // backward x basis in the accumulator row order of the forward product
+        C abx2[4];
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const int rr = lane % 16, kk = Mfma<C>::row(lane, ks);
+            abx2[ks] = (rr < nP && kk < nP) ? fx[rr * nP + kk] : (C)0;
+        }
+        mfma_pass_x2<C, nP, WPP>(pv, afx, abx2, lane, sub, lx, ly, lz);
+    }
     mfma_pass<C, nP, 1, 0, WPP>(pv, aby, lane, sub, lx, ly, lz);
     mfma_pass<C, nP, 2, 0, WPP>(pv, abz, lane, sub, lx, ly, lz);
     // patch-major buffer: each patch's values are one contiguous run
