@@ -231,8 +231,11 @@ fem_status fem_batch_autotune(fem_batch* B, int prec, int* choice);
 typedef struct fem_server fem_server;
 
 /* A continuous-batching solve server on the current device.  hbm_budget:
- * bytes of device memory its active solves may hold; max_active: slot
- * count.  smoother_prec/sweeps/omega: smoother of every solve. */
+ * bytes of device memory its active solves may hold (allocated once, as the
+ * arena the solves are carved from); max_active: slot count.
+ * smoother_prec/sweeps/omega: smoother of every solve.  Kernels run on
+ * `stream`; the server also creates a stream of its own (default priority)
+ * for request uploads and solution downloads, ordered by events. */
 fem_status fem_server_create(size_t hbm_budget, int max_active, int smoother_prec, int sweeps,
                              double omega, void* stream, fem_server** out);
 fem_status fem_server_destroy(fem_server* S);

@@ -303,10 +303,17 @@ struct fem_server {
     int cur = 0;
     char* stage = nullptr;
     size_t stage_cap = 0, stage_used = 0;
+    // admitted solves whose right-hand sides are being uploaded (event ev_up)
+    std::vector<Active*> staged;
     // solves whose solutions are being copied out (event ev_retire)
     std::vector<Active*> retiring;
     std::vector<char*> retiring_at;
     hipEvent_t ev_retire = nullptr, ev_scalars = nullptr;
+    // request uploads and solution downloads run on their own stream (at the
+    // default priority), ordered against the compute stream by events, so
+    // the copy engine overlaps the iterations of the other solves
+    hipStream_t copy = nullptr;
+    hipEvent_t ev_up = nullptr, ev_ext = nullptr;
     // host seconds per step phase: admission, launches, waits for the
     // scalars, retirement hand-over, retirement start; and steps taken
     double t_phase[5] = {0, 0, 0, 0, 0};
@@ -360,7 +367,8 @@ static char* stage_take(fem_server* S, size_t bytes) {
     bytes = align256(bytes);
     if (S->stage_used + bytes > S->stage_cap) {
         if (S->stage_used > 0) return nullptr;          // caller retries next step
-        if (hipStreamSynchronize(S->stream) != hipSuccess) return nullptr;
+        if (hipStreamSynchronize(S->stream) != hipSuccess || hipStreamSynchronize(S->copy) != hipSuccess)
+            return nullptr;
         if (S->stage) hipHostFree(S->stage);
         S->stage = nullptr;
         S->stage_cap = 0;
@@ -403,13 +411,19 @@ extern "C" fem_status fem_server_create(size_t hbm_budget, int max_active, int s
         hipHostMalloc((void**)&S->h_collect, sizeof(double) * 4 * max_active, hipHostMallocDefault) != hipSuccess ||
         hipMalloc((void**)&S->arena, hbm_budget) != hipSuccess ||
         hipEventCreateWithFlags(&S->ev_retire, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&S->ev_scalars, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&S->ev_scalars, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&S->ev_up, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&S->ev_ext, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&S->copy, hipStreamNonBlocking) != hipSuccess) {
         S->st.destroy();
         hipFree(S->d_collect);
         if (S->h_collect) hipHostFree(S->h_collect);
         if (S->arena) hipFree(S->arena);
         if (S->ev_retire) hipEventDestroy(S->ev_retire);
         if (S->ev_scalars) hipEventDestroy(S->ev_scalars);
+        if (S->ev_up) hipEventDestroy(S->ev_up);
+        if (S->ev_ext) hipEventDestroy(S->ev_ext);
+        if (S->copy) hipStreamDestroy(S->copy);
         delete S;
         return set_error(FEM_ENOMEM, "fem_server_create: allocation failed");
     }
@@ -428,16 +442,21 @@ static void release_active(fem_server* S, Active* A) {
 extern "C" fem_status fem_server_destroy(fem_server* S) {
     if (!S) return FEM_OK;
     hipStreamSynchronize(S->stream);
+    hipStreamSynchronize(S->copy);
     for (Active* A : S->active) release_active(S, A);
     S->st.destroy();
     hipFree(S->d_collect);
     hipHostFree(S->h_collect);
     for (Active* A : S->retiring) release_active(S, A);
+    for (Active* A : S->staged) release_active(S, A);
     hipFree(S->arena);
     for (int k = 0; k < 2; ++k)
         if (S->stage_buf[k]) hipHostFree(S->stage_buf[k]);
     hipEventDestroy(S->ev_retire);
     hipEventDestroy(S->ev_scalars);
+    hipEventDestroy(S->ev_up);
+    hipEventDestroy(S->ev_ext);
+    hipStreamDestroy(S->copy);
     delete S;
     return FEM_OK;
 }
@@ -481,8 +500,8 @@ static fem_status admit(fem_server* S, Request& R) {
     const size_t need = solve_block_bytes(&d, S->sp);
     size_t off = 0;
     if (S->in_use + need > S->budget || !arena_alloc(S, need, &off)) return FEM_EAGAIN;
-    char* hs = stage_take(S, problem_stage_bytes(&d) + sizeof(double) * R.f.size());
-    if (!hs) {
+    char* hf = stage_take(S, sizeof(double) * R.f.size());
+    if (!hf) {
         arena_free(S, off, need);
         return FEM_EAGAIN;
     }
@@ -494,20 +513,49 @@ static fem_status admit(fem_server* S, Request& R) {
     A->req = std::move(R);
     A->block_off = off;
     A->block_bytes = need;
+    S->in_use += need;
+    S->high_water = std::max(S->high_water, S->in_use);
+    A->req.t_admit = std::chrono::steady_clock::now();
+    // f goes to the tail of the block (the solve's q vector) on the copy
+    // stream; the solve starts in the next step, when the copy is done
+    const size_t len = desc_cell_len(&d);
+    const size_t wsb = workspace_bytes(&d), v64 = align256(8 * len);
+    double* q = reinterpret_cast<double*>(S->arena + off + wsb + 4 * v64);
+    std::memcpy(hf, A->req.f.data(), sizeof(double) * A->req.f.size());
+    FEM_HIP(hipMemcpyAsync(q, hf, sizeof(double) * A->req.f.size(), hipMemcpyHostToDevice, S->copy),
+            "server upload");
+    A->req.f.clear();
+    A->req.f.shrink_to_fit();
+    S->staged.push_back(A);
+    S->state[A->req.ticket] = 1;
+    return FEM_OK;
+}
+
+// Start the solves whose right-hand sides were uploaded in the previous
+// step: set up the problem in its block, form b = P_I M f, and run the
+// iteration's start (r = b, z = P(r), p = z, <r,z>) with single-problem
+// launches on the server stream.
+static fem_status activate(fem_server* S, Active* A) {
+    fem_desc d = A->req.desc;
     for (int k = 0; k < 3; ++k) d.widths[k] = A->req.widths[k].empty() ? nullptr : A->req.widths[k].data();
-    const size_t wsb = workspace_bytes(&d);
-    ProblemMem pm{S->arena + off, wsb, hs, problem_stage_bytes(&d)};
-    fem_status st = create_problem(&d, S->stream, &A->P, &pm);
-    if (st != FEM_OK) {
-        arena_free(S, off, need);
-        delete A;
-        return st;
+    char* hs = stage_take(S, problem_stage_bytes(&d));
+    if (!hs) {
+        // this step's staging is full: free it after the copies reading it
+        FEM_HIP(hipStreamSynchronize(S->stream), "server activate");
+        FEM_HIP(hipStreamSynchronize(S->copy), "server activate");
+        S->stage_used = 0;
+        hs = stage_take(S, problem_stage_bytes(&d));
+        if (!hs) return set_error(FEM_ENOMEM, "server activate: pinned staging allocation failed");
     }
+    const size_t wsb = workspace_bytes(&d);
+    ProblemMem pm{S->arena + A->block_off, wsb, hs, problem_stage_bytes(&d)};
+    fem_status st = create_problem(&d, S->stream, &A->P, &pm);
+    if (st != FEM_OK) return st;
     A->P->owned_by_batch = true;
     fem_problem* P = A->P;
     const size_t len = P->cell_len;
     const size_t v64 = align256(8 * len), vs = align256(pbytes(S->sp) * len);
-    A->mem = S->arena + off + wsb;
+    A->mem = S->arena + A->block_off + wsb;
     A->u = reinterpret_cast<double*>(A->mem);
     A->b = reinterpret_cast<double*>(A->mem + v64);
     A->r = reinterpret_cast<double*>(A->mem + 2 * v64);
@@ -515,17 +563,9 @@ static fem_status admit(fem_server* S, Request& R) {
     A->q = reinterpret_cast<double*>(A->mem + 4 * v64);
     A->z = A->mem + 5 * v64;
     A->rs = S->sp == FEM_F64 ? (void*)A->r : (void*)(A->mem + 5 * v64 + vs);
-    S->in_use += need;
-    S->high_water = std::max(S->high_water, S->in_use);
-    A->req.t_admit = std::chrono::steady_clock::now();
-    char* hf = hs + align256(problem_stage_bytes(&d));
-    std::memcpy(hf, A->req.f.data(), sizeof(double) * A->req.f.size());
-    A->req.f.clear();
-    A->req.f.shrink_to_fit();
 
     hipStream_t s = S->stream;
-    // f (global) staged in q, gathered into p, b = P_I M f
-    FEM_HIP(hipMemcpyAsync(A->q, hf, sizeof(double) * P->global_len, hipMemcpyHostToDevice, s), "server upload");
+    // f (global, uploaded into q), gathered into p, b = P_I M f
     FEM_HIP(run_gather(P, A->q, A->p, FEM_F64), "server gather");
     {
         ProbEntry e = entry_of(P);
@@ -542,7 +582,6 @@ static fem_status admit(fem_server* S, Request& R) {
     FEM_HIP(run_convert(P, A->z, S->sp, A->p, FEM_F64), "server p0");
     FEM_HIP(run_dot(P, A->r, FEM_F64, A->z, S->sp, kSlotRZ), "server dot");
     S->active.push_back(A);
-    S->state[A->req.ticket] = 1;
     return FEM_OK;
 }
 
@@ -579,22 +618,26 @@ static fem_status retire_start(fem_server* S, std::vector<Active*>& fin) {
     if (!hs) {
         // this step's staging is taken by admissions: let their copies finish
         FEM_HIP(hipStreamSynchronize(S->stream), "server retire");
+        FEM_HIP(hipStreamSynchronize(S->copy), "server retire");
         S->stage_used = 0;
         hs = stage_take(S, bytes);
         if (!hs) return set_error(FEM_ENOMEM, "server retire: pinned staging allocation failed");
     }
+    // u (FP64) to global order (staged in each solve's q) on the compute
+    // stream, then the downloads on the copy stream
+    for (Active* A : fin) FEM_HIP(run_extract(A->P, A->u, A->q, FEM_F64), "server extract");
+    FEM_HIP(hipEventRecord(S->ev_ext, S->stream), "server retire");
+    FEM_HIP(hipStreamWaitEvent(S->copy, S->ev_ext, 0), "server retire");
     char* q = hs;
     for (Active* A : fin) {
         fem_problem* P = A->P;
         S->retiring.push_back(A);
         S->retiring_at.push_back(q);
-        // u (FP64) to global order, staged in q
-        FEM_HIP(run_extract(P, A->u, A->q, FEM_F64), "server extract");
-        FEM_HIP(hipMemcpyAsync(q, A->q, sizeof(double) * P->global_len, hipMemcpyDeviceToHost, S->stream),
+        FEM_HIP(hipMemcpyAsync(q, A->q, sizeof(double) * P->global_len, hipMemcpyDeviceToHost, S->copy),
                 "server download");
         q += align256(sizeof(double) * P->global_len);
     }
-    FEM_HIP(hipEventRecord(S->ev_retire, S->stream), "server retire");
+    FEM_HIP(hipEventRecord(S->ev_retire, S->copy), "server retire");
     return FEM_OK;
 }
 
@@ -607,12 +650,23 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
     S->stage = S->stage_buf[S->cur];
     S->stage_cap = S->stage_capv[S->cur];
     S->stage_used = 0;
-    while (!S->queue.empty() && (int)S->active.size() < S->max_active) {
+    if (!S->staged.empty()) {
+        FEM_HIP(hipStreamWaitEvent(S->stream, S->ev_up, 0), "server activate");
+        std::vector<Active*> staged;
+        staged.swap(S->staged);
+        for (Active* A : staged) {
+            fem_status st = activate(S, A);
+            if (st != FEM_OK) return st;
+        }
+    }
+    const size_t nstaged0 = S->staged.size();
+    while (!S->queue.empty() && (int)(S->active.size() + S->staged.size()) < S->max_active) {
         fem_status st = admit(S, S->queue.front());
         if (st == FEM_EAGAIN) break;
         if (st != FEM_OK) return st;
         S->queue.pop_front();
     }
+    if (S->staged.size() > nstaged0) FEM_HIP(hipEventRecord(S->ev_up, S->copy), "server upload");
     hipStream_t s = S->stream;
     const int na = (int)S->active.size();
     S->t_phase[0] += clk.lap();
