@@ -14,7 +14,7 @@ import pytest
 import synth
 from oracle import operators, patches
 from oracle.mesh import Mesh
-from tests.gpu_util import l2_rel, note, rel_err, to_dev, to_np
+from tests.gpu_util import graded, l2_rel, note, rel_err, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -122,3 +122,24 @@ def test_q7_24_solves_mixed_precision(F):
               f"{info['seconds']:.3f} s", flush=True)
     for name in ("fp32", "bf16"):
         assert l2_rel(sol[name], sol["fp64"]) <= 1e-5
+
+
+def test_q7_48_apply_sampled_max_serving_size(F):
+    """The largest request the serving stream draws (p = 7, 48^3 cells,
+    56.6M cell DoFs): FP64 apply on sampled cells against the oracle, and
+    FP32 patch inverse continuity and zero boundary at full size."""
+    note("q7 48^3 max size")
+    m, w, rng = graded(7, 48, 17)
+    P = F.Problem(7, 48, w)
+    x = rng.uniform(-1, 1, m.nglob)
+    xd = P.gather(to_dev(x))
+    y = P.apply(xd)
+    cells = np.sort(rng.choice(m.ncells, 200, replace=False))
+    cells = np.unique(np.concatenate([cells, [0, m.ncells - 1]]))
+    yc = to_np(P.unpack(y))[cells]
+    ref = operators.apply_cells(m, operators.gather(m, x)[cells], cells=cells)
+    assert rel_err(yc, ref) <= 1e-12
+    z = P.patch_inverse(P.convert(y, 1))
+    zc = to_np(P.unpack(z))
+    np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(z), 1))), zc)
+    assert not np.any(zc[operators.boundary_copies(m)])

@@ -146,7 +146,8 @@ def test_dot_and_assembled_norm(F):
 
 # ---------------------------------------------------------- patch inverse
 @pytest.mark.parametrize("p,n", [(1, (4, 3, 5)), (2, (5, 4, 3)), (3, (4, 5, 3)), (4, (3, 4, 3)),
-                                 (7, (3, 3, 2)), (2, (2, 2, 2)), (3, (9, 2, 3))])
+                                 (5, (3, 2, 3)), (6, (2, 3, 2)), (7, (3, 3, 2)), (2, (2, 2, 2)),
+                                 (3, (9, 2, 3))])
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_patch_inverse_matches_lu(F, p, n, prec):
     note(f"patch_inverse p={p} n={n} prec={prec}")
@@ -331,3 +332,21 @@ def test_patch_inverse_slabs_identical(F, p, n, prec):
         F.set_option(F.OPT_PI_FUSED, -1)
     np.testing.assert_array_equal(z1, z0)
     np.testing.assert_array_equal(s1, s0)
+
+
+@pytest.mark.parametrize("p,n", [(3, (1, 4, 3)), (2, (5, 1, 1)), (7, (2, 1, 2)), (1, (1, 1, 1))])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_degenerate_meshes(F, p, n, prec):
+    """Meshes with one cell along a direction have no interior vertex: the
+    patch inverse (and so the smoother) returns exactly zero, the apply still
+    matches the oracle, and a solve converges at once on the zero system."""
+    note(f"degenerate p={p} n={n} prec={prec}")
+    m, w, rng = graded(p, n, 11)
+    P = make(F, m)
+    xc = rng.uniform(-1, 1, (m.ncells, m.n1 ** 3))
+    xd = P.pack(to_dev(xc.ravel()), prec)
+    z = to_np(P.unpack(P.patch_inverse(xd)))
+    assert not np.any(z)
+    assert not np.any(to_np(P.unpack(P.smoother_step(xd, sweeps=2, omega=0.3))))
+    y = to_np(P.unpack(P.apply(xd)))
+    assert rel_err(y, operators.apply_cells(m, to_np(P.unpack(xd)))) <= TOL[prec]
