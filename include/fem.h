@@ -235,7 +235,11 @@ typedef struct fem_server fem_server;
  * arena the solves are carved from); max_active: slot count.
  * smoother_prec/sweeps/omega: smoother of every solve.  Kernels run on
  * `stream`; the server also creates a stream of its own (default priority)
- * for request uploads and solution downloads, ordered by events. */
+ * for request uploads and solution downloads, ordered by events.
+ * Threads: one host thread drives fem_server_step; fem_server_submit,
+ * fem_server_poll, fem_server_finished, fem_server_memory and
+ * fem_server_stats may be called concurrently from other threads (they take
+ * the server's lock); create and destroy must not overlap any other call. */
 fem_status fem_server_create(size_t hbm_budget, int max_active, int smoother_prec, int sweeps,
                              double omega, void* stream, fem_server** out);
 fem_status fem_server_destroy(fem_server* S);

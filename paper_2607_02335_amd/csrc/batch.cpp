@@ -13,6 +13,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <new>
 #include <unordered_map>
 #include <vector>
@@ -276,6 +277,10 @@ struct Done {
 }  // namespace
 
 struct fem_server {
+    // guards the request queue, the ticket states, the finished results and
+    // the memory counters: submit/poll/finished/memory may run on other host
+    // threads than fem_server_step (which holds it only for short updates)
+    std::mutex mu;
     size_t budget = 0, in_use = 0, high_water = 0;
     int max_active = 0;
     int sp = FEM_F32, sweeps = 2, variant = FEM_CG_FCG;
@@ -435,7 +440,10 @@ extern "C" fem_status fem_server_create(size_t hbm_budget, int max_active, int s
 static void release_active(fem_server* S, Active* A) {
     destroy_problem_internal(A->P);
     arena_free(S, A->block_off, A->block_bytes);
-    S->in_use -= A->block_bytes;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->in_use -= A->block_bytes;
+    }
     delete A;
 }
 
@@ -482,6 +490,7 @@ extern "C" fem_status fem_server_submit(fem_server* S, const fem_desc* desc, con
     R.f.assign(f_glob, f_glob + glen);
     R.rtol = rtol;
     R.maxit = maxit;
+    std::lock_guard<std::mutex> lk(S->mu);
     R.ticket = S->next_ticket++;
     *ticket = R.ticket;
     S->state[R.ticket] = 0;
@@ -513,8 +522,12 @@ static fem_status admit(fem_server* S, Request& R) {
     A->req = std::move(R);
     A->block_off = off;
     A->block_bytes = need;
-    S->in_use += need;
-    S->high_water = std::max(S->high_water, S->in_use);
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->in_use += need;
+        S->high_water = std::max(S->high_water, S->in_use);
+        S->state[A->req.ticket] = 1;
+    }
     A->req.t_admit = std::chrono::steady_clock::now();
     // f goes to the tail of the block (the solve's q vector) on the copy
     // stream; the solve starts in the next step, when the copy is done
@@ -527,7 +540,6 @@ static fem_status admit(fem_server* S, Request& R) {
     A->req.f.clear();
     A->req.f.shrink_to_fit();
     S->staged.push_back(A);
-    S->state[A->req.ticket] = 1;
     return FEM_OK;
 }
 
@@ -601,8 +613,11 @@ static fem_status retire_finish(fem_server* S) {
         D.info.status = A->status;
         D.info.relres = A->relres;
         D.info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - A->req.t_admit).count();
-        S->done[A->req.ticket] = std::move(D);
-        S->state[A->req.ticket] = 2;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->done[A->req.ticket] = std::move(D);
+            S->state[A->req.ticket] = 2;
+        }
         release_active(S, A);
     }
     S->retiring.clear();
@@ -660,11 +675,22 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
         }
     }
     const size_t nstaged0 = S->staged.size();
-    while (!S->queue.empty() && (int)(S->active.size() + S->staged.size()) < S->max_active) {
-        fem_status st = admit(S, S->queue.front());
-        if (st == FEM_EAGAIN) break;
+    while ((int)(S->active.size() + S->staged.size()) < S->max_active) {
+        Request R;
+        {
+            std::lock_guard<std::mutex> lk(S->mu);
+            if (S->queue.empty()) break;
+            R = std::move(S->queue.front());
+            S->queue.pop_front();
+        }
+        fem_status st = admit(S, R);
+        if (st == FEM_EAGAIN) {
+            // not yet: back to the head of the queue (only this thread pops)
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->queue.push_front(std::move(R));
+            break;
+        }
         if (st != FEM_OK) return st;
-        S->queue.pop_front();
     }
     if (S->staged.size() > nstaged0) FEM_HIP(hipEventRecord(S->ev_up, S->copy), "server upload");
     hipStream_t s = S->stream;
@@ -805,6 +831,7 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
         if (stf != FEM_OK) return stf;
     }
     if (n_active) *n_active = (int)S->active.size();
+    std::lock_guard<std::mutex> lk(S->mu);
     if (n_queued) *n_queued = (int)S->queue.size();
     if (n_done) *n_done = (int)S->done.size();
     return FEM_OK;
@@ -812,6 +839,7 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
 
 extern "C" fem_status fem_server_poll(fem_server* S, uint64_t ticket, double* u_glob, fem_solve_info* info) {
     if (!S) return set_error(FEM_EINVAL, "fem_server_poll: NULL server");
+    std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->state.find(ticket);
     if (it == S->state.end()) return set_error(FEM_ENOTFOUND, "fem_server_poll: unknown ticket");
     if (it->second != 2) return FEM_EAGAIN;
@@ -834,6 +862,7 @@ extern "C" fem_status fem_server_stats(fem_server* S, double* out, int n) {
 extern "C" int fem_server_finished(fem_server* S, uint64_t* out, int max_tickets) {
     if (!S) return 0;
     std::vector<uint64_t> t;
+    std::lock_guard<std::mutex> lk(S->mu);
     t.reserve(S->done.size());
     for (const auto& kv : S->done) t.push_back(kv.first);
     std::sort(t.begin(), t.end());
@@ -844,6 +873,7 @@ extern "C" int fem_server_finished(fem_server* S, uint64_t* out, int max_tickets
 
 extern "C" fem_status fem_server_memory(fem_server* S, size_t* in_use, size_t* high_water) {
     if (!S) return set_error(FEM_EINVAL, "fem_server_memory: NULL server");
+    std::lock_guard<std::mutex> lk(S->mu);
     if (in_use) *in_use = S->in_use;
     if (high_water) *high_water = S->high_water;
     return FEM_OK;

@@ -136,3 +136,15 @@ def test_server_admission_by_memory(F):
     assert not pending
     assert S.memory()[1] <= budget
     S.close()
+
+
+def test_threaded_stream_driver(F):
+    """The stream driver steps the server on its own thread while the client
+    thread submits and collects; every request of a short burst completes."""
+    from paper_2607_02335_amd import serve
+    reqs = synth.serve_stream(count=40, rate=400.0, seed=9, nmax=8)
+    note("threaded stream of 40 requests")
+    res = serve.run_stream(reqs, hbm_budget=4 << 30, max_active=16)
+    assert res["requests"] == 40 and res["failures"] == 0
+    assert res["mean_iters"] > 0 and res["p99_latency_s"] >= res["p50_latency_s"] > 0
+    assert res["hbm_high_water_bytes"] <= 4 << 30
