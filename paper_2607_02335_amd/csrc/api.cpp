@@ -227,6 +227,12 @@ extern "C" fem_status fem_problem_create(const fem_desc* d, void* stream, fem_pr
     return create_problem(d, static_cast<hipStream_t>(stream), out, nullptr);
 }
 
+namespace fem {
+// Free a problem without waiting for its stream: for callers that know no
+// queued work still uses it (the solve server, after a solve's last copy).
+void destroy_problem_nosync(fem_problem* P) { free_problem(P); }
+}  // namespace fem
+
 extern "C" fem_status fem_problem_destroy(fem_problem* P) {
     if (!P) return FEM_OK;
     if (P->owned_by_batch) return set_error(FEM_EINVAL, "problem belongs to a batch");

@@ -298,11 +298,10 @@ struct fem_server {
     // of (offset -> bytes), coalesced on release
     char* arena = nullptr;
     std::map<size_t, size_t> free_blocks;
-    // pinned staging for uploads at admission and downloads at retirement:
-    // two bump regions used by alternate steps.  A step's region is free again
-    // two steps later: its uploads were consumed before the step's scalar
-    // read-back completed, and its downloads are handed over (retire_finish)
-    // during the next step.
+    // pinned staging for uploads (request right-hand sides at admission,
+    // set-up data at activation): two bump regions used by alternate steps.
+    // A step's region is free again two steps later, its copies having been
+    // consumed before that step's scalar read-back completed.
     char* stage_buf[2] = {nullptr, nullptr};
     size_t stage_capv[2] = {0, 0};
     int cur = 0;
@@ -310,10 +309,19 @@ struct fem_server {
     size_t stage_cap = 0, stage_used = 0;
     // admitted solves whose right-hand sides are being uploaded (event ev_up)
     std::vector<Active*> staged;
-    // solves whose solutions are being copied out (event ev_retire)
-    std::vector<Active*> retiring;
-    std::vector<char*> retiring_at;
-    hipEvent_t ev_retire = nullptr, ev_scalars = nullptr;
+    // solves whose solutions are being copied out: one batch per step, each
+    // with its own pinned buffer and event, handed over once complete
+    struct RetireBatch {
+        std::vector<Active*> fin;
+        std::vector<size_t> at;        // offset of each solution in buf
+        char* buf = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+    };
+    std::deque<RetireBatch> rbatches;
+    std::vector<std::pair<char*, size_t>> rpool;   // free pinned download buffers
+    std::vector<hipEvent_t> evpool;
+    hipEvent_t ev_scalars = nullptr;
     // request uploads and solution downloads run on their own stream (at the
     // default priority), ordered against the compute stream by events, so
     // the copy engine overlaps the iterations of the other solves
@@ -415,7 +423,6 @@ extern "C" fem_status fem_server_create(size_t hbm_budget, int max_active, int s
         hipMalloc((void**)&S->d_collect, sizeof(double) * 4 * max_active) != hipSuccess ||
         hipHostMalloc((void**)&S->h_collect, sizeof(double) * 4 * max_active, hipHostMallocDefault) != hipSuccess ||
         hipMalloc((void**)&S->arena, hbm_budget) != hipSuccess ||
-        hipEventCreateWithFlags(&S->ev_retire, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&S->ev_scalars, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&S->ev_up, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&S->ev_ext, hipEventDisableTiming) != hipSuccess ||
@@ -424,7 +431,6 @@ extern "C" fem_status fem_server_create(size_t hbm_budget, int max_active, int s
         hipFree(S->d_collect);
         if (S->h_collect) hipHostFree(S->h_collect);
         if (S->arena) hipFree(S->arena);
-        if (S->ev_retire) hipEventDestroy(S->ev_retire);
         if (S->ev_scalars) hipEventDestroy(S->ev_scalars);
         if (S->ev_up) hipEventDestroy(S->ev_up);
         if (S->ev_ext) hipEventDestroy(S->ev_ext);
@@ -438,7 +444,8 @@ extern "C" fem_status fem_server_create(size_t hbm_budget, int max_active, int s
 }
 
 static void release_active(fem_server* S, Active* A) {
-    destroy_problem_internal(A->P);
+    // the solve's last work (its download) has completed: no stream wait
+    destroy_problem_nosync(A->P);
     arena_free(S, A->block_off, A->block_bytes);
     {
         std::lock_guard<std::mutex> lk(S->mu);
@@ -455,12 +462,17 @@ extern "C" fem_status fem_server_destroy(fem_server* S) {
     S->st.destroy();
     hipFree(S->d_collect);
     hipHostFree(S->h_collect);
-    for (Active* A : S->retiring) release_active(S, A);
+    for (auto& b : S->rbatches) {
+        for (Active* A : b.fin) release_active(S, A);
+        hipHostFree(b.buf);
+        hipEventDestroy(b.ev);
+    }
+    for (auto& pb : S->rpool) hipHostFree(pb.first);
+    for (hipEvent_t e : S->evpool) hipEventDestroy(e);
     for (Active* A : S->staged) release_active(S, A);
     hipFree(S->arena);
     for (int k = 0; k < 2; ++k)
         if (S->stage_buf[k]) hipHostFree(S->stage_buf[k]);
-    hipEventDestroy(S->ev_retire);
     hipEventDestroy(S->ev_scalars);
     hipEventDestroy(S->ev_up);
     hipEventDestroy(S->ev_ext);
@@ -597,62 +609,81 @@ static fem_status activate(fem_server* S, Active* A) {
     return FEM_OK;
 }
 
-// Retire finished solves in two halves.  start: every solution goes to
-// global order and into the pinned staging with asynchronous copies, and an
-// event marks their end; finish (next step, or destroy): wait for the event,
-// hand the solutions to the host and free the solves' arena blocks.
-static fem_status retire_finish(fem_server* S) {
-    if (S->retiring.empty()) return FEM_OK;
-    FEM_HIP(hipEventSynchronize(S->ev_retire), "server retire");
-    for (size_t i = 0; i < S->retiring.size(); ++i) {
-        Active* A = S->retiring[i];
-        Done D;
-        const double* src = reinterpret_cast<const double*>(S->retiring_at[i]);
-        D.u.assign(src, src + A->P->global_len);
-        D.info.iters = A->iters;
-        D.info.status = A->status;
-        D.info.relres = A->relres;
-        D.info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - A->req.t_admit).count();
-        {
-            std::lock_guard<std::mutex> lk(S->mu);
-            S->done[A->req.ticket] = std::move(D);
-            S->state[A->req.ticket] = 2;
+// Retire finished solves: start moves every solution to global order
+// (compute stream) and downloads it into a pinned buffer of the batch (copy
+// stream, after an event), then records the batch's event; collect hands
+// the solutions of completed batches to the host and frees the solves'
+// arena blocks, waiting only when asked to (or when many batches are open).
+static fem_status retire_collect(fem_server* S, bool block) {
+    while (!S->rbatches.empty()) {
+        fem_server::RetireBatch& b = S->rbatches.front();
+        if (block || S->rbatches.size() > 8) {
+            FEM_HIP(hipEventSynchronize(b.ev), "server retire");
+        } else {
+            const hipError_t q = hipEventQuery(b.ev);
+            if (q == hipErrorNotReady) break;
+            if (q != hipSuccess) return hip_error(q, "server retire");
         }
-        release_active(S, A);
+        for (size_t i = 0; i < b.fin.size(); ++i) {
+            Active* A = b.fin[i];
+            Done D;
+            const double* src = reinterpret_cast<const double*>(b.buf + b.at[i]);
+            D.u.assign(src, src + A->P->global_len);
+            D.info.iters = A->iters;
+            D.info.status = A->status;
+            D.info.relres = A->relres;
+            D.info.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - A->req.t_admit).count();
+            {
+                std::lock_guard<std::mutex> lk(S->mu);
+                S->done[A->req.ticket] = std::move(D);
+                S->state[A->req.ticket] = 2;
+            }
+            release_active(S, A);
+        }
+        S->rpool.emplace_back(b.buf, b.cap);
+        S->evpool.push_back(b.ev);
+        S->rbatches.pop_front();
     }
-    S->retiring.clear();
-    S->retiring_at.clear();
     return FEM_OK;
 }
 
 static fem_status retire_start(fem_server* S, std::vector<Active*>& fin) {
     if (fin.empty()) return FEM_OK;
+    fem_server::RetireBatch b;
     size_t bytes = 0;
-    for (Active* A : fin) bytes += align256(sizeof(double) * A->P->global_len);
-    char* hs = stage_take(S, bytes);
-    if (!hs) {
-        // this step's staging is taken by admissions: let their copies finish
-        FEM_HIP(hipStreamSynchronize(S->stream), "server retire");
-        FEM_HIP(hipStreamSynchronize(S->copy), "server retire");
-        S->stage_used = 0;
-        hs = stage_take(S, bytes);
-        if (!hs) return set_error(FEM_ENOMEM, "server retire: pinned staging allocation failed");
+    for (Active* A : fin) {
+        b.at.push_back(bytes);
+        bytes += align256(sizeof(double) * A->P->global_len);
     }
-    // u (FP64) to global order (staged in each solve's q) on the compute
-    // stream, then the downloads on the copy stream
+    // a pooled pinned buffer that is large enough, else a new one
+    for (size_t k = 0; k < S->rpool.size(); ++k) {
+        if (S->rpool[k].second >= bytes) {
+            b.buf = S->rpool[k].first;
+            b.cap = S->rpool[k].second;
+            S->rpool.erase(S->rpool.begin() + k);
+            break;
+        }
+    }
+    if (!b.buf) {
+        b.cap = std::max<size_t>(bytes, 32u << 20);
+        FEM_HIP(hipHostMalloc((void**)&b.buf, b.cap, hipHostMallocDefault), "server retire buffer");
+    }
+    if (!S->evpool.empty()) {
+        b.ev = S->evpool.back();
+        S->evpool.pop_back();
+    } else {
+        FEM_HIP(hipEventCreateWithFlags(&b.ev, hipEventDisableTiming), "server retire event");
+    }
     for (Active* A : fin) FEM_HIP(run_extract(A->P, A->u, A->q, FEM_F64), "server extract");
     FEM_HIP(hipEventRecord(S->ev_ext, S->stream), "server retire");
     FEM_HIP(hipStreamWaitEvent(S->copy, S->ev_ext, 0), "server retire");
-    char* q = hs;
-    for (Active* A : fin) {
-        fem_problem* P = A->P;
-        S->retiring.push_back(A);
-        S->retiring_at.push_back(q);
-        FEM_HIP(hipMemcpyAsync(q, A->q, sizeof(double) * P->global_len, hipMemcpyDeviceToHost, S->copy),
+    for (size_t i = 0; i < fin.size(); ++i)
+        FEM_HIP(hipMemcpyAsync(b.buf + b.at[i], fin[i]->q, sizeof(double) * fin[i]->P->global_len,
+                               hipMemcpyDeviceToHost, S->copy),
                 "server download");
-        q += align256(sizeof(double) * P->global_len);
-    }
-    FEM_HIP(hipEventRecord(S->ev_retire, S->copy), "server retire");
+    FEM_HIP(hipEventRecord(b.ev, S->copy), "server retire");
+    b.fin = fin;
+    S->rbatches.push_back(std::move(b));
     return FEM_OK;
 }
 
@@ -794,9 +825,9 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
             FEM_HIP(launch_cg_p(S->sp, S->variant, ents.data(), n, &S->st, s), "server direction");
         }
         S->t_phase[1] += clk.lap();
-        // the previous step's retirements reach the host while the GPU runs
-        // this step's work
-        fem_status stf = retire_finish(S);
+        // completed downloads of earlier steps reach the host while the GPU
+        // runs this step's work
+        fem_status stf = retire_collect(S, false);
         if (stf != FEM_OK) return stf;
         S->t_phase[3] += clk.lap();
         FEM_HIP(hipEventSynchronize(S->ev_scalars), "server read-back");
@@ -826,8 +857,8 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
         S->t_phase[4] += clk.lap();
     }
     if (na == 0) {
-        // nothing ran this step: hand over the previous step's retirements now
-        fem_status stf = retire_finish(S);
+        // nothing ran this step: hand over what is pending (waiting for it)
+        fem_status stf = retire_collect(S, true);
         if (stf != FEM_OK) return stf;
     }
     if (n_active) *n_active = (int)S->active.size();

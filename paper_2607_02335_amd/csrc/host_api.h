@@ -30,6 +30,8 @@ size_t desc_cell_len(const fem_desc* d);
 fem_status create_problem(const fem_desc* d, hipStream_t stream, fem_problem** out, const ProblemMem* mem = nullptr);
 // Pinned staging bytes create_problem needs with caller memory.
 size_t problem_stage_bytes(const fem_desc* d);
+// Free a problem without synchronising its stream (no queued work may use it).
+void destroy_problem_nosync(fem_problem* P);
 
 // Solver pieces reused by the server (all asynchronous on P->stream).
 fem_status smoother_run(fem_problem* P, const void* r, void* z, int prec, int sweeps, double omega);
