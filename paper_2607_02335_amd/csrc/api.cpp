@@ -127,6 +127,11 @@ fem_status create_problem(const fem_desc* d, hipStream_t stream, fem_problem** o
     P->stream = stream;
     hipGetDevice(&P->device);
     P->fd_dir_stride = fd_stride(d);
+    if (entry_of(P).ntiles_red > kRedParts) {
+        // reduction partials would run past their group in the workspace
+        free_problem(P);
+        return set_error(FEM_EINVAL, "create_problem: reduction tiling exceeds kRedParts");
+    }
 
     // geometry
     std::vector<double> h;
@@ -506,18 +511,21 @@ extern "C" fem_status pcg_solve(fem_problem* P, const double* b, double* u, doub
         if (!(qp > 0) || !std::isfinite(qp)) return finish(FEM_EBREAKDOWN, k, rel);
         rel = std::sqrt(P->h_red[kSlotRN]) / bn;
         if (!std::isfinite(rel)) return finish(FEM_EBREAKDOWN, k, rel);
-        if (rel <= rtol) return finish(FEM_OK, k, rel);
-        if (k >= maxit) break;
+        if (rel <= rtol || k >= maxit) {
+            // the last r update's u step (u catches up one update late)
+            FEM_HIP(run_cg_update_u(P, u, p), "pcg_solve update u");
+            FEM_HIP(hipStreamSynchronize(P->stream), "pcg_solve");
+            return finish(rel <= rtol ? FEM_OK : FEM_ENOTCONV, k, rel);
+        }
         st = smoother_run(P, rs, z, sp, sweeps, omega);
         if (st != FEM_OK) return finish(st, k, rel);
         if (variant == FEM_CG_PCG) {
             FEM_HIP(run_slot_copy(P, kSlotRZOld, kSlotRZ), "pcg_solve slots");
             FEM_HIP(run_dot(P, r, FEM_F64, z, sp, kSlotRZ), "pcg_solve dot");
         } else {
-            FEM_HIP(run_dot(P, q, FEM_F64, z, sp, kSlotQZ), "pcg_solve dot");
-            FEM_HIP(run_dot(P, r, FEM_F64, z, sp, kSlotRZ), "pcg_solve dot");
+            FEM_HIP(run_dot_qz_rz(P, q, r, z, sp), "pcg_solve dot");
         }
-        FEM_HIP(run_cg_update_p(P, p, z, sp, variant), "pcg_solve update p");
+        FEM_HIP(run_cg_update_p(P, p, u, z, sp, variant), "pcg_solve update p");
     }
     return finish(FEM_ENOTCONV, k, rel);
 }

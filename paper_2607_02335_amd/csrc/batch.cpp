@@ -756,9 +756,7 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
             FEM_HIP(launch_dot(FEM_F64, FEM_F64, ents.data(), n, &S->st, s, kSlotQP), "server dot");
             for (int i = 0; i < n; ++i) {
                 ents[i] = entry_of(g[i]->P);
-                ents[i].a = g[i]->p;
                 ents[i].b = g[i]->q;
-                ents[i].c = g[i]->u;
                 ents[i].d = g[i]->r;
             }
             FEM_HIP(launch_cg_ur(ents.data(), n, &S->st, s), "server update");
@@ -803,24 +801,29 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
             if (S->variant == FEM_CG_PCG) {
                 for (int i = 0; i < n; ++i) ents[i] = entry_of(g[i]->P);
                 FEM_HIP(launch_slot_copy(ents.data(), n, &S->st, s, kSlotRZOld, kSlotRZ), "server slots");
+                for (int i = 0; i < n; ++i) {
+                    ents[i] = entry_of(g[i]->P);
+                    ents[i].a = g[i]->r;
+                    ents[i].b = g[i]->z;
+                }
+                FEM_HIP(launch_dot(FEM_F64, S->sp, ents.data(), n, &S->st, s, kSlotRZ), "server dot");
             } else {
                 for (int i = 0; i < n; ++i) {
                     ents[i] = entry_of(g[i]->P);
                     ents[i].a = g[i]->q;
+                    ents[i].d = g[i]->r;
                     ents[i].b = g[i]->z;
                 }
-                FEM_HIP(launch_dot(FEM_F64, S->sp, ents.data(), n, &S->st, s, kSlotQZ), "server dot");
+                FEM_HIP(launch_dot_qz_rz(S->sp, ents.data(), n, &S->st, s), "server dots");
             }
-            for (int i = 0; i < n; ++i) {
-                ents[i] = entry_of(g[i]->P);
-                ents[i].a = g[i]->r;
-                ents[i].b = g[i]->z;
-            }
-            FEM_HIP(launch_dot(FEM_F64, S->sp, ents.data(), n, &S->st, s, kSlotRZ), "server dot");
+            // also the u step of this iteration's r update (every solve runs
+            // this phase before its convergence is known, so a finishing
+            // solve's u is complete here)
             for (int i = 0; i < n; ++i) {
                 ents[i] = entry_of(g[i]->P);
                 ents[i].a = g[i]->z;
                 ents[i].c = g[i]->p;
+                ents[i].d = g[i]->u;
             }
             FEM_HIP(launch_cg_p(S->sp, S->variant, ents.data(), n, &S->st, s), "server direction");
         }

@@ -301,24 +301,24 @@ __global__ void __launch_bounds__(256) k_fill_zero(S* __restrict__ a, size_t n) 
 }
 
 // --------------------------------------------------------- (F)PCG updates
-// u += alpha p; r -= alpha q with alpha = <r,z>/<q,p> from the slots; the
-// smoother's copy of r (precision RS) is written in the same pass.
+// r -= alpha q with alpha = <r,z>/<q,p> from the slots; alpha is saved in a
+// slot and u += alpha p happens in the next p update (which reads p anyway),
+// or in k_cg_u when the iteration stops.  The smoother's copy of r
+// (precision RS) is written in the same pass when requested.
 template <typename RS, bool MULTI>
 __global__ void __launch_bounds__(256) k_cg_ur(LaunchTable L) {
     for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
         const ProbEntry& pe = entry<MULTI>(L, tile);
         const int t = tile - pe.tile_begin;
-        const double* sl = red_slots(pe.red);
+        double* sl = red_slots(pe.red);
         const double alpha = sl[kSlotRZ] / sl[kSlotQP];
+        if (t == 0 && threadIdx.x == 0) sl[kSlotAlpha] = alpha;
         size_t lo, hi;
         red_range(pe, t, lo, hi);
-        const double* p = static_cast<const double*>(pe.a);
         const double* q = static_cast<const double*>(pe.b);
-        double* u = static_cast<double*>(pe.c);
         double* r = static_cast<double*>(pe.d);
         RS* rs = static_cast<RS*>(pe.e);
         for (size_t i = lo + threadIdx.x; i < hi; i += 256) {
-            u[i] = u[i] + alpha * p[i];
             const double rn = r[i] - alpha * q[i];
             r[i] = rn;
             if (rs) store_from(rs + i, (typename Prec<RS>::C)rn);
@@ -326,7 +326,8 @@ __global__ void __launch_bounds__(256) k_cg_ur(LaunchTable L) {
     }
 }
 
-// p = z + beta p; beta = <r',z'>/<r,z> (PCG) or -<q,z'>/<q,p> (FCG)
+// u += alpha p with the saved alpha; then p = z + beta p with
+// beta = <r',z'>/<r,z> (PCG) or -<q,z'>/<q,p> (FCG).  pe: a = z, c = p, d = u.
 template <typename SZ, bool MULTI>
 __global__ void __launch_bounds__(256) k_cg_p(LaunchTable L, int variant) {
     for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
@@ -334,12 +335,60 @@ __global__ void __launch_bounds__(256) k_cg_p(LaunchTable L, int variant) {
         const int t = tile - pe.tile_begin;
         const double* sl = red_slots(pe.red);
         const double beta = variant == FEM_CG_PCG ? sl[kSlotRZ] / sl[kSlotRZOld] : -sl[kSlotQZ] / sl[kSlotQP];
+        const double alpha = sl[kSlotAlpha];
         size_t lo, hi;
         red_range(pe, t, lo, hi);
         const SZ* z = static_cast<const SZ*>(pe.a);
         double* p = static_cast<double*>(pe.c);
-        for (size_t i = lo + threadIdx.x; i < hi; i += 256)
-            p[i] = load_as<double>(z + i) + beta * p[i];
+        double* u = static_cast<double*>(pe.d);
+        for (size_t i = lo + threadIdx.x; i < hi; i += 256) {
+            const double pi = p[i];
+            u[i] = u[i] + alpha * pi;
+            p[i] = load_as<double>(z + i) + beta * pi;
+        }
+    }
+}
+
+// u += alpha p with the saved alpha (the iteration's last step)
+template <bool MULTI>
+__global__ void __launch_bounds__(256) k_cg_u(LaunchTable L) {
+    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+        const ProbEntry& pe = entry<MULTI>(L, tile);
+        const int t = tile - pe.tile_begin;
+        const double alpha = red_slots(pe.red)[kSlotAlpha];
+        size_t lo, hi;
+        red_range(pe, t, lo, hi);
+        const double* p = static_cast<const double*>(pe.a);
+        double* u = static_cast<double*>(pe.c);
+        for (size_t i = lo + threadIdx.x; i < hi; i += 256) u[i] = u[i] + alpha * p[i];
+    }
+}
+
+// partials of <q, z> (group 0) and <r, z> (group 3) in one pass.
+// pe: a = q, d = r (FP64), b = z (SZ).
+template <typename SZ, bool MULTI>
+__global__ void __launch_bounds__(256) k_dot_qz_rz(LaunchTable L) {
+    __shared__ double sh[4];
+    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+        const ProbEntry& pe = entry<MULTI>(L, tile);
+        const int t = tile - pe.tile_begin;
+        size_t lo, hi;
+        red_range(pe, t, lo, hi);
+        const double* q = static_cast<const double*>(pe.a);
+        const double* r = static_cast<const double*>(pe.d);
+        const SZ* z = static_cast<const SZ*>(pe.b);
+        double aq = 0.0, ar = 0.0;
+        for (size_t i = lo + threadIdx.x; i < hi; i += 256) {
+            const double zi = load_as<double>(z + i);
+            aq += q[i] * zi;
+            ar += r[i] * zi;
+        }
+        const double sq = block_sum(aq, sh);
+        const double sr = block_sum(ar, sh);
+        if (threadIdx.x == 0) {
+            pe.red[0 * kRedParts + t] = sq;
+            pe.red[3 * kRedParts + t] = sr;
+        }
     }
 }
 
@@ -410,6 +459,7 @@ ProbEntry entry_of(const fem_problem* P) {
     } else {
         e.blocks_per_red = 1;
         int split = (int)((want + P->nblk - 1) / P->nblk);
+        if (split > kRedParts / P->nblk) split = kRedParts / P->nblk;   // nblk * split <= kRedParts
         if (split > (nn + 3) / 4) split = (nn + 3) / 4;        // at least 4 node planes per tile
         if (split < 1) split = 1;
         const int lchunk = (nn + split - 1) / split;
@@ -616,10 +666,10 @@ hipError_t run_distribute(fem_problem* P, const double* r, void* out, int prec, 
 
 hipError_t run_cg_update_ur(fem_problem* P, double* u, double* r, const double* p, const double* q,
                             void* rs, int rs_prec) {
+    (void)u;
+    (void)p;
     ProbEntry e = entry_of(P);
-    e.a = p;
     e.b = q;
-    e.c = u;
     e.d = r;
     e.e = rs;
     e.tile_begin = 0;
@@ -636,10 +686,11 @@ hipError_t run_cg_update_ur(fem_problem* P, double* u, double* r, const double* 
     });
 }
 
-hipError_t run_cg_update_p(fem_problem* P, double* p, const void* z, int zprec, int variant) {
+hipError_t run_cg_update_p(fem_problem* P, double* p, double* u, const void* z, int zprec, int variant) {
     ProbEntry e = entry_of(P);
     e.a = z;
     e.c = p;
+    e.d = u;
     e.tile_begin = 0;
     LaunchTable L{};
     L.nprob = 1;
@@ -652,6 +703,43 @@ hipError_t run_cg_update_p(fem_problem* P, double* p, const void* z, int zprec, 
         hipLaunchKernelGGL((k_cg_p<S, false>), dim3(grid), dim3(256), 0, P->stream, L, variant);
         return hipGetLastError();
     });
+}
+
+hipError_t run_cg_update_u(fem_problem* P, double* u, const double* p) {
+    ProbEntry e = entry_of(P);
+    e.a = p;
+    e.c = u;
+    e.tile_begin = 0;
+    LaunchTable L{};
+    L.nprob = 1;
+    L.total_tiles = e.ntiles_red;
+    L.one = e;
+    const int grid = e.ntiles_red < kMaxGrid ? e.ntiles_red : kMaxGrid;
+    TraceSpan ts("cg_update_u", P->p, FEM_F64, P->stream);
+    hipLaunchKernelGGL(k_cg_u<false>, dim3(grid), dim3(256), 0, P->stream, L);
+    return hipGetLastError();
+}
+
+hipError_t run_dot_qz_rz(fem_problem* P, const double* q, const double* r, const void* z, int zprec) {
+    ProbEntry e = entry_of(P);
+    e.a = q;
+    e.d = const_cast<double*>(r);
+    e.b = z;
+    e.tile_begin = 0;
+    LaunchTable L{};
+    L.nprob = 1;
+    L.total_tiles = e.ntiles_red;
+    L.one = e;
+    hipError_t err = dispatch_prec(zprec, [&](auto tag) {
+        using S = decltype(tag);
+        TraceSpan ts("dot", P->p, Prec<S>::id, P->stream);
+        hipLaunchKernelGGL((k_dot_qz_rz<S, false>), dim3(L.total_tiles), dim3(256), 0, P->stream, L);
+        return hipGetLastError();
+    });
+    if (err != hipSuccess) return err;
+    err = finish_reduction(P, e, 0, kSlotQZ);
+    if (err != hipSuccess) return err;
+    return finish_reduction(P, e, 3, kSlotRZ);
 }
 
 hipError_t run_slot_copy(fem_problem* P, int dst, int src) {
@@ -788,6 +876,26 @@ hipError_t launch_cg_p(int zprec, int variant, ProbEntry* ents, int nprob, Table
         else hipLaunchKernelGGL((k_cg_p<S, false>), dim3(grid), dim3(256), 0, s, L, variant);
         return hipGetLastError();
     });
+}
+
+hipError_t launch_dot_qz_rz(int zprec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s) {
+    if (nprob <= 0) return hipSuccess;
+    LaunchTable L{};
+    L.nprob = nprob;
+    L.total_tiles = tiles_red(ents, nprob);
+    hipError_t err = stage_table(L, ents, nprob, st, s);
+    if (err != hipSuccess) return err;
+    const int grid = L.total_tiles < kMaxGrid ? L.total_tiles : kMaxGrid;
+    err = dispatch_prec(zprec, [&](auto tag) {
+        using S = decltype(tag);
+        if (nprob > 1) hipLaunchKernelGGL((k_dot_qz_rz<S, true>), dim3(grid), dim3(256), 0, s, L);
+        else hipLaunchKernelGGL((k_dot_qz_rz<S, false>), dim3(grid), dim3(256), 0, s, L);
+        return hipGetLastError();
+    });
+    if (err != hipSuccess) return err;
+    err = final_multi(L, s, 0, kSlotQZ);
+    if (err != hipSuccess) return err;
+    return final_multi(L, s, 3, kSlotRZ);
 }
 
 hipError_t launch_slot_copy(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int dst, int src) {

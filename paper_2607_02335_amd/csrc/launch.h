@@ -20,6 +20,7 @@ enum RedSlot {
     kSlotRZOld = 4,   // previous <r, z>
     kSlotTmp = 5,     // generic dot result
     kSlotB2 = 6,      // ||G^T b||^2
+    kSlotAlpha = 7,   // alpha of the last r update (u catches up in the next p update)
     kSlotCount = 8
 };
 constexpr int kRedStride = kRedParts * 4 + kSlotCount;   // 4 partial groups + slots
@@ -107,9 +108,14 @@ hipError_t launch_distribute(int p, int prec, ProbEntry* ents, int nprob, TableS
 // assembled norm (one degree p): a = r (FP64); slot <- ||G^T r||^2
 hipError_t launch_anorm(int p, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int slot);
 // u += alpha p, r -= alpha q: a = p, b = q, c = u, d = r
+// r -= alpha q (alpha saved in kSlotAlpha); u is updated later by launch_cg_p
+// (or launch_cg_u when the iteration stops)
 hipError_t launch_cg_ur(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s);
 // p = z + beta p: a = z (zprec), c = p
+// u += alpha p (saved alpha), then p = z + beta p; entries a = z, c = p, d = u
 hipError_t launch_cg_p(int zprec, int variant, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s);
+// <q, z> -> kSlotQZ and <r, z> -> kSlotRZ in one pass; entries a = q, d = r, b = z
+hipError_t launch_dot_qz_rz(int zprec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s);
 hipError_t launch_slot_copy(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int dst, int src);
 // out[2i] = slot a, out[2i+1] = slot b of problem i (device array)
 hipError_t launch_collect_slots(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int sa, int sb,
@@ -136,10 +142,13 @@ hipError_t run_assembled_norm2(fem_problem* P, const void* r, int prec, int slot
 hipError_t run_distribute(fem_problem* P, const double* r, void* out, int prec, int slot);
 // (F)PCG vector updates, scalars read from the device slots.
 // u += alpha p; r -= alpha q; optionally rs = (smoother precision) r.
+// u += alpha p with the saved alpha (the step the last r update left out)
+hipError_t run_cg_update_u(fem_problem* P, double* u, const double* p);
+hipError_t run_dot_qz_rz(fem_problem* P, const double* q, const double* r, const void* z, int zprec);
 hipError_t run_cg_update_ur(fem_problem* P, double* u, double* r, const double* p, const double* q,
                             void* rs, int rs_prec);
 // p = z + beta p  (beta from slots, variant 1 = PCG, 2 = FCG); z in zprec.
-hipError_t run_cg_update_p(fem_problem* P, double* p, const void* z, int zprec, int variant);
+hipError_t run_cg_update_p(fem_problem* P, double* p, double* u, const void* z, int zprec, int variant);
 // rz_old <- rz (slot copy), on device
 hipError_t run_slot_copy(fem_problem* P, int dst, int src);
 
