@@ -790,28 +790,51 @@ template <> struct SweepShape<3, double> { static constexpr int TX = 8, TY = 2, 
 template <> struct SweepShape<3, float> { static constexpr int TX = 8, TY = 4, NS = 64; };
 template <> struct SweepShape<3, bf16_t> { static constexpr int TX = 8, TY = 4, NS = 64; };
 
-// Phase 1 for p <= 3 reading the assembled residual: the tile's CBP patches
-// along x cover, for each of their (2p-1)^2 (y, z) rows, one contiguous run
-// of CBP*p + p - 1 global nodes; each node is loaded once (coalesced) and
-// placed in the one or two patches that contain it.  Then the FD solve as
-// in k_pi_solve_r.
+// Reciprocal of a positive normal value: the hardware estimate refined by
+// Newton-Raphson steps r <- r + r (1 - d r), two for FP64 and one for FP32
+// (each step doubles the correct bits), so the FD scaling multiplies instead
+// of running the full IEEE division sequence.
+__device__ __forceinline__ double recip_nr(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-d, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float recip_nr(float d) {
+    const float r = __builtin_amdgcn_rcpf(d);
+    const float e = __builtin_fmaf(-d, r, 1.0f);
+    return __builtin_fmaf(r, e, r);
+}
+
+// Phase 1 for p <= 3 reading the assembled residual.  A tile is CBP patches
+// along x sharing one (y, z) vertex; thread (pc, group) takes patch pc and
+// every LPT-th line.  The five 1D passes run x forward (a line of a patch is
+// 2p-1 consecutive nodes of the global-node array, loaded into registers
+// before the x bases are staged, so both loads are in flight together), y
+// forward, z forward + eigenvalue scaling + z backward (in registers), y
+// backward, and x backward (straight to the patch buffer).  The y and z
+// eigenbases are the same for the whole tile and are read as uniform
+// (scalar) loads; the per-patch x bases sit in LDS rows of odd stride so the
+// lanes of a wavefront hit distinct banks.
+template <int P> constexpr int solve_g_tile() { return P >= 3 ? 32 : 64; }
+
 template <int P, typename S, int CBP, bool MULTI>
 __global__ void __launch_bounds__(256) k_pi_solve_g(LaunchTable L) {
     using C = typename Prec<S>::C;
     constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
     constexpr int REC = fd_record(P);
     constexpr int NT = 256, LPT = NT / CBP;
-    constexpr int RUN = CBP * P + P - 1;
+    constexpr int KL = (nP2 + LPT - 1) / LPT;       // lines per thread (upper bound)
+    constexpr int SXS = nP2 | 1;                    // odd row stride of the x bases
     static_assert(NT % CBP == 0, "patches per tile must divide the workgroup");
     __shared__ C sv[nP3 * CBP];
-    __shared__ C sSx[CBP][nP2 + 1];
-    __shared__ C sLx[CBP][nP];
-    __shared__ C sSyz[2][nP2];
-    __shared__ C sLyz[2][nP];
+    __shared__ C sSx[CBP * SXS];
+    __shared__ C sLx[CBP * nP];
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= L.total_tiles) return;
     const int tid = threadIdx.x;
-    const int pc = tid % CBP;
+    const int pc = tid % CBP, grp = tid / CBP;
     const ProbEntry& pe = entry<MULTI>(L, tile);
     const int t = tile - pe.tile_begin;
     const int npx = pe.n[0] - 1, npy = pe.n[1] - 1;
@@ -821,125 +844,148 @@ __global__ void __launch_bounds__(256) k_pi_solve_g(LaunchTable L) {
     const int vi0 = 1 + xt * CBP;
     const int vi = vi0 + pc;
     const bool valid = vi <= npx;
-    {
-        const C* fx = static_cast<const C*>(pe.fd[0]) + (size_t)((valid ? vi : npx) - 1) * REC;
-        for (int w = tid / CBP; w < nP2 + nP; w += LPT) {
-            const C v = fx[w];
-            if (w < nP2) sSx[pc][w] = v; else sLx[pc][w - nP2] = v;
-        }
-        for (int w = tid; w < 2 * (nP2 + nP); w += NT) {
-            const int d = w / (nP2 + nP), o = w % (nP2 + nP);
-            const C v = static_cast<const C*>(pe.fd[1 + d])[(size_t)((d == 0 ? vj : vk) - 1) * REC + o];
-            if (o < nP2) sSyz[d][o] = v; else sLyz[d][o - nP2] = v;
-        }
-    }
+    const C* fy = static_cast<const C*>(pe.fd[1]) + (size_t)(vj - 1) * REC;
+    const C* fz = static_cast<const C*>(pe.fd[2]) + (size_t)(vk - 1) * REC;
+    C lines[KL][nP];
     {
         const C* g = static_cast<const C*>(pe.e);
         const size_t G0 = (size_t)pe.n[0] * P + 1, G1 = (size_t)pe.n[1] * P + 1;
-        const int Ibase = (vi0 - 1) * P + 1;
-        const int Iend = min(Ibase + RUN, npx * P + P);          // last interior node plane + 1
-        for (int item = tid; item < RUN * nP2; item += NT) {
-            const int x = item % RUN, yz = item / RUN;
-            const int qy = yz % nP, qz = yz / nP;
-            if (Ibase + x >= Iend) continue;
-            const C v = g[(size_t)(Ibase + x) + G0 * ((size_t)((vj - 1) * P + 1 + qy) + G1 * (size_t)((vk - 1) * P + 1 + qz))];
-            const int p1 = x / P;                                // patch whose qx = x - p1 P lies in [0, P-1]
+        const size_t base = (size_t)(vi - 1) * P + 1 + G0 * (((size_t)(vj - 1) * P + 1) + G1 * ((size_t)(vk - 1) * P + 1));
 #pragma unroll
-            for (int d = 0; d < 2; ++d) {
-                const int pp = p1 - d;
-                const int qx = x - pp * P;
-                if (pp >= 0 && pp < CBP && qx >= 0 && qx < nP) sv[(qx + nP * (qy + nP * qz)) * CBP + pp] = v;
+        for (int k = 0; k < KL; ++k) {
+            const int ln = grp + LPT * k;
+            const int qy = ln % nP, qz = ln / nP;
+            const C* src = g + base + G0 * (qy + G1 * qz);
+#pragma unroll
+            for (int i = 0; i < nP; ++i) lines[k][i] = (valid && ln < nP2) ? src[i] : (C)0;
+        }
+    }
+    {
+        // x bases and eigenvalues of the tile's patches (clamped past the end)
+        const C* fx0 = static_cast<const C*>(pe.fd[0]);
+        for (int w = tid; w < CBP * (nP2 + nP); w += NT) {
+            const int c = w / (nP2 + nP), o = w % (nP2 + nP);
+            const int line = min(vi0 + c, npx) - 1;
+            const C v = fx0[(size_t)line * REC + o];
+            if (o < nP2) sSx[c * SXS + o] = v; else sLx[c * nP + o - nP2] = v;
+        }
+    }
+    __syncthreads();
+    {
+        C Sm[nP2];
+#pragma unroll
+        for (int i = 0; i < nP2; ++i) Sm[i] = sSx[pc * SXS + i];
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {                              // x forward
+            const int ln = grp + LPT * k;
+            if (ln >= nP2) break;
+#pragma unroll
+            for (int j = 0; j < nP; ++j) {
+                C s = 0;
+#pragma unroll
+                for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * lines[k][i];
+                sv[(j + nP * ln) * CBP + pc] = s;
             }
         }
     }
     __syncthreads();
-    C Sm[nP2];
+    {
+        C Sm[nP2];
 #pragma unroll
-    for (int i = 0; i < nP2; ++i) Sm[i] = sSyz[1][i];
-    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // forward z
-        C v[nP];
+        for (int i = 0; i < nP2; ++i) Sm[i] = fy[i];
 #pragma unroll
-        for (int i = 0; i < nP; ++i) v[i] = sv[(ln + nP2 * i) * CBP + pc];
+        for (int k = 0; k < KL; ++k) {                              // y forward
+            const int ln = grp + LPT * k;
+            if (ln >= nP2) break;
+            const int qx = ln % nP, qz = ln / nP;
+            C v[nP];
 #pragma unroll
-        for (int j = 0; j < nP; ++j) {
-            C s = 0;
+            for (int i = 0; i < nP; ++i) v[i] = sv[(qx + nP * i + nP2 * qz) * CBP + pc];
 #pragma unroll
-            for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
-            sv[(ln + nP2 * j) * CBP + pc] = s;
+            for (int j = 0; j < nP; ++j) {
+                C s = 0;
+#pragma unroll
+                for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
+                sv[(qx + nP * j + nP2 * qz) * CBP + pc] = s;
+            }
         }
     }
     __syncthreads();
+    {
+        C Sm[nP2], lz[nP];
 #pragma unroll
-    for (int i = 0; i < nP2; ++i) Sm[i] = sSyz[0][i];
-    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // forward y
-        const int qx = ln % nP, qz = ln / nP;
-        C v[nP];
+        for (int i = 0; i < nP2; ++i) Sm[i] = fz[i];
 #pragma unroll
-        for (int i = 0; i < nP; ++i) v[i] = sv[(qx + nP * i + nP2 * qz) * CBP + pc];
+        for (int i = 0; i < nP; ++i) lz[i] = fz[nP2 + i];
 #pragma unroll
-        for (int j = 0; j < nP; ++j) {
-            C s = 0;
+        for (int k = 0; k < KL; ++k) {                              // z: forward, scale, backward
+            const int ln = grp + LPT * k;
+            if (ln >= nP2) break;
+            const int qx = ln % nP, qy = ln / nP;
+            const C lxy = sLx[pc * nP + qx] + fy[nP2 + qy];
+            C v[nP], w[nP];
 #pragma unroll
-            for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
-            sv[(qx + nP * j + nP2 * qz) * CBP + pc] = s;
+            for (int i = 0; i < nP; ++i) v[i] = sv[(ln + nP2 * i) * CBP + pc];
+#pragma unroll
+            for (int j = 0; j < nP; ++j) {
+                C s = 0;
+#pragma unroll
+                for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
+                w[j] = s * recip_nr(lxy + lz[j]);
+            }
+#pragma unroll
+            for (int i = 0; i < nP; ++i) {
+                C s = 0;
+#pragma unroll
+                for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * w[j];
+                sv[(ln + nP2 * i) * CBP + pc] = s;
+            }
         }
     }
     __syncthreads();
+    {
+        C Sm[nP2];
 #pragma unroll
-    for (int i = 0; i < nP2; ++i) Sm[i] = sSx[pc][i];
-    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // x: forward, scale, backward
-        const int qy = ln % nP, qz = ln / nP;
-        C v[nP], w[nP];
+        for (int i = 0; i < nP2; ++i) Sm[i] = fy[i];
 #pragma unroll
-        for (int i = 0; i < nP; ++i) v[i] = sv[(i + nP * ln) * CBP + pc];
-        const C lyz = sLyz[0][qy] + sLyz[1][qz];
+        for (int k = 0; k < KL; ++k) {                              // y backward
+            const int ln = grp + LPT * k;
+            if (ln >= nP2) break;
+            const int qx = ln % nP, qz = ln / nP;
+            C v[nP];
 #pragma unroll
-        for (int j = 0; j < nP; ++j) {
-            C s = 0;
+            for (int j = 0; j < nP; ++j) v[j] = sv[(qx + nP * j + nP2 * qz) * CBP + pc];
 #pragma unroll
-            for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
-            w[j] = s / (sLx[pc][j] + lyz);
-        }
+            for (int i = 0; i < nP; ++i) {
+                C s = 0;
 #pragma unroll
-        for (int i = 0; i < nP; ++i) {
-            C s = 0;
-#pragma unroll
-            for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * w[j];
-            sv[(i + nP * ln) * CBP + pc] = s;
+                for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * v[j];
+                sv[(qx + nP * i + nP2 * qz) * CBP + pc] = s;
+            }
         }
     }
     __syncthreads();
+    {
+        C Sm[nP2];
 #pragma unroll
-    for (int i = 0; i < nP2; ++i) Sm[i] = sSyz[0][i];
-    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // backward y
-        const int qx = ln % nP, qz = ln / nP;
-        C v[nP];
+        for (int i = 0; i < nP2; ++i) Sm[i] = sSx[pc * SXS + i];
+        C* pbuf = static_cast<C*>(pe.d);
+        const int pidx = (vi - 1) + npx * ((vj - 1) + npy * (vk - 1));
+        C* out = pbuf + (size_t)(pidx / kLanes) * nP3 * kLanes + (pidx % kLanes);
 #pragma unroll
-        for (int j = 0; j < nP; ++j) v[j] = sv[(qx + nP * j + nP2 * qz) * CBP + pc];
+        for (int k = 0; k < KL; ++k) {                              // x backward to the patch buffer
+            const int ln = grp + LPT * k;
+            if (ln >= nP2) break;
+            C v[nP];
 #pragma unroll
-        for (int i = 0; i < nP; ++i) {
-            C s = 0;
+            for (int j = 0; j < nP; ++j) v[j] = sv[(j + nP * ln) * CBP + pc];
 #pragma unroll
-            for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * v[j];
-            sv[(qx + nP * i + nP2 * qz) * CBP + pc] = s;
-        }
-    }
-    __syncthreads();
+            for (int i = 0; i < nP; ++i) {
+                C s = 0;
 #pragma unroll
-    for (int i = 0; i < nP2; ++i) Sm[i] = sSyz[1][i];
-    C* pbuf = static_cast<C*>(pe.d);
-    const int pidx = (vi - 1) + npx * ((vj - 1) + npy * (vk - 1));
-    C* out = pbuf + (size_t)(pidx / kLanes) * nP3 * kLanes + (pidx % kLanes);
-    for (int ln = tid / CBP; ln < nP2; ln += LPT) {                 // backward z, store
-        C v[nP];
-#pragma unroll
-        for (int j = 0; j < nP; ++j) v[j] = sv[(ln + nP2 * j) * CBP + pc];
-#pragma unroll
-        for (int i = 0; i < nP; ++i) {
-            C s = 0;
-#pragma unroll
-            for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * v[j];
-            if (valid) out[(size_t)(ln + nP2 * i) * kLanes] = s;
+                for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * v[j];
+                if (valid) out[(size_t)(i + nP * ln) * kLanes] = s;
+            }
         }
     }
 }
@@ -1373,7 +1419,9 @@ __global__ void __launch_bounds__(256) k_pi_combine_planes(LaunchTable L) {
     constexpr int BS = combine_brows<P>();          // b rows per wavefront
     constexpr int NBG = (N + BS - 1) / BS;          // row groups per plane
     const int lane = threadIdx.x & 63;
-    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+    // consecutive storage blocks (cell rows that read the same patch rows)
+    // on one XCD, so its L2 serves the shared patch values
+    const int tile = xcd_tile(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
     if (tile >= L.total_tiles) return;
     const ProbEntry& pe = entry<MULTI>(L, tile);
     const int blk = (tile - pe.tile_begin) / (N * NBG);
@@ -1545,7 +1593,7 @@ __global__ void __launch_bounds__(256) k_pi_combine_pm(LaunchTable L) {
     constexpr int CH = sizeof(C) >= 8 ? kLanes / 2 : kLanes;
     constexpr int RS = CH + 1;                      // padded LDS row
     __shared__ C sz[N2 * RS];
-    const int tile = blockIdx.x;
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);      // neighbouring blocks on one XCD
     if (tile >= L.total_tiles) return;
     const ProbEntry& pe = entry<MULTI>(L, tile);
     const int blk = (tile - pe.tile_begin) / N;
@@ -1777,7 +1825,7 @@ static hipError_t launch_pi_mfma(int accumulate, ProbEntry* ents, int nprob, Tab
     L2.total_tiles = tiles2;
     err = stage_table(L2, ents, nprob, d_tab, s);
     if (err != hipSuccess) return err;
-    const int grid2 = tiles2;
+    const int grid2 = (tiles2 + 7) / 8 * 8;
     TraceSpan ts("pi_combine", P, Prec<S>::id, s);
     if (nprob > 1) {
         if (accumulate) hipLaunchKernelGGL((k_pi_combine_pm<P, S, 1, true>), dim3(grid2), dim3(256), 0, s, L2);
@@ -1797,8 +1845,7 @@ static hipError_t launch_pi_mfma(int accumulate, ProbEntry* ents, int nprob, Tab
 // offset through the entry's tile_begin.
 template <int P, typename S>
 static hipError_t launch_pi_slabs(int accumulate, ProbEntry e, hipStream_t s, int nslab, int gcap) {
-    using C = typename Prec<S>::C;
-    constexpr int CBP = pi_patches_per_tile<P, C>();
+    constexpr int CBP = solve_g_tile<P>();
     constexpr int N = P + 1;
     hipError_t err = launch_assemble<P, S>(&e, 1, nullptr, s, gcap);
     if (err != hipSuccess) return err;
@@ -1828,7 +1875,7 @@ static hipError_t launch_pi_slabs(int accumulate, ProbEntry e, hipStream_t s, in
             L.one.tile_begin = -bdone * N;
             L.total_tiles = (bb - bdone) * N;
             TraceSpan ts("pi_combine", P, Prec<S>::id, s);
-            const int grid = (L.total_tiles + 3) / 4;
+            const int grid = ((L.total_tiles + 3) / 4 + 7) / 8 * 8;
             if (accumulate) hipLaunchKernelGGL((k_pi_combine_planes<P, S, 1, false>), dim3(grid), dim3(256), 0, s, L);
             else hipLaunchKernelGGL((k_pi_combine_planes<P, S, 0, false>), dim3(grid), dim3(256), 0, s, L);
             bdone = bb;
@@ -1897,7 +1944,8 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
                 for (int i = 0; i < nprob; ++i) {
                     const int npx = ents[i].n[0] - 1, npy = ents[i].n[1] - 1, npz = ents[i].n[2] - 1;
                     ents[i].tile_begin = t1;
-                    ents[i].ntiles = (npx > 0 && npy > 0 && npz > 0) ? ((npx + CBP - 1) / CBP) * npy * npz : 0;
+                    constexpr int TG = solve_g_tile<P>();
+                    ents[i].ntiles = (npx > 0 && npy > 0 && npz > 0) ? ((npx + TG - 1) / TG) * npy * npz : 0;
                     t1 += ents[i].ntiles;
                 }
                 LaunchTable Lg{};
@@ -1906,8 +1954,10 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
                 err = stage_table(Lg, ents, nprob, d_tab, s);
                 if (err != hipSuccess) return err;
                 TraceSpan ts("pi_solve", P, Prec<S>::id, s);
-                if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_g<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, Lg);
-                else hipLaunchKernelGGL((k_pi_solve_g<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, Lg);
+                constexpr int TG = solve_g_tile<P>();
+                const int grid_g = (t1 + 7) / 8 * 8;
+                if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_g<P, S, TG, true>), dim3(grid_g), dim3(256), 0, s, Lg);
+                else hipLaunchKernelGGL((k_pi_solve_g<P, S, TG, false>), dim3(grid_g), dim3(256), 0, s, Lg);
             }
         } else if constexpr (P == 4) {
             const int grid = (tiles + 7) / 8 * 8;
@@ -1960,7 +2010,7 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
         L3.total_tiles = t3;
         err = stage_table(L3, ents, nprob, d_tab, s);
         if (err != hipSuccess) return err;
-        const int grid = (t3 + 3) / 4;
+        const int grid = ((t3 + 3) / 4 + 7) / 8 * 8;
         TraceSpan ts("pi_combine", P, Prec<S>::id, s);
         if (nprob > 1) {
             if (accumulate) hipLaunchKernelGGL((k_pi_combine_planes<P, S, 1, true>), dim3(grid), dim3(256), 0, s, L3);
