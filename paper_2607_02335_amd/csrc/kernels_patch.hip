@@ -1031,6 +1031,82 @@ __global__ void __launch_bounds__(256) k_assemble_nodes(LaunchTable L) {
     }
 }
 
+// The same assembly for long rows: one wavefront per node row (Y, Z) with
+// lane i on cell column i (64 cells per pass along x).  For each of the
+// row's y/z copies (uniform over the wavefront) a lane loads its cell's p+1
+// nodes along x, so every load is a run of consecutive cells of a storage
+// block; the node a cell shares with its left neighbour takes the
+// neighbour's last node through a lane shuffle.  Terms are added in the same
+// order as k_assemble_nodes (ascending cell order along z, y, x), so the two
+// kernels give identical results.
+template <int P, typename S, typename C, bool MULTI>
+__global__ void __launch_bounds__(256) k_assemble_cells(LaunchTable L) {
+    constexpr int N = P + 1, NN = N * N * N;
+    const int tile = blockIdx.x;
+    if (tile >= L.total_tiles) return;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+    const int G0 = n0 * P + 1, G1 = n1 * P + 1, G2 = n2 * P + 1;
+    const int row = (tile - pe.tile_begin) * 4 + (int)(threadIdx.x / 64);
+    if (row >= G1 * G2) return;
+    const int lane = threadIdx.x % 64;
+    const int J = row % G1, K = row / G1;
+    const int qy = J / P, ry = J - qy * P, qz = K / P, rz = K - qz * P;
+    const int ny = (ry == 0 && qy >= 1 && qy <= n1 - 1) ? 2 : 1;
+    const int nz = (rz == 0 && qz >= 1 && qz <= n2 - 1) ? 2 : 1;
+    const int cy0 = (ry == 0 && qy >= 1) ? qy - 1 : qy, by0 = (ry == 0 && qy >= 1) ? P : ry;
+    const int cz0 = (rz == 0 && qz >= 1) ? qz - 1 : qz, bz0 = (rz == 0 && qz >= 1) ? P : rz;
+    const S* v = static_cast<const S*>(pe.a);
+    C* out = static_cast<C*>(pe.e) + (size_t)row * G0;
+    for (int i0 = 0; i0 < n0; i0 += 64) {
+        const int i = i0 + lane;
+        const bool in = i < n0;
+        double val[2][2][N], left[2][2];
+#pragma unroll
+        for (int z = 0; z < 2; ++z)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+#pragma unroll
+                for (int a = 0; a < N; ++a) val[z][y][a] = 0.0;
+                left[z][y] = 0.0;
+                if (z < nz && y < ny) {                        // uniform
+                    const int e = i + n0 * ((cy0 + y) + n1 * (cz0 + z));
+                    const int lyz = N * ((y ? 0 : by0) + N * (z ? 0 : bz0));
+                    if (in) {
+#pragma unroll
+                        for (int a = 0; a < N; ++a) val[z][y][a] = load_as<double>(v + cell_offset(e, a + lyz, NN));
+                    }
+                    left[z][y] = __shfl_up(val[z][y][P], 1, 64);
+                    if (lane == 0 && i0 > 0) left[z][y] = load_as<double>(v + cell_offset(e - 1, P + lyz, NN));
+                }
+            }
+        if (in) {
+#pragma unroll
+            for (int a = 0; a < P; ++a) {
+                double s = 0.0;
+#pragma unroll
+                for (int z = 0; z < 2; ++z)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) {
+                        if (z >= nz || y >= ny) continue;
+                        if (a == 0 && i >= 1) s += left[z][y];    // lower cell first
+                        s += val[z][y][a];
+                    }
+                out[i * P + a] = (C)s;
+            }
+            if (i == n0 - 1) {
+                double s = 0.0;
+#pragma unroll
+                for (int z = 0; z < 2; ++z)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y)
+                        if (z < nz && y < ny) s += val[z][y][P];
+                out[n0 * P] = (C)s;
+            }
+        }
+    }
+}
+
 // Fused sweep from the assembled residual (p <= 3): like k_pi_sweep, but the
 // patch values are read from a ring of global-node z-planes instead of being
 // summed from cell copies, so the restriction is a plain copy folded into the
@@ -1305,8 +1381,17 @@ static hipError_t launch_assemble_nodes(ProbEntry* ents, int nprob, TableStager*
     hipError_t err = stage_table(L, ents, nprob, d_tab, s);
     if (err != hipSuccess || tiles == 0) return err;
     TraceSpan ts("pi_assemble", P, Prec<S>::id, s);
-    if (nprob > 1) hipLaunchKernelGGL((k_assemble_nodes<P, S, C, true>), dim3(tiles), dim3(256), 0, s, L);
-    else hipLaunchKernelGGL((k_assemble_nodes<P, S, C, false>), dim3(tiles), dim3(256), 0, s, L);
+    // lanes over cells when every row is long (coalesced loads, no idle
+    // tail pass), lanes over nodes otherwise; identical results either way
+    bool long_rows = true;
+    for (int i = 0; i < nprob; ++i) long_rows = long_rows && ents[i].n[0] >= 48;
+    if (long_rows) {
+        if (nprob > 1) hipLaunchKernelGGL((k_assemble_cells<P, S, C, true>), dim3(tiles), dim3(256), 0, s, L);
+        else hipLaunchKernelGGL((k_assemble_cells<P, S, C, false>), dim3(tiles), dim3(256), 0, s, L);
+    } else {
+        if (nprob > 1) hipLaunchKernelGGL((k_assemble_nodes<P, S, C, true>), dim3(tiles), dim3(256), 0, s, L);
+        else hipLaunchKernelGGL((k_assemble_nodes<P, S, C, false>), dim3(tiles), dim3(256), 0, s, L);
+    }
     return hipGetLastError();
 }
 
@@ -1446,22 +1531,24 @@ __global__ void __launch_bounds__(256) k_pi_combine_planes(LaunchTable L) {
     int nz = 0, szs[2], qzs[2];
     if (c != P) { szs[nz] = 0; qzs[nz] = P - 1 + c; ++nz; }
     if (c != 0) { szs[nz] = 1; qzs[nz] = c - 1; ++nz; }
+    // corner patches: a missing one (boundary vertex, or no second vertex
+    // layer) reads element 0 of the buffer and its term is dropped by a
+    // select, so every load of the wavefront can be in flight at once
     const C* corner[2][2][2];
+    bool cok[2][2][2];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
         for (int sy = 0; sy < 2; ++sy)
 #pragma unroll
             for (int sx = 0; sx < 2; ++sx) {
-                corner[t][sy][sx] = nullptr;
-                if (t < nz) {
-                    const int vx = i + sx, vy = j + sy, vz = k + szs[t];
-                    const bool ok = vx >= 1 && vx <= npx && vy >= 1 && vy <= npy && vz >= 1 && vz <= n2 - 1;
-                    const int pidx = ok ? (vx - 1) + npx * ((vy - 1) + npy * (vz - 1)) : 0;
-                    if (ok)
-                        corner[t][sy][sx] = pbuf + (size_t)(pidx / kLanes) * nP3 * kLanes + (pidx % kLanes) +
-                                            (size_t)nP2 * qzs[t] * kLanes;
-                }
+                const int vx = i + sx, vy = j + sy, vz = k + szs[t < nz ? t : 0];
+                const bool ok = t < nz && vx >= 1 && vx <= npx && vy >= 1 && vy <= npy && vz >= 1 && vz <= n2 - 1;
+                const int pidx = ok ? (vx - 1) + npx * ((vy - 1) + npy * (vz - 1)) : 0;
+                cok[t][sy][sx] = ok;
+                corner[t][sy][sx] = ok ? pbuf + (size_t)(pidx / kLanes) * nP3 * kLanes + (pidx % kLanes) +
+                                             (size_t)nP2 * qzs[t] * kLanes
+                                       : pbuf;     // element 0 exists even when the mesh has no patch
             }
 #pragma unroll
     for (int bb = 0; bb < BS; ++bb)
@@ -1480,8 +1567,9 @@ __global__ void __launch_bounds__(256) k_pi_combine_planes(LaunchTable L) {
                     for (int sx = 0; sx < 2; ++sx) {
                         if ((sx == 0 && a == P) || (sx == 1 && a == 0)) continue;
                         const int qx = sx == 0 ? P - 1 + a : a - 1;
-                        const C* src = corner[t][sy][sx];
-                        if (src) sum += src[(size_t)(qx + nP * qy) * kLanes];
+                        const bool ok = cok[t][sy][sx];
+                        const C v = corner[t][sy][sx][ok ? (size_t)(qx + nP * qy) * kLanes : 0];
+                        sum = ok ? sum + v : sum;
                     }
                 }
             }
