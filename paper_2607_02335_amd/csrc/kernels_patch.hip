@@ -1017,16 +1017,32 @@ __global__ void __launch_bounds__(256) k_assemble_nodes(LaunchTable L) {
     C* out = static_cast<C*>(pe.e) + (size_t)row * G0;
     for (int I = lane; I < G0; I += 64) {
         const int qx = I / P, rx = I - qx * P;
-        const int nx = (rx == 0 && qx >= 1 && qx <= n0 - 1) ? 2 : 1;
+        const bool two = rx == 0 && qx >= 1 && qx <= n0 - 1;        // a second copy along x
         const int cx0 = (rx == 0 && qx >= 1) ? qx - 1 : qx, ax0 = (rx == 0 && qx >= 1) ? P : rx;
-        double s = 0.0;
-        for (int z = 0; z < nz; ++z)
-            for (int y = 0; y < ny; ++y)
-                for (int x = 0; x < nx; ++x) {
-                    const int e = (cx0 + x) + n0 * ((cy0 + y) + n1 * (cz0 + z));
-                    const int l = (x ? 0 : ax0) + N * ((y ? 0 : by0) + N * (z ? 0 : bz0));
-                    s += load_as<double>(v + cell_offset(e, l, NN));
+        // copies along y/z in uniform branches, the x pair loaded together
+        // (the second from the first's address when absent) and selected
+        double val[2][2][2];
+#pragma unroll
+        for (int z = 0; z < 2; ++z)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                val[z][y][0] = val[z][y][1] = 0.0;
+                if (z < nz && y < ny) {
+                    const int e = cx0 + n0 * ((cy0 + y) + n1 * (cz0 + z));
+                    const int lyz = N * ((y ? 0 : by0) + N * (z ? 0 : bz0));
+                    val[z][y][0] = load_as<double>(v + cell_offset(e, ax0 + lyz, NN));
+                    val[z][y][1] = load_as<double>(v + (two ? cell_offset(e + 1, lyz, NN) : cell_offset(e, ax0 + lyz, NN)));
                 }
+            }
+        double s = 0.0;
+#pragma unroll
+        for (int z = 0; z < 2; ++z)
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                if (z >= nz || y >= ny) continue;
+                s += val[z][y][0];
+                s = two ? s + val[z][y][1] : s;
+            }
         out[I] = (C)s;
     }
 }
@@ -1701,29 +1717,32 @@ __global__ void __launch_bounds__(256) k_pi_combine_pm(LaunchTable L) {
         if (ab < N2) {
             for (int cl = wv; cl < CH; cl += 4) {
                 const int e = blk * kLanes + h + cl;
+                // every corner term is loaded (a missing one from element 0
+                // of the buffer) and dropped by a select, so the loads of all
+                // corners are in flight together; terms enter in ascending
+                // vertex order along z, y, x
                 C sum = 0;
-                if (e < pe.ncells) {
-                    const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
+                const bool cell_ok = e < pe.ncells;
+                const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
 #pragma unroll
-                    for (int t = 0; t < 2; ++t) {
-                        if (t >= nz) break;
-                        const int vz = k + szs[t];
-                        if (vz < 1 || vz > n2 - 1) continue;
+                for (int t = 0; t < 2; ++t) {
+                    const int vz = k + szs[t < nz ? t : 0];
+                    const bool zok = cell_ok && t < nz && vz >= 1 && vz <= n2 - 1;
 #pragma unroll
-                        for (int sy = 0; sy < 2; ++sy) {
-                            if ((sy == 0 && b == P) || (sy == 1 && b == 0)) continue;
-                            const int vy = j + sy;
-                            if (vy < 1 || vy > npy) continue;
-                            const int qy = sy == 0 ? P - 1 + b : b - 1;
+                    for (int sy = 0; sy < 2; ++sy) {
+                        const int vy = j + sy;
+                        const bool yok = zok && !((sy == 0 && b == P) || (sy == 1 && b == 0)) && vy >= 1 && vy <= npy;
+                        const int qy = sy == 0 ? P - 1 + b : b - 1;
 #pragma unroll
-                            for (int sx = 0; sx < 2; ++sx) {
-                                if ((sx == 0 && a == P) || (sx == 1 && a == 0)) continue;
-                                const int vx = i + sx;
-                                if (vx < 1 || vx > npx) continue;
-                                const int qx = sx == 0 ? P - 1 + a : a - 1;
-                                const int pidx = (vx - 1) + npx * ((vy - 1) + npy * (vz - 1));
-                                sum += pbuf[(size_t)pidx * nP3 + qx + nP * qy + nP2 * qzs[t]];
-                            }
+                        for (int sx = 0; sx < 2; ++sx) {
+                            const int vx = i + sx;
+                            const bool ok = yok && !((sx == 0 && a == P) || (sx == 1 && a == 0)) && vx >= 1 && vx <= npx;
+                            const int qx = sx == 0 ? P - 1 + a : a - 1;
+                            const size_t off = ok ? (size_t)((vx - 1) + npx * ((vy - 1) + npy * (vz - 1))) * nP3 +
+                                                        qx + nP * qy + nP2 * qzs[t < nz ? t : 0]
+                                                  : 0;
+                            const C v = pbuf[off];
+                            sum = ok ? sum + v : sum;
                         }
                     }
                 }
