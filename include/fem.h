@@ -288,7 +288,7 @@ fem_status fem_host_fd_1d(int p, double h0, double h1, double* S, double* lambda
  * summing the residual's cell copies on chip, 2 assembly plus one fused
  * sweep reading the assembled residual; for p >= 4, 2 selects line (VALU)
  * patch solves instead of MFMA; -1 (default) picks by degree and precision
- * only (2 for p = 2 in FP64/FP32, else 0).  FEM_OPT_COMBINE_PER_CELL = 1 makes
+ * only (2 for p = 2 in FP64, else 0).  FEM_OPT_COMBINE_PER_CELL = 1 makes
  * the p <= 3 combine use one wavefront per 64-cell block (all node planes)
  * instead of one per (block, plane).  FEM_OPT_RESTRICT_FROM_CELLS = 1 makes
  * the p <= 3 patch solves sum the residual copies from the cell vector

@@ -1641,41 +1641,38 @@ __device__ __forceinline__ void wave_sync() {
 
 // out(j, line) = sum_i Op(j, i) v(i, line) in place over all lines of the
 // patch; Op's 16x4 slices for the four k-steps are in `a`.  The patch's WPP
-// wavefronts (sub = this one's index) take every WPP-th 16-line tile.  MODE 1
-// additionally divides by lambda_x(j) + lambda_y(y) + lambda_z(z) (x pass).
-template <typename C, int nP, int DIR, int MODE, int WPP>
-__device__ __forceinline__ void mfma_pass(C* pv, const C (&a)[4], int lane, int sub, const C* lx, const C* ly,
-                                          const C* lz) {
+// wavefronts (sub = this one's index) take every WPP-th 16-line tile.
+// Branch-free: the B operand of k >= 2p-1 is read from the clamped index
+// (the A slice is zero there, so it adds exact zeros), the tail lines of the
+// last tile read the last line, and every result row that is not part of the
+// patch is stored to the wavefront's dump slot instead.
+template <typename C, int nP, int DIR, int WPP>
+__device__ __forceinline__ void mfma_pass(C* pv, C* dump, const C (&a)[4], int lane, int sub) {
     using M = Mfma<C>;
     constexpr int NL = nP * nP, NT = (NL + 15) / 16;
     // element (i, line) of the pass's lines sits at base(line) + STRIDE * i
     constexpr int STRIDE = DIR == 2 ? NL : DIR == 1 ? nP : 1;
     const int col = lane % 16, g = lane / 16;
+    int koff[4], joff[4];
+    bool jok[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) koff[ks] = STRIDE * min(4 * ks + g, nP - 1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int j = M::row(lane, r);
+        jok[r] = j < nP;
+        joff[r] = STRIDE * (jok[r] ? j : 0);
+    }
     for (int t = sub; t < NT; t += WPP) {
         const int line = 16 * t + col;
         const bool lok = line < NL;
-        const int base = DIR == 2 ? line : DIR == 1 ? (line % nP) + NL * (line / nP) : nP * line;
-        const C* src = pv + base + STRIDE * g;
+        const int lc = lok ? line : NL - 1;
+        const int base = DIR == 2 ? lc : DIR == 1 ? (lc % nP) + NL * (lc / nP) : nP * lc;
         typename M::V acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const int k = 4 * ks + g;
-            const C b = (k < nP && lok) ? src[4 * STRIDE * ks] : (C)0;
-            acc = M::mma(a[ks], b, acc);
-        }
-        if (lok) {
-            C lyz = 0;
-            if (MODE == 1) lyz = ly[line % nP] + lz[line / nP];
+        for (int ks = 0; ks < 4; ++ks) acc = M::mma(a[ks], pv[base + koff[ks]], acc);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int j = M::row(lane, r);
-                if (j < nP) {
-                    C v = acc[r];
-                    if (MODE == 1) v = v * recip(lx[j] + lyz);
-                    pv[base + STRIDE * j] = v;
-                }
-            }
-        }
+        for (int r = 0; r < 4; ++r) *((lok && jok[r]) ? pv + base + joff[r] : dump + lane) = acc[r];
     }
     if (WPP == 1) wave_sync();
     else __syncthreads();
@@ -1767,40 +1764,43 @@ __global__ void __launch_bounds__(256) k_pi_combine_pm(LaunchTable L) {
 // forward product's accumulators are the backward product's B operand.  A
 // lane holds accumulator rows row(lane, 0..3), so the backward k-steps take
 // k = row(lane, ks) for lane group g = lane/16; `ab` holds the backward
-// basis slices in that order (A[m][row(16 g + m, ks)]).
+// basis slices in that order (A[m][row(16 g + m, ks)]).  Branch-free as
+// mfma_pass; a lane's four lambda_x values are loaded once.
 template <typename C, int nP, int WPP>
-__device__ __forceinline__ void mfma_pass_x2(C* pv, const C (&af)[4], const C (&ab)[4], int lane, int sub,
+__device__ __forceinline__ void mfma_pass_x2(C* pv, C* dump, const C (&af)[4], const C (&ab)[4], int lane, int sub,
                                              const C* lx, const C* ly, const C* lz) {
     using M = Mfma<C>;
     constexpr int NL = nP * nP, NT = (NL + 15) / 16;
     const int col = lane % 16, g = lane / 16;
+    int koff[4], jr[4];
+    bool jok[4];
+    C lxr[4];
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) koff[ks] = min(4 * ks + g, nP - 1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int j = M::row(lane, r);
+        jok[r] = j < nP;
+        jr[r] = jok[r] ? j : 0;
+        lxr[r] = lx[jr[r]];
+    }
     for (int t = sub; t < NT; t += WPP) {
         const int line = 16 * t + col;
         const bool lok = line < NL;
-        const C* src = pv + nP * line + g;
+        const int lc = lok ? line : NL - 1;
+        const int qy = lc % nP, qz = lc / nP;
+        const C* src = pv + nP * lc;
         typename M::V acc = {0, 0, 0, 0};
 #pragma unroll
-        for (int ks = 0; ks < 4; ++ks) {
-            const int k = 4 * ks + g;
-            const C b = (k < nP && lok) ? src[4 * ks] : (C)0;
-            acc = M::mma(af[ks], b, acc);
-        }
-        const C lyz = lok ? ly[line % nP] + lz[line / nP] : (C)1;
+        for (int ks = 0; ks < 4; ++ks) acc = M::mma(af[ks], src[koff[ks]], acc);
+        const C lyz = ly[qy] + lz[qz];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int j = M::row(lane, r);
-            acc[r] = j < nP ? acc[r] * recip(lx[j] + lyz) : (C)0;
-        }
+        for (int r = 0; r < 4; ++r) acc[r] = jok[r] ? acc[r] * recip(lxr[r] + lyz) : (C)0;
         typename M::V out = {0, 0, 0, 0};
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) out = M::mma(ab[ks], acc[ks], out);
-        if (lok) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int j = M::row(lane, r);
-                if (j < nP) pv[nP * line + j] = out[r];
-            }
-        }
+        for (int r = 0; r < 4; ++r) *((lok && jok[r]) ? pv + nP * lc + jr[r] : dump + lane) = out[r];
     }
     if (WPP == 1) wave_sync();
     else __syncthreads();
@@ -1819,6 +1819,7 @@ __global__ void __launch_bounds__(256) k_pi_solve_mfma(LaunchTable L) {
     constexpr int PPW = 4 / WPP;                      // patches per workgroup
     static_assert(nP <= 16, "one MFMA tile per contraction");
     __shared__ C spv[PPW][nP3];
+    __shared__ C sdump[4][64];                        // per-wavefront sink for rows outside the patch
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int slot = wv / WPP, sub = wv % WPP;
     const int tile = blockIdx.x * PPW + slot;
@@ -1852,18 +1853,37 @@ __global__ void __launch_bounds__(256) k_pi_solve_mfma(LaunchTable L) {
         const C* g = static_cast<const C*>(pe.e);
         const size_t G0 = (size_t)pe.n[0] * P + 1, G1 = (size_t)pe.n[1] * P + 1;
         const size_t I0 = (size_t)(vi - 1) * P + 1, J0 = (size_t)(vj - 1) * P + 1, K0 = (size_t)(vk - 1) * P + 1;
-        for (int q = t64; q < nP3; q += 64 * WPP) {
-            const int qx = q % nP, qy = (q / nP) % nP, qz = q / nP2;
-            pv[q] = g[(I0 + qx) + G0 * ((J0 + qy) + G1 * (K0 + qz))];
+        // element q = qx + nP qy + nP^2 qz; the thread's (qx, qy, qz) advance
+        // by the fixed stride without divisions, and all loads are issued
+        // before the first LDS store
+        constexpr int STEP = 64 * WPP, NIT = (nP3 + STEP - 1) / STEP;
+        constexpr int DX = STEP % nP, DY = (STEP / nP) % nP, DZ = STEP / nP2;
+        int qx = t64 % nP, qy = (t64 / nP) % nP;
+        size_t off = (I0 + qx) + G0 * ((J0 + qy) + G1 * (K0 + (size_t)(t64 / nP2)));
+        const size_t dstep = DX + G0 * (DY + G1 * DZ);              // uniform node-offset steps
+        const size_t cx = G0 - nP, cy = G0 * (G1 - nP);             // carries into y and z
+        C vals[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            vals[it] = t64 + STEP * it < nP3 ? g[off] : (C)0;
+            qx += DX;
+            qy += DY;
+            off += dstep;
+            if (qx >= nP) { qx -= nP; ++qy; off += cx; }
+            if (qy >= nP) { qy -= nP; off += cy; }
         }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it)
+            if (t64 + STEP * it < nP3) pv[t64 + STEP * it] = vals[it];
     }
     if (WPP == 1) wave_sync();
     else __syncthreads();
     const C* lx = fx + nP2;
     const C* ly = fy + nP2;
     const C* lz = fz + nP2;
-    mfma_pass<C, nP, 2, 0, WPP>(pv, afz, lane, sub, lx, ly, lz);
-    mfma_pass<C, nP, 1, 0, WPP>(pv, afy, lane, sub, lx, ly, lz);
+    C* dump = sdump[wv];
+    mfma_pass<C, nP, 2, WPP>(pv, dump, afz, lane, sub);
+    mfma_pass<C, nP, 1, WPP>(pv, dump, afy, lane, sub);
     {
         // backward x basis in the accumulator row order of the forward product
         C abx2[4];
@@ -1872,10 +1892,10 @@ __global__ void __launch_bounds__(256) k_pi_solve_mfma(LaunchTable L) {
             const int rr = lane % 16, kk = Mfma<C>::row(lane, ks);
             abx2[ks] = (rr < nP && kk < nP) ? fx[rr * nP + kk] : (C)0;
         }
-        mfma_pass_x2<C, nP, WPP>(pv, afx, abx2, lane, sub, lx, ly, lz);
+        mfma_pass_x2<C, nP, WPP>(pv, dump, afx, abx2, lane, sub, lx, ly, lz);
     }
-    mfma_pass<C, nP, 1, 0, WPP>(pv, aby, lane, sub, lx, ly, lz);
-    mfma_pass<C, nP, 2, 0, WPP>(pv, abz, lane, sub, lx, ly, lz);
+    mfma_pass<C, nP, 1, WPP>(pv, dump, aby, lane, sub);
+    mfma_pass<C, nP, 2, WPP>(pv, dump, abz, lane, sub);
     // patch-major buffer: each patch's values are one contiguous run
     C* out = static_cast<C*>(pe.d) + (size_t)pidx * nP3;
     for (int q = t64; q < nP3; q += 64 * WPP) out[q] = pv[q];
@@ -1999,9 +2019,9 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
     if constexpr (P <= 3) {
         // default by degree and precision only (never by size or launch mix, so
         // a problem gets the same variant alone and batched): the fused sweep
-        // from the assembled residual for p = 2 in FP64/FP32 (measured faster
+        // from the assembled residual for p = 2 in FP64 (measured faster
         // there), the two launches through the patch buffer otherwise
-        const int dflt = (P == 2 && Prec<S>::id != FEM_BF16) ? 2 : 0;
+        const int dflt = (P == 2 && Prec<S>::id == FEM_F64) ? 2 : 0;
         const int fused = cfg.pi_fused >= 0 ? cfg.pi_fused : g_pi_fused >= 0 ? g_pi_fused : dflt;
         if (fused == 2) return launch_pi_sweep_g<P, S>(accumulate, ents, nprob, d_tab, s);
         if (fused) return launch_pi_sweep<P, S>(accumulate, ents, nprob, d_tab, s);
