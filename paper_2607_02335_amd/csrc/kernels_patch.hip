@@ -41,6 +41,23 @@ int g_restrict_from_cells = 0;
 // inverse for p <= 3; 0 runs one solve and one combine launch.
 int g_pi_slab_mb = 0;
 
+// Reciprocal of a positive normal value (the FD eigenvalue sums): the
+// hardware estimate refined by Newton-Raphson steps r <- r + r (1 - d r),
+// two for FP64 and one for FP32 (each step doubles the correct bits), so the
+// FD scaling multiplies instead of running the full IEEE division sequence.
+__device__ __forceinline__ double recip(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-d, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float d) {
+    const float r = __builtin_amdgcn_rcpf(d);
+    const float e = __builtin_fmaf(-d, r, 1.0f);
+    return __builtin_fmaf(r, e, r);
+}
+
 template <int P, typename C> constexpr int pi_patches_per_tile() {
     constexpr int nP = 2 * P - 1;
     int cb = 64;
@@ -148,7 +165,7 @@ __global__ void __launch_bounds__(256) k_pi_solve(LaunchTable L) {
                 C s = 0;
 #pragma unroll
                 for (int i = 0; i < nP; ++i) s += sS[0][pc][i * nP + j] * v[i];
-                w[j] = s / (sL[0][pc][j] + lyz);
+                w[j] = s * recip(sL[0][pc][j] + lyz);
             }
 #pragma unroll
             for (int i = 0; i < nP; ++i) {
@@ -369,7 +386,7 @@ __global__ void __launch_bounds__(256) k_pi_solve_r(LaunchTable L) {
             C s = 0;
 #pragma unroll
             for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
-            w[j] = s / (sLx[pc][j] + lyz);
+            w[j] = s * recip(sLx[pc][j] + lyz);
         }
 #pragma unroll
         for (int i = 0; i < nP; ++i) {
@@ -677,7 +694,7 @@ __global__ void __launch_bounds__(256) k_pi_sweep(LaunchTable L) {
                         C s = 0;
 #pragma unroll
                         for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
-                        w[j] = s / (sLx[pxo][j] + lyz);
+                        w[j] = s * recip(sLx[pxo][j] + lyz);
                     }
 #pragma unroll
                     for (int i = 0; i < nP; ++i) {
@@ -789,23 +806,6 @@ template <> struct SweepShape<2, double> { static constexpr int TX = 16, TY = 2,
 template <> struct SweepShape<3, double> { static constexpr int TX = 8, TY = 2, NS = 32; };
 template <> struct SweepShape<3, float> { static constexpr int TX = 8, TY = 4, NS = 64; };
 template <> struct SweepShape<3, bf16_t> { static constexpr int TX = 8, TY = 4, NS = 64; };
-
-// Reciprocal of a positive normal value: the hardware estimate refined by
-// Newton-Raphson steps r <- r + r (1 - d r), two for FP64 and one for FP32
-// (each step doubles the correct bits), so the FD scaling multiplies instead
-// of running the full IEEE division sequence.
-__device__ __forceinline__ double recip_nr(double d) {
-    double r = __builtin_amdgcn_rcp(d);
-    double e = __builtin_fma(-d, r, 1.0);
-    r = __builtin_fma(r, e, r);
-    e = __builtin_fma(-d, r, 1.0);
-    return __builtin_fma(r, e, r);
-}
-__device__ __forceinline__ float recip_nr(float d) {
-    const float r = __builtin_amdgcn_rcpf(d);
-    const float e = __builtin_fmaf(-d, r, 1.0f);
-    return __builtin_fmaf(r, e, r);
-}
 
 // Phase 1 for p <= 3 reading the assembled residual.  A tile is CBP patches
 // along x sharing one (y, z) vertex; thread (pc, group) takes patch pc and
@@ -931,7 +931,7 @@ __global__ void __launch_bounds__(256) k_pi_solve_g(LaunchTable L) {
                 C s = 0;
 #pragma unroll
                 for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
-                w[j] = s * recip_nr(lxy + lz[j]);
+                w[j] = s * recip(lxy + lz[j]);
             }
 #pragma unroll
             for (int i = 0; i < nP; ++i) {
@@ -1290,7 +1290,7 @@ __global__ void __launch_bounds__(256) k_pi_sweep_g(LaunchTable L) {
                     C s = 0;
 #pragma unroll
                     for (int i = 0; i < nP; ++i) s += sSx[pxo][i * nP + j] * v[i];
-                    w[j] = s / (sLx[pxo][j] + lyz);
+                    w[j] = s * recip(sLx[pxo][j] + lyz);
                 }
 #pragma unroll
                 for (int i = 0; i < nP; ++i) {
@@ -1621,18 +1621,6 @@ template <> struct Mfma<float> {
     __device__ static V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
     __device__ static int row(int l, int r) { return 4 * (l / 16) + r; }
 };
-
-// 1/d for the positive eigenvalue sums: hardware reciprocal refined by two
-// Newton steps (about 1 ulp; the patch solve does not need IEEE division).
-__device__ __forceinline__ double recip(double d) {
-    double r = __builtin_amdgcn_rcp(d);
-    r = r * (2.0 - d * r);
-    return r * (2.0 - d * r);
-}
-__device__ __forceinline__ float recip(float d) {
-    float r = __builtin_amdgcn_rcpf(d);
-    return r * (2.0f - d * r);
-}
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
