@@ -350,3 +350,32 @@ def test_degenerate_meshes(F, p, n, prec):
     assert not np.any(to_np(P.unpack(P.smoother_step(xd, sweeps=2, omega=0.3))))
     y = to_np(P.unpack(P.apply(xd)))
     assert rel_err(y, operators.apply_cells(m, to_np(P.unpack(xd)))) <= TOL[prec]
+
+
+@pytest.mark.parametrize("p,n", [(3, (48, 2, 3)), (3, (65, 3, 2)), (2, (129, 2, 3)), (7, (48, 2, 2)), (7, (64, 2, 2))])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_patch_inverse_long_rows(F, p, n, prec):
+    """Rows of at least 48 cells take the assembly with lanes over cells (64
+    cells per pass, the first lane of a later pass reading its left
+    neighbour directly): at the threshold, one past a full pass, and two
+    passes with a ragged tail, the patch inverse matches the oracle's
+    additive Schwarz (all cells for p <= 3; for p = 7 the cells at both ends
+    and the middle of every row, whose corner patches the oracle factors
+    densely) and stays continuous bit for bit."""
+    note(f"long rows p={p} n={n} prec={prec}")
+    m, w, rng = graded(p, n, 60 + p)
+    P = make(F, m)
+    rd = P.pack(to_dev(rng.uniform(-1, 1, m.ncells * m.n1 ** 3)), prec)
+    zc = P.patch_inverse(rd)
+    z = to_np(P.unpack(zc))
+    np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(zc), prec))), z)
+    r_glob = operators.scatter(m, to_np(P.unpack(rd)).astype(np.float64))
+    tol = {0: 1e-11, 1: 5e-5}[prec]
+    if p <= 3:
+        zref = patches.SchwarzFactors(m)(r_glob)
+        assert rel_err(z, zref[m.dofs]) <= tol
+    else:
+        rows = np.arange(m.n[1] * m.n[2]) * m.n[0]
+        cells = np.unique(np.concatenate([rows, rows + m.n[0] // 2, rows + m.n[0] - 1]))
+        zref = patches.additive_schwarz_at_cells(m, r_glob, cells)
+        assert rel_err(z[cells], zref) <= tol
