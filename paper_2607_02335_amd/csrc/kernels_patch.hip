@@ -1596,6 +1596,122 @@ __global__ void __launch_bounds__(256) k_pi_combine_planes(LaunchTable L) {
         }
 }
 
+// Combine by global node rows, for long rows (p <= 3): one wavefront per
+// node row (Y, Z) with lane i on cell column i.  Every patch value belongs to
+// exactly one global node, so each node's terms are read once, and the sum
+// goes to every cell copy of the node (a vertex-plane node also into the
+// left neighbour's last slot).  The terms enter in ascending vertex order
+// along z, y, x, as in k_pi_combine_planes, so the two kernels give
+// identical results.  The first wavefront of a problem also zeroes the
+// padding cells of its last storage block.
+template <int P, typename S, int ACC, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_combine_rows(LaunchTable L) {
+    using C = typename Prec<S>::C;
+    constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
+    constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
+    const int tile = blockIdx.x;
+    if (tile >= L.total_tiles) return;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+    const int npx = n0 - 1, npy = n1 - 1;
+    const int G1 = n1 * P + 1, G2 = n2 * P + 1;
+    const int row = (tile - pe.tile_begin) * 4 + (int)(threadIdx.x / 64);
+    if (row >= G1 * G2) return;
+    const int lane = threadIdx.x % 64;
+    const C* pbuf = static_cast<const C*>(pe.d);
+    S* z = static_cast<S*>(pe.c);
+    const C alpha = (C)pe.alpha;
+    if (row == 0) {
+#pragma unroll 1
+        for (int l = 0; l < NN; ++l) {
+            const int e = (pe.nblk - 1) * kLanes + lane;
+            if (e >= pe.ncells) store_from(z + cell_offset(e, l, NN), (C)0);
+        }
+    }
+    const int Y = row % G1, Z = row / G1;
+    // patches containing the row's nodes along y and z (ascending vertex)
+    // and the cell copies of the row along y and z
+    int vyp[2], qyp[2], nyp = 0, vzp[2], qzp[2], nzp = 0;
+    int cyc[2], byc[2], nyc = 0, czc[2], bzc[2], nzc = 0;
+    {
+        const int qy = Y / P, ry = Y - qy * P;
+        if (ry == 0) {
+            if (qy >= 1 && qy <= npy) { vyp[nyp] = qy; qyp[nyp] = P - 1; ++nyp; }
+            if (qy >= 1) { cyc[nyc] = qy - 1; byc[nyc] = P; ++nyc; }
+            if (qy <= n1 - 1) { cyc[nyc] = qy; byc[nyc] = 0; ++nyc; }
+        } else {
+            if (qy >= 1) { vyp[nyp] = qy; qyp[nyp] = ry + P - 1; ++nyp; }
+            if (qy + 1 <= npy) { vyp[nyp] = qy + 1; qyp[nyp] = ry - 1; ++nyp; }
+            cyc[nyc] = qy; byc[nyc] = ry; ++nyc;
+        }
+        const int qz = Z / P, rz = Z - qz * P;
+        if (rz == 0) {
+            if (qz >= 1 && qz <= n2 - 1) { vzp[nzp] = qz; qzp[nzp] = P - 1; ++nzp; }
+            if (qz >= 1) { czc[nzc] = qz - 1; bzc[nzc] = P; ++nzc; }
+            if (qz <= n2 - 1) { czc[nzc] = qz; bzc[nzc] = 0; ++nzc; }
+        } else {
+            if (qz >= 1) { vzp[nzp] = qz; qzp[nzp] = rz + P - 1; ++nzp; }
+            if (qz + 1 <= n2 - 1) { vzp[nzp] = qz + 1; qzp[nzp] = rz - 1; ++nzp; }
+            czc[nzc] = qz; bzc[nzc] = rz; ++nzc;
+        }
+    }
+    for (int i0 = 0; i0 < n0; i0 += 64) {
+        const int i = i0 + lane;
+        const bool in = i < n0;
+#pragma unroll
+        for (int a = 0; a < P; ++a) {                      // node X = i P + a
+            C sum = 0;
+#pragma unroll
+            for (int tz = 0; tz < 2; ++tz) {
+#pragma unroll
+                for (int ty = 0; ty < 2; ++ty) {
+#pragma unroll
+                    for (int sx = 0; sx < 2; ++sx) {
+                        const int vx = i + sx;
+                        const bool ok = in && tz < nzp && ty < nyp && !(sx == 1 && a == 0) && vx >= 1 && vx <= npx;
+                        const int qx = sx == 0 ? P - 1 + a : a - 1;
+                        size_t off = 0;
+                        if (ok) {
+                            const int pidx = (vx - 1) + npx * ((vyp[ty] - 1) + npy * (vzp[tz] - 1));
+                            off = (size_t)(pidx / kLanes) * nP3 * kLanes + (pidx % kLanes) +
+                                  (size_t)(qx + nP * (qyp[ty] + nP * qzp[tz])) * kLanes;
+                        }
+                        const C v = pbuf[off];
+                        sum = ok ? sum + v : sum;
+                    }
+                }
+            }
+            if (!in) continue;
+#pragma unroll
+            for (int cz = 0; cz < 2; ++cz) {
+                if (cz >= nzc) break;
+#pragma unroll
+                for (int cy = 0; cy < 2; ++cy) {
+                    if (cy >= nyc) break;
+                    const int e = i + n0 * (cyc[cy] + n1 * czc[cz]);
+                    const int lyz = N * (byc[cy] + N * bzc[cz]);
+                    S* d0 = z + cell_offset(e, a + lyz, NN);
+                    C o0 = alpha * sum;
+                    if (ACC) o0 = load_as<C>(d0) + o0;
+                    store_from(d0, o0);
+                    if (a == 0 && i >= 1) {                    // the left cell's copy of the node
+                        S* d1 = z + cell_offset(e - 1, P + lyz, NN);
+                        C o1 = alpha * sum;
+                        if (ACC) o1 = load_as<C>(d1) + o1;
+                        store_from(d1, o1);
+                    }
+                    if (i == n0 - 1) {                         // the row's last node: no patch
+                        S* d2 = z + cell_offset(e, P + lyz, NN);
+                        C o2 = alpha * (C)0;
+                        if (ACC) o2 = load_as<C>(d2) + o2;
+                        store_from(d2, o2);
+                    }
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // High-degree variant (4 <= p <= 7): the six 1D contractions of a patch are
 // dense products of a (2p-1)x(2p-1) eigenbasis with the (2p-1) x (2p-1)^2
@@ -2110,6 +2226,34 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
             } else {
                 if (accumulate) hipLaunchKernelGGL((k_pi_combine_cell<P, S, 1, false>), dim3(grid), dim3(256), 0, s, L2);
                 else hipLaunchKernelGGL((k_pi_combine_cell<P, S, 0, false>), dim3(grid), dim3(256), 0, s, L2);
+            }
+            return hipGetLastError();
+        }
+        // FP64 on long rows: one wavefront per global node row, each patch
+        // value read once (identical results to the per-plane combine below,
+        // which is the faster one for 4-byte values)
+        bool long_rows = Prec<S>::id == FEM_F64;
+        for (int i = 0; i < nprob; ++i) long_rows = long_rows && ents[i].n[0] >= 48;
+        if (long_rows) {
+            int t4 = 0;
+            for (int i = 0; i < nprob; ++i) {
+                const int rows = (ents[i].n[1] * P + 1) * (ents[i].n[2] * P + 1);
+                ents[i].tile_begin = t4;
+                ents[i].ntiles = (rows + 3) / 4;
+                t4 += ents[i].ntiles;
+            }
+            LaunchTable L4{};
+            L4.nprob = nprob;
+            L4.total_tiles = t4;
+            err = stage_table(L4, ents, nprob, d_tab, s);
+            if (err != hipSuccess) return err;
+            TraceSpan ts("pi_combine", P, Prec<S>::id, s);
+            if (nprob > 1) {
+                if (accumulate) hipLaunchKernelGGL((k_pi_combine_rows<P, S, 1, true>), dim3(t4), dim3(256), 0, s, L4);
+                else hipLaunchKernelGGL((k_pi_combine_rows<P, S, 0, true>), dim3(t4), dim3(256), 0, s, L4);
+            } else {
+                if (accumulate) hipLaunchKernelGGL((k_pi_combine_rows<P, S, 1, false>), dim3(t4), dim3(256), 0, s, L4);
+                else hipLaunchKernelGGL((k_pi_combine_rows<P, S, 0, false>), dim3(t4), dim3(256), 0, s, L4);
             }
             return hipGetLastError();
         }

@@ -311,11 +311,15 @@ def test_patch_inverse_variants_agree(F, p, n, prec, opt, val):
     np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(zc), prec))), z1)
 
 
-@pytest.mark.parametrize("p,n,prec", [(3, (12, 10, 20), 0), (3, (9, 11, 30), 1), (2, (20, 9, 17), 0)])
+@pytest.mark.parametrize("p,n,prec", [(3, (12, 10, 20), 0), (3, (9, 11, 30), 1), (2, (20, 9, 17), 0),
+                                      (3, (50, 3, 8), 0), (2, (70, 4, 9), 1)])
 def test_patch_inverse_slabs_identical(F, p, n, prec):
-    """The z-slab schedule runs the same kernels on the same data: results are
-    identical to one solve and one combine launch, for the plain and the
-    accumulating (smoother) form."""
+    """The z-slab schedule runs the same solve kernel on the same data:
+    results are identical to one solve and one combine launch, for the plain
+    and the accumulating (smoother) form.  In FP64 on rows of at least 48
+    cells the single launch combines by global node rows while the slabs
+    combine per (block, plane), so that case also shows the two combines
+    agree bit for bit."""
     note(f"slabs p={p} n={n} prec={prec}")
     m, w, rng = graded(p, n, 70 + p)
     P = make(F, m)
