@@ -288,9 +288,11 @@ fem_status fem_host_fd_1d(int p, double h0, double h1, double* S, double* lambda
  * summing the residual's cell copies on chip, 2 assembly plus one fused
  * sweep reading the assembled residual; for p >= 4, 2 selects line (VALU)
  * patch solves instead of MFMA; -1 (default) picks by degree and precision
- * only (2 for p = 2 in FP64, else 0).  FEM_OPT_COMBINE_PER_CELL = 1 makes
- * the p <= 3 combine use one wavefront per 64-cell block (all node planes)
- * instead of one per (block, plane).  FEM_OPT_RESTRICT_FROM_CELLS = 1 makes
+ * only (2 for p = 2 in FP64, else 0).  The p <= 3 combine of the two-launch
+ * form runs by global node rows (FP64, every mesh with at least 48 cells
+ * along x) or by (block, node plane), with identical results;
+ * FEM_OPT_COMBINE_PER_CELL = 1 makes it use one wavefront per 64-cell block
+ * (all node planes) instead.  FEM_OPT_RESTRICT_FROM_CELLS = 1 makes
  * the p <= 3 patch solves sum the residual copies from the cell vector
  * instead of reading the assembled global-node array.  FEM_OPT_PI_SLAB_MB =
  * m > 0 runs the p <= 3 two-launch patch inverse of a single problem in
