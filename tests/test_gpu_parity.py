@@ -357,7 +357,7 @@ def test_degenerate_meshes(F, p, n, prec):
 
 
 @pytest.mark.parametrize("p,n", [(3, (48, 2, 3)), (3, (65, 3, 2)), (2, (129, 2, 3)), (7, (48, 2, 2)), (7, (64, 2, 2))])
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_patch_inverse_long_rows(F, p, n, prec):
     """Rows of at least 48 cells take the assembly with lanes over cells (64
     cells per pass, the first lane of a later pass reading its left
@@ -374,7 +374,7 @@ def test_patch_inverse_long_rows(F, p, n, prec):
     z = to_np(P.unpack(zc))
     np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(zc), prec))), z)
     r_glob = operators.scatter(m, to_np(P.unpack(rd)).astype(np.float64))
-    tol = {0: 1e-11, 1: 5e-5}[prec]
+    tol = {0: 1e-11, 1: 5e-5, 2: TOL[2]}[prec]
     if p <= 3:
         zref = patches.SchwarzFactors(m)(r_glob)
         assert rel_err(z, zref[m.dofs]) <= tol
