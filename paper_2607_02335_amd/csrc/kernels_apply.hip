@@ -378,8 +378,16 @@ k_apply_planes(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
     constexpr int ZPT = (ZL + NT - 1) / NT;  // z lines per thread
     __shared__ C s1[SL];                   // u -> T1 -> P1
     __shared__ C s2[SL];                   // T2 -> P2
+    // the 1D matrices (2 (p+1)^2 values) do not fit the scalar registers for
+    // p = 7, so they are read as LDS broadcasts instead of being spilled
+    __shared__ C sM[N2], sK[N2];
     static_assert(NT % CB == 0 && kLanes % CB == 0, "cells per workgroup must divide the block");
     const int tid = threadIdx.x;
+    for (int i = tid; i < N2; i += NT) {
+        sM[i] = R.M[i];
+        sK[i] = R.K[i];
+    }
+    __syncthreads();
     const int cl = tid % CB;               // the cell this thread serves in line passes
     for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
         const ProbEntry& pe = entry<MULTI>(L, tile);
@@ -424,8 +432,8 @@ k_apply_planes(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
                     C sm = 0, sk = 0;
 #pragma unroll
                     for (int m = 0; m < N; ++m) {
-                        sm += R.M[a * N + m] * v[m];
-                        if (MODE != kApplyMass) sk += R.K[a * N + m] * v[m];
+                        sm += sM[a * N + m] * v[m];
+                        if (MODE != kApplyMass) sk += sK[a * N + m] * v[m];
                     }
                     s2[(a + N * r) * CB + cl] = sm;
                     if (MODE != kApplyMass) s1[(a + N * r) * CB + cl] = sk;
@@ -447,10 +455,10 @@ k_apply_planes(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
                     C m1 = 0, k2 = 0, m2 = 0;
 #pragma unroll
                     for (int m = 0; m < N; ++m) {
-                        m2 += R.M[b * N + m] * v2[m];
+                        m2 += sM[b * N + m] * v2[m];
                         if (MODE != kApplyMass) {
-                            m1 += R.M[b * N + m] * v1[m];
-                            k2 += R.K[b * N + m] * v2[m];
+                            m1 += sM[b * N + m] * v1[m];
+                            k2 += sK[b * N + m] * v2[m];
                         }
                     }
                     s2[(a + N * b + N2 * kk) * CB + cl] = m2;
@@ -472,8 +480,8 @@ k_apply_planes(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
                     const C p1 = MODE != kApplyMass ? s1[(ab + N2 * kk) * CB + cl] : (C)0;
 #pragma unroll
                     for (int kp = 0; kp < N; ++kp) {
-                        if (MODE == kApplyMass) acc[q][kp] += R.M[kp * N + k] * p2;
-                        else acc[q][kp] += R.M[kp * N + k] * p1 + g.cz * R.K[kp * N + k] * p2;
+                        if (MODE == kApplyMass) acc[q][kp] += sM[kp * N + k] * p2;
+                        else acc[q][kp] += sM[kp * N + k] * p1 + g.cz * sK[kp * N + k] * p2;
                     }
                 }
             }
