@@ -501,7 +501,7 @@ extern "C" fem_status pcg_solve(fem_problem* P, const double* b, double* u, doub
         e.c = q;
         FEM_HIP(launch_apply(P->p, FEM_F64, 0, &e, 1, nullptr, P->stream), "pcg_solve apply");
         FEM_HIP(run_dot(P, q, FEM_F64, p, FEM_F64, kSlotQP), "pcg_solve dot");
-        FEM_HIP(run_cg_update_ur(P, u, r, p, q, nullptr, FEM_F64), "pcg_solve update");
+        FEM_HIP(run_cg_update_r(P, r, q, nullptr, FEM_F64), "pcg_solve update");
         if (sp == FEM_F64) FEM_HIP(run_assembled_norm2(P, r, FEM_F64, kSlotRN), "pcg_solve norm");
         else FEM_HIP(run_distribute(P, r, rs, sp, kSlotRN), "pcg_solve distribute");
         st = read_slots(P);

@@ -664,10 +664,7 @@ hipError_t run_distribute(fem_problem* P, const double* r, void* out, int prec, 
     return finish_reduction(P, e, 2, slot);
 }
 
-hipError_t run_cg_update_ur(fem_problem* P, double* u, double* r, const double* p, const double* q,
-                            void* rs, int rs_prec) {
-    (void)u;
-    (void)p;
+hipError_t run_cg_update_r(fem_problem* P, double* r, const double* q, void* rs, int rs_prec) {
     ProbEntry e = entry_of(P);
     e.b = q;
     e.d = r;

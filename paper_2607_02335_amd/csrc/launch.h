@@ -107,12 +107,12 @@ hipError_t launch_distribute(int p, int prec, ProbEntry* ents, int nprob, TableS
                              int slot);
 // assembled norm (one degree p): a = r (FP64); slot <- ||G^T r||^2
 hipError_t launch_anorm(int p, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int slot);
-// u += alpha p, r -= alpha q: a = p, b = q, c = u, d = r
-// r -= alpha q (alpha saved in kSlotAlpha); u is updated later by launch_cg_p
-// (or launch_cg_u when the iteration stops)
+// r -= alpha q with alpha = <r,z>/<q,p> (saved in kSlotAlpha); entries b = q,
+// d = r.  u is updated later by launch_cg_p (or run_cg_update_u when the
+// iteration stops)
 hipError_t launch_cg_ur(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s);
-// p = z + beta p: a = z (zprec), c = p
-// u += alpha p (saved alpha), then p = z + beta p; entries a = z, c = p, d = u
+// u += alpha p (saved alpha), then p = z + beta p; entries a = z (zprec),
+// c = p, d = u
 hipError_t launch_cg_p(int zprec, int variant, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s);
 // <q, z> -> kSlotQZ and <r, z> -> kSlotRZ in one pass; entries a = q, d = r, b = z
 hipError_t launch_dot_qz_rz(int zprec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s);
@@ -141,13 +141,15 @@ hipError_t run_assembled_norm2(fem_problem* P, const void* r, int prec, int slot
 // `prec`; ||G^T r||^2 into slot `slot` (same pass).
 hipError_t run_distribute(fem_problem* P, const double* r, void* out, int prec, int slot);
 // (F)PCG vector updates, scalars read from the device slots.
-// u += alpha p; r -= alpha q; optionally rs = (smoother precision) r.
+// r -= alpha q (alpha saved for the next u update); optionally rs = r in the
+// smoother precision.
+hipError_t run_cg_update_r(fem_problem* P, double* r, const double* q, void* rs, int rs_prec);
 // u += alpha p with the saved alpha (the step the last r update left out)
 hipError_t run_cg_update_u(fem_problem* P, double* u, const double* p);
+// <q, z> -> kSlotQZ and <r, z> -> kSlotRZ in one pass
 hipError_t run_dot_qz_rz(fem_problem* P, const double* q, const double* r, const void* z, int zprec);
-hipError_t run_cg_update_ur(fem_problem* P, double* u, double* r, const double* p, const double* q,
-                            void* rs, int rs_prec);
-// p = z + beta p  (beta from slots, variant 1 = PCG, 2 = FCG); z in zprec.
+// u += alpha p, then p = z + beta p (beta from slots, variant 1 = PCG,
+// 2 = FCG); z in zprec.
 hipError_t run_cg_update_p(fem_problem* P, double* p, double* u, const void* z, int zprec, int variant);
 // rz_old <- rz (slot copy), on device
 hipError_t run_slot_copy(fem_problem* P, int dst, int src);
