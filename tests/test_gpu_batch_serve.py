@@ -52,6 +52,27 @@ def test_batch_equals_single_and_oracle(F):
         assert rel_err(to_np(P.unpack(z)), zref[m.dofs]) <= 5e-5
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_long_rows_equals_single(F, prec):
+    """Every mesh of a launch has at least 48 cells along x, so the batched
+    launches take the assembly with lanes over cells and (FP64, p <= 3) the
+    combine by global node rows: each problem's patch inverse equals its own
+    single-problem launch bit for bit and matches the oracle."""
+    probs = [(3, (50, 2, 3)), (3, (64, 3, 2)), (2, (70, 2, 2)), (2, (49, 3, 2))]
+    note(f"long-row batch prec={prec}")
+    B = F.Batch([(p, n, None) for p, n in probs])
+    rng = np.random.default_rng(8)
+    meshes = [Mesh(p, n) for p, n in probs]
+    rs = [P.pack(to_dev(rng.uniform(-1, 1, m.ncells * m.n1 ** 3)), prec) for P, m in zip(B.problems, meshes)]
+    zs = [P.cell_vector(prec) for P in B.problems]
+    B.patch_inverse(rs, zs)
+    for P, m, r, z in zip(B.problems, meshes, rs, zs):
+        z1 = P.patch_inverse(r)
+        assert bool((z1 == z).all()), f"patch inverse q{m.p} n{m.n}"
+        zref = patches.SchwarzFactors(m)(operators.scatter(m, to_np(P.unpack(r)).astype(np.float64)))
+        assert rel_err(to_np(P.unpack(z)), zref[m.dofs]) <= {0: 1e-11, 1: 5e-5}[prec]
+
+
 def test_batch_autotune(F):
     wls = small_batch(count=9, seed=5)
     B = F.Batch([(w.p, w.n, None) for w in wls])
