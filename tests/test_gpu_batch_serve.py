@@ -127,6 +127,40 @@ def test_server_matches_standalone_solves(F, sp):
     S.close()
 
 
+def test_server_long_rows_fp64_smoother(F):
+    """Requests of 48^3 cells with the FP64 smoother: two p = 3 solves share
+    the batched launches, so the server's smoother takes the assembly with
+    lanes over cells and the accumulating combine by global node rows; every
+    solve equals its standalone pcg_solve bit for bit."""
+    rng = np.random.default_rng(5)
+    reqs = [(3, 48, synth.request_rhs_nodal(3, (48, 48, 48), int(rng.integers(0, 2**31 - 1)))),
+            (3, 48, synth.request_rhs_nodal(3, (48, 48, 48), int(rng.integers(0, 2**31 - 1)))),
+            (2, 48, synth.request_rhs_nodal(2, (48, 48, 48), int(rng.integers(0, 2**31 - 1))))]
+    note("server long rows, FP64 smoother")
+    S = F.Server(hbm_budget=16 << 30, max_active=4, smoother_prec=F.F64)
+    tickets = [S.submit(p, n, f, rtol=1e-8, maxit=800) for p, n, f in reqs]
+    results = {}
+    for _ in range(100000):
+        S.step()
+        for t in tickets:
+            if t not in results:
+                r = S.poll(t)
+                if r is not None:
+                    results[t] = r
+        if len(results) == len(tickets):
+            break
+    assert len(results) == len(tickets)
+    for t, (p, n, f) in zip(tickets, reqs):
+        u_srv, info = results[t]
+        assert info["status"] == 0 and info["relres"] <= 1e-8
+        P = F.Problem(p, n)
+        b = P.mass_apply(P.gather(to_dev(f)))
+        u, inf1 = P.pcg_solve(b, rtol=1e-8, maxit=800, smoother_prec=F.F64)
+        assert inf1["iters"] == info["iters"]
+        np.testing.assert_array_equal(u_srv, to_np(P.extract(u)))
+    S.close()
+
+
 def test_server_admission_by_memory(F):
     reqs = _requests(F, 6, 21)
     fps = [F.footprint_bytes(p, n, F.F32) for p, n, _ in reqs]
