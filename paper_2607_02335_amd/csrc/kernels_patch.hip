@@ -1937,19 +1937,18 @@ __global__ void __launch_bounds__(256) k_pi_solve_mfma(LaunchTable L) {
     const C* fx = static_cast<const C*>(pe.fd[0]) + (size_t)(vi - 1) * REC;
     const C* fy = static_cast<const C*>(pe.fd[1]) + (size_t)(vj - 1) * REC;
     const C* fz = static_cast<const C*>(pe.fd[2]) + (size_t)(vk - 1) * REC;
-    // A operands: forward uses S^T (A[j][i] = S[i][j]), backward uses S
-    C afx[4], afy[4], afz[4], abx[4], aby[4], abz[4];
+    // A operands: forward uses S^T (A[j][i] = S[i][j]), backward uses S;
+    // each pass's slices are loaded while the previous pass runs
+    auto loadA = [&](const C* f, bool fwd, C (&a)[4]) {
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-        const int rr = lane % 16, kk = 4 * ks + lane / 16;
-        const bool ok = rr < nP && kk < nP;
-        afx[ks] = ok ? fx[kk * nP + rr] : (C)0;
-        afy[ks] = ok ? fy[kk * nP + rr] : (C)0;
-        afz[ks] = ok ? fz[kk * nP + rr] : (C)0;
-        abx[ks] = ok ? fx[rr * nP + kk] : (C)0;
-        aby[ks] = ok ? fy[rr * nP + kk] : (C)0;
-        abz[ks] = ok ? fz[rr * nP + kk] : (C)0;
-    }
+        for (int ks = 0; ks < 4; ++ks) {
+            const int rr = lane % 16, kk = 4 * ks + lane / 16;
+            const bool ok = rr < nP && kk < nP;
+            a[ks] = ok ? (fwd ? f[kk * nP + rr] : f[rr * nP + kk]) : (C)0;
+        }
+    };
+    C a0[4], a1[4];
+    loadA(fz, true, a0);
     C* pv = spv[slot];
     const int t64 = sub * 64 + lane;                  // thread index within the patch's wavefronts
     // restrict: the patch's box of the assembled residual
@@ -1986,20 +1985,23 @@ __global__ void __launch_bounds__(256) k_pi_solve_mfma(LaunchTable L) {
     const C* ly = fy + nP2;
     const C* lz = fz + nP2;
     C* dump = sdump[wv];
-    mfma_pass<C, nP, 2, WPP>(pv, dump, afz, lane, sub);
-    mfma_pass<C, nP, 1, WPP>(pv, dump, afy, lane, sub);
+    loadA(fy, true, a1);
+    mfma_pass<C, nP, 2, WPP>(pv, dump, a0, lane, sub);
+    loadA(fx, true, a0);
+    mfma_pass<C, nP, 1, WPP>(pv, dump, a1, lane, sub);
     {
         // backward x basis in the accumulator row order of the forward product
-        C abx2[4];
 #pragma unroll
         for (int ks = 0; ks < 4; ++ks) {
             const int rr = lane % 16, kk = Mfma<C>::row(lane, ks);
-            abx2[ks] = (rr < nP && kk < nP) ? fx[rr * nP + kk] : (C)0;
+            a1[ks] = (rr < nP && kk < nP) ? fx[rr * nP + kk] : (C)0;
         }
-        mfma_pass_x2<C, nP, WPP>(pv, dump, afx, abx2, lane, sub, lx, ly, lz);
+        mfma_pass_x2<C, nP, WPP>(pv, dump, a0, a1, lane, sub, lx, ly, lz);
     }
-    mfma_pass<C, nP, 1, WPP>(pv, dump, aby, lane, sub);
-    mfma_pass<C, nP, 2, WPP>(pv, dump, abz, lane, sub);
+    loadA(fy, false, a0);
+    loadA(fz, false, a1);
+    mfma_pass<C, nP, 1, WPP>(pv, dump, a0, lane, sub);
+    mfma_pass<C, nP, 2, WPP>(pv, dump, a1, lane, sub);
     // patch-major buffer: each patch's values are one contiguous run
     C* out = static_cast<C*>(pe.d) + (size_t)pidx * nP3;
     for (int q = t64; q < nP3; q += 64 * WPP) out[q] = pv[q];
