@@ -356,7 +356,8 @@ def test_degenerate_meshes(F, p, n, prec):
     assert rel_err(y, operators.apply_cells(m, to_np(P.unpack(xd)))) <= TOL[prec]
 
 
-@pytest.mark.parametrize("p,n", [(3, (48, 2, 3)), (3, (65, 3, 2)), (2, (129, 2, 3)), (7, (48, 2, 2)), (7, (64, 2, 2))])
+@pytest.mark.parametrize("p,n", [(3, (48, 2, 3)), (3, (65, 3, 2)), (2, (129, 2, 3)), (1, (80, 3, 2)), (7, (48, 2, 2)),
+                                 (7, (64, 2, 2))])
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_patch_inverse_long_rows(F, p, n, prec):
     """Rows of at least 48 cells take the assembly with lanes over cells (64
