@@ -198,18 +198,21 @@ def test_smoother_matches_oracle(F, prec):
 
 
 # ---------------------------------------------------------------- solver
-def test_pcg_iterates_equal_assembled_iterates(F):
+@pytest.mark.parametrize("variant,code", [("pcg", 1), ("fcg", 2)])
+def test_pcg_iterates_equal_assembled_iterates(F, variant, code):
     """Equivalence theorem (Section 3.2): cell-wise iterates = G (assembled
-    iterates), checked for the first iterations with the FP64 smoother."""
+    iterates), checked for the first iterations with the FP64 smoother, for
+    the static (PCG) and the flexible (FCG) beta.  Stopping after k steps
+    also checks the u update the direction pass carries one step late."""
     m, w, rng = graded(2, (4, 4, 5), 41)
     P = make(F, m)
     f = rng.uniform(-1, 1, m.nglob)
     b_glob = operators.mass_global(m, f)
-    _, _, _, its = solver.solve_poisson(m, b_glob, rtol=1e-30, maxit=6, variant="pcg", record=True)
+    _, _, _, its = solver.solve_poisson(m, b_glob, rtol=1e-30, maxit=6, variant=variant, record=True)
     bd = P.mass_apply(P.gather(to_dev(f)))
     for k in range(1, 7):
-        note(f"pcg iterate k={k}")
-        u, info = P.pcg_solve(bd, rtol=1e-30, maxit=k, smoother_prec=0, raise_on_error=False)
+        note(f"{variant} iterate k={k}")
+        u, info = P.pcg_solve(bd, rtol=1e-30, maxit=k, smoother_prec=0, variant=code, raise_on_error=False)
         assert info["status"] == 4 and info["iters"] == k
         uk = to_np(P.extract(u))
         assert l2_rel(uk, its[k]) <= 1e-10
