@@ -328,8 +328,8 @@ def main():
                     help="storage precision of --only q2_96 / q7_24")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only (the hot path is single-device; "
-              "multi-GPU sharding is a design note, not a measured configuration)", file=sys.stderr)
+        print("bench.py: measures one GPU only (the library runs each problem on one device; "
+              "splitting a mesh over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2607_02335_amd import fem
