@@ -10,6 +10,9 @@
 * ``apply_cells``  -- the local operator A: V_cell -> V_cell^* (Section 3.1):
   y_K = A_K (mask x_K) per cell with boundary copies of y set to zero.  Its
   scatter is ``apply_global`` of any x whose gather it was applied to.
+* ``diagonal`` -- the diagonal d of the assembled A_CG, the vector the Jacobi
+  preconditioner of Section 3.3 scales by: the diagonal of
+  sum_K G_K^T A_K G_K is sum_K G_K^T diag(A_K), each A_K by plain quadrature.
 """
 from __future__ import annotations
 
@@ -81,6 +84,19 @@ def apply_global(mesh: Mesh, x: np.ndarray, dirichlet: bool = True) -> np.ndarra
 def mass_global(mesh: Mesh, x: np.ndarray, dirichlet: bool = True) -> np.ndarray:
     """y = P_I M_CG x (or M_CG x), matrix-free."""
     return scatter(mesh, mass_cells(mesh, gather(mesh, x), dirichlet))
+
+
+def diagonal(mesh: Mesh) -> np.ndarray:
+    """Diagonal of the assembled (Neumann) A_CG, summed from element diagonals."""
+    hx, hy, hz = mesh.cell_sizes()
+    cache = {}
+    dcell = np.empty((mesh.ncells, mesh.n1 ** 3))
+    for e in range(mesh.ncells):
+        key = (hx[e], hy[e], hz[e])
+        if key not in cache:
+            cache[key] = np.diag(element_stiffness(mesh.p, *key)).copy()
+        dcell[e] = cache[key]
+    return scatter(mesh, dcell)
 
 
 def assemble(mesh: Mesh, kind: str = "stiffness", dirichlet: bool = False):

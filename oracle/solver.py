@@ -5,6 +5,13 @@
   names overlapping Schwarz patch smoothers but gives no damping or sweep
   count; this is the reading the repository documents (omega = 1/8, two
   sweeps by default).
+* ``dss_preconditioner`` and ``jacobi``: the simple preconditioners of
+  Section 3.3 on assembled vectors.  P = S = G I_Riesz G^T is, in the
+  assembled space, the Riesz identity: the assembled residual read as nodal
+  values.  The Jacobi variant scales it by the inverse diagonal of A_CG
+  (Eq. "dss_operator" and the identity G D_CG^{-1} = D_cell^{-1} G after it).
+  With homogeneous Dirichlet conditions both act on the interior nodes only
+  (the boundary rows of A_D are zero, so its boundary diagonal is empty).
 * ``fcg``: the paper's Algorithm "Communication-Free (F)PCG" (Section 3.2),
   run on the assembled system A_CG u = b_CG.  By the equivalence theorem of
   that section the cell-wise iteration produces u_k = G u_k^global, so these
@@ -20,7 +27,7 @@ from __future__ import annotations
 import numpy as np
 
 from .mesh import Mesh
-from .operators import apply_global
+from .operators import apply_global, diagonal
 from .patches import SchwarzFactors, additive_schwarz
 
 
@@ -33,6 +40,21 @@ def smoother(mesh: Mesh, r: np.ndarray, sweeps: int = 2, omega: float = 0.125,
     for _ in range(sweeps):
         z = z + omega * schwarz(r - apply_global(mesh, z))
     return z
+
+
+def dss_preconditioner(mesh: Mesh, r: np.ndarray) -> np.ndarray:
+    """P r for P = S: the assembled residual as nodal values (interior only)."""
+    return np.where(mesh.boundary_mask(), 0.0, r)
+
+
+def jacobi(mesh: Mesh, r: np.ndarray, diag=None) -> np.ndarray:
+    """P r for P = D_CG^{-1} S: the assembled residual divided by the
+    diagonal of the assembled operator (interior only)."""
+    d = diagonal(mesh) if diag is None else diag
+    out = np.zeros_like(r)
+    inner = ~mesh.boundary_mask()
+    out[inner] = r[inner] / d[inner]
+    return out
 
 
 def fcg(apply, precond, b: np.ndarray, u0=None, rtol: float = 1e-8, maxit: int = 1000,
@@ -75,14 +97,26 @@ def fcg(apply, precond, b: np.ndarray, u0=None, rtol: float = 1e-8, maxit: int =
 
 def solve_poisson(mesh: Mesh, b: np.ndarray, rtol: float = 1e-8, maxit: int = 1000,
                   sweeps: int = 2, omega: float = 0.125, variant: str = "pcg",
-                  record: bool = False):
-    """FCG/PCG on A_D u = b preconditioned by the Schwarz smoother."""
+                  record: bool = False, precond: str = "schwarz"):
+    """FCG/PCG on A_D u = b preconditioned by the Schwarz smoother (or, with
+    ``precond`` "dss" or "jacobi", by the simple preconditioners)."""
     def apply(v):
         return apply_global(mesh, v)
 
-    factors = SchwarzFactors(mesh)
+    if precond == "schwarz":
+        factors = SchwarzFactors(mesh)
 
-    def precond(v):
-        return smoother(mesh, v, sweeps, omega, schwarz=factors)
+        def precond_fn(v):
+            return smoother(mesh, v, sweeps, omega, schwarz=factors)
+    elif precond == "dss":
+        def precond_fn(v):
+            return dss_preconditioner(mesh, v)
+    elif precond == "jacobi":
+        d = diagonal(mesh)
 
-    return fcg(apply, precond, b, rtol=rtol, maxit=maxit, variant=variant, record=record)
+        def precond_fn(v):
+            return jacobi(mesh, v, d)
+    else:
+        raise ValueError(precond)
+    return fcg(apply, precond_fn, b, rtol=rtol, maxit=maxit, variant=variant, record=record)
+

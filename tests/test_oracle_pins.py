@@ -314,3 +314,100 @@ def test_storage_ratio_table():
         # cell-wise apply moves read+write per stored DoF, the assembled one
         # read + read-accumulate-write per unique DoF: ratio 2/3 of storage
         assert abs(2 * stored / (3 * unique) - float(tr)) < 0.006
+
+
+# ------------------------------------------------- smoother sweep algebra
+@pytest.mark.parametrize("p", [2, 3])
+def test_smoother_sweeps_on_a_single_patch(p):
+    """n = 2: the one patch covers the whole interior, so P_AS = A_D^{-1} there
+    and every damped sweep shrinks the error by (1 - omega):
+    z_nu = (1 - (1 - omega)^nu) A_D^{-1} r.  With omega = 1/2 two sweeps give
+    3/4 of the exact solve, with omega = 1 every sweep count gives the solve."""
+    m = graded_mesh(p, 2)
+    A = operators.assemble(m, dirichlet=True).tocsr()
+    inner = np.nonzero(~m.boundary_mask())[0]
+    r = np.zeros(m.nglob)
+    r[inner] = np.random.default_rng(13).standard_normal(len(inner))
+    exact = np.zeros(m.nglob)
+    exact[inner] = spla.spsolve(A[inner][:, inner].tocsc(), r[inner])
+    for omega, nu in ((0.5, 2), (1.0, 2), (1.0, 3), (0.5, 3), (0.3, 4)):
+        z = solver.smoother(m, r, sweeps=nu, omega=omega)
+        np.testing.assert_allclose(z, (1 - (1 - omega) ** nu) * exact, rtol=0,
+                                   atol=1e-12 * np.abs(exact).max())
+    assert abs(np.abs(solver.smoother(m, r, 2, 0.5)).max() / np.abs(exact).max() - 0.75) < 1e-12
+
+
+def test_smoother_sweeps_closed_form():
+    """nu sweeps of damped Richardson from zero are the polynomial
+    (I - (I - omega B A)^nu) A^{-1} in the dense preconditioner B = P_AS and
+    operator A = A_D on the interior of a mesh with 8 overlapping patches."""
+    m = graded_mesh(2, 3)
+    inner = np.nonzero(~m.boundary_mask())[0]
+    nI = len(inner)
+    A = operators.assemble(m, dirichlet=True).toarray()[np.ix_(inner, inner)]
+    f = patches.SchwarzFactors(m)
+    B = np.zeros((nI, nI))
+    for t in range(nI):
+        e = np.zeros(m.nglob)
+        e[inner[t]] = 1
+        B[:, t] = f(e)[inner]
+    r = np.random.default_rng(17).standard_normal(nI)
+    rg = np.zeros(m.nglob)
+    rg[inner] = r
+    Ainv_r = np.linalg.solve(A, r)
+    for omega, nu in ((0.125, 2), (0.2, 3), (0.3, 2)):
+        E = np.linalg.matrix_power(np.eye(nI) - omega * B @ A, nu)
+        ref = Ainv_r - E @ Ainv_r
+        z = solver.smoother(m, rg, sweeps=nu, omega=omega, schwarz=f)
+        np.testing.assert_allclose(z[inner], ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+        assert not np.any(z[m.boundary_mask()])
+
+
+# ------------------------------------------- Section 3.3 preconditioners
+def test_diagonal_closed_forms():
+    """Diagonal of the assembled Laplacian on uniform cubes of side h, from
+    the textbook 1D matrices: Q1 interior vertex 8 (h/3) = 8h/3; Q2 cell
+    centre 3 h K11 M11^2 = 1024h/225, interior vertex 8 * 3 h K00 M00^2 =
+    224h/225."""
+    n = 4
+    h = 1.0 / n
+    m1 = Mesh(1, (n, n, n))
+    d1 = operators.diagonal(m1)
+    I = m1.gidx(2, 1, 3)
+    assert abs(d1[I] - 8 * h / 3) < 1e-15
+    m2 = Mesh(2, (n, n, n))
+    d2 = operators.diagonal(m2)
+    assert abs(d2[m2.gidx(3, 5, 1)] - 1024 * h / 225) < 1e-14        # (1,1,1) node of cell (1,2,0)
+    assert abs(d2[m2.gidx(2, 4, 6)] - 224 * h / 225) < 1e-14         # interior vertex (1,2,3)
+    # face-centre node shared by two cells: 2 h (K11 M11 M00 + M11 K11 M00 + M11 M11 K00)
+    K, M = np.array([7, 16]) / 3, np.array([4, 16]) / 30
+    face = 2 * h * (K[1] * M[1] * M[0] + M[1] * K[1] * M[0] + M[1] * M[1] * K[0])
+    assert abs(d2[m2.gidx(3, 3, 2)] - face) < 1e-14
+    # the element sum equals the diagonal of the assembled sparse matrix
+    mg = graded_mesh(3, 3)
+    np.testing.assert_allclose(operators.diagonal(mg), operators.assemble(mg).diagonal(), rtol=1e-13)
+
+
+def test_jacobi_pcg_is_cg_on_the_scaled_system():
+    """PCG with P = D^{-1} (Section 3.3, Jacobi) is textbook CG on
+    D^{-1/2} A D^{-1/2} y = D^{-1/2} b with u = D^{-1/2} y: iterate by
+    iterate."""
+    m = graded_mesh(2, 4)
+    inner = np.nonzero(~m.boundary_mask())[0]
+    A = operators.assemble(m, dirichlet=True).tocsr()[inner][:, inner]
+    d = operators.diagonal(m)
+    b = np.zeros(m.nglob)
+    b[inner] = np.random.default_rng(19).standard_normal(len(inner))
+    s = 1 / np.sqrt(d[inner])
+    As = (A.multiply(s[:, None]).multiply(s[None, :])).tocsr()
+    ref = []
+    spla.cg(As, s * b[inner], rtol=1e-14, maxiter=8, callback=lambda yk: ref.append(s * yk))
+    _, _, _, its = solver.solve_poisson(m, b, rtol=1e-30, maxit=8, precond="jacobi", record=True)
+    for k in range(1, 8):
+        np.testing.assert_allclose(its[k][inner], ref[k - 1], rtol=0, atol=1e-10 * np.abs(ref[k - 1]).max())
+    # P = S is the Riesz identity on the assembled interior: plain CG
+    ref = []
+    spla.cg(A, b[inner], rtol=1e-14, maxiter=6, callback=lambda yk: ref.append(yk.copy()))
+    _, _, _, its = solver.solve_poisson(m, b, rtol=1e-30, maxit=6, precond="dss", record=True)
+    for k in range(1, 6):
+        np.testing.assert_allclose(its[k][inner], ref[k - 1], rtol=0, atol=1e-10 * np.abs(ref[k - 1]).max())
