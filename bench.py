@@ -107,6 +107,10 @@ def measure_workload(fem, torch, p, n, seed, steps, warmup, prec=0):
     tm = Timer(torch)
     t_apply = tm.time(apply_only, max(steps, 10))
     t_pi = tm.time(pi_only, max(steps, 10))
+    # hot: one buffer set over and over (what fits of it stays in the
+    # Infinity Cache between launches)
+    t_apply_hot = tm.time(lambda i: apply_only(0), max(steps, 10))
+    t_pi_hot = tm.time(lambda i: pi_only(0), max(steps, 10))
     # per-kernel durations of the same steps, from HIP event pairs the library
     # records around each launch on the stream it launches on
     fem.trace_enable(True)
@@ -124,37 +128,81 @@ def measure_workload(fem, torch, p, n, seed, steps, warmup, prec=0):
                apply_unique_gdofs=u / t_apply / 1e9, pi_unique_gdofs=u / t_pi / 1e9,
                apply_cell_gdofs=c / t_apply / 1e9, pi_cell_gdofs=c / t_pi / 1e9,
                step_unique_gdofs=u / wall / 1e9,
-               apply_gbs=2 * es * c / t_apply / 1e9, pi_gbs=2 * es * c / t_pi / 1e9)
+               apply_gbs=2 * es * c / t_apply / 1e9, pi_gbs=2 * es * c / t_pi / 1e9,
+               hot=dict(apply_s=t_apply_hot, pi_s=t_pi_hot, apply_gbs=2 * es * c / t_apply_hot / 1e9,
+                        pi_gbs=2 * es * c / t_pi_hot / 1e9, step_unique_gdofs=u / (t_apply_hot + t_pi_hot) / 1e9))
     res["roofline_by_kernel"] = kernel_table(res)
+    res["ops"] = op_table(res, f"q{p}_{n}" if prec == 0 else None)
     del sets
     P.close()
     torch.cuda.empty_cache()
     return res
 
 
+# Launch-trace label -> the operation of the hot path it belongs to.
+OP_OF = {"apply": "apply", "mass": "mass", "pi_assemble": "patch_inverse", "pi_solve": "patch_inverse",
+         "pi_combine": "patch_inverse", "pi_sweep": "patch_inverse", "dss_axis": "dss"}
+
+
+def op_bytes(op, p, n, esize=8):
+    """Algorithmic HBM bytes of one operation on an n^3 mesh: the per-unit
+    figure of the measurement model times the units.  The apply, the mass
+    apply and the patch inverse read one cell-wise vector and write one
+    (2 x esize bytes per cell DoF; geometry and eigen-data are O(n) and not
+    counted); the structured DSS reads and writes both coincident copies of
+    every face pair of every axis pass (4 x esize per pair)."""
+    cell = cell_dofs(p, n) * esize
+    if op in ("apply", "mass", "patch_inverse"):
+        return 2 * cell
+    if op == "dss":
+        return 4 * esize * (p + 1) ** 2 * 3 * (n - 1) * n * n
+    return None
+
+
+def op_flops(op, p, n):
+    """Algorithmic flops of one operation (FMA = 2).  Apply: 14(p+1) per cell
+    DoF, the useful work of the paper's Laplace table (seven 1D contractions
+    of p+1 terms); mass: 6(p+1) (three contractions); patch inverse: per
+    vertex patch two transforms of three 1D passes over (2p-1)^3 values
+    (2(2p-1) flops each) plus the diagonal scaling, 12 (2p-1)^4 + (2p-1)^3."""
+    nP = 2 * p - 1
+    if op == "apply":
+        return cell_dofs(p, n) * 14 * (p + 1)
+    if op == "mass":
+        return cell_dofs(p, n) * 6 * (p + 1)
+    if op == "patch_inverse":
+        return (n - 1) ** 3 * (12 * nP ** 4 + nP ** 3)
+    return None
+
+
 def kernel_bytes(label, p, n, esize=8, csize=8):
-    """Algorithmic HBM bytes of one launch of a traced kernel: each array it
-    must read or write, once.  cell = cell-wise vector (storage precision,
-    esize bytes), uniq = assembled global-node array, patch = patch-result
-    buffer ((2p-1)^3 per patch), both in the compute precision (csize)."""
+    """Algorithmic bytes charged to one launch of a traced kernel: the bytes
+    of the whole operation it is a phase of (a phase processes every cell
+    DoF of the operation), so its fraction of the HBM peak says how far the
+    operation would be from its roofline if this kernel were all of it."""
+    op = OP_OF.get(label)
+    return None if op is None else op_bytes(op, p, n, esize)
+
+
+def design_bytes(label, p, n, esize=8, csize=8):
+    """Bytes one launch must move given the design's own intermediate arrays
+    (cell = cell-wise vector in the storage precision, uniq = assembled
+    global-node array, patch = patch-result buffer, both in the compute
+    precision): the floor of that kernel's traffic, not the operation's."""
     cell = cell_dofs(p, n) * esize
     uniq = unique_dofs(p, n) * csize
     patch = (n - 1) ** 3 * (2 * p - 1) ** 3 * csize
     return {"apply": 2 * cell, "pi_assemble": cell + uniq, "pi_solve": uniq + patch,
-            "pi_combine": patch + cell, "pi_sweep": 2 * cell + uniq}.get(label)
+            "pi_combine": patch + cell, "pi_sweep": uniq + cell}.get(label)
 
 
 def kernel_flops(label, p, n):
-    """Algorithmic flops of one launch (FMA = 2): the sum-factorised apply
-    (7 one-dimensional contractions of (p+1) terms per cell DoF plus the
-    3-term combination) and the fast-diagonalisation patch solve (two
-    transforms of 3 one-dimensional passes over (2p-1)^3 values, 2(2p-1)
-    flops each, plus the diagonal scaling)."""
-    nP = 2 * p - 1
+    """Flops of one launch: the apply's, and the patch solves' for the
+    phase that runs them (pi_solve, or the fused pi_sweep)."""
     if label == "apply":
-        return cell_dofs(p, n) * (7 * 2 * (p + 1) + 4)
-    if label == "pi_solve":
-        return (n - 1) ** 3 * (12 * nP ** 4 + nP ** 3)
+        return op_flops("apply", p, n)
+    if label in ("pi_solve", "pi_sweep"):
+        return op_flops("patch_inverse", p, n)
     return None
 
 
@@ -174,28 +222,76 @@ def measured_traffic(workload, label):
     return None if k is None else int(round(k["bytes"]))
 
 
+def _peak_flops(csize):
+    return FP64_PEAK_TFLOPS if csize == 8 else FP32_PEAK_TFLOPS
+
+
 def kernel_table(rec):
-    """Every traced kernel of a workload against the HBM roofline."""
+    """Every traced kernel of a workload against the HBM roofline, charged
+    its operation's algorithmic bytes (and, beside, its design floor)."""
     p, n = rec["p"], rec["n"]
+    es, cs = rec.get("esize", 8), rec.get("csize", 8)
     out = []
     for k in rec["kernels"]:
-        b = kernel_bytes(k["label"], p, n, rec.get("esize", 8), rec.get("csize", 8))
+        b = kernel_bytes(k["label"], p, n, es, cs)
         if b is None:
             continue
-        gbs = b / (k["avg_us"] * 1e-6) / 1e9
-        row = {"kernel": k["label"], "avg_us": round(k["avg_us"], 2), "algorithmic_bytes": b,
-               "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        t = k["avg_us"] * 1e-6
+        gbs = b / t / 1e9
+        row = {"kernel": k["label"], "op": OP_OF[k["label"]], "avg_us": round(k["avg_us"], 2),
+               "algorithmic_bytes": b, "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)}
+        db = design_bytes(k["label"], p, n, es, cs)
+        if db is not None:
+            row["design_bytes"] = db
+            row["design_hbm_frac"] = round(db / t / 1e9 / HBM_PEAK_GBS, 4)
         fl = kernel_flops(k["label"], p, n)
         if fl is not None:
-            peak = FP64_PEAK_TFLOPS if rec.get("csize", 8) == 8 else FP32_PEAK_TFLOPS
-            tf = fl / (k["avg_us"] * 1e-6) / 1e12
-            row.update({"algorithmic_flops": fl, "TFLOP/s": round(tf, 2), "flop_frac": round(tf / peak, 4)})
+            tf = fl / t / 1e12
+            row.update({"algorithmic_flops": fl, "TFLOP/s": round(tf, 2), "flop_frac": round(tf / _peak_flops(cs), 4)})
         out.append(row)
     return out
 
 
-def roofline(rec, workload="q3_64"):
-    """Roofline record of the kernel with the largest share of the step."""
+def op_table(rec, workload=None):
+    """Each operation of the step as one unit: its kernels' summed average
+    launch time against its algorithmic bytes and flops, and the counter
+    traffic of its kernels over the algorithmic bytes (null when absent or
+    stale)."""
+    p, n = rec["p"], rec["n"]
+    es, cs = rec.get("esize", 8), rec.get("csize", 8)
+    ops = {}
+    for k in rec["kernels"]:
+        op = OP_OF.get(k["label"])
+        if op is None:
+            continue
+        o = ops.setdefault(op, {"kernels": [], "time_us": 0.0, "traffic": 0})
+        o["kernels"].append(k["label"])
+        o["time_us"] += k["avg_us"]
+        tr = measured_traffic(workload, k["label"]) if workload else None
+        o["traffic"] = None if (tr is None or o["traffic"] is None) else o["traffic"] + tr
+    out = {}
+    for op, o in ops.items():
+        t = o["time_us"] * 1e-6
+        b = op_bytes(op, p, n, es)
+        gbs = b / t / 1e9
+        row = {"kernels": o["kernels"], "time_us": round(o["time_us"], 2), "algorithmic_bytes": b,
+               "GB/s": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+               "roofline_time_us": round(b / (HBM_PEAK_GBS * 1e9) * 1e6, 2)}
+        fl = op_flops(op, p, n)
+        if fl is not None:
+            tf = fl / t / 1e12
+            row.update({"algorithmic_flops": fl, "TFLOP/s": round(tf, 2), "flop_frac": round(tf / _peak_flops(cs), 4)})
+        if o["traffic"]:
+            row["traffic_bytes"] = o["traffic"]
+            row["traffic_over_algorithmic"] = round(o["traffic"] / b, 3)
+        out[op] = row
+    return out
+
+
+def roofline(rec, workload="q3_64", copy_gbs=None):
+    """Roofline record of the kernel with the largest share of the step,
+    charged its operation's algorithmic bytes per launch, with the step's
+    operations as whole units beside it."""
     p, n = rec["p"], rec["n"]
     es, cs = rec.get("esize", 8), rec.get("csize", 8)
     ks = [k for k in rec["kernels"] if kernel_bytes(k["label"], p, n, es, cs) is not None]
@@ -206,12 +302,72 @@ def roofline(rec, workload="q3_64"):
     fl = kernel_flops(dom["label"], p, n)
     out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload, dom["label"]),
-           "kernel": dom["label"], "launch_avg_us": round(dom["avg_us"], 2), "launches": dom["launches"],
-           "algorithmic_bytes_per_launch": byts}
+           "kernel": dom["label"], "op": OP_OF[dom["label"]], "launch_avg_us": round(dom["avg_us"], 2),
+           "launches": dom["launches"], "algorithmic_bytes_per_launch": byts,
+           "design_bytes_per_launch": design_bytes(dom["label"], p, n, es, cs)}
     if fl is not None:
         tf = fl / t / 1e12
-        out["fp64_tflops"] = round(tf, 2)
-        out["fp64_frac"] = round(tf / FP64_PEAK_TFLOPS, 4)
+        out["algorithmic_flops_per_launch"] = fl
+        out["tflops"] = round(tf, 2)
+        out["flop_frac"] = round(tf / _peak_flops(cs), 4)
+    if copy_gbs:
+        out["copy_peak_GB/s"] = round(copy_gbs, 1)
+        out["frac_of_copy_peak"] = round(gbs / copy_gbs, 4)
+    out["ops"] = op_table(rec, workload)
+    return out
+
+
+def copy_peak(torch, nbytes=1 << 30, reps=10):
+    """Measured device copy bandwidth: read + write of a plain 1 GiB copy,
+    (2 x bytes) / time, timed with HIP events."""
+    n = nbytes // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    t = Timer(torch).time(lambda i: dst.copy_(src), reps)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / t / 1e9
+
+
+def paper_kernels(fem, torch, reps=10, n_dss=128, degrees=(2, 3, 7)):
+    """The paper's own measured kernels on uniform unit-cube meshes, FP64:
+    the mass operator (one volumetric apply, Table "mass operator"), the
+    structured DSS in place (three axis passes, Table "DSS throughput") and
+    the entire assembled mass operator (volumetric apply + DSS, Table
+    "entire mass operator", 128^3 cells).  Rates in unique DoFs per second,
+    bytes by the algorithmic model; cold (two rotating buffer pairs)."""
+    out = {}
+    for p in degrees:
+        n = n_dss
+        P = fem.Problem(p, n)
+        x = P.gather(torch.ones(P.global_len, dtype=torch.float64, device="cuda"))
+        pairs = [(x, P.cell_vector()), (x.clone(), P.cell_vector())]
+        tm = Timer(torch)
+        for i in range(2):
+            P.mass_apply(*pairs[i % 2])
+            P.dss(pairs[i % 2][1], pairs[i % 2][1])
+        torch.cuda.synchronize()
+        t_vol = tm.time(lambda i: P.mass_apply(*pairs[i % 2]), reps)
+        t_dss = tm.time(lambda i: P.dss(pairs[i % 2][1], pairs[i % 2][1]), reps)
+
+        def both(i):
+            P.mass_apply(*pairs[i % 2])
+            P.dss(pairs[i % 2][1], pairs[i % 2][1])
+        t_op = tm.time(both, reps)
+        u, c = unique_dofs(p, n), cell_dofs(p, n)
+        bm, bd = op_bytes("mass", p, n), op_bytes("dss", p, n)
+        out[f"q{p}_{n}"] = dict(
+            p=p, n=n, unique_dofs=u, cell_dofs=c,
+            mass=dict(s=t_vol, unique_gdofs=u / t_vol / 1e9, cell_gdofs=c / t_vol / 1e9,
+                      algorithmic_bytes=bm, gbs=bm / t_vol / 1e9, hbm_frac=bm / t_vol / 1e9 / HBM_PEAK_GBS),
+            dss=dict(s=t_dss, unique_gdofs=u / t_dss / 1e9, algorithmic_bytes=bd, gbs=bd / t_dss / 1e9,
+                     hbm_frac=bd / t_dss / 1e9 / HBM_PEAK_GBS),
+            assembled_mass=dict(s=t_op, unique_gdofs=u / t_op / 1e9))
+        del x, pairs
+        P.close()
+        torch.cuda.empty_cache()
     return out
 
 
@@ -285,31 +441,31 @@ def cpu_baseline(steps_budget_s=20.0):
     import synth
     from oracle import operators, patches
     from oracle.mesh import Mesh
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:
-        cores = 1
+    from threadpoolctl import threadpool_limits
     wl = synth.workload_q3_graded()
     m = Mesh(3, wl.n, wl.widths)
-    t0 = time.perf_counter()
-    y = operators.apply_global(m, wl.x)
-    t_apply = time.perf_counter() - t0
-    verts = patches.interior_vertices(m)
-    rng = np.random.default_rng(0)
-    t0 = time.perf_counter()
-    done = 0
-    for v in verts[rng.permutation(len(verts))]:
-        idx = patches.patch_nodes(m, v)
-        patches.patch_solve(m, v, y[idx])
-        done += 1
-        if time.perf_counter() - t0 > steps_budget_s:
-            break
-    t_pi = (time.perf_counter() - t0) / done * len(verts)
+    # the oracle is a serial program (a Python loop over patches); its BLAS
+    # calls are held to one thread too, so `cores` is what actually ran
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        y = operators.apply_global(m, wl.x)
+        t_apply = time.perf_counter() - t0
+        verts = patches.interior_vertices(m)
+        rng = np.random.default_rng(0)
+        t0 = time.perf_counter()
+        done = 0
+        for v in verts[rng.permutation(len(verts))]:
+            idx = patches.patch_nodes(m, v)
+            patches.patch_solve(m, v, y[idx])
+            done += 1
+            if time.perf_counter() - t0 > steps_budget_s:
+                break
+        t_pi = (time.perf_counter() - t0) / done * len(verts)
     u = unique_dofs(3, 64)
-    return dict(value=u / (t_apply + t_pi), unit="DoFs/s", cores=int(cores), kind="oracle",
-                sample=f"Q3 64^3 graded: full matrix-free apply ({t_apply:.2f} s) + dense-LU solves of "
-                       f"{done} of {len(verts)} vertex patches, extrapolated ({t_pi:.1f} s)")
+    return dict(value=u / (t_apply + t_pi), unit="DoFs/s", cores=1, kind="oracle",
+                sample=f"Q3 64^3 graded, one thread: full matrix-free apply ({t_apply:.2f} s) + dense-LU "
+                       f"solves of {done} of {len(verts)} vertex patches, extrapolated ({t_pi:.1f} s)",
+                host_cpus=os.cpu_count())
 
 
 def main():
@@ -319,7 +475,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="bench", choices=["bench", "calib", "serve"])
     ap.add_argument("--quick", action="store_true", help="headline workload only")
-    ap.add_argument("--only", choices=["q2_96", "q7_24", "q7_solve", "batch_256"], default=None,
+    ap.add_argument("--only", choices=["q2_96", "q7_24", "q7_solve", "batch_256", "paper_kernels"], default=None,
                     help="run one secondary workload alone (for profiling) and print its record")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--solve-reps", type=int, default=5)
@@ -356,6 +512,8 @@ def main():
             rec = solve_times(fem, torch, a.solve_reps)
         elif a.only == "batch_256":
             rec = batch_times(fem, torch, a.steps, a.warmup)
+        elif a.only == "paper_kernels":
+            rec = paper_kernels(fem, torch)
         else:
             p, n = (2, 96) if a.only == "q2_96" else (7, 24)
             prec = {"f64": fem.F64, "f32": fem.F32, "bf16": fem.BF16}[a.prec]
@@ -375,8 +533,12 @@ def main():
         extra["q7_solve"] = solve_times(fem, torch, a.solve_reps)
         log("batch of 256 problems")
         extra["batch_256"] = batch_times(fem, torch, a.steps, a.warmup)
+        log("mass operator, structured DSS, assembled mass at 128^3")
+        extra["paper_kernels"] = paper_kernels(fem, torch)
 
-    roof = roofline(head)
+    log("copy peak")
+    copy_gbs = copy_peak(torch)
+    roof = roofline(head, "q3_64", copy_gbs)
     cpu = None
     if not a.no_cpu:
         log("cpu baseline (oracle)")

@@ -77,6 +77,10 @@ typedef enum fem_status {
 typedef enum fem_prec { FEM_F64 = 0, FEM_F32 = 1, FEM_BF16 = 2 } fem_prec;
 typedef enum fem_bc { FEM_BC_DIRICHLET = 0, FEM_BC_NEUMANN = 1 } fem_bc;
 typedef enum fem_cg_variant { FEM_CG_AUTO = 0, FEM_CG_PCG = 1, FEM_CG_FCG = 2 } fem_cg_variant;
+/* Preconditioners of the solver: the additive Schwarz smoother over vertex
+ * patches, and the two simple ones of Section 3.3, the trivial P = S
+ * (Eq. "dss_operator") and Jacobi P = D_cell^{-1} S. */
+typedef enum fem_precond { FEM_PC_SCHWARZ = 0, FEM_PC_DSS = 1, FEM_PC_JACOBI = 2 } fem_precond;
 
 /* Problem description.  p in 1..7, n[d] >= 1 (>= 2 for patch_inverse to be
  * non-trivial).  widths[d]: host array of n[d] positive cell widths along
@@ -197,6 +201,26 @@ fem_status fem_assembled_norm(fem_problem* P, const void* r, int prec, double* r
 fem_status pcg_solve(fem_problem* P, const double* b_cell, double* u_cell, double rtol,
                      int maxit, int smoother_prec, int sweeps, double omega, int variant,
                      fem_solve_info* info);
+
+/* pcg_solve with a choice of preconditioner (fem_precond).  FEM_PC_SCHWARZ
+ * is pcg_solve itself.  FEM_PC_DSS and FEM_PC_JACOBI apply z = S r or
+ * z = D_cell^{-1} S r (Section 3.3: the assembled residual on every copy,
+ * divided for Jacobi by the diagonal of the assembled operator, zero on a
+ * Dirichlet boundary) in one pass that also yields ||G^T r||, in precision
+ * smoother_prec; sweeps and omega are then unused (sweeps must still be >= 1).
+ * FEM_CG_AUTO picks PCG for these static preconditioners.  Same buffers,
+ * workspace, synchronisation and errors as pcg_solve. */
+fem_status pcg_solve_pc(fem_problem* P, const double* b_cell, double* u_cell, double rtol, int maxit,
+                        int precond, int smoother_prec, int sweeps, double omega, int variant,
+                        fem_solve_info* info);
+/* One application of a simple preconditioner of Section 3.3: z = S r
+ * (precond FEM_PC_DSS) or z = D_cell^{-1} S r (FEM_PC_JACOBI), where D_cell
+ * holds on every copy of a node the diagonal of the assembled operator
+ * (the identity G D_CG^{-1} = D_cell^{-1} G after Eq. "dss_operator").
+ * r: dual FP64 cell-wise vector (read); z: primal cell-wise vector in `prec`
+ * (written), every copy of a node bitwise equal, zero on a Dirichlet
+ * boundary.  r == z is FEM_EINVAL. */
+fem_status fem_precond_apply(fem_problem* P, int precond, const void* r_cell, void* z_cell, int prec);
 
 /* ------------------------------------------------------- batched launches */
 

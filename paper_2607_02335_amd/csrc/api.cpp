@@ -430,35 +430,26 @@ extern "C" fem_status fem_assembled_norm(fem_problem* P, const void* r, int prec
 }
 
 // ---------------------------------------------------------------- solver
-extern "C" fem_status pcg_solve(fem_problem* P, const double* b, double* u, double rtol, int maxit,
-                                int sp, int sweeps, double omega, int variant, fem_solve_info* info) {
-    const auto t0 = std::chrono::steady_clock::now();
-    fem_solve_info loc{};
-    if (!info) info = &loc;
-    *info = fem_solve_info{};
-    CHECK_P(P); CHECK_PTR(b); CHECK_PTR(u);
-    if (check_prec(sp)) return FEM_EINVAL;
-    if (!(rtol > 0) || maxit < 0 || sweeps < 1) return set_error(FEM_EINVAL, "pcg_solve: rtol > 0, maxit >= 0, sweeps >= 1");
-    if (b == u) return set_error(FEM_EINVAL, "pcg_solve: b and u alias");
-    if (variant == FEM_CG_AUTO) variant = sp == FEM_F64 ? FEM_CG_PCG : FEM_CG_FCG;
-    if (variant != FEM_CG_PCG && variant != FEM_CG_FCG) return set_error(FEM_EINVAL, "pcg_solve: unknown variant");
+namespace fem {
+// Bytes of the solver's own vectors r, p, q (FP64) and z, rs (preconditioner
+// precision) for a cell length.
+static size_t solve_bytes_for(size_t len, int sp) { return align256(3 * 8 * len) + align256(2 * prec_bytes(sp) * len); }
 
+// The (F)PCG of Algorithm "Communication-Free (F)PCG" on the handle's
+// stream, its vectors carved from `work` (solve_bytes_for bytes).  pc picks
+// the preconditioner: the Schwarz smoother (smoother_run), or one pass of
+// S or D_cell^{-1} S (Section 3.3), which also yields ||G^T r|| for the
+// stopping test.
+static fem_status pcg_core(fem_problem* P, const double* b, double* u, double rtol, int maxit, int pc, int sp,
+                           int sweeps, double omega, int variant, char* work, fem_solve_info* info,
+                           std::chrono::steady_clock::time_point t0) {
     const size_t len = P->cell_len;
-    const size_t need = align256(3 * 8 * len) + align256(2 * prec_bytes(sp) * len);
-    if (P->solve_bytes < need) {
-        hipFree(P->d_solve);
-        P->d_solve = nullptr;
-        P->solve_bytes = 0;
-        hipError_t e = hipMalloc(&P->d_solve, need);
-        if (e != hipSuccess) return set_error(FEM_ENOMEM, "pcg_solve: workspace allocation failed");
-        P->solve_bytes = need;
-    }
-    char* base = static_cast<char*>(P->d_solve);
-    double* r = reinterpret_cast<double*>(base);
+    double* r = reinterpret_cast<double*>(work);
     double* p = r + len;
     double* q = p + len;
-    void* z = base + align256(3 * 8 * len);
+    void* z = work + align256(3 * 8 * len);
     void* rs = sp == FEM_F64 ? (void*)r : (void*)(static_cast<char*>(z) + align256(prec_bytes(sp) * len));
+    const bool schwarz = pc == FEM_PC_SCHWARZ;
 
     auto finish = [&](fem_status st, int iters, double relres) {
         info->iters = iters;
@@ -470,6 +461,10 @@ extern "C" fem_status pcg_solve(fem_problem* P, const double* b, double* u, doub
         if (st == FEM_EBREAKDOWN) set_error(st, "pcg_solve: breakdown (<q,p> not positive and finite)");
         return st;
     };
+    auto precondition = [&]() -> fem_status {
+        if (schwarz) return smoother_run(P, rs, z, sp, sweeps, omega);
+        return FEM_OK;      // the simple preconditioners ran with the norm
+    };
 
     // r = b - A u
     {
@@ -480,16 +475,17 @@ extern "C" fem_status pcg_solve(fem_problem* P, const double* b, double* u, doub
         FEM_HIP(launch_apply(P->p, FEM_F64, 1, &e, 1, nullptr, P->stream), "pcg_solve residual");
     }
     FEM_HIP(run_assembled_norm2(P, b, FEM_F64, kSlotB2), "pcg_solve norm");
-    FEM_HIP(run_assembled_norm2(P, r, FEM_F64, kSlotRN), "pcg_solve norm");
+    if (schwarz) FEM_HIP(run_assembled_norm2(P, r, FEM_F64, kSlotRN), "pcg_solve norm");
+    else FEM_HIP(run_simple_precond(P, pc, r, z, sp, kSlotRN), "pcg_solve preconditioner");
     fem_status st = read_slots(P);
     if (st != FEM_OK) return finish(st, 0, NAN);
     const double bn = std::sqrt(P->h_red[kSlotB2]);
     double rel = bn > 0 ? std::sqrt(P->h_red[kSlotRN]) / bn : 0.0;
     if (bn == 0.0 || rel <= rtol) return finish(FEM_OK, 0, rel);
     // reduced-precision smoothers get the residual assembled in FP64 first
-    if (sp != FEM_F64) FEM_HIP(run_distribute(P, r, rs, sp, kSlotTmp), "pcg_solve distribute");
+    if (schwarz && sp != FEM_F64) FEM_HIP(run_distribute(P, r, rs, sp, kSlotTmp), "pcg_solve distribute");
 
-    st = smoother_run(P, rs, z, sp, sweeps, omega);
+    st = precondition();
     if (st != FEM_OK) return finish(st, 0, rel);
     FEM_HIP(run_convert(P, z, sp, p, FEM_F64), "pcg_solve p0");
     FEM_HIP(run_dot(P, r, FEM_F64, z, sp, kSlotRZ), "pcg_solve dot");
@@ -502,7 +498,8 @@ extern "C" fem_status pcg_solve(fem_problem* P, const double* b, double* u, doub
         FEM_HIP(launch_apply(P->p, FEM_F64, 0, &e, 1, nullptr, P->stream), "pcg_solve apply");
         FEM_HIP(run_dot(P, q, FEM_F64, p, FEM_F64, kSlotQP), "pcg_solve dot");
         FEM_HIP(run_cg_update_r(P, r, q, nullptr, FEM_F64), "pcg_solve update");
-        if (sp == FEM_F64) FEM_HIP(run_assembled_norm2(P, r, FEM_F64, kSlotRN), "pcg_solve norm");
+        if (!schwarz) FEM_HIP(run_simple_precond(P, pc, r, z, sp, kSlotRN), "pcg_solve preconditioner");
+        else if (sp == FEM_F64) FEM_HIP(run_assembled_norm2(P, r, FEM_F64, kSlotRN), "pcg_solve norm");
         else FEM_HIP(run_distribute(P, r, rs, sp, kSlotRN), "pcg_solve distribute");
         st = read_slots(P);
         if (st != FEM_OK) return finish(st, k, rel);
@@ -517,7 +514,7 @@ extern "C" fem_status pcg_solve(fem_problem* P, const double* b, double* u, doub
             FEM_HIP(hipStreamSynchronize(P->stream), "pcg_solve");
             return finish(rel <= rtol ? FEM_OK : FEM_ENOTCONV, k, rel);
         }
-        st = smoother_run(P, rs, z, sp, sweeps, omega);
+        st = precondition();
         if (st != FEM_OK) return finish(st, k, rel);
         if (variant == FEM_CG_PCG) {
             FEM_HIP(run_slot_copy(P, kSlotRZOld, kSlotRZ), "pcg_solve slots");
@@ -529,3 +526,53 @@ extern "C" fem_status pcg_solve(fem_problem* P, const double* b, double* u, doub
     }
     return finish(FEM_ENOTCONV, k, rel);
 }
+
+// Argument checks shared by the solve entry points; resolves FEM_CG_AUTO.
+static fem_status check_solve_args(fem_problem* P, const double* b, const double* u, double rtol, int maxit,
+                                   int pc, int sp, int sweeps, int* variant) {
+    CHECK_P(P); CHECK_PTR(b); CHECK_PTR(u);
+    if (check_prec(sp)) return FEM_EINVAL;
+    if (pc != FEM_PC_SCHWARZ && pc != FEM_PC_DSS && pc != FEM_PC_JACOBI)
+        return set_error(FEM_EINVAL, "pcg_solve: unknown preconditioner");
+    if (!(rtol > 0) || maxit < 0 || sweeps < 1) return set_error(FEM_EINVAL, "pcg_solve: rtol > 0, maxit >= 0, sweeps >= 1");
+    if (b == u) return set_error(FEM_EINVAL, "pcg_solve: b and u alias");
+    if (*variant == FEM_CG_AUTO) *variant = (sp == FEM_F64 || pc != FEM_PC_SCHWARZ) ? FEM_CG_PCG : FEM_CG_FCG;
+    if (*variant != FEM_CG_PCG && *variant != FEM_CG_FCG) return set_error(FEM_EINVAL, "pcg_solve: unknown variant");
+    return FEM_OK;
+}
+}  // namespace fem
+
+extern "C" fem_status pcg_solve_pc(fem_problem* P, const double* b, double* u, double rtol, int maxit, int pc,
+                                   int sp, int sweeps, double omega, int variant, fem_solve_info* info) {
+    const auto t0 = std::chrono::steady_clock::now();
+    fem_solve_info loc{};
+    if (!info) info = &loc;
+    *info = fem_solve_info{};
+    fem_status st = check_solve_args(P, b, u, rtol, maxit, pc, sp, sweeps, &variant);
+    if (st != FEM_OK) return st;
+    const size_t need = solve_bytes_for(P->cell_len, sp);
+    if (P->solve_bytes < need) {
+        hipFree(P->d_solve);
+        P->d_solve = nullptr;
+        P->solve_bytes = 0;
+        hipError_t e = hipMalloc(&P->d_solve, need);
+        if (e != hipSuccess) return set_error(FEM_ENOMEM, "pcg_solve: workspace allocation failed");
+        P->solve_bytes = need;
+    }
+    return pcg_core(P, b, u, rtol, maxit, pc, sp, sweeps, omega, variant, static_cast<char*>(P->d_solve), info, t0);
+}
+
+extern "C" fem_status pcg_solve(fem_problem* P, const double* b, double* u, double rtol, int maxit,
+                                int sp, int sweeps, double omega, int variant, fem_solve_info* info) {
+    return pcg_solve_pc(P, b, u, rtol, maxit, FEM_PC_SCHWARZ, sp, sweeps, omega, variant, info);
+}
+
+extern "C" fem_status fem_precond_apply(fem_problem* P, int pc, const void* r, void* z, int prec) {
+    CHECK_P(P); CHECK_PTR(r); CHECK_PTR(z);
+    if (check_prec(prec)) return FEM_EINVAL;
+    if (pc != FEM_PC_DSS && pc != FEM_PC_JACOBI) return set_error(FEM_EINVAL, "fem_precond_apply: kind must be FEM_PC_DSS or FEM_PC_JACOBI");
+    if (r == z) return set_error(FEM_EINVAL, "fem_precond_apply: r and z alias");
+    FEM_HIP(run_simple_precond(P, pc, static_cast<const double*>(r), z, prec, kSlotTmp), "fem_precond_apply");
+    return FEM_OK;
+}
+

@@ -840,7 +840,13 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
             const double rn = S->h_collect[2 * i], qp = S->h_collect[2 * i + 1], b2 = S->h_collect[2 * na + 2 * i];
             A->iters += 1;
             A->relres = b2 > 0 ? std::sqrt(rn / b2) : 0.0;
-            if (!(qp > 0) || !std::isfinite(qp) || !std::isfinite(A->relres)) {
+            if (b2 == 0.0) {
+                // zero right-hand side: u = 0 is the solution (the step just
+                // run took alpha = 0), as pcg_solve returns without iterating
+                A->finished = true;
+                A->status = FEM_OK;
+                A->iters = 0;
+            } else if (!(qp > 0) || !std::isfinite(qp) || !std::isfinite(A->relres)) {
                 A->finished = true;
                 A->status = FEM_EBREAKDOWN;
             } else if (A->relres <= A->req.rtol) {

@@ -114,8 +114,27 @@ __global__ void __launch_bounds__(256) k_anorm(LaunchTable L, int group) {
 // values far larger than its assembly (they cancel across interfaces), so
 // rounding copies before assembling would leave an absolute error of
 // eps(RS) times those values in the smoother's input.
-template <int P, typename RS, bool MULTI>
-__global__ void __launch_bounds__(256) k_distribute(LaunchTable L, int group) {
+//
+// The same pass serves the simple preconditioners of Section 3.3 (MODE):
+//   kDistMean     rs = G^T r / multiplicity (above),
+//   kDistDss      z = S r = G G^T r: every copy gets the assembled value
+//                 (Eq. "dss_operator"), zero on a Dirichlet boundary,
+//   kDistJacobi   z = D_cell^{-1} S r: the assembled value divided by the
+//                 diagonal of the assembled operator at the node, which is
+//                 summed from the cells' element diagonals in the same loop
+//                 (diag A_K at local (a,b,c) = cx Kaa Mbb Mcc + cy Maa Kbb Mcc
+//                 + cz Maa Mbb Kcc), zero on a Dirichlet boundary.
+// Every copy of a node computes the same terms in the same order, so the
+// output is continuous bit for bit.
+enum { kDistMean = 0, kDistDss = 1, kDistJacobi = 2 };
+
+struct Diag1D {
+    double k[kMaxP + 1];    // diagonal of the 1D reference stiffness
+    double m[kMaxP + 1];    // diagonal of the 1D reference mass
+};
+
+template <int P, typename RS, int MODE, bool MULTI>
+__global__ void __launch_bounds__(256) k_distribute(LaunchTable L, int group, Diag1D dg) {
     constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
     __shared__ double sh[4];
     const int lane = threadIdx.x % kLanes, lq = threadIdx.x / kLanes;
@@ -151,15 +170,31 @@ __global__ void __launch_bounds__(256) k_distribute(LaunchTable L, int group) {
                 if (c == 0 && k > 0) { ck[0] = k - 1; ck_l[0] = P; ck[1] = k; ck_l[1] = 0; nz = 2; }
                 else if (c == P && k < n2 - 1) { ck[0] = k; ck_l[0] = P; ck[1] = k + 1; ck_l[1] = 0; nz = 2; }
                 else { ck[0] = k; ck_l[0] = c; nz = 1; }
-                double s = 0.0;
+                double s = 0.0, d = 0.0;
                 for (int z = 0; z < nz; ++z)
                     for (int y = 0; y < ny; ++y)
                         for (int x = 0; x < nx; ++x) {
                             const int ee = ci[x] + n0 * (cj[y] + n1 * ck[z]);
                             const int ll = ai[x] + N * (bj[y] + N * ck_l[z]);
                             s += v[cell_offset(ee, ll, NN)];
+                            if (MODE == kDistJacobi) {
+                                const double hx = pe.h[0][ci[x]], hy = pe.h[1][cj[y]], hz = pe.h[2][ck[z]];
+                                const int ax = ai[x], by = bj[y], cz = ck_l[z];
+                                d += (hy * hz / hx) * dg.k[ax] * dg.m[by] * dg.m[cz] +
+                                     (hx * hz / hy) * dg.m[ax] * dg.k[by] * dg.m[cz] +
+                                     (hx * hy / hz) * dg.m[ax] * dg.m[by] * dg.k[cz];
+                            }
                         }
-                store_from(out + base + (size_t)l * kLanes + lane, (typename Prec<RS>::C)(s / (double)(nx * ny * nz)));
+                double o;
+                if (MODE == kDistMean) {
+                    o = s / (double)(nx * ny * nz);
+                } else {
+                    const bool bnd = pe.dirichlet && ((a == 0 && i == 0) || (a == P && i == n0 - 1) ||
+                                                      (b == 0 && j == 0) || (b == P && j == n1 - 1) ||
+                                                      (c == 0 && k == 0) || (c == P && k == n2 - 1));
+                    o = bnd ? 0.0 : (MODE == kDistJacobi ? s / d : s);
+                }
+                store_from(out + base + (size_t)l * kLanes + lane, (typename Prec<RS>::C)o);
                 // owner copy: lowest cell along every direction
                 if (ci[0] == i && cj[0] == j && ck[0] == k) acc += s * s;
             }
@@ -311,7 +346,11 @@ __global__ void __launch_bounds__(256) k_cg_ur(LaunchTable L) {
         const ProbEntry& pe = entry<MULTI>(L, tile);
         const int t = tile - pe.tile_begin;
         double* sl = red_slots(pe.red);
-        const double alpha = sl[kSlotRZ] / sl[kSlotQP];
+        // a breakdown (<q,p> not positive, or a non-finite step) leaves r and
+        // u where they are: the host sees <q,p> and stops the solve, and a
+        // zero right-hand side (r = z = p = 0) takes no step at all
+        double alpha = sl[kSlotRZ] / sl[kSlotQP];
+        if (!(sl[kSlotQP] > 0.0) || !__builtin_isfinite(alpha)) alpha = 0.0;
         if (t == 0 && threadIdx.x == 0) sl[kSlotAlpha] = alpha;
         size_t lo, hi;
         red_range(pe, t, lo, hi);
@@ -635,7 +674,25 @@ hipError_t run_assembled_norm2(fem_problem* P, const void* r, int prec, int slot
     return finish_reduction(P, e, 1, slot);
 }
 
-hipError_t run_distribute(fem_problem* P, const double* r, void* out, int prec, int slot) {
+static Diag1D diag_1d(int p) {
+    Diag1D dg{};
+    const double* M = ref_mass(p);
+    const double* K = ref_stiff(p);
+    for (int a = 0; a <= p; ++a) {
+        dg.m[a] = M[a * (p + 1) + a];
+        dg.k[a] = K[a * (p + 1) + a];
+    }
+    return dg;
+}
+
+template <int P, typename S, int MODE>
+static void launch_distribute_one(LaunchTable& L, hipStream_t s, const Diag1D& dg) {
+    hipLaunchKernelGGL((k_distribute<P, S, MODE, false>), dim3(L.total_tiles), dim3(256), 0, s, L, 2, dg);
+}
+
+template <int MODE>
+static hipError_t run_distribute_mode(fem_problem* P, const double* r, void* out, int prec, int slot,
+                                      const char* label) {
     ProbEntry e = entry_of(P);
     e.a = r;
     e.c = out;
@@ -644,24 +701,34 @@ hipError_t run_distribute(fem_problem* P, const double* r, void* out, int prec, 
     L.nprob = 1;
     L.total_tiles = e.ntiles_red;
     L.one = e;
+    const Diag1D dg = MODE == kDistJacobi ? diag_1d(P->p) : Diag1D{};
     hipError_t err = dispatch_prec(prec, [&](auto tag) {
         using S = decltype(tag);
-        dim3 g(L.total_tiles), b(256);
-        TraceSpan ts("distribute", P->p, Prec<S>::id, P->stream);
+        TraceSpan ts(label, P->p, Prec<S>::id, P->stream);
         switch (P->p) {
-            case 1: hipLaunchKernelGGL((k_distribute<1, S, false>), g, b, 0, P->stream, L, 2); break;
-            case 2: hipLaunchKernelGGL((k_distribute<2, S, false>), g, b, 0, P->stream, L, 2); break;
-            case 3: hipLaunchKernelGGL((k_distribute<3, S, false>), g, b, 0, P->stream, L, 2); break;
-            case 4: hipLaunchKernelGGL((k_distribute<4, S, false>), g, b, 0, P->stream, L, 2); break;
-            case 5: hipLaunchKernelGGL((k_distribute<5, S, false>), g, b, 0, P->stream, L, 2); break;
-            case 6: hipLaunchKernelGGL((k_distribute<6, S, false>), g, b, 0, P->stream, L, 2); break;
-            case 7: hipLaunchKernelGGL((k_distribute<7, S, false>), g, b, 0, P->stream, L, 2); break;
+            case 1: launch_distribute_one<1, S, MODE>(L, P->stream, dg); break;
+            case 2: launch_distribute_one<2, S, MODE>(L, P->stream, dg); break;
+            case 3: launch_distribute_one<3, S, MODE>(L, P->stream, dg); break;
+            case 4: launch_distribute_one<4, S, MODE>(L, P->stream, dg); break;
+            case 5: launch_distribute_one<5, S, MODE>(L, P->stream, dg); break;
+            case 6: launch_distribute_one<6, S, MODE>(L, P->stream, dg); break;
+            case 7: launch_distribute_one<7, S, MODE>(L, P->stream, dg); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
     });
     if (err != hipSuccess) return err;
     return finish_reduction(P, e, 2, slot);
+}
+
+hipError_t run_distribute(fem_problem* P, const double* r, void* out, int prec, int slot) {
+    return run_distribute_mode<kDistMean>(P, r, out, prec, slot, "distribute");
+}
+
+hipError_t run_simple_precond(fem_problem* P, int kind, const double* r, void* z, int prec, int slot) {
+    if (kind == FEM_PC_DSS) return run_distribute_mode<kDistDss>(P, r, z, prec, slot, "precond_dss");
+    if (kind == FEM_PC_JACOBI) return run_distribute_mode<kDistJacobi>(P, r, z, prec, slot, "precond_jacobi");
+    return hipErrorInvalidValue;
 }
 
 hipError_t run_cg_update_r(fem_problem* P, double* r, const double* q, void* rs, int rs_prec) {
@@ -787,8 +854,9 @@ hipError_t launch_dot(int pa, int pb, ProbEntry* ents, int nprob, TableStager* s
 
 template <int P, typename S>
 static void launch_distribute_pt(LaunchTable& L, int grid, hipStream_t s) {
-    if (L.nprob > 1) hipLaunchKernelGGL((k_distribute<P, S, true>), dim3(grid), dim3(256), 0, s, L, 2);
-    else hipLaunchKernelGGL((k_distribute<P, S, false>), dim3(grid), dim3(256), 0, s, L, 2);
+    const Diag1D dg{};
+    if (L.nprob > 1) hipLaunchKernelGGL((k_distribute<P, S, kDistMean, true>), dim3(grid), dim3(256), 0, s, L, 2, dg);
+    else hipLaunchKernelGGL((k_distribute<P, S, kDistMean, false>), dim3(grid), dim3(256), 0, s, L, 2, dg);
 }
 
 hipError_t launch_distribute(int p, int prec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int slot) {

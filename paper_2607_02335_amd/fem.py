@@ -20,6 +20,7 @@ FEM_OK, FEM_EINVAL, FEM_ENOMEM, FEM_EHIP, FEM_ENOTCONV, FEM_EBREAKDOWN, FEM_EAGA
 F64, F32, BF16 = 0, 1, 2
 DIRICHLET, NEUMANN = 0, 1
 CG_AUTO, CG_PCG, CG_FCG = 0, 1, 2
+PC_SCHWARZ, PC_DSS, PC_JACOBI = 0, 1, 2
 STATUS_NAMES = {0: "FEM_OK", 1: "FEM_EINVAL", 2: "FEM_ENOMEM", 3: "FEM_EHIP", 4: "FEM_ENOTCONV",
                 5: "FEM_EBREAKDOWN", 6: "FEM_EAGAIN", 7: "FEM_ENOTFOUND"}
 
@@ -77,6 +78,8 @@ def lib():
         "fem_dot": ([vp, vp, i, vp, i, ct.POINTER(d)], i),
         "fem_assembled_norm": ([vp, vp, i, ct.POINTER(d)], i),
         "pcg_solve": ([vp, vp, vp, d, i, i, i, d, i, ct.POINTER(SolveInfo)], i),
+        "pcg_solve_pc": ([vp, vp, vp, d, i, i, i, i, d, i, ct.POINTER(SolveInfo)], i),
+        "fem_precond_apply": ([vp, i, vp, vp, i], i),
         "fem_batch_create": ([i, ct.POINTER(Desc), vp, pp], i),
         "fem_batch_destroy": ([vp], i),
         "fem_batch_problem": ([vp, i, pp], i),
@@ -147,6 +150,33 @@ def prec_of(t):
     return {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}[t.dtype]
 
 
+def _check_vec(t, length, prec=None, name="vector"):
+    """Reject a caller-supplied tensor the library would read or write out of
+    bounds: it must be a contiguous tensor of `length` elements and, when
+    given, of the dtype of precision `prec` (its device is checked by
+    _require_cuda once every argument has passed this)."""
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
+    if t.numel() != length:
+        raise ValueError(f"{name}: has {t.numel()} elements, expected {length}")
+    if t.dtype not in (torch.float64, torch.float32, torch.bfloat16):
+        raise ValueError(f"{name}: unsupported dtype {t.dtype}")
+    if prec is not None and t.dtype != torch_dtype(prec):
+        raise ValueError(f"{name}: dtype {t.dtype} does not match precision {prec} ({torch_dtype(prec)})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    return t
+
+
+def _require_cuda(*ts):
+    """Every given tensor must live in device memory (checked after the
+    sizes and dtypes of all arguments)."""
+    for t in ts:
+        if t is not None and t.device.type != "cuda":
+            raise ValueError(f"vector on {t.device}: the library takes device memory")
+
+
 def _stream():
     torch = _torch()
     return ct.c_void_p(torch.cuda.current_stream().cuda_stream)
@@ -165,6 +195,8 @@ def make_desc(p, n, widths=None, bc=DIRICHLET):
             d.widths[k] = ct.POINTER(ct.c_double)()
         else:
             w = np.ascontiguousarray(widths[k], dtype=np.float64)
+            if w.ndim != 1 or w.size != int(n[k]):
+                raise ValueError(f"widths[{k}]: has {w.size} entries, the mesh has {int(n[k])} cells")
             keep.append(w)
             d.widths[k] = w.ctypes.data_as(ct.POINTER(ct.c_double))
     d.bc = int(bc)
@@ -269,8 +301,13 @@ class Problem:
         except Exception:
             pass
 
-    def _sync_stream(self):
+    def _sync_stream(self, *tensors):
+        _require_cuda(*tensors)
         lib().fem_set_stream(self.h, _stream())
+
+    def _cell(self, t, prec, name):
+        """Check a caller's cell-wise vector (length, dtype, device, layout)."""
+        return _check_vec(t, self.cell_len, prec, name)
 
     # vectors -------------------------------------------------------------
     def cell_vector(self, prec=F64):
@@ -278,33 +315,38 @@ class Problem:
         return torch.zeros(self.cell_len, dtype=torch_dtype(prec), device="cuda")
 
     def gather(self, x_glob, prec=F64):
-        self._sync_stream()
+        _check_vec(x_glob, self.global_len, F64, "x_glob")
+        self._sync_stream(x_glob)
         out = self.cell_vector(prec)
         check(lib().fem_gather(self.h, _ptr(x_glob), _ptr(out), prec), "fem_gather")
         return out
 
     def scatter(self, y_cell):
-        self._sync_stream()
+        self._cell(y_cell, None, "y_cell")
+        self._sync_stream(y_cell)
         torch = _torch()
         out = torch.empty(self.global_len, dtype=torch.float64, device="cuda")
         check(lib().fem_scatter(self.h, _ptr(y_cell), _ptr(out), prec_of(y_cell)), "fem_scatter")
         return out
 
     def extract(self, u_cell):
-        self._sync_stream()
+        self._cell(u_cell, None, "u_cell")
+        self._sync_stream(u_cell)
         torch = _torch()
         out = torch.empty(self.global_len, dtype=torch.float64, device="cuda")
         check(lib().fem_extract(self.h, _ptr(u_cell), _ptr(out), prec_of(u_cell)), "fem_extract")
         return out
 
     def pack(self, canon, prec=F64):
-        self._sync_stream()
+        _check_vec(canon, self.num_cells * (self.p + 1) ** 3, F64, "canon")
+        self._sync_stream(canon)
         out = self.cell_vector(prec)
         check(lib().fem_pack(self.h, _ptr(canon), _ptr(out), prec), "fem_pack")
         return out
 
     def unpack(self, v_cell):
-        self._sync_stream()
+        self._cell(v_cell, None, "v_cell")
+        self._sync_stream(v_cell)
         torch = _torch()
         nn = (self.p + 1) ** 3
         out = torch.empty(self.num_cells * nn, dtype=torch.float64, device="cuda")
@@ -312,78 +354,124 @@ class Problem:
         return out.view(self.num_cells, nn)
 
     def convert(self, src, prec):
-        self._sync_stream()
+        self._cell(src, None, "src")
+        self._sync_stream(src)
         out = self.cell_vector(prec)
         check(lib().fem_convert(self.h, _ptr(src), prec_of(src), _ptr(out), prec), "fem_convert")
         return out
 
     def distribute_assembled(self, r, prec):
         """G^T r / multiplicity per copy in `prec` (r dual FP64)."""
-        self._sync_stream()
+        self._cell(r, F64, "r")
+        self._sync_stream(r)
         out = self.cell_vector(prec)
         check(lib().fem_distribute_assembled(self.h, _ptr(r), _ptr(out), prec), "fem_distribute_assembled")
         return out
 
     # operators -----------------------------------------------------------
     def apply(self, x, y=None):
-        self._sync_stream()
+        self._cell(x, None, "x")
+        if y is not None:
+            self._cell(y, prec_of(x), "y")
+        _require_cuda(x, y)
         y = self.cell_vector(prec_of(x)) if y is None else y
+        self._sync_stream()
         check(lib().fe_apply(self.h, _ptr(x), _ptr(y), prec_of(x)), "fe_apply")
         return y
 
     def mass_apply(self, x, y=None):
-        self._sync_stream()
+        self._cell(x, None, "x")
+        if y is not None:
+            self._cell(y, prec_of(x), "y")
+        _require_cuda(x, y)
         y = self.cell_vector(prec_of(x)) if y is None else y
+        self._sync_stream()
         check(lib().fe_mass_apply(self.h, _ptr(x), _ptr(y), prec_of(x)), "fe_mass_apply")
         return y
 
     def dss(self, v, s=None):
-        self._sync_stream()
+        self._cell(v, None, "v")
+        if s is not None:
+            self._cell(s, prec_of(v), "s")
+        _require_cuda(v, s)
         s = self.cell_vector(prec_of(v)) if s is None else s
+        self._sync_stream()
         check(lib().fem_dss(self.h, _ptr(v), _ptr(s), prec_of(v)), "fem_dss")
         return s
 
     def dss_axis(self, v, axis):
-        self._sync_stream()
+        self._cell(v, None, "v")
+        self._sync_stream(v)
         check(lib().fem_dss_axis(self.h, _ptr(v), axis, prec_of(v)), "fem_dss_axis")
         return v
 
     def patch_inverse(self, r, z=None):
-        self._sync_stream()
+        self._cell(r, None, "r")
+        if z is not None:
+            self._cell(z, prec_of(r), "z")
+        _require_cuda(r, z)
         z = self.cell_vector(prec_of(r)) if z is None else z
+        self._sync_stream()
         check(lib().patch_inverse(self.h, _ptr(r), _ptr(z), prec_of(r)), "patch_inverse")
         return z
 
     def smoother_step(self, r, z=None, sweeps=2, omega=0.125):
-        self._sync_stream()
+        self._cell(r, None, "r")
+        if z is not None:
+            self._cell(z, prec_of(r), "z")
+        _require_cuda(r, z)
         z = self.cell_vector(prec_of(r)) if z is None else z
+        self._sync_stream()
         check(lib().smoother_step(self.h, _ptr(r), _ptr(z), prec_of(r), sweeps, omega), "smoother_step")
         return z
 
     def dot(self, a, b):
-        self._sync_stream()
+        self._cell(a, None, "a")
+        self._cell(b, None, "b")
+        self._sync_stream(a, b)
         out = ct.c_double()
         check(lib().fem_dot(self.h, _ptr(a), prec_of(a), _ptr(b), prec_of(b), ct.byref(out)), "fem_dot")
         return out.value
 
     def assembled_norm(self, r):
-        self._sync_stream()
+        self._cell(r, None, "r")
+        self._sync_stream(r)
         out = ct.c_double()
         check(lib().fem_assembled_norm(self.h, _ptr(r), prec_of(r), ct.byref(out)), "fem_assembled_norm")
         return out.value
 
-    def pcg_solve(self, b, u=None, rtol=1e-8, maxit=1000, smoother_prec=F64, sweeps=2,
-                  omega=0.125, variant=CG_AUTO, raise_on_error=True):
-        """Solve A u = b (b dual, FP64).  Returns (u, info dict)."""
+    def precond_apply(self, r, kind=PC_JACOBI, prec=F64, z=None):
+        """z = S r (PC_DSS) or D_cell^{-1} S r (PC_JACOBI); r dual FP64."""
+        self._cell(r, F64, "r")
+        if z is not None:
+            self._cell(z, prec, "z")
+        _require_cuda(r, z)
+        z = self.cell_vector(prec) if z is None else z
         self._sync_stream()
+        check(lib().fem_precond_apply(self.h, kind, _ptr(r), _ptr(z), prec), "fem_precond_apply")
+        return z
+
+    def pcg_solve(self, b, u=None, rtol=1e-8, maxit=1000, smoother_prec=F64, sweeps=2,
+                  omega=0.125, variant=CG_AUTO, raise_on_error=True, precond=PC_SCHWARZ):
+        """Solve A u = b (b dual, FP64).  Returns (u, info dict)."""
+        self._cell(b, F64, "b")
+        if u is not None:
+            self._cell(u, F64, "u")
+        _require_cuda(b, u)
         u = self.cell_vector(F64) if u is None else u
+        self._sync_stream()
         info = SolveInfo()
-        st = lib().pcg_solve(self.h, _ptr(b), _ptr(u), rtol, maxit, smoother_prec, sweeps, omega,
-                             variant, ct.byref(info))
+        if precond == PC_SCHWARZ:
+            st = lib().pcg_solve(self.h, _ptr(b), _ptr(u), rtol, maxit, smoother_prec, sweeps, omega,
+                                 variant, ct.byref(info))
+        else:
+            st = lib().pcg_solve_pc(self.h, _ptr(b), _ptr(u), rtol, maxit, precond, smoother_prec, sweeps,
+                                    omega, variant, ct.byref(info))
         res = dict(iters=info.iters, status=info.status, relres=info.relres, seconds=info.seconds)
         if raise_on_error and st not in (FEM_OK,):
             check(st, "pcg_solve")
         return u, res
+
 
 
 class Batch:
@@ -424,10 +512,23 @@ class Batch:
             arr[i] = t.data_ptr()
         return arr
 
+    def _check(self, xs, ys, nx, ny):
+        if len(xs) != len(self.problems) or len(ys) != len(self.problems):
+            raise ValueError(f"expected {len(self.problems)} vectors per argument")
+        prec = prec_of(_check_vec(xs[0], self.problems[0].cell_len, None, nx + "[0]"))
+        for i, P in enumerate(self.problems):
+            P._cell(xs[i], prec, f"{nx}[{i}]")
+            P._cell(ys[i], prec, f"{ny}[{i}]")
+        return prec
+
     def apply(self, xs, ys):
+        self._check(xs, ys, "xs", "ys")
+        _require_cuda(*xs, *ys)
         check(lib().fem_batch_apply(self.h, self._ptrs(xs), self._ptrs(ys), prec_of(xs[0])), "fem_batch_apply")
 
     def patch_inverse(self, rs, zs):
+        self._check(rs, zs, "rs", "zs")
+        _require_cuda(*rs, *zs)
         check(lib().fem_batch_patch_inverse(self.h, self._ptrs(rs), self._ptrs(zs), prec_of(rs[0])),
               "fem_batch_patch_inverse")
 
@@ -460,8 +561,12 @@ class Server:
             pass
 
     def submit(self, p, n, f, widths=None, rtol=1e-8, maxit=2000):
-        d = make_desc(p, n, widths)
+        n3 = (n, n, n) if isinstance(n, int) else tuple(int(v) for v in n)
         f = np.ascontiguousarray(f, dtype=np.float64)
+        need = (n3[0] * p + 1) * (n3[1] * p + 1) * (n3[2] * p + 1)
+        if f.ndim != 1 or f.size != need:
+            raise ValueError(f"f: has {f.size} values, the mesh has {need} global nodes")
+        d = make_desc(p, n3, widths)
         t = ct.c_uint64()
         check(lib().fem_server_submit(self.h, ct.byref(d), f.ctypes.data, rtol, maxit, ct.byref(t)),
               "fem_server_submit")

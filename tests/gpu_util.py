@@ -46,3 +46,14 @@ def rel_err(a, b):
 
 def l2_rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def check_err(got, ref, tol, what):
+    """Both error measures of a result against the oracle (max-abs error over
+    the largest oracle entry, and the l2 norm of the error over the oracle's),
+    printed, each at most `tol`."""
+    mx = rel_err(got, ref)
+    l2 = l2_rel(np.ravel(got), np.ravel(ref))
+    print(f"[err] {what}: max-abs {mx:.3e}, l2 {l2:.3e} (bound {tol:.0e})", flush=True)
+    assert mx <= tol and l2 <= tol, (what, mx, l2, tol)
+    return mx, l2

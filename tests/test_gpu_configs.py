@@ -14,7 +14,7 @@ import pytest
 import synth
 from oracle import operators, patches
 from oracle.mesh import Mesh
-from tests.gpu_util import graded, l2_rel, note, rel_err, to_dev, to_np
+from tests.gpu_util import check_err, graded, l2_rel, note, rel_err, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
@@ -42,7 +42,7 @@ def test_q2_8cubed_patch_sweep_full(F):
     r = P.gather(to_dev(wl.x))
     z = to_np(P.unpack(P.patch_inverse(r)))
     ref = patches.SchwarzFactors(m)(operators.scatter(m, operators.gather(m, wl.x)))
-    assert rel_err(z, ref[m.dofs]) <= 1e-11
+    check_err(z, ref[m.dofs], 1e-12, "q2 8^3 patch inverse")
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -54,7 +54,7 @@ def test_q3_64_apply_full(F, prec):
     xd = P.gather(to_dev(wl.x), prec)
     y = to_np(P.unpack(P.apply(xd)))
     ref = operators.apply_cells(m, to_np(P.unpack(xd)))
-    assert rel_err(y, ref) <= {0: 1e-12, 1: 1e-5}[prec]
+    check_err(y, ref, {0: 1e-12, 1: 1e-5}[prec], f"q3 64^3 apply prec={prec}")
 
 
 @pytest.mark.parametrize("prec", [0, 1])
@@ -69,7 +69,7 @@ def test_q3_64_patch_inverse_sampled(F, prec):
     zc = to_np(P.unpack(z))[cells]
     r = operators.scatter(m, to_np(P.unpack(y)))
     ref = patches.additive_schwarz_at_cells(m, r, cells)
-    assert rel_err(zc, ref) <= {0: 1e-11, 1: 2e-5}[prec]
+    check_err(zc, ref, {0: 1e-12, 1: 1e-5}[prec], f"q3 64^3 patch inverse prec={prec}")
     # the whole output is continuous to the bit
     zz = P.unpack(P.gather(P.extract(z), prec))
     assert bool((zz == P.unpack(z)).all())
@@ -97,7 +97,7 @@ def test_q7_24_patch_inverse_sampled(F, prec):
     cells = np.array([0, 24 * 24 * 12 + 24 * 5 + 7, m.ncells - 1])
     zc = to_np(P.unpack(z))[cells]
     ref = patches.additive_schwarz_at_cells(m, operators.scatter(m, to_np(P.unpack(y))), cells)
-    assert rel_err(zc, ref) <= {0: 1e-10, 1: 5e-5}[prec]
+    check_err(zc, ref, {0: 1e-12, 1: 1e-5}[prec], f"q7 24^3 patch inverse prec={prec}")
 
 
 def test_q7_24_solves_mixed_precision(F):
@@ -151,7 +151,7 @@ def test_q7_33_solve_reduction_tiles(F, variant):
     blocks into node-plane slices and must keep the tile count within the
     partial buffer of each group, or partials overwrite the next group and,
     from the last group, the scalars.  PCG (1) and FCG (2) solves converge,
-    agree, and meet the oracle's true residual on sampled rows' norm."""
+    agree, and meet the target on the oracle's true residual."""
     note(f"q7 33^3 solve variant={variant}")
     m, w, rng = graded(7, 33, 23)
     P = F.Problem(7, 33, w)
@@ -162,9 +162,9 @@ def test_q7_33_solve_reduction_tiles(F, variant):
     u_ref, info_ref = P.pcg_solve(bd, rtol=1e-8, maxit=2000, variant=3 - variant)
     assert info_ref["status"] == 0, info_ref
     assert l2_rel(to_np(P.extract(u)), to_np(P.extract(u_ref))) <= 1e-6
-    # true residual with the library's own apply (the oracle's global apply
-    # at 11M DoFs takes minutes); the apply itself is checked against the
-    # oracle at full size by the q7 48^3 test
-    r = to_np(P.scatter(bd)) - to_np(P.scatter(P.apply(P.gather(P.extract(u)))))
-    assert np.linalg.norm(r) / np.linalg.norm(to_np(P.scatter(bd))) <= 2e-8
+    # true residual with the oracle's own apply and load vector
+    b_glob = operators.mass_global(m, f)
+    true = np.linalg.norm(b_glob - operators.apply_global(m, to_np(P.extract(u)))) / np.linalg.norm(b_glob)
+    print(f"q7 33^3 variant {variant}: {info['iters']} iterations, oracle residual {true:.2e}", flush=True)
+    assert true <= 2e-8
 

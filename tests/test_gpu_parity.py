@@ -1,21 +1,23 @@
 """Parity of the HIP path against the oracle on small meshes that span
 several storage blocks and end in a ragged block.
 
-Tolerances (max-abs error relative to the largest oracle entry): FP64
-1e-12 (apply) / 1e-11 (patch inverse, which divides by eigenvalue sums of
-size up to ~1e3 and sums up to 8 patch results); FP32 1e-5; BF16 storage with
-FP32 arithmetic 3e-2 (one BF16 rounding of input and output, 2^-8 each).
+Tolerances, for both the max-abs error relative to the largest oracle entry
+and the l2-relative error (each printed): FP64 1e-12 (apply, patch inverse,
+smoother); FP32 1e-5, the bound stated for the FP32 smoother step; BF16
+storage with FP32 arithmetic 1e-2 (one BF16 rounding of input and output,
+2^-9 relative each, amplified by the patch operators' conditioning; the
+measured worst case is 4e-3).
 """
 import numpy as np
 import pytest
 
 from oracle import operators, patches, solver
 from oracle.mesh import Mesh
-from tests.gpu_util import graded, l2_rel, note, rel_err, to_dev, to_np
+from tests.gpu_util import check_err, graded, l2_rel, note, rel_err, to_dev, to_np
 
 pytestmark = pytest.mark.gpu
 
-TOL = {0: 1e-12, 1: 1e-5, 2: 3e-2}
+TOL = {0: 1e-12, 1: 1e-5, 2: 1e-2}
 
 
 @pytest.fixture(scope="module")
@@ -58,7 +60,7 @@ def test_apply_all_degrees_ragged(F, p, prec):
     xin = to_np(P.unpack(xd))                            # what the device holds after rounding
     y = to_np(P.unpack(P.apply(xd)))
     ref = operators.apply_cells(m, xin)
-    assert rel_err(y, ref) <= TOL[prec] * (3 if prec == 1 and p == 7 else 1)
+    check_err(y, ref, TOL[prec], f"apply p={p} prec={prec}")
 
 
 @pytest.mark.parametrize("p", [2, 3, 7])
@@ -159,8 +161,7 @@ def test_patch_inverse_matches_lu(F, p, n, prec):
     z = P.patch_inverse(rd)
     zc = to_np(P.unpack(z))
     ref = patches.SchwarzFactors(m)(operators.scatter(m, rin))
-    tol = {0: 1e-11, 1: 2e-5, 2: 3e-2}[prec]
-    assert rel_err(zc, ref[m.dofs]) <= tol
+    check_err(zc, ref[m.dofs], TOL[prec], f"patch_inverse p={p} n={n} prec={prec}")
     # exact continuity: every copy of a node holds the same bits
     zz = to_np(P.unpack(P.gather(P.extract(z), prec)))
     np.testing.assert_array_equal(zz, zc)
@@ -181,7 +182,7 @@ def test_patch_inverse_sees_only_the_assembly(F):
     assert rel_err(za, zb) <= 1e-12
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 2])
 def test_smoother_matches_oracle(F, prec):
     note(f"smoother prec={prec}")
     m, w, rng = graded(2, (4, 5, 4), 31)
@@ -191,10 +192,10 @@ def test_smoother_matches_oracle(F, prec):
     z = to_np(P.unpack(P.smoother_step(rd, sweeps=2, omega=0.125)))
     f = patches.SchwarzFactors(m)
     ref = solver.smoother(m, operators.scatter(m, to_np(P.unpack(rd))), 2, 0.125, schwarz=f)
-    assert rel_err(z, ref[m.dofs]) <= {0: 1e-11, 1: 2e-5}[prec]
+    check_err(z, ref[m.dofs], TOL[prec], f"smoother 2 sweeps prec={prec}")
     z3 = to_np(P.unpack(P.smoother_step(rd, sweeps=3, omega=0.2)))
     ref3 = solver.smoother(m, operators.scatter(m, to_np(P.unpack(rd))), 3, 0.2, schwarz=f)
-    assert rel_err(z3, ref3[m.dofs]) <= {0: 1e-11, 1: 2e-5}[prec]
+    check_err(z3, ref3[m.dofs], TOL[prec], f"smoother 3 sweeps prec={prec}")
 
 
 # ---------------------------------------------------------------- solver
@@ -286,7 +287,7 @@ def test_fused_sweep_matches_two_phase(F, p, n, prec, mode):
     assert rel_err(z1, z2) <= {0: 1e-14, 1: 1e-6}[prec]
     np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(zc), prec))), to_np(P.unpack(zc)))
     zref = patches.SchwarzFactors(m)(operators.scatter(m, to_np(P.unpack(rd)).astype(np.float64)))
-    assert rel_err(to_np(P.unpack(zc)), zref[m.dofs]) <= {0: 1e-12, 1: 5e-5}[prec]
+    check_err(to_np(P.unpack(zc)), zref[m.dofs], TOL[prec], f"sweep mode {mode} p={p} n={n} prec={prec}")
 
 
 @pytest.mark.parametrize("p,n", [(2, (9, 5, 4)), (3, (7, 4, 5)), (7, (3, 4, 2))])
@@ -378,12 +379,12 @@ def test_patch_inverse_long_rows(F, p, n, prec):
     z = to_np(P.unpack(zc))
     np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(zc), prec))), z)
     r_glob = operators.scatter(m, to_np(P.unpack(rd)).astype(np.float64))
-    tol = {0: 1e-11, 1: 5e-5, 2: TOL[2]}[prec]
+    tol = TOL[prec]
     if p <= 3:
         zref = patches.SchwarzFactors(m)(r_glob)
-        assert rel_err(z, zref[m.dofs]) <= tol
+        check_err(z, zref[m.dofs], tol, f"long rows p={p} n={n} prec={prec}")
     else:
         rows = np.arange(m.n[1] * m.n[2]) * m.n[0]
         cells = np.unique(np.concatenate([rows, rows + m.n[0] // 2, rows + m.n[0] - 1]))
         zref = patches.additive_schwarz_at_cells(m, r_glob, cells)
-        assert rel_err(z[cells], zref) <= tol
+        check_err(z[cells], zref, tol, f"long rows p={p} n={n} prec={prec}")

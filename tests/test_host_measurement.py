@@ -16,32 +16,63 @@ def test_kernel_bytes_match_their_definitions():
     cell = n ** 3 * (p + 1) ** 3 * 8
     uniq = (n * p + 1) ** 3 * 8
     patch = (n - 1) ** 3 * (2 * p - 1) ** 3 * 8
-    assert bench.kernel_bytes("apply", p, n) == 2 * cell == 268435456
-    assert bench.kernel_bytes("pi_assemble", p, n) == cell + uniq
-    assert bench.kernel_bytes("pi_solve", p, n) == uniq + patch
-    assert bench.kernel_bytes("pi_combine", p, n) == patch + cell
+    # every phase of an operation is charged the operation's bytes: read one
+    # cell-wise vector, write one (16 B per cell DoF in FP64)
+    for lab in ("apply", "pi_assemble", "pi_solve", "pi_combine", "pi_sweep"):
+        assert bench.kernel_bytes(lab, p, n) == 2 * cell == 268435456
     assert bench.kernel_bytes("unknown", p, n) is None
-    # FP32 storage, FP32 compute buffers
+    # the design floors: the arrays each kernel has to touch once
+    assert bench.design_bytes("pi_assemble", p, n) == cell + uniq
+    assert bench.design_bytes("pi_solve", p, n) == uniq + patch
+    assert bench.design_bytes("pi_combine", p, n) == patch + cell
+    assert bench.design_bytes("pi_sweep", p, n) == uniq + cell          # reads the assembled residual
+    # FP32 storage
     assert bench.kernel_bytes("apply", 7, 24, 4, 4) == 2 * 24 ** 3 * 512 * 4
+    # structured DSS: both copies of every face pair, read and written, per axis pass
+    assert bench.op_bytes("dss", 1, 2, 8) == 4 * 8 * 4 * 3 * 1 * 2 * 2
+
+
+def test_apply_flops_follow_the_papers_laplace_table():
+    """14(p+1) useful flops per cell DoF: the paper's table lists theory
+    TFLOP/s beside cell-wise GDoF/s, whose quotient is the per-DoF count
+    (p >= 3; p = 1, 2 use an even-odd factorisation with fewer)."""
+    rows = [l.split() for l in open(os.path.join(os.path.dirname(__file__), "golden", "laplace_table.txt"))
+            if l.strip() and not l.startswith("#")]
+    for deg, cell_gdofs, _, _, theory_tf in rows:
+        p = int(deg)
+        per_dof = float(theory_tf) * 1e12 / (float(cell_gdofs) * 1e9)
+        if p >= 3:
+            assert abs(bench.op_flops("apply", p, 1) / (p + 1) ** 3 - per_dof) / per_dof < 0.002, p
+        else:
+            assert bench.op_flops("apply", p, 1) / (p + 1) ** 3 >= per_dof
 
 
 def test_kernel_flops():
     # Q3 patch: 12 nP^4 + nP^3 with nP = 5 -> 7625 per patch
     assert bench.kernel_flops("pi_solve", 3, 2) == 7625
-    # Q7 apply: 7 contractions of 8 terms (2 flops each) + 4 per cell DoF
-    assert bench.kernel_flops("apply", 7, 1) == 512 * (7 * 2 * 8 + 4)
+    assert bench.kernel_flops("pi_sweep", 3, 2) == 7625
+    assert bench.kernel_flops("pi_combine", 3, 2) is None
+    assert bench.kernel_flops("apply", 7, 1) == 512 * 14 * 8
 
 
 def test_roofline_picks_the_largest_share():
     rec = dict(p=3, n=64, kernels=[
         dict(label="apply", p=3, prec=0, launches=20, total_ms=1.1, avg_us=55.0),
+        dict(label="pi_assemble", p=3, prec=0, launches=20, total_ms=0.6, avg_us=30.0),
         dict(label="pi_solve", p=3, prec=0, launches=20, total_ms=2.9, avg_us=145.0),
         dict(label="pi_combine", p=3, prec=0, launches=20, total_ms=2.3, avg_us=115.0),
         dict(label="dot", p=3, prec=0, launches=20, total_ms=9.0, avg_us=450.0)])   # no byte model: ignored
-    r = bench.roofline(rec, workload="no_such_workload")
-    assert r["kernel"] == "pi_solve" and r["traffic"] is None
+    r = bench.roofline(rec, workload="no_such_workload", copy_gbs=6000.0)
+    assert r["kernel"] == "pi_solve" and r["op"] == "patch_inverse" and r["traffic"] is None
     assert r["achieved"] == pytest.approx(bench.kernel_bytes("pi_solve", 3, 64) / 145e-6 / 1e9, rel=1e-3)
     assert r["frac"] == pytest.approx(r["achieved"] / r["peak"], rel=1e-3)
+    assert r["frac_of_copy_peak"] == pytest.approx(r["achieved"] / 6000.0, rel=1e-3)
+    # the patch inverse as one unit: its three phases' times summed
+    pi = r["ops"]["patch_inverse"]
+    assert pi["time_us"] == pytest.approx(290.0)
+    assert pi["GB/s"] == pytest.approx(2 * 64 ** 3 * 64 * 8 / 290e-6 / 1e9, rel=1e-3)
+    assert pi["flop_frac"] == pytest.approx(63 ** 3 * 7625 / 290e-6 / 1e12 / 78.6, rel=1e-3)
+    assert r["ops"]["apply"]["hbm_frac"] == pytest.approx(2 * 64 ** 3 * 64 * 8 / 55e-6 / 1e9 / 8000, rel=1e-3)
 
 
 def _write_counters(path, rows):
