@@ -222,6 +222,26 @@ fem_status pcg_solve_pc(fem_problem* P, const double* b_cell, double* u_cell, do
  * boundary.  r == z is FEM_EINVAL. */
 fem_status fem_precond_apply(fem_problem* P, int precond, const void* r_cell, void* z_cell, int prec);
 
+/* pcg_solve_pc for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same solve, bit for bit, with the solver's own vectors (r, p, q in FP64,
+ * z and the smoother's residual copy in smoother_prec, 24 + 2 x
+ * fem_prec_bytes(smoother_prec) bytes per cell-wise entry) taken from one
+ * device array of fem_noalloc_scratch_bytes() bytes (64 MiB) that the
+ * library holds on every device it runs on until the process ends, instead
+ * of the handle's lazily allocated workspace.  It calls no allocator; the
+ * problem handle (created beforehand) supplies everything else.  Call it
+ * with the problem's device current.  Calls on one device share that array:
+ * calls that overlap on one GPU (from several threads or streams) race and
+ * must be serialised by the caller; the array keeps the last call's contents
+ * and every vector is written before it is read.  FEM_EINVAL when the
+ * vectors exceed the array (the message gives both sizes) or the current
+ * device is not the problem's; otherwise as pcg_solve_pc. */
+fem_status pcg_solve_noalloc(fem_problem* P, const double* b_cell, double* u_cell, double rtol, int maxit,
+                             int precond, int smoother_prec, int sweeps, double omega, int variant,
+                             fem_solve_info* info);
+size_t fem_noalloc_scratch_bytes(void);
+
 /* ------------------------------------------------------- batched launches */
 
 typedef struct fem_batch fem_batch;

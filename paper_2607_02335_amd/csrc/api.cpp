@@ -3,7 +3,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "fem_internal.h"
@@ -576,3 +578,47 @@ extern "C" fem_status fem_precond_apply(fem_problem* P, int pc, const void* r, v
     return FEM_OK;
 }
 
+// ------------------------------------------------ solve without allocation
+// The solver vectors of pcg_solve_noalloc live in one file-scope device
+// array, resolved per device on the first call there (hipGetSymbolAddress
+// with that device current); host code uses only the resolved address.
+namespace fem {
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+}  // namespace fem
+
+static __device__ __align__(256) char scratch[fem::kNoAllocScratchBytes];
+
+namespace {
+std::once_flag g_scratch_once[fem::kMaxDevices];
+void* g_scratch_ptr[fem::kMaxDevices];
+hipError_t g_scratch_err[fem::kMaxDevices];
+}  // namespace
+
+extern "C" size_t fem_noalloc_scratch_bytes(void) { return fem::kNoAllocScratchBytes; }
+
+extern "C" fem_status pcg_solve_noalloc(fem_problem* P, const double* b, double* u, double rtol, int maxit, int pc,
+                                        int sp, int sweeps, double omega, int variant, fem_solve_info* info) {
+    const auto t0 = std::chrono::steady_clock::now();
+    fem_solve_info loc{};
+    if (!info) info = &loc;
+    *info = fem_solve_info{};
+    fem_status st = check_solve_args(P, b, u, rtol, maxit, pc, sp, sweeps, &variant);
+    if (st != FEM_OK) return st;
+    const size_t need = solve_bytes_for(P->cell_len, sp);
+    if (need > kNoAllocScratchBytes)
+        return set_error(FEM_EINVAL, "pcg_solve_noalloc: the solver vectors need " + std::to_string(need) +
+                                         " bytes, more than the " + std::to_string(kNoAllocScratchBytes) +
+                                         "-byte device scratch");
+    int dev = -1;
+    FEM_HIP(hipGetDevice(&dev), "pcg_solve_noalloc");
+    if (dev != P->device) return set_error(FEM_EINVAL, "pcg_solve_noalloc: call with the problem's device current");
+    if (dev < 0 || dev >= kMaxDevices) return set_error(FEM_EINVAL, "pcg_solve_noalloc: device index out of range");
+    std::call_once(g_scratch_once[dev], [dev]() {
+        g_scratch_err[dev] = hipGetSymbolAddress(&g_scratch_ptr[dev], HIP_SYMBOL(scratch));
+    });
+    if (g_scratch_err[dev] != hipSuccess) return hip_error(g_scratch_err[dev], "pcg_solve_noalloc: scratch address");
+    if (!g_scratch_ptr[dev]) return set_error(FEM_EHIP, "pcg_solve_noalloc: scratch address is null");
+    return pcg_core(P, b, u, rtol, maxit, pc, sp, sweeps, omega, variant, static_cast<char*>(g_scratch_ptr[dev]),
+                    info, t0);
+}

@@ -80,6 +80,8 @@ def lib():
         "pcg_solve": ([vp, vp, vp, d, i, i, i, d, i, ct.POINTER(SolveInfo)], i),
         "pcg_solve_pc": ([vp, vp, vp, d, i, i, i, i, d, i, ct.POINTER(SolveInfo)], i),
         "fem_precond_apply": ([vp, i, vp, vp, i], i),
+        "pcg_solve_noalloc": ([vp, vp, vp, d, i, i, i, i, d, i, ct.POINTER(SolveInfo)], i),
+        "fem_noalloc_scratch_bytes": ([], sz),
         "fem_batch_create": ([i, ct.POINTER(Desc), vp, pp], i),
         "fem_batch_destroy": ([vp], i),
         "fem_batch_problem": ([vp, i, pp], i),
@@ -472,6 +474,22 @@ class Problem:
             check(st, "pcg_solve")
         return u, res
 
+    def pcg_solve_noalloc(self, b, u, rtol=1e-8, maxit=1000, smoother_prec=F64, sweeps=2, omega=0.125,
+                          variant=CG_AUTO, precond=PC_SCHWARZ, raise_on_error=True):
+        """pcg_solve whose solver vectors live in the library's fixed device
+        scratch (no allocation in the call): u (initial guess, solution) is
+        the caller's."""
+        self._cell(b, F64, "b")
+        self._cell(u, F64, "u")
+        _require_cuda(b, u)
+        self._sync_stream()
+        info = SolveInfo()
+        st = lib().pcg_solve_noalloc(self.h, _ptr(b), _ptr(u), rtol, maxit, precond, smoother_prec, sweeps, omega,
+                                     variant, ct.byref(info))
+        res = dict(iters=info.iters, status=info.status, relres=info.relres, seconds=info.seconds)
+        if raise_on_error and st not in (FEM_OK,):
+            check(st, "pcg_solve")
+        return u, res
 
 
 class Batch:
