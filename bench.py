@@ -5,8 +5,10 @@ widths U[0.5,1.5] (seed 1), FP64, x ~ U[-1,1]) is one pass of the operator
 and the smoother's patch solve:  y = A x (fe_apply), then z = P_AS y
 (patch_inverse).  The reported rate counts unique DoFs ((64*3+1)^3) per
 second of that pass; the per-operation rates, the Q2 (96^3) and Q7 (24^3)
-workloads and the Q7 solve times with FP64/FP32/BF16 smoothers are reported
-beside it.
+workloads, the Q7 solve times with FP64/FP32/BF16 smoothers, the 256-problem
+batch, the paper's own kernels (mass operator, structured DSS, assembled
+mass) and the 10,000-request serving stream (p50/p99 latency, solved DoF/s)
+are reported beside it.
 
 Inputs live in HBM before timing starts; the timed region rotates through
 several independent (x, y, z) buffer sets larger than the 256 MB Infinity
@@ -480,6 +482,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--solve-reps", type=int, default=5)
     ap.add_argument("--requests", type=int, default=10000, help="serving mode: stream length")
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="requests of the serving stream in the default run (0: skip)")
     ap.add_argument("--prec", choices=["f64", "f32", "bf16"], default="f64",
                     help="storage precision of --only q2_96 / q7_24")
     a = ap.parse_args()
@@ -535,6 +539,10 @@ def main():
         extra["batch_256"] = batch_times(fem, torch, a.steps, a.warmup)
         log("mass operator, structured DSS, assembled mass at 128^3")
         extra["paper_kernels"] = paper_kernels(fem, torch)
+        if a.serve_requests > 0:
+            from paper_2607_02335_amd import serve
+            log(f"serving stream of {a.serve_requests} requests at 200/s")
+            extra["serve"] = serve.run_stream_bench(count=a.serve_requests, log=log)
 
     log("copy peak")
     copy_gbs = copy_peak(torch)

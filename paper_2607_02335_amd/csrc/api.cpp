@@ -468,6 +468,13 @@ static fem_status pcg_core(fem_problem* P, const double* b, double* u, double rt
         return FEM_OK;      // the simple preconditioners ran with the norm
     };
 
+    // the solve is running (the state the r and p updates consult)
+    {
+        ProbEntry e = entry_of(P);
+        e.alpha = rtol;
+        e.zchunk = maxit;
+        FEM_HIP(launch_solve_init(&e, 1, nullptr, P->stream), "pcg_solve init");
+    }
     // r = b - A u
     {
         ProbEntry e = entry_of(P);

@@ -598,6 +598,12 @@ static fem_status activate(fem_server* S, Active* A) {
         FEM_HIP(launch_apply(P->p, FEM_F64, 2, &e, 1, nullptr, s), "server rhs");
     }
     FEM_HIP(run_fill_zero(P, A->u, FEM_F64), "server init");
+    {
+        ProbEntry e = entry_of(P);
+        e.alpha = A->req.rtol;
+        e.zchunk = A->req.maxit;
+        FEM_HIP(launch_solve_init(&e, 1, nullptr, s), "server init");
+    }
     FEM_HIP(hipMemcpyAsync(A->r, A->b, sizeof(double) * len, hipMemcpyDeviceToDevice, s), "server init");
     FEM_HIP(run_assembled_norm2(P, A->b, FEM_F64, kSlotB2), "server norm");
     if (S->sp != FEM_F64) FEM_HIP(run_distribute(P, A->r, A->rs, S->sp, kSlotRN), "server distribute");
@@ -729,104 +735,113 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
     S->t_phase[0] += clk.lap();
     if (na > 0) {
         std::vector<ProbEntry> ents;
-        auto group_of = [&](int p) {
-            std::vector<Active*> g;
-            for (Active* A : S->active)
-                if (A->P->p == p && !A->finished) g.push_back(A);
-            return g;
-        };
-        // 2. q = A p, <q,p>, u += alpha p, r -= alpha q, residual norm (and the
-        //    smoother's copy of r), one launch per degree and operation
-        for (int p = 1; p <= kMaxP; ++p) {
-            std::vector<Active*> g = group_of(p);
-            if (g.empty()) continue;
-            const int n = (int)g.size();
-            ents.resize(n);
-            for (int i = 0; i < n; ++i) {
-                ents[i] = entry_of(g[i]->P);
-                ents[i].a = g[i]->p;
-                ents[i].c = g[i]->q;
-            }
-            FEM_HIP(launch_apply(p, FEM_F64, 0, ents.data(), n, &S->st, s), "server apply");
-            for (int i = 0; i < n; ++i) {
-                ents[i] = entry_of(g[i]->P);
-                ents[i].a = g[i]->q;
-                ents[i].b = g[i]->p;
-            }
-            FEM_HIP(launch_dot(FEM_F64, FEM_F64, ents.data(), n, &S->st, s, kSlotQP), "server dot");
-            for (int i = 0; i < n; ++i) {
-                ents[i] = entry_of(g[i]->P);
-                ents[i].b = g[i]->q;
-                ents[i].d = g[i]->r;
-            }
-            FEM_HIP(launch_cg_ur(ents.data(), n, &S->st, s), "server update");
-            for (int i = 0; i < n; ++i) {
-                ents[i] = entry_of(g[i]->P);
-                ents[i].a = g[i]->r;
-                ents[i].c = g[i]->rs;
-            }
-            if (S->sp == FEM_F64) FEM_HIP(launch_anorm(p, ents.data(), n, &S->st, s, kSlotRN), "server norm");
-            else FEM_HIP(launch_distribute(p, S->sp, ents.data(), n, &S->st, s, kSlotRN), "server norm");
+        // 2. iterations.  Every active solve takes one (F)PCG iteration per
+        //    step; a solve smaller than the largest active one takes up to
+        //    kInnerMax, as many as its size fits into the largest one's, so
+        //    small requests do not advance at the pace of the large ones.
+        //    Convergence is decided on the device after every iteration
+        //    (launch_cg_check), so the host waits once per step; a solve that
+        //    finishes early in a step runs its remaining iterations in vain
+        //    with u kept.
+        constexpr int kInnerMax = 8;
+        size_t maxlen = 1;
+        for (Active* A : S->active) maxlen = std::max(maxlen, A->P->cell_len);
+        std::vector<int> reps(na);
+        int kmax = 1;
+        for (int i = 0; i < na; ++i) {
+            const size_t len = std::max<size_t>(S->active[i]->P->cell_len, 1);
+            reps[i] = (int)std::min<size_t>(kInnerMax, std::max<size_t>(1, maxlen / len));
+            kmax = std::max(kmax, reps[i]);
         }
-        // 3. one read-back of every solve's scalars, waited for only after the
-        //    smoother of this iteration is queued (a solve that has just
-        //    converged runs it once more in vain; its u is final already)
+        for (int it = 0; it < kmax; ++it) {
+            for (int p = 1; p <= kMaxP; ++p) {
+                std::vector<Active*> g;
+                for (int i = 0; i < na; ++i)
+                    if (S->active[i]->P->p == p && reps[i] > it) g.push_back(S->active[i]);
+                if (g.empty()) continue;
+                const int n = (int)g.size();
+                ents.resize(n);
+                // q = A p, <q,p>, r -= alpha q, residual norm (and the smoother's
+                // copy of r), the convergence test
+                for (int i = 0; i < n; ++i) {
+                    ents[i] = entry_of(g[i]->P);
+                    ents[i].a = g[i]->p;
+                    ents[i].c = g[i]->q;
+                }
+                FEM_HIP(launch_apply(p, FEM_F64, 0, ents.data(), n, &S->st, s), "server apply");
+                for (int i = 0; i < n; ++i) {
+                    ents[i] = entry_of(g[i]->P);
+                    ents[i].a = g[i]->q;
+                    ents[i].b = g[i]->p;
+                }
+                FEM_HIP(launch_dot(FEM_F64, FEM_F64, ents.data(), n, &S->st, s, kSlotQP), "server dot");
+                for (int i = 0; i < n; ++i) {
+                    ents[i] = entry_of(g[i]->P);
+                    ents[i].b = g[i]->q;
+                    ents[i].d = g[i]->r;
+                }
+                FEM_HIP(launch_cg_ur(ents.data(), n, &S->st, s), "server update");
+                for (int i = 0; i < n; ++i) {
+                    ents[i] = entry_of(g[i]->P);
+                    ents[i].a = g[i]->r;
+                    ents[i].c = g[i]->rs;
+                }
+                if (S->sp == FEM_F64) FEM_HIP(launch_anorm(p, ents.data(), n, &S->st, s, kSlotRN), "server norm");
+                else FEM_HIP(launch_distribute(p, S->sp, ents.data(), n, &S->st, s, kSlotRN), "server norm");
+                for (int i = 0; i < n; ++i) ents[i] = entry_of(g[i]->P);
+                FEM_HIP(launch_cg_check(ents.data(), n, &S->st, s), "server convergence");
+                // smoother, pairings and the new direction (with the u step of
+                // this iteration's r update, which completes a finishing solve's u)
+                for (int i = 0; i < n; ++i) ents[i] = pi_entry(g[i]->P, g[i]->rs, g[i]->z, S->sp, S->omega);
+                FEM_HIP(launch_patch_inverse(p, S->sp, 0, ents.data(), n, &S->st, s), "server smoother");
+                for (int sw = 1; sw < S->sweeps; ++sw) {
+                    for (int i = 0; i < n; ++i) {
+                        ents[i] = entry_of(g[i]->P);
+                        ents[i].a = g[i]->z;
+                        ents[i].b = g[i]->rs;
+                        ents[i].c = g[i]->P->d_tmp;
+                    }
+                    FEM_HIP(launch_apply(p, S->sp, 1, ents.data(), n, &S->st, s), "server smoother residual");
+                    for (int i = 0; i < n; ++i) ents[i] = pi_entry(g[i]->P, g[i]->P->d_tmp, g[i]->z, S->sp, S->omega);
+                    FEM_HIP(launch_patch_inverse(p, S->sp, 1, ents.data(), n, &S->st, s), "server smoother");
+                }
+                if (S->variant == FEM_CG_PCG) {
+                    for (int i = 0; i < n; ++i) ents[i] = entry_of(g[i]->P);
+                    FEM_HIP(launch_slot_copy(ents.data(), n, &S->st, s, kSlotRZOld, kSlotRZ), "server slots");
+                    for (int i = 0; i < n; ++i) {
+                        ents[i] = entry_of(g[i]->P);
+                        ents[i].a = g[i]->r;
+                        ents[i].b = g[i]->z;
+                    }
+                    FEM_HIP(launch_dot(FEM_F64, S->sp, ents.data(), n, &S->st, s, kSlotRZ), "server dot");
+                } else {
+                    for (int i = 0; i < n; ++i) {
+                        ents[i] = entry_of(g[i]->P);
+                        ents[i].a = g[i]->q;
+                        ents[i].d = g[i]->r;
+                        ents[i].b = g[i]->z;
+                    }
+                    FEM_HIP(launch_dot_qz_rz(S->sp, ents.data(), n, &S->st, s), "server dots");
+                }
+                for (int i = 0; i < n; ++i) {
+                    ents[i] = entry_of(g[i]->P);
+                    ents[i].a = g[i]->z;
+                    ents[i].c = g[i]->p;
+                    ents[i].d = g[i]->u;
+                }
+                FEM_HIP(launch_cg_p(S->sp, S->variant, ents.data(), n, &S->st, s), "server direction");
+            }
+        }
+        // 3. one read-back of every solve's convergence state
         ents.resize(na);
         for (int i = 0; i < na; ++i) ents[i] = entry_of(S->active[i]->P);
-        FEM_HIP(launch_collect_slots(ents.data(), na, &S->st, s, kSlotRN, kSlotQP, S->d_collect), "server collect");
-        FEM_HIP(launch_collect_slots(ents.data(), na, &S->st, s, kSlotB2, kSlotB2, S->d_collect + 2 * na),
+        FEM_HIP(launch_collect_slots(ents.data(), na, &S->st, s, kSlotState, kSlotIters, S->d_collect),
+                "server collect");
+        FEM_HIP(launch_collect_slots(ents.data(), na, &S->st, s, kSlotRel, kSlotStatus, S->d_collect + 2 * na),
                 "server collect");
         FEM_HIP(hipMemcpyAsync(S->h_collect, S->d_collect, sizeof(double) * 4 * na, hipMemcpyDeviceToHost, s),
                 "server read-back");
         FEM_HIP(hipEventRecord(S->ev_scalars, s), "server read-back");
-        // 4. smoother, pairings and the new direction for the unfinished solves
-        for (int p = 1; p <= kMaxP; ++p) {
-            std::vector<Active*> g = group_of(p);
-            if (g.empty()) continue;
-            const int n = (int)g.size();
-            ents.resize(n);
-            for (int i = 0; i < n; ++i) ents[i] = pi_entry(g[i]->P, g[i]->rs, g[i]->z, S->sp, S->omega);
-            FEM_HIP(launch_patch_inverse(p, S->sp, 0, ents.data(), n, &S->st, s), "server smoother");
-            for (int sw = 1; sw < S->sweeps; ++sw) {
-                for (int i = 0; i < n; ++i) {
-                    ents[i] = entry_of(g[i]->P);
-                    ents[i].a = g[i]->z;
-                    ents[i].b = g[i]->rs;
-                    ents[i].c = g[i]->P->d_tmp;
-                }
-                FEM_HIP(launch_apply(p, S->sp, 1, ents.data(), n, &S->st, s), "server smoother residual");
-                for (int i = 0; i < n; ++i) ents[i] = pi_entry(g[i]->P, g[i]->P->d_tmp, g[i]->z, S->sp, S->omega);
-                FEM_HIP(launch_patch_inverse(p, S->sp, 1, ents.data(), n, &S->st, s), "server smoother");
-            }
-            if (S->variant == FEM_CG_PCG) {
-                for (int i = 0; i < n; ++i) ents[i] = entry_of(g[i]->P);
-                FEM_HIP(launch_slot_copy(ents.data(), n, &S->st, s, kSlotRZOld, kSlotRZ), "server slots");
-                for (int i = 0; i < n; ++i) {
-                    ents[i] = entry_of(g[i]->P);
-                    ents[i].a = g[i]->r;
-                    ents[i].b = g[i]->z;
-                }
-                FEM_HIP(launch_dot(FEM_F64, S->sp, ents.data(), n, &S->st, s, kSlotRZ), "server dot");
-            } else {
-                for (int i = 0; i < n; ++i) {
-                    ents[i] = entry_of(g[i]->P);
-                    ents[i].a = g[i]->q;
-                    ents[i].d = g[i]->r;
-                    ents[i].b = g[i]->z;
-                }
-                FEM_HIP(launch_dot_qz_rz(S->sp, ents.data(), n, &S->st, s), "server dots");
-            }
-            // also the u step of this iteration's r update (every solve runs
-            // this phase before its convergence is known, so a finishing
-            // solve's u is complete here)
-            for (int i = 0; i < n; ++i) {
-                ents[i] = entry_of(g[i]->P);
-                ents[i].a = g[i]->z;
-                ents[i].c = g[i]->p;
-                ents[i].d = g[i]->u;
-            }
-            FEM_HIP(launch_cg_p(S->sp, S->variant, ents.data(), n, &S->st, s), "server direction");
-        }
         S->t_phase[1] += clk.lap();
         // completed downloads of earlier steps reach the host while the GPU
         // runs this step's work
@@ -837,27 +852,16 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
         S->t_phase[2] += clk.lap();
         for (int i = 0; i < na; ++i) {
             Active* A = S->active[i];
-            const double rn = S->h_collect[2 * i], qp = S->h_collect[2 * i + 1], b2 = S->h_collect[2 * na + 2 * i];
-            A->iters += 1;
-            A->relres = b2 > 0 ? std::sqrt(rn / b2) : 0.0;
-            if (b2 == 0.0) {
-                // zero right-hand side: u = 0 is the solution (the step just
-                // run took alpha = 0), as pcg_solve returns without iterating
+            const double state = S->h_collect[2 * i], iters = S->h_collect[2 * i + 1];
+            const double rel = S->h_collect[2 * na + 2 * i], status = S->h_collect[2 * na + 2 * i + 1];
+            A->iters = (int)iters;
+            A->relres = rel;
+            if (state != 0.0) {
                 A->finished = true;
-                A->status = FEM_OK;
-                A->iters = 0;
-            } else if (!(qp > 0) || !std::isfinite(qp) || !std::isfinite(A->relres)) {
-                A->finished = true;
-                A->status = FEM_EBREAKDOWN;
-            } else if (A->relres <= A->req.rtol) {
-                A->finished = true;
-                A->status = FEM_OK;
-            } else if (A->iters >= A->req.maxit) {
-                A->finished = true;
-                A->status = FEM_ENOTCONV;
+                A->status = (int)status;
             }
         }
-        // 5. retire finished solves (frees their memory for the next admissions)
+        // 4. retire finished solves (frees their memory for the next admissions)
         std::vector<Active*> keep, fin;
         for (Active* A : S->active) (A->finished ? fin : keep).push_back(A);
         S->active.swap(keep);

@@ -1926,10 +1926,13 @@ __global__ void __launch_bounds__(256) k_pi_solve_mfma(LaunchTable L) {
     __shared__ C sdump[4][64];                        // per-wavefront sink for rows outside the patch
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int slot = wv / WPP, sub = wv % WPP;
-    const int tile = blockIdx.x * PPW + slot;
-    // a workgroup's patches are consecutive tiles; with WPP > 1 the whole
-    // workgroup serves one patch, so this exit is uniform over it
-    if (tile >= L.total_tiles) return;
+    // a workgroup's patches are consecutive tiles.  A slot past the last
+    // patch (the tail of an odd patch count) solves the last patch again in
+    // its own LDS slot and stores nothing, so every wavefront of the
+    // workgroup reaches every barrier
+    const int tile_raw = blockIdx.x * PPW + slot;
+    const bool active = tile_raw < L.total_tiles;
+    const int tile = active ? tile_raw : L.total_tiles - 1;
     const ProbEntry& pe = entry<MULTI>(L, tile);
     const int pidx = tile - pe.tile_begin;
     const int npx = pe.n[0] - 1, npy = pe.n[1] - 1;
@@ -2004,7 +2007,8 @@ __global__ void __launch_bounds__(256) k_pi_solve_mfma(LaunchTable L) {
     mfma_pass<C, nP, 2, WPP>(pv, dump, a1, lane, sub);
     // patch-major buffer: each patch's values are one contiguous run
     C* out = static_cast<C*>(pe.d) + (size_t)pidx * nP3;
-    for (int q = t64; q < nP3; q += 64 * WPP) out[q] = pv[q];
+    if (active)
+        for (int q = t64; q < nP3; q += 64 * WPP) out[q] = pv[q];
 }
 
 template <int P, typename S>

@@ -346,6 +346,7 @@ __global__ void __launch_bounds__(256) k_cg_ur(LaunchTable L) {
         const ProbEntry& pe = entry<MULTI>(L, tile);
         const int t = tile - pe.tile_begin;
         double* sl = red_slots(pe.red);
+        if (sl[kSlotState] != 0.0) continue;       // finished: r and alpha stay
         // a breakdown (<q,p> not positive, or a non-finite step) leaves r and
         // u where they are: the host sees <q,p> and stops the solve, and a
         // zero right-hand side (r = z = p = 0) takes no step at all
@@ -373,6 +374,7 @@ __global__ void __launch_bounds__(256) k_cg_p(LaunchTable L, int variant) {
         const ProbEntry& pe = entry<MULTI>(L, tile);
         const int t = tile - pe.tile_begin;
         const double* sl = red_slots(pe.red);
+        if (sl[kSlotState] == 2.0) continue;       // frozen: u and p stay
         const double beta = variant == FEM_CG_PCG ? sl[kSlotRZ] / sl[kSlotRZOld] : -sl[kSlotQZ] / sl[kSlotQP];
         const double alpha = sl[kSlotAlpha];
         size_t lo, hi;
@@ -380,9 +382,11 @@ __global__ void __launch_bounds__(256) k_cg_p(LaunchTable L, int variant) {
         const SZ* z = static_cast<const SZ*>(pe.a);
         double* p = static_cast<double*>(pe.c);
         double* u = static_cast<double*>(pe.d);
+        // a zero step (breakdown, zero right-hand side) leaves u untouched
+        const bool step = alpha != 0.0;
         for (size_t i = lo + threadIdx.x; i < hi; i += 256) {
             const double pi = p[i];
-            u[i] = u[i] + alpha * pi;
+            if (step) u[i] = u[i] + alpha * pi;
             p[i] = load_as<double>(z + i) + beta * pi;
         }
     }
@@ -454,6 +458,54 @@ __global__ void k_collect_slots(LaunchTable L, int sa, int sb, double* out) {
     const double* sl = red_slots(pe.red);
     out[2 * i] = sl[sa];
     out[2 * i + 1] = sl[sb];
+}
+
+// device-side convergence state (see launch_cg_check)
+template <bool MULTI>
+__global__ void k_solve_init(LaunchTable L) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.nprob) return;
+    const ProbEntry& pe = entry_at<MULTI>(L, i);
+    double* sl = red_slots(pe.red);
+    sl[kSlotState] = 0.0;
+    sl[kSlotIters] = 0.0;
+    sl[kSlotRel] = 1.0;
+    sl[kSlotStatus] = (double)FEM_OK;
+    sl[kSlotRtol] = pe.alpha;
+    sl[kSlotMaxit] = (double)pe.zchunk;
+}
+
+template <bool MULTI>
+__global__ void k_cg_check(LaunchTable L) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= L.nprob) return;
+    const ProbEntry& pe = entry_at<MULTI>(L, i);
+    double* sl = red_slots(pe.red);
+    if (sl[kSlotState] == 1.0) {
+        sl[kSlotState] = 2.0;
+        return;
+    }
+    if (sl[kSlotState] != 0.0) return;
+    const double it = sl[kSlotIters] + 1.0;
+    sl[kSlotIters] = it;
+    const double b2 = sl[kSlotB2], rn = sl[kSlotRN], qp = sl[kSlotQP];
+    const double rel = b2 > 0.0 ? sqrt(rn / b2) : 0.0;
+    sl[kSlotRel] = rel;
+    int status = -1;
+    if (b2 == 0.0) {
+        status = FEM_OK;                 // zero right-hand side: u = 0, no iteration counted
+        sl[kSlotIters] = 0.0;
+    } else if (!(qp > 0.0) || !__builtin_isfinite(qp) || !__builtin_isfinite(rel)) {
+        status = FEM_EBREAKDOWN;
+    } else if (rel <= sl[kSlotRtol]) {
+        status = FEM_OK;
+    } else if (it >= sl[kSlotMaxit]) {
+        status = FEM_ENOTCONV;
+    }
+    if (status >= 0) {
+        sl[kSlotStatus] = (double)status;
+        sl[kSlotState] = 1.0;
+    }
 }
 
 // p = z (initial direction), z in precision SZ
@@ -972,6 +1024,30 @@ hipError_t launch_slot_copy(ProbEntry* ents, int nprob, TableStager* st, hipStre
     const int grid = (nprob + 63) / 64;
     if (nprob > 1) hipLaunchKernelGGL(k_slot_copy<true>, dim3(grid), dim3(64), 0, s, L, dst, src);
     else hipLaunchKernelGGL(k_slot_copy<false>, dim3(grid), dim3(64), 0, s, L, dst, src);
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_init(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s) {
+    if (nprob <= 0) return hipSuccess;
+    LaunchTable L{};
+    L.nprob = nprob;
+    hipError_t err = stage_table(L, ents, nprob, st, s);
+    if (err != hipSuccess) return err;
+    const int grid = (nprob + 63) / 64;
+    if (nprob > 1) hipLaunchKernelGGL(k_solve_init<true>, dim3(grid), dim3(64), 0, s, L);
+    else hipLaunchKernelGGL(k_solve_init<false>, dim3(grid), dim3(64), 0, s, L);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_check(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s) {
+    if (nprob <= 0) return hipSuccess;
+    LaunchTable L{};
+    L.nprob = nprob;
+    hipError_t err = stage_table(L, ents, nprob, st, s);
+    if (err != hipSuccess) return err;
+    const int grid = (nprob + 63) / 64;
+    if (nprob > 1) hipLaunchKernelGGL(k_cg_check<true>, dim3(grid), dim3(64), 0, s, L);
+    else hipLaunchKernelGGL(k_cg_check<false>, dim3(grid), dim3(64), 0, s, L);
     return hipGetLastError();
 }
 

@@ -21,7 +21,15 @@ enum RedSlot {
     kSlotTmp = 5,     // generic dot result
     kSlotB2 = 6,      // ||G^T b||^2
     kSlotAlpha = 7,   // alpha of the last r update (u catches up in the next p update)
-    kSlotCount = 8
+    // device-side convergence state of a solve (the server's batched
+    // iterations decide convergence on the device, see launch_cg_check)
+    kSlotState = 8,   // 0 running, 1 finished in the current iteration, 2 frozen
+    kSlotIters = 9,   // iterations taken
+    kSlotRel = 10,    // ||G^T r|| / ||G^T b|| after the last iteration
+    kSlotStatus = 11, // fem_status once finished
+    kSlotRtol = 12,   // stopping tolerance
+    kSlotMaxit = 13,  // iteration limit
+    kSlotCount = 16
 };
 constexpr int kRedStride = kRedParts * 4 + kSlotCount;   // 4 partial groups + slots
 __host__ __device__ inline double* red_slots(double* red) { return red + kRedParts * 4; }
@@ -117,6 +125,17 @@ hipError_t launch_cg_p(int zprec, int variant, ProbEntry* ents, int nprob, Table
 // <q, z> -> kSlotQZ and <r, z> -> kSlotRZ in one pass; entries a = q, d = r, b = z
 hipError_t launch_dot_qz_rz(int zprec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s);
 hipError_t launch_slot_copy(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int dst, int src);
+// Start of a solve's device-side convergence state: running, 0 iterations,
+// rtol = entry alpha, maxit = entry zchunk.
+hipError_t launch_solve_init(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s);
+// After an iteration's residual norm: every running solve counts the
+// iteration and finishes (state 1, status) on a zero right-hand side, a
+// breakdown (<q,p> not positive or a non-finite residual), rtol or maxit, in
+// that order, as pcg_solve decides on the host; a solve finished in the
+// previous iteration is frozen (state 2).  The r update skips solves that are
+// not running, and the p update (which also applies the last u step) skips
+// frozen ones, so further iterations leave a finished solve's u unchanged.
+hipError_t launch_cg_check(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s);
 // out[2i] = slot a, out[2i+1] = slot b of problem i (device array)
 hipError_t launch_collect_slots(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int sa, int sb,
                                 double* out);
