@@ -21,6 +21,10 @@ What it computes, each from its plain definition:
   eight element matrices, inverted by dense LU, and the additive Schwarz
   preconditioner built from them (the overlapping Schwarz patch smoother the
   paper names in its Remark "Beyond DSS").
+* ``twolevel`` -- the Schwarz smoother plus an exact coarse correction on the
+  Q_1 space of the same mesh (prolongation by interpolation, Galerkin coarse
+  operator, sparse LU): the two-level member of the multigrid family the
+  paper's solver is built for (Remark after the equivalence theorem).
 * ``solver``  -- damped Richardson smoothing on additive Schwarz and the
   (flexible) preconditioned conjugate gradient of the paper's Algorithm
   "Communication-Free (F)PCG", run on assembled global vectors, which the
@@ -30,4 +34,4 @@ Readings where the paper is silent (node set, quadrature, Dirichlet
 treatment, damping) are listed in the repository's design notes; the oracle
 follows exactly those readings.
 """
-from . import basis, mesh, element, operators, patches, solver  # noqa: F401
+from . import basis, mesh, element, operators, patches, solver, twolevel  # noqa: F401

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
 
-from oracle import basis, element, operators, patches, solver
+from oracle import basis, element, operators, patches, solver, twolevel
 from oracle.mesh import Mesh
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -411,3 +411,58 @@ def test_jacobi_pcg_is_cg_on_the_scaled_system():
     _, _, _, its = solver.solve_poisson(m, b, rtol=1e-30, maxit=6, precond="dss", record=True)
     for k in range(1, 6):
         np.testing.assert_allclose(its[k][inner], ref[k - 1], rtol=0, atol=1e-10 * np.abs(ref[k - 1]).max())
+
+
+# --------------------------------------------------- two-level (Q1 coarse)
+def test_hat_functions_partition_and_linear_reproduction():
+    v = np.array([0.0, 0.2, 0.5, 0.55, 1.0])
+    x = np.linspace(0, 1, 41)
+    H = twolevel.hat_values(v, x)
+    np.testing.assert_allclose(H.sum(axis=1), 1, atol=1e-15)
+    np.testing.assert_allclose(H @ v, x, atol=1e-15)
+    np.testing.assert_allclose(twolevel.hat_values(v, v), np.eye(len(v)), atol=0)
+
+
+def test_prolongation_is_lagrange_at_vertices():
+    m = graded_mesh(3, (4, 3, 5))
+    P0 = twolevel.prolongation(m).toarray()
+    i, j, k = twolevel.coarse_vertices(m)
+    g = m.gidx(i * m.p, j * m.p, k * m.p)
+    np.testing.assert_array_equal(P0[g], np.eye(len(g)))
+    assert not np.any(P0[m.boundary_mask()])
+    assert np.all(P0.sum(axis=1) <= 1 + 1e-14)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_galerkin_coarse_operator_is_the_q1_stiffness(p):
+    """Q1 is a subspace of Qp and (p+1)-point Gauss integrates its gradients
+    exactly, so P0^T A_D P0 equals the Q1 Laplacian of the same mesh."""
+    m = graded_mesh(p, (4, 3, 5))
+    T = twolevel.TwoLevel(m)
+    m1 = Mesh(1, m.n, m.h)
+    A1 = operators.assemble(m1, dirichlet=True).toarray()
+    inner = ~m1.boundary_mask()
+    np.testing.assert_allclose(T.A0.toarray(), A1[np.ix_(inner, inner)], atol=1e-13 * np.abs(A1).max())
+
+
+def test_two_level_is_exact_for_linear_elements_and_symmetric():
+    """p = 1: the coarse space is the whole space, so the coarse correction
+    solves exactly and the post-smoother adds nothing: B = A^{-1}.  For p = 2
+    with equal pre- and post-sweeps B is symmetric."""
+    m = graded_mesh(1, (4, 5, 3))
+    inner = np.nonzero(~m.boundary_mask())[0]
+    A = operators.assemble(m, dirichlet=True).tocsr()[inner][:, inner]
+    r = np.zeros(m.nglob)
+    r[inner] = np.random.default_rng(23).standard_normal(len(inner))
+    z = twolevel.TwoLevel(m, omega=0.2)(r)
+    np.testing.assert_allclose(z[inner], spla.spsolve(A.tocsc(), r[inner]), atol=1e-12 * np.abs(z).max())
+    m2 = graded_mesh(2, 3)
+    inner = np.nonzero(~m2.boundary_mask())[0]
+    T = twolevel.TwoLevel(m2, omega=0.2)
+    B = np.zeros((len(inner), len(inner)))
+    for t in range(len(inner)):
+        e = np.zeros(m2.nglob)
+        e[inner[t]] = 1
+        B[:, t] = T(e)[inner]
+    assert np.abs(B - B.T).max() <= 1e-12 * np.abs(B).max()
+    assert np.linalg.eigvalsh((B + B.T) / 2).min() > 0
