@@ -410,7 +410,8 @@ def batch_times(fem, torch, steps, warmup, count=256, seed=3):
 
 
 def solve_times(fem, torch, reps):
-    """Q7 24^3 graded solve to 1e-8 with FP64/FP32/BF16 smoothers."""
+    """Q7 24^3 graded solve to 1e-8 with FP64/FP32/BF16 smoothers, for the
+    Schwarz smoother alone and for the two-level preconditioner."""
     import synth
     wl = synth.workload_q7_graded()
     P = fem.Problem(7, 24, wl.widths)
@@ -419,19 +420,23 @@ def solve_times(fem, torch, reps):
     f = f + 0.01 * wl.noise
     b = P.mass_apply(P.gather(torch.as_tensor(f, device="cuda")))
     out = {}
-    for name, sp in (("fp64", fem.F64), ("fp32", fem.F32), ("bf16", fem.BF16)):
-        times, iters = [], None
-        P.pcg_solve(b, smoother_prec=sp)                  # warm
-        for _ in range(reps):
-            u = P.cell_vector(fem.F64)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            u, info = P.pcg_solve(b, u=u, rtol=1e-8, maxit=2000, smoother_prec=sp)
-            times.append(time.perf_counter() - t0)
-            iters = info["iters"]
-        ts = np.sort(np.asarray(times))
-        out[name] = dict(iters=iters, p50_s=float(np.percentile(ts, 50)), p99_s=float(np.percentile(ts, 99)),
-                         relres=info["relres"])
+    # the Schwarz smoother (2 sweeps, omega 1/8) and the two-level method
+    # (1 + 1 sweeps, omega 1/5, exact FP64 coarse correction)
+    for pre, pc, sweeps, omega in (("", fem.PC_SCHWARZ, 2, 0.125), ("two_level_", fem.PC_TWO_LEVEL, 1, 0.2)):
+        for name, sp in (("fp64", fem.F64), ("fp32", fem.F32), ("bf16", fem.BF16)):
+            times, iters = [], None
+            P.pcg_solve(b, smoother_prec=sp, precond=pc, sweeps=sweeps, omega=omega)          # warm
+            for _ in range(reps):
+                u = P.cell_vector(fem.F64)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                u, info = P.pcg_solve(b, u=u, rtol=1e-8, maxit=2000, smoother_prec=sp, precond=pc, sweeps=sweeps,
+                                      omega=omega)
+                times.append(time.perf_counter() - t0)
+                iters = info["iters"]
+            ts = np.sort(np.asarray(times))
+            out[pre + name] = dict(iters=iters, p50_s=float(np.percentile(ts, 50)),
+                                   p99_s=float(np.percentile(ts, 99)), relres=info["relres"])
     P.close()
     return out
 

@@ -78,9 +78,14 @@ typedef enum fem_prec { FEM_F64 = 0, FEM_F32 = 1, FEM_BF16 = 2 } fem_prec;
 typedef enum fem_bc { FEM_BC_DIRICHLET = 0, FEM_BC_NEUMANN = 1 } fem_bc;
 typedef enum fem_cg_variant { FEM_CG_AUTO = 0, FEM_CG_PCG = 1, FEM_CG_FCG = 2 } fem_cg_variant;
 /* Preconditioners of the solver: the additive Schwarz smoother over vertex
- * patches, and the two simple ones of Section 3.3, the trivial P = S
- * (Eq. "dss_operator") and Jacobi P = D_cell^{-1} S. */
-typedef enum fem_precond { FEM_PC_SCHWARZ = 0, FEM_PC_DSS = 1, FEM_PC_JACOBI = 2 } fem_precond;
+ * patches; the two simple ones of Section 3.3, the trivial P = S
+ * (Eq. "dss_operator") and Jacobi P = D_cell^{-1} S; and the two-level
+ * method (smoother plus an exact coarse correction on the trilinear
+ * functions of the same mesh), the multigrid family the Remark after the
+ * Theorem "Equivalence of Communication-Free FCG" names (fem_two_level). */
+typedef enum fem_precond {
+    FEM_PC_SCHWARZ = 0, FEM_PC_DSS = 1, FEM_PC_JACOBI = 2, FEM_PC_TWO_LEVEL = 3
+} fem_precond;
 
 /* Problem description.  p in 1..7, n[d] >= 1 (>= 2 for patch_inverse to be
  * non-trivial).  widths[d]: host array of n[d] positive cell widths along
@@ -177,6 +182,20 @@ fem_status patch_inverse(fem_problem* P, const void* r_cell, void* z_cell, int p
 fem_status smoother_step(fem_problem* P, const void* r_cell, void* z_cell, int prec,
                          int sweeps, double omega);
 
+/* z = B r, one application of the two-level preconditioner (the multigrid
+ * V-cycle of the Remark after the Theorem "Equivalence of Communication-Free
+ * FCG" with two levels, the coarse one solved exactly): z_0 = 0, `sweeps`
+ * damped Richardson sweeps z <- z + omega P_AS (r - A z), the coarse
+ * correction z <- z + P_0 A_0^{-1} P_0^T (r - A z), `sweeps` more sweeps.
+ * The coarse space is the trilinear (Q1) functions on the interior vertices
+ * of the same mesh; P_0 interpolates them at the nodes of every cell, A_0 is
+ * the Q1 Laplacian of the mesh (the Galerkin operator of the nested spaces)
+ * and its inverse is applied in FP64 by fast diagonalisation.  r dual, z
+ * primal (continuous bit for bit), both in `prec`; the input is used only
+ * through G^T r.  r == z is FEM_EINVAL; omega in (0, 1/4) keeps the
+ * smoother convergent (the Schwarz operator's spectrum lies in (0, 8]). */
+fem_status fem_two_level(fem_problem* P, const void* r_cell, void* z_cell, int prec, int sweeps, double omega);
+
 /* ------------------------------------------------------------ reductions */
 
 /* *result = <a, b> over all cell-wise entries, accumulated in FP64 with a
@@ -208,7 +227,9 @@ fem_status pcg_solve(fem_problem* P, const double* b_cell, double* u_cell, doubl
  * divided for Jacobi by the diagonal of the assembled operator, zero on a
  * Dirichlet boundary) in one pass that also yields ||G^T r||, in precision
  * smoother_prec; sweeps and omega are then unused (sweeps must still be >= 1).
- * FEM_CG_AUTO picks PCG for these static preconditioners.  Same buffers,
+ * FEM_PC_TWO_LEVEL applies fem_two_level(sweeps, omega) in smoother_prec.
+ * FEM_CG_AUTO picks PCG for FP64 and for the static simple preconditioners,
+ * FCG otherwise.  Same buffers,
  * workspace, synchronisation and errors as pcg_solve. */
 fem_status pcg_solve_pc(fem_problem* P, const double* b_cell, double* u_cell, double rtol, int maxit,
                         int precond, int smoother_prec, int sweeps, double omega, int variant,

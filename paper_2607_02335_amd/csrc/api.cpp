@@ -54,8 +54,31 @@ static size_t fd_stride(const fem_desc* d) {
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+static size_t coarse_fd_len(const fem_desc* d) {
+    size_t c = 0;
+    for (int k = 0; k < 3; ++k) {
+        const size_t m = d->n[k] > 1 ? d->n[k] - 1 : 0;
+        c += m * m + m;
+    }
+    return c;
+}
+
+static size_t coarse_len(const fem_desc* d) {
+    size_t c = 1;
+    for (int k = 0; k < 3; ++k) c *= d->n[k] > 1 ? d->n[k] - 1 : 0;
+    return c;
+}
+
+static size_t corner_len(const fem_desc* d) {
+    const size_t nc = (size_t)d->n[0] * d->n[1] * d->n[2];
+    return 8 * ((nc + kLanes - 1) / kLanes * kLanes);
+}
+
 size_t workspace_bytes(const fem_desc* d) {
     size_t b = 0;
+    b += align256(sizeof(double) * std::max<size_t>(coarse_fd_len(d), 1));
+    b += align256(sizeof(double) * std::max<size_t>(2 * coarse_len(d), 1));
+    b += align256(sizeof(double) * corner_len(d));
     b += align256(sizeof(double) * (d->n[0] + d->n[1] + d->n[2]));
     b += align256(sizeof(double) * 3 * fd_stride(d));
     b += align256(sizeof(float) * 3 * fd_stride(d));
@@ -98,6 +121,9 @@ static void free_problem(fem_problem* P) {
     hipFree(P->d_tmp);
     hipFree(P->d_glob);
     hipFree(P->d_solve);
+    hipFree(P->d_cfd);
+    hipFree(P->d_cvec);
+    hipFree(P->d_corner);
     if (P->h_red) hipHostFree(P->h_red);
     delete P;
 }
@@ -105,7 +131,7 @@ static void free_problem(fem_problem* P) {
 namespace fem {
 size_t problem_stage_bytes(const fem_desc* d) {
     return align256(sizeof(double) * (d->n[0] + d->n[1] + d->n[2])) + align256(sizeof(double) * 3 * fd_stride(d)) +
-           align256(sizeof(float) * 3 * fd_stride(d));
+           align256(sizeof(float) * 3 * fd_stride(d)) + align256(sizeof(double) * std::max<size_t>(coarse_fd_len(d), 1));
 }
 
 fem_status create_problem(const fem_desc* d, hipStream_t stream, fem_problem** out, const ProblemMem* mem) {
@@ -156,6 +182,22 @@ fem_status create_problem(const fem_desc* d, hipStream_t stream, fem_problem** o
         off += d->n[k];
     }
     for (size_t i = 0; i < fd.size(); ++i) fd32[i] = (float)fd[i];
+    // coarse level: Q1 fast-diagonalisation data per direction
+    std::vector<double> cfd(std::max<size_t>(coarse_fd_len(d), 1), 0.0);
+    {
+        size_t o = 0, hoff = 0;
+        for (int k = 0; k < 3; ++k) {
+            P->cm[k] = d->n[k] > 1 ? d->n[k] - 1 : 0;
+            P->cfd_off[k] = o;
+            const int m = P->cm[k];
+            if (m > 0 && host_coarse_1d(d->n[k], &h[hoff], &cfd[o], &cfd[o + (size_t)m * m]) != 0) {
+                free_problem(P);
+                return set_error(FEM_EINVAL, "coarse 1D eigenproblem failed");
+            }
+            o += (size_t)m * m + m;
+            hoff += d->n[k];
+        }
+    }
 
     hipError_t e;
     if (mem) {
@@ -171,6 +213,9 @@ fem_status create_problem(const fem_desc* d, hipStream_t stream, fem_problem** o
             off += align256(bytes);
             return q;
         };
+        P->d_cfd = reinterpret_cast<double*>(take(sizeof(double) * cfd.size()));
+        P->d_cvec = reinterpret_cast<double*>(take(sizeof(double) * std::max<size_t>(2 * coarse_len(d), 1)));
+        P->d_corner = reinterpret_cast<double*>(take(sizeof(double) * corner_len(d)));
         P->d_h = reinterpret_cast<double*>(take(sizeof(double) * h.size()));
         P->d_fd64 = reinterpret_cast<double*>(take(sizeof(double) * fd.size()));
         P->d_fd32 = reinterpret_cast<float*>(take(sizeof(float) * fd32.size()));
@@ -184,7 +229,11 @@ fem_status create_problem(const fem_desc* d, hipStream_t stream, fem_problem** o
         std::memcpy(hf, fd.data(), sizeof(double) * fd.size());
         char* hf32 = hf + align256(sizeof(double) * fd.size());
         std::memcpy(hf32, fd32.data(), sizeof(float) * fd32.size());
+        char* hc = hf32 + align256(sizeof(float) * fd32.size());
+        std::memcpy(hc, cfd.data(), sizeof(double) * cfd.size());
         e = hipMemcpyAsync(P->d_h, hs, sizeof(double) * h.size(), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(P->d_cfd, hc, sizeof(double) * cfd.size(), hipMemcpyHostToDevice, stream);
         if (e == hipSuccess)
             e = hipMemcpyAsync(P->d_fd64, hf, sizeof(double) * fd.size(), hipMemcpyHostToDevice, stream);
         if (e == hipSuccess)
@@ -209,6 +258,9 @@ fem_status create_problem(const fem_desc* d, hipStream_t stream, fem_problem** o
     ALLOC(P->d_patch, sizeof(double) * std::max<size_t>(P->patch_len, 1));
     ALLOC(P->d_tmp, sizeof(double) * P->cell_len);
     ALLOC(P->d_glob, sizeof(double) * P->global_len);
+    ALLOC(P->d_cfd, sizeof(double) * cfd.size());
+    ALLOC(P->d_cvec, sizeof(double) * std::max<size_t>(2 * coarse_len(d), 1));
+    ALLOC(P->d_corner, sizeof(double) * corner_len(d));
 #undef ALLOC
     e = hipHostMalloc((void**)&P->h_red, sizeof(double) * kSlotCount, hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -220,6 +272,8 @@ fem_status create_problem(const fem_desc* d, hipStream_t stream, fem_problem** o
         e = hipMemcpyAsync(P->d_fd64, fd.data(), sizeof(double) * fd.size(), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(P->d_fd32, fd32.data(), sizeof(float) * fd32.size(), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(P->d_cfd, cfd.data(), sizeof(double) * cfd.size(), hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
         free_problem(P);
@@ -369,16 +423,38 @@ static fem_status pi_run(fem_problem* P, const void* r, void* z, int prec, int a
     return FEM_OK;
 }
 
+// t = r - A z into the scratch vector
+static fem_status residual_to_tmp(fem_problem* P, const void* r, const void* z, int prec) {
+    ProbEntry e = entry_of(P);
+    e.a = z;
+    e.b = r;
+    e.c = P->d_tmp;
+    FEM_HIP(launch_apply(P->p, prec, 1, &e, 1, nullptr, P->stream), "smoother residual");
+    return FEM_OK;
+}
+
 fem_status smoother_run(fem_problem* P, const void* r, void* z, int prec, int sweeps, double omega) {
     fem_status st = pi_run(P, r, z, prec, 0, omega);
     if (st != FEM_OK) return st;
     for (int s = 1; s < sweeps; ++s) {
         // t = r - A z (scratch), z += omega P_AS t
-        ProbEntry e = entry_of(P);
-        e.a = z;
-        e.b = r;
-        e.c = P->d_tmp;
-        FEM_HIP(launch_apply(P->p, prec, 1, &e, 1, nullptr, P->stream), "smoother residual");
+        st = residual_to_tmp(P, r, z, prec);
+        if (st != FEM_OK) return st;
+        st = pi_run(P, P->d_tmp, z, prec, 1, omega);
+        if (st != FEM_OK) return st;
+    }
+    return FEM_OK;
+}
+
+fem_status two_level_run(fem_problem* P, const void* r, void* z, int prec, int sweeps, double omega) {
+    fem_status st = smoother_run(P, r, z, prec, sweeps, omega);
+    if (st != FEM_OK) return st;
+    st = residual_to_tmp(P, r, z, prec);
+    if (st != FEM_OK) return st;
+    FEM_HIP(run_coarse_correction(P, P->d_tmp, z, prec), "coarse correction");
+    for (int s = 0; s < sweeps; ++s) {
+        st = residual_to_tmp(P, r, z, prec);
+        if (st != FEM_OK) return st;
         st = pi_run(P, P->d_tmp, z, prec, 1, omega);
         if (st != FEM_OK) return st;
     }
@@ -391,6 +467,15 @@ extern "C" fem_status patch_inverse(fem_problem* P, const void* r, void* z, int 
     if (check_prec(prec)) return FEM_EINVAL;
     if (r == z) return set_error(FEM_EINVAL, "patch_inverse: r and z alias");
     return pi_run(P, r, z, prec, 0, 1.0);
+}
+
+extern "C" fem_status fem_two_level(fem_problem* P, const void* r, void* z, int prec, int sweeps, double omega) {
+    CHECK_P(P); CHECK_PTR(r); CHECK_PTR(z);
+    if (check_prec(prec)) return FEM_EINVAL;
+    if (r == z) return set_error(FEM_EINVAL, "fem_two_level: r and z alias");
+    if (sweeps < 1) return set_error(FEM_EINVAL, "fem_two_level: sweeps >= 1");
+    if (!std::isfinite(omega)) return set_error(FEM_EINVAL, "fem_two_level: omega must be finite");
+    return two_level_run(P, r, z, prec, sweeps, omega);
 }
 
 extern "C" fem_status smoother_step(fem_problem* P, const void* r, void* z, int prec, int sweeps, double omega) {
@@ -451,7 +536,8 @@ static fem_status pcg_core(fem_problem* P, const double* b, double* u, double rt
     double* q = p + len;
     void* z = work + align256(3 * 8 * len);
     void* rs = sp == FEM_F64 ? (void*)r : (void*)(static_cast<char*>(z) + align256(prec_bytes(sp) * len));
-    const bool schwarz = pc == FEM_PC_SCHWARZ;
+    // the smoother-type preconditioners see the residual as the smoother does
+    const bool schwarz = pc == FEM_PC_SCHWARZ || pc == FEM_PC_TWO_LEVEL;
 
     auto finish = [&](fem_status st, int iters, double relres) {
         info->iters = iters;
@@ -464,7 +550,8 @@ static fem_status pcg_core(fem_problem* P, const double* b, double* u, double rt
         return st;
     };
     auto precondition = [&]() -> fem_status {
-        if (schwarz) return smoother_run(P, rs, z, sp, sweeps, omega);
+        if (pc == FEM_PC_SCHWARZ) return smoother_run(P, rs, z, sp, sweeps, omega);
+        if (pc == FEM_PC_TWO_LEVEL) return two_level_run(P, rs, z, sp, sweeps, omega);
         return FEM_OK;      // the simple preconditioners ran with the norm
     };
 
@@ -541,11 +628,12 @@ static fem_status check_solve_args(fem_problem* P, const double* b, const double
                                    int pc, int sp, int sweeps, int* variant) {
     CHECK_P(P); CHECK_PTR(b); CHECK_PTR(u);
     if (check_prec(sp)) return FEM_EINVAL;
-    if (pc != FEM_PC_SCHWARZ && pc != FEM_PC_DSS && pc != FEM_PC_JACOBI)
+    if (pc != FEM_PC_SCHWARZ && pc != FEM_PC_DSS && pc != FEM_PC_JACOBI && pc != FEM_PC_TWO_LEVEL)
         return set_error(FEM_EINVAL, "pcg_solve: unknown preconditioner");
     if (!(rtol > 0) || maxit < 0 || sweeps < 1) return set_error(FEM_EINVAL, "pcg_solve: rtol > 0, maxit >= 0, sweeps >= 1");
     if (b == u) return set_error(FEM_EINVAL, "pcg_solve: b and u alias");
-    if (*variant == FEM_CG_AUTO) *variant = (sp == FEM_F64 || pc != FEM_PC_SCHWARZ) ? FEM_CG_PCG : FEM_CG_FCG;
+    if (*variant == FEM_CG_AUTO)
+        *variant = (sp == FEM_F64 || pc == FEM_PC_DSS || pc == FEM_PC_JACOBI) ? FEM_CG_PCG : FEM_CG_FCG;
     if (*variant != FEM_CG_PCG && *variant != FEM_CG_FCG) return set_error(FEM_EINVAL, "pcg_solve: unknown variant");
     return FEM_OK;
 }

@@ -166,6 +166,12 @@ struct fem_problem {
     size_t solve_bytes;
     double* h_red;         // pinned host mirror of the scalar slots (null for arena problems)
     bool external_mem;     // buffers carved from caller memory (freed with it)
+    // coarse (Q1 on the interior vertices) level of the two-level preconditioner
+    int cm[3];             // interior vertices per direction (n - 1)
+    double* d_cfd;         // per direction: S (cm x cm, row-major) then lambda (cm)
+    size_t cfd_off[3];     // offsets of the directions in d_cfd
+    double* d_cvec;        // two coarse vectors of cm[0] cm[1] cm[2] values
+    double* d_corner;      // per-cell corner sums of a restriction: [8][nblk * 64]
 };
 
 // Caller-provided memory for a problem (the solve server's arena): device

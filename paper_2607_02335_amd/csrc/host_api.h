@@ -16,6 +16,13 @@ void host_gauss(int nq, std::vector<double>& x, std::vector<double>& w);
 void host_ref_matrices(int p, double* M, double* K);
 void host_patch_1d(int p, double h0, double h1, std::vector<double>& M, std::vector<double>& K);
 int host_fd_1d(int p, double h0, double h1, double* S, double* lam);
+// Generalised eigenproblem K S = M S diag(lam) with S^T M S = I (n x n).
+int host_gen_eig(int n, const std::vector<double>& M, const std::vector<double>& K, double* S, double* lam);
+// The coarse (Q1, interior vertices) 1D fast-diagonalisation data of a 1D
+// mesh of n cells: S ((n-1) x (n-1), row-major, columns eigenvectors) and
+// lam (n-1).  n < 2 writes nothing.
+int host_coarse_1d(int n, const double* h, double* S, double* lam);
+void host_q1_1d(int n, const double* h, std::vector<double>& M, std::vector<double>& K);
 
 // Validate a description; on failure sets the error message.
 fem_status check_desc(const fem_desc* d);
@@ -35,6 +42,9 @@ void destroy_problem_nosync(fem_problem* P);
 
 // Solver pieces reused by the server (all asynchronous on P->stream).
 fem_status smoother_run(fem_problem* P, const void* r, void* z, int prec, int sweeps, double omega);
+// The two-level preconditioner: `sweeps` smoothing sweeps from z = 0, the
+// exact coarse correction, `sweeps` more smoothing sweeps.
+fem_status two_level_run(fem_problem* P, const void* r, void* z, int prec, int sweeps, double omega);
 
 #define FEM_HIP(call, what)                                   \
     do {                                                      \

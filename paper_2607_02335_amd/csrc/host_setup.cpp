@@ -211,6 +211,7 @@ void host_patch_1d(int p, double h0, double h1, std::vector<double>& M, std::vec
 }
 
 static int host_fd_1d_compute(int p, double h0, double h1, double* S, double* lam);
+int host_gen_eig(int n, const std::vector<double>& M, const std::vector<double>& K, double* S, double* lam);
 
 // The 1D data depend only on (p, h0, h1); uniform meshes and repeated
 // requests reuse them, so results are memoised (bounded, process-wide).
@@ -251,9 +252,50 @@ int host_fd_1d(int p, double h0, double h1, double* S, double* lam) {
 }
 
 static int host_fd_1d_compute(int p, double h0, double h1, double* S, double* lam) {
-    const int n = 2 * p - 1;
     std::vector<double> M, K;
     host_patch_1d(p, h0, h1, M, K);
+    return host_gen_eig(2 * p - 1, M, K, S, lam);
+}
+
+// 1D Q1 matrices on the interior vertices of a 1D mesh of n cells (widths h)
+// with homogeneous Dirichlet ends: tridiagonal stiffness (1/h per cell) and
+// consistent mass (h/3 on the diagonal per cell, h/6 off it).
+void host_q1_1d(int n, const double* h, std::vector<double>& M, std::vector<double>& K) {
+    const int m = n - 1;
+    M.assign((size_t)m * m, 0.0);
+    K.assign((size_t)m * m, 0.0);
+    for (int c = 0; c < n; ++c) {          // cell c joins vertices c and c+1 (interior index c-1, c)
+        const int i0 = c - 1, i1 = c;
+        const double kh = 1.0 / h[c], mh = h[c];
+        if (i0 >= 0) {
+            K[i0 * m + i0] += kh;
+            M[i0 * m + i0] += mh / 3.0;
+        }
+        if (i1 < m) {
+            K[i1 * m + i1] += kh;
+            M[i1 * m + i1] += mh / 3.0;
+        }
+        if (i0 >= 0 && i1 < m) {
+            K[i0 * m + i1] -= kh;
+            K[i1 * m + i0] -= kh;
+            M[i0 * m + i1] += mh / 6.0;
+            M[i1 * m + i0] += mh / 6.0;
+        }
+    }
+}
+
+int host_coarse_1d(int n, const double* h, double* S, double* lam) {
+    if (n < 2) return 0;
+    std::vector<double> M, K;
+    host_q1_1d(n, h, M, K);
+    return host_gen_eig(n - 1, M, K, S, lam);
+}
+
+// Generalised symmetric eigenproblem K S = M S diag(lam), S^T M S = I, M SPD
+// (n x n, row-major): Cholesky M = L L^T, cyclic Jacobi on L^{-1} K L^{-T},
+// S = L^{-T} Q; ascending eigenvalues, each eigenvector's largest-magnitude
+// entry positive.
+int host_gen_eig(int n, const std::vector<double>& M, const std::vector<double>& K, double* S, double* lam) {
     // Cholesky M = L L^T
     std::vector<double> L(n * n, 0.0);
     for (int j = 0; j < n; ++j) {

@@ -142,6 +142,11 @@ hipError_t launch_collect_slots(ProbEntry* ents, int nprob, TableStager* st, hip
 // elementwise convert a (sp) -> c (dp) over whole cell vectors
 hipError_t launch_convert(int sp, int dp, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s);
 
+// z += P_0 A_0^{-1} R_0 t: the exact Q1 coarse correction of the two-level
+// preconditioner (t dual and z primal, both in `prec`; the coarse solve in
+// FP64).  No-op when the mesh has no interior vertex.
+hipError_t run_coarse_correction(fem_problem* P, const void* t, void* z, int prec);
+
 // Single-problem helpers (problem handle in, stream of the handle).
 ProbEntry entry_of(const fem_problem* P);
 hipError_t run_dss_axis(fem_problem* P, void* v, int axis, int prec);

@@ -20,7 +20,7 @@ FEM_OK, FEM_EINVAL, FEM_ENOMEM, FEM_EHIP, FEM_ENOTCONV, FEM_EBREAKDOWN, FEM_EAGA
 F64, F32, BF16 = 0, 1, 2
 DIRICHLET, NEUMANN = 0, 1
 CG_AUTO, CG_PCG, CG_FCG = 0, 1, 2
-PC_SCHWARZ, PC_DSS, PC_JACOBI = 0, 1, 2
+PC_SCHWARZ, PC_DSS, PC_JACOBI, PC_TWO_LEVEL = 0, 1, 2, 3
 STATUS_NAMES = {0: "FEM_OK", 1: "FEM_EINVAL", 2: "FEM_ENOMEM", 3: "FEM_EHIP", 4: "FEM_ENOTCONV",
                 5: "FEM_EBREAKDOWN", 6: "FEM_EAGAIN", 7: "FEM_ENOTFOUND"}
 
@@ -75,6 +75,7 @@ def lib():
         "fem_dss": ([vp, vp, vp, i], i), "fem_dss_axis": ([vp, vp, i, i], i),
         "patch_inverse": ([vp, vp, vp, i], i),
         "smoother_step": ([vp, vp, vp, i, i, d], i),
+        "fem_two_level": ([vp, vp, vp, i, i, d], i),
         "fem_dot": ([vp, vp, i, vp, i, ct.POINTER(d)], i),
         "fem_assembled_norm": ([vp, vp, i, ct.POINTER(d)], i),
         "pcg_solve": ([vp, vp, vp, d, i, i, i, d, i, ct.POINTER(SolveInfo)], i),
@@ -425,6 +426,17 @@ class Problem:
         z = self.cell_vector(prec_of(r)) if z is None else z
         self._sync_stream()
         check(lib().smoother_step(self.h, _ptr(r), _ptr(z), prec_of(r), sweeps, omega), "smoother_step")
+        return z
+
+    def two_level(self, r, z=None, sweeps=1, omega=0.2):
+        """z = B r: smoothing sweeps, exact Q1 coarse correction, sweeps."""
+        self._cell(r, None, "r")
+        if z is not None:
+            self._cell(z, prec_of(r), "z")
+        _require_cuda(r, z)
+        z = self.cell_vector(prec_of(r)) if z is None else z
+        self._sync_stream()
+        check(lib().fem_two_level(self.h, _ptr(r), _ptr(z), prec_of(r), sweeps, omega), "fem_two_level")
         return z
 
     def dot(self, a, b):
