@@ -307,6 +307,12 @@ typedef struct fem_server fem_server;
  * the server's lock); create and destroy must not overlap any other call. */
 fem_status fem_server_create(size_t hbm_budget, int max_active, int smoother_prec, int sweeps,
                              double omega, void* stream, fem_server** out);
+/* fem_server_create with a choice of preconditioner for every solve:
+ * FEM_PC_SCHWARZ (the smoother, as fem_server_create) or FEM_PC_TWO_LEVEL
+ * (fem_two_level with `sweeps` pre- and post-sweeps, batched over the
+ * active solves like every other phase).  Other values are FEM_EINVAL. */
+fem_status fem_server_create_pc(size_t hbm_budget, int max_active, int precond, int smoother_prec, int sweeps,
+                                double omega, void* stream, fem_server** out);
 fem_status fem_server_destroy(fem_server* S);
 /* Queue a solve of A u = P_I M f (f: host double[global_len] nodal source
  * values, copied).  Returns FEM_ENOMEM if the request can never fit the

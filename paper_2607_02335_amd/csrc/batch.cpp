@@ -284,6 +284,7 @@ struct fem_server {
     size_t budget = 0, in_use = 0, high_water = 0;
     int max_active = 0;
     int sp = FEM_F32, sweeps = 2, variant = FEM_CG_FCG;
+    int pc = FEM_PC_SCHWARZ;       // FEM_PC_SCHWARZ or FEM_PC_TWO_LEVEL
     double omega = 0.125;
     hipStream_t stream = nullptr;
     uint64_t next_ticket = 1;
@@ -406,12 +407,20 @@ static size_t solve_block_bytes(const fem_desc* d, int sp) { return fem_footprin
 
 extern "C" fem_status fem_server_create(size_t hbm_budget, int max_active, int smoother_prec, int sweeps,
                                         double omega, void* stream, fem_server** out) {
+    return fem_server_create_pc(hbm_budget, max_active, FEM_PC_SCHWARZ, smoother_prec, sweeps, omega, stream, out);
+}
+
+extern "C" fem_status fem_server_create_pc(size_t hbm_budget, int max_active, int precond, int smoother_prec,
+                                           int sweeps, double omega, void* stream, fem_server** out) {
     if (!out) return set_error(FEM_EINVAL, "out is NULL");
     *out = nullptr;
     if (max_active < 1 || sweeps < 1 || smoother_prec < FEM_F64 || smoother_prec > FEM_BF16 || !std::isfinite(omega))
         return set_error(FEM_EINVAL, "fem_server_create: bad arguments");
+    if (precond != FEM_PC_SCHWARZ && precond != FEM_PC_TWO_LEVEL)
+        return set_error(FEM_EINVAL, "fem_server_create: preconditioner must be FEM_PC_SCHWARZ or FEM_PC_TWO_LEVEL");
     fem_server* S = new (std::nothrow) fem_server();
     if (!S) return set_error(FEM_ENOMEM, "host allocation failed");
+    S->pc = precond;
     S->budget = hbm_budget;
     S->max_active = max_active;
     S->sp = smoother_prec;
@@ -607,7 +616,8 @@ static fem_status activate(fem_server* S, Active* A) {
     FEM_HIP(hipMemcpyAsync(A->r, A->b, sizeof(double) * len, hipMemcpyDeviceToDevice, s), "server init");
     FEM_HIP(run_assembled_norm2(P, A->b, FEM_F64, kSlotB2), "server norm");
     if (S->sp != FEM_F64) FEM_HIP(run_distribute(P, A->r, A->rs, S->sp, kSlotRN), "server distribute");
-    st = smoother_run(P, A->rs, A->z, S->sp, S->sweeps, S->omega);
+    st = S->pc == FEM_PC_TWO_LEVEL ? two_level_run(P, A->rs, A->z, S->sp, S->sweeps, S->omega)
+                                   : smoother_run(P, A->rs, A->z, S->sp, S->sweeps, S->omega);
     if (st != FEM_OK) return st;
     FEM_HIP(run_convert(P, A->z, S->sp, A->p, FEM_F64), "server p0");
     FEM_HIP(run_dot(P, A->r, FEM_F64, A->z, S->sp, kSlotRZ), "server dot");
@@ -792,9 +802,9 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
                 FEM_HIP(launch_cg_check(ents.data(), n, &S->st, s), "server convergence");
                 // smoother, pairings and the new direction (with the u step of
                 // this iteration's r update, which completes a finishing solve's u)
-                for (int i = 0; i < n; ++i) ents[i] = pi_entry(g[i]->P, g[i]->rs, g[i]->z, S->sp, S->omega);
-                FEM_HIP(launch_patch_inverse(p, S->sp, 0, ents.data(), n, &S->st, s), "server smoother");
-                for (int sw = 1; sw < S->sweeps; ++sw) {
+                // z = P(rs): Schwarz sweeps, or for the two-level method
+                // pre-sweeps, the coarse correction and post-sweeps
+                auto residual = [&]() -> fem_status {       // tmp = rs - A z
                     for (int i = 0; i < n; ++i) {
                         ents[i] = entry_of(g[i]->P);
                         ents[i].a = g[i]->z;
@@ -802,8 +812,30 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
                         ents[i].c = g[i]->P->d_tmp;
                     }
                     FEM_HIP(launch_apply(p, S->sp, 1, ents.data(), n, &S->st, s), "server smoother residual");
+                    return FEM_OK;
+                };
+                auto sweep_acc = [&]() -> fem_status {      // z += omega P_AS tmp
                     for (int i = 0; i < n; ++i) ents[i] = pi_entry(g[i]->P, g[i]->P->d_tmp, g[i]->z, S->sp, S->omega);
                     FEM_HIP(launch_patch_inverse(p, S->sp, 1, ents.data(), n, &S->st, s), "server smoother");
+                    return FEM_OK;
+                };
+                for (int i = 0; i < n; ++i) ents[i] = pi_entry(g[i]->P, g[i]->rs, g[i]->z, S->sp, S->omega);
+                FEM_HIP(launch_patch_inverse(p, S->sp, 0, ents.data(), n, &S->st, s), "server smoother");
+                for (int sw = 1; sw < S->sweeps; ++sw) {
+                    fem_status sst = residual();
+                    if (sst == FEM_OK) sst = sweep_acc();
+                    if (sst != FEM_OK) return sst;
+                }
+                if (S->pc == FEM_PC_TWO_LEVEL) {
+                    fem_status sst = residual();
+                    if (sst != FEM_OK) return sst;
+                    for (int i = 0; i < n; ++i) ents[i] = coarse_entry(g[i]->P, g[i]->P->d_tmp, g[i]->z);
+                    FEM_HIP(launch_coarse_correction(p, S->sp, ents.data(), n, &S->st, s), "server coarse correction");
+                    for (int sw = 0; sw < S->sweeps; ++sw) {
+                        sst = residual();
+                        if (sst == FEM_OK) sst = sweep_acc();
+                        if (sst != FEM_OK) return sst;
+                    }
                 }
                 if (S->variant == FEM_CG_PCG) {
                     for (int i = 0; i < n; ++i) ents[i] = entry_of(g[i]->P);

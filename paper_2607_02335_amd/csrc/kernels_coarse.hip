@@ -37,20 +37,31 @@ struct GllNodes {
     double xi[kMaxP + 1];
 };
 
+// Operands of every coarse kernel, per problem entry: a = t (dual, the
+// storage precision S), c = z (primal, S), d = corner sums
+// ([8][nblk * 64] doubles), e = two coarse vectors (2 x (n0-1)(n1-1)(n2-1)
+// doubles), fd[0..2] = per direction the coarse S ((n-1) x (n-1)) followed by
+// lambda (n-1).  Tiles are 256 cells (restriction and prolongation) or 256
+// coarse values (vertex sums and solve passes) of one problem.
+__device__ __forceinline__ int coarse_m(const ProbEntry& pe, int d) { return pe.n[d] > 1 ? pe.n[d] - 1 : 0; }
+
 // Cell -> its 8 corner sums, one thread per cell (lanes on the cells of a
 // storage block, so every load is a contiguous run); sums in FP64, streamed
-// over the z node planes.  corner[(sx + 2 sy + 4 sz) * stride + e].
-template <int P, typename S>
-__global__ void __launch_bounds__(256) k_restrict_cells(ProbEntry pe, const S* __restrict__ t,
-                                                        double* __restrict__ corner, int stride, GllNodes g) {
+// over the z node planes.  corner[(sx + 2 sy + 4 sz) * nblk * 64 + e].
+template <int P, typename S, bool MULTI>
+__global__ void __launch_bounds__(256) k_restrict_cells(LaunchTable L, GllNodes g) {
     constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
-    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int tile = blockIdx.x;
+    if (tile >= L.total_tiles) return;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int stride = pe.nblk * kLanes;
+    const int e = (tile - pe.tile_begin) * 256 + threadIdx.x;
     if (e >= stride) return;
     double out[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) out[i] = 0.0;
     if (e < pe.ncells) {
-        const S* v = t + (size_t)(e / kLanes) * NN * kLanes + (e % kLanes);
+        const S* v = static_cast<const S*>(pe.a) + (size_t)(e / kLanes) * NN * kLanes + (e % kLanes);
         for (int c = 0; c < N; ++c) {
             double ux[2][N];
 #pragma unroll
@@ -82,18 +93,26 @@ __global__ void __launch_bounds__(256) k_restrict_cells(ProbEntry pe, const S* _
             }
         }
     }
+    double* corner = static_cast<double*>(pe.d);
 #pragma unroll
     for (int i = 0; i < 8; ++i) corner[(size_t)i * stride + e] = out[i];
 }
 
-// Corner sums -> coarse right-hand side at the interior vertices, one thread
-// per vertex, the (up to) eight cells added in ascending cell order.
-__global__ void __launch_bounds__(256) k_restrict_vertices(ProbEntry pe, const double* __restrict__ corner, int stride,
-                                                           double* __restrict__ c, int m0, int m1, int m2) {
-    const long v = (long)blockIdx.x * 256 + threadIdx.x;
+// Corner sums -> coarse right-hand side at the interior vertices (the first
+// coarse vector), one thread per vertex, the eight cells added in ascending
+// cell order.
+template <bool MULTI>
+__global__ void __launch_bounds__(256) k_restrict_vertices(LaunchTable L) {
+    const int tile = blockIdx.x;
+    if (tile >= L.total_tiles) return;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int m0 = coarse_m(pe, 0), m1 = coarse_m(pe, 1), m2 = coarse_m(pe, 2);
+    const long v = (long)(tile - pe.tile_begin) * 256 + threadIdx.x;
     if (v >= (long)m0 * m1 * m2) return;
     const int vi = 1 + (int)(v % m0), vj = 1 + (int)((v / m0) % m1), vk = 1 + (int)(v / ((long)m0 * m1));
     const int n0 = pe.n[0], n1 = pe.n[1];
+    const int stride = pe.nblk * kLanes;
+    const double* corner = static_cast<const double*>(pe.d);
     double s = 0.0;
 #pragma unroll
     for (int dz = 0; dz < 2; ++dz)
@@ -105,48 +124,63 @@ __global__ void __launch_bounds__(256) k_restrict_vertices(ProbEntry pe, const d
                 const int e = (vi - 1 + dx) + n0 * ((vj - 1 + dy) + n1 * (vk - 1 + dz));
                 s += corner[(size_t)((1 - dx) + 2 * (1 - dy) + 4 * (1 - dz)) * stride + e];
             }
-    c[v] = s;
+    static_cast<double*>(pe.e)[v] = s;
 }
 
-// One 1D pass of the coarse fast-diagonalisation solve along `axis` (0 = x):
-// forward (fwd = 1) out(j) = sum_i S(i, j) x(i) (S^T), backward out(i) =
-// sum_j S(i, j) x(j).  With `scale`, the forward result is divided by
-// lx + ly + lz (the last forward pass).
-__global__ void __launch_bounds__(256) k_coarse_pass(const double* __restrict__ src, double* __restrict__ dst,
-                                                     const double* __restrict__ Sd, int m0, int m1, int m2,
-                                                     int axis, int fwd, const double* __restrict__ lx,
-                                                     const double* __restrict__ ly, const double* __restrict__ lz) {
-    const long id = (long)blockIdx.x * 256 + threadIdx.x;
+// One 1D pass of the coarse fast-diagonalisation solve along `axis` (0 = x)
+// from coarse vector `src` (0 or 1) to the other: forward (fwd = 1)
+// out(j) = sum_i S(i, j) x(i) (S^T), backward out(i) = sum_j S(i, j) x(j).
+// With `scale` the result is divided by lx + ly + lz (the last forward pass).
+template <bool MULTI>
+__global__ void __launch_bounds__(256) k_coarse_pass(LaunchTable L, int axis, int fwd, int src_half, int scale) {
+    const int tile = blockIdx.x;
+    if (tile >= L.total_tiles) return;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int m0 = coarse_m(pe, 0), m1 = coarse_m(pe, 1), m2 = coarse_m(pe, 2);
     const long tot = (long)m0 * m1 * m2;
+    const long id = (long)(tile - pe.tile_begin) * 256 + threadIdx.x;
     if (id >= tot) return;
     const int i0 = (int)(id % m0), i1 = (int)((id / m0) % m1), i2 = (int)(id / ((long)m0 * m1));
     const int m = axis == 0 ? m0 : axis == 1 ? m1 : m2;
     const int o = axis == 0 ? i0 : axis == 1 ? i1 : i2;
     const long stride = axis == 0 ? 1 : axis == 1 ? m0 : (long)m0 * m1;
-    const double* x = src + (id - (long)o * stride);
+    double* cv = static_cast<double*>(pe.e);
+    const double* x = cv + (src_half ? tot : 0) + (id - (long)o * stride);
+    double* dst = cv + (src_half ? 0 : tot);
+    const double* Sd = static_cast<const double*>(pe.fd[axis]);
     double s = 0.0;
     if (fwd) {
         for (int i = 0; i < m; ++i) s += Sd[(size_t)i * m + o] * x[(long)i * stride];
     } else {
         for (int j = 0; j < m; ++j) s += Sd[(size_t)o * m + j] * x[(long)j * stride];
     }
-    if (lx) s /= lx[i0] + ly[i1] + lz[i2];
+    if (scale) {
+        const double* lx = static_cast<const double*>(pe.fd[0]) + (size_t)m0 * m0;
+        const double* ly = static_cast<const double*>(pe.fd[1]) + (size_t)m1 * m1;
+        const double* lz = static_cast<const double*>(pe.fd[2]) + (size_t)m2 * m2;
+        s /= lx[i0] + ly[i1] + lz[i2];
+    }
     dst[id] = s;
 }
 
-// z += P_0 e: trilinear interpolation of the coarse correction at the cell
-// nodes, one thread per cell.  Only corners with a nonzero weight at a node
-// are summed, in (sz, sy, sx) order, so the copies of a node shared by
-// several cells add the same terms in the same order (bitwise continuous).
-template <int P, typename S>
-__global__ void __launch_bounds__(256) k_prolong_add(ProbEntry pe, const double* __restrict__ ev, S* __restrict__ z,
-                                                     int m0, int m1, GllNodes g) {
+// z += P_0 e: trilinear interpolation of the coarse correction (the first
+// coarse vector) at the cell nodes, one thread per cell.  Only corners with
+// a nonzero weight at a node are summed, in (sz, sy, sx) order, so the
+// copies of a node shared by several cells add the same terms in the same
+// order (bitwise continuous).
+template <int P, typename S, bool MULTI>
+__global__ void __launch_bounds__(256) k_prolong_add(LaunchTable L, GllNodes g) {
     using C = typename Prec<S>::C;
     constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
-    const int e = blockIdx.x * 256 + threadIdx.x;
+    const int tile = blockIdx.x;
+    if (tile >= L.total_tiles) return;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int e = (tile - pe.tile_begin) * 256 + threadIdx.x;
     if (e >= pe.ncells) return;
     const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+    const int m0 = coarse_m(pe, 0), m1 = coarse_m(pe, 1);
     const int i = e % n0, j = (e / n0) % n1, k = e / (n0 * n1);
+    const double* ev = static_cast<const double*>(pe.e);
     double cv[8];
 #pragma unroll
     for (int sz = 0; sz < 2; ++sz)
@@ -158,7 +192,7 @@ __global__ void __launch_bounds__(256) k_prolong_add(ProbEntry pe, const double*
                 const bool in = vi >= 1 && vi <= n0 - 1 && vj >= 1 && vj <= n1 - 1 && vk >= 1 && vk <= n2 - 1;
                 cv[sx + 2 * sy + 4 * sz] = in ? ev[(vi - 1) + (long)m0 * ((vj - 1) + (long)m1 * (vk - 1))] : 0.0;
             }
-    S* out = z + (size_t)(e / kLanes) * NN * kLanes + (e % kLanes);
+    S* out = static_cast<S*>(pe.c) + (size_t)(e / kLanes) * NN * kLanes + (e % kLanes);
     for (int c = 0; c < N; ++c) {
         const double wz[2] = {1.0 - g.xi[c], g.xi[c]};
         for (int b = 0; b < N; ++b) {
@@ -197,72 +231,86 @@ static hipError_t by_prec(int prec, F&& f) {
 }
 
 template <int P>
-static hipError_t coarse_transfers_p(fem_problem* P_, int prec, const void* t, void* z, bool restrict_, GllNodes g) {
-    const ProbEntry pe = entry_of(P_);
-    const int stride = P_->nblk * kLanes;
-    hipStream_t s = P_->stream;
+static hipError_t coarse_p(int prec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s) {
+    GllNodes g{};
+    const std::vector<double>& xi = gll_cached(P);
+    for (int a = 0; a <= P; ++a) g.xi[a] = xi[a];
+    const bool multi = nprob > 1;
+    // cell-based tables (restriction, prolongation)
+    LaunchTable Lc{};
+    int tc = 0;
+    for (int i = 0; i < nprob; ++i) {
+        ents[i].tile_begin = tc;
+        ents[i].ntiles = (ents[i].nblk * kLanes + 255) / 256;
+        tc += ents[i].ntiles;
+    }
+    Lc.nprob = nprob;
+    Lc.total_tiles = tc;
+    hipError_t err = stage_table(Lc, ents, nprob, st, s);
+    if (err != hipSuccess) return err;
+    // coarse-value tables (vertex sums, solve passes)
+    LaunchTable Lv{};
+    int tv = 0;
+    for (int i = 0; i < nprob; ++i) {
+        long nv = 1;
+        for (int d = 0; d < 3; ++d) nv *= ents[i].n[d] > 1 ? ents[i].n[d] - 1 : 0;
+        ents[i].tile_begin = tv;
+        ents[i].ntiles = (int)((nv + 255) / 256);
+        tv += ents[i].ntiles;
+    }
+    Lv.nprob = nprob;
+    Lv.total_tiles = tv;
+    if (tv == 0) return hipSuccess;                 // no interior vertex anywhere: no coarse space
+    err = stage_table(Lv, ents, nprob, st, s);
+    if (err != hipSuccess) return err;
     return by_prec(prec, [&](auto tag) {
         using S = decltype(tag);
-        if (restrict_) {
-            TraceSpan ts("coarse_restrict", P, Prec<S>::id, s);
-            hipLaunchKernelGGL((k_restrict_cells<P, S>), dim3((stride + 255) / 256), dim3(256), 0, s, pe,
-                               static_cast<const S*>(t), P_->d_corner, stride, g);
-            const long nv = (long)P_->cm[0] * P_->cm[1] * P_->cm[2];
-            hipLaunchKernelGGL(k_restrict_vertices, dim3((unsigned)((nv + 255) / 256)), dim3(256), 0, s, pe,
-                               P_->d_corner, stride, P_->d_cvec, P_->cm[0], P_->cm[1], P_->cm[2]);
-        } else {
-            TraceSpan ts("coarse_prolong", P, Prec<S>::id, s);
-            hipLaunchKernelGGL((k_prolong_add<P, S>), dim3((P_->ncells + 255) / 256), dim3(256), 0, s, pe,
-                               P_->d_cvec, static_cast<S*>(z), P_->cm[0], P_->cm[1], g);
+        TraceSpan ts("coarse_correction", P, Prec<S>::id, s);
+        if (multi) hipLaunchKernelGGL((k_restrict_cells<P, S, true>), dim3(tc), dim3(256), 0, s, Lc, g);
+        else hipLaunchKernelGGL((k_restrict_cells<P, S, false>), dim3(tc), dim3(256), 0, s, Lc, g);
+        if (multi) hipLaunchKernelGGL(k_restrict_vertices<true>, dim3(tv), dim3(256), 0, s, Lv);
+        else hipLaunchKernelGGL(k_restrict_vertices<false>, dim3(tv), dim3(256), 0, s, Lv);
+        // x, y, z forward (then the eigenvalue scaling), z, y, x backward;
+        // vector 0 -> 1 -> 0 -> 1 -> 0 -> 1 -> 0
+        const int axis[6] = {0, 1, 2, 2, 1, 0}, fwd[6] = {1, 1, 1, 0, 0, 0};
+        for (int k = 0; k < 6; ++k) {
+            if (multi) hipLaunchKernelGGL(k_coarse_pass<true>, dim3(tv), dim3(256), 0, s, Lv, axis[k], fwd[k], k % 2, k == 2 ? 1 : 0);
+            else hipLaunchKernelGGL(k_coarse_pass<false>, dim3(tv), dim3(256), 0, s, Lv, axis[k], fwd[k], k % 2, k == 2 ? 1 : 0);
         }
+        if (multi) hipLaunchKernelGGL((k_prolong_add<P, S, true>), dim3(tc), dim3(256), 0, s, Lc, g);
+        else hipLaunchKernelGGL((k_prolong_add<P, S, false>), dim3(tc), dim3(256), 0, s, Lc, g);
         return hipGetLastError();
     });
 }
 
-static hipError_t coarse_transfers(fem_problem* P, int prec, const void* t, void* z, bool restrict_) {
-    GllNodes g{};
-    const std::vector<double>& xi = gll_cached(P->p);
-    for (int a = 0; a <= P->p; ++a) g.xi[a] = xi[a];
-    switch (P->p) {
-        case 1: return coarse_transfers_p<1>(P, prec, t, z, restrict_, g);
-        case 2: return coarse_transfers_p<2>(P, prec, t, z, restrict_, g);
-        case 3: return coarse_transfers_p<3>(P, prec, t, z, restrict_, g);
-        case 4: return coarse_transfers_p<4>(P, prec, t, z, restrict_, g);
-        case 5: return coarse_transfers_p<5>(P, prec, t, z, restrict_, g);
-        case 6: return coarse_transfers_p<6>(P, prec, t, z, restrict_, g);
-        case 7: return coarse_transfers_p<7>(P, prec, t, z, restrict_, g);
+// Entry of a problem for the coarse kernels: a = t, c = z.
+ProbEntry coarse_entry(fem_problem* P, const void* t, void* z) {
+    ProbEntry e = entry_of(P);
+    e.a = t;
+    e.c = z;
+    e.d = P->d_corner;
+    e.e = P->d_cvec;
+    for (int k = 0; k < 3; ++k) e.fd[k] = P->d_cfd + P->cfd_off[k];
+    return e;
+}
+
+hipError_t launch_coarse_correction(int p, int prec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s) {
+    if (nprob <= 0) return hipSuccess;
+    switch (p) {
+        case 1: return coarse_p<1>(prec, ents, nprob, st, s);
+        case 2: return coarse_p<2>(prec, ents, nprob, st, s);
+        case 3: return coarse_p<3>(prec, ents, nprob, st, s);
+        case 4: return coarse_p<4>(prec, ents, nprob, st, s);
+        case 5: return coarse_p<5>(prec, ents, nprob, st, s);
+        case 6: return coarse_p<6>(prec, ents, nprob, st, s);
+        case 7: return coarse_p<7>(prec, ents, nprob, st, s);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t run_coarse_correction(fem_problem* P, const void* t, void* z, int prec) {
-    const int m0 = P->cm[0], m1 = P->cm[1], m2 = P->cm[2];
-    const long nv = (long)m0 * m1 * m2;
-    if (nv == 0) return hipSuccess;                     // no interior vertex: no coarse space
-    hipError_t err = coarse_transfers(P, prec, t, z, true);
-    if (err != hipSuccess) return err;
-    double* c = P->d_cvec;
-    double* w = P->d_cvec + nv;
-    const double* Sx = P->d_cfd + P->cfd_off[0];
-    const double* Sy = P->d_cfd + P->cfd_off[1];
-    const double* Sz = P->d_cfd + P->cfd_off[2];
-    const double* lx = Sx + (size_t)m0 * m0;
-    const double* ly = Sy + (size_t)m1 * m1;
-    const double* lz = Sz + (size_t)m2 * m2;
-    const dim3 grid((unsigned)((nv + 255) / 256)), blk(256);
-    hipStream_t s = P->stream;
-    {
-        TraceSpan ts("coarse_solve", P->p, FEM_F64, s);
-        hipLaunchKernelGGL(k_coarse_pass, grid, blk, 0, s, c, w, Sx, m0, m1, m2, 0, 1, nullptr, nullptr, nullptr);
-        hipLaunchKernelGGL(k_coarse_pass, grid, blk, 0, s, w, c, Sy, m0, m1, m2, 1, 1, nullptr, nullptr, nullptr);
-        hipLaunchKernelGGL(k_coarse_pass, grid, blk, 0, s, c, w, Sz, m0, m1, m2, 2, 1, lx, ly, lz);
-        hipLaunchKernelGGL(k_coarse_pass, grid, blk, 0, s, w, c, Sz, m0, m1, m2, 2, 0, nullptr, nullptr, nullptr);
-        hipLaunchKernelGGL(k_coarse_pass, grid, blk, 0, s, c, w, Sy, m0, m1, m2, 1, 0, nullptr, nullptr, nullptr);
-        hipLaunchKernelGGL(k_coarse_pass, grid, blk, 0, s, w, c, Sx, m0, m1, m2, 0, 0, nullptr, nullptr, nullptr);
-    }
-    err = hipGetLastError();
-    if (err != hipSuccess) return err;
-    return coarse_transfers(P, prec, nullptr, z, false);
+    ProbEntry e = coarse_entry(P, t, z);
+    return launch_coarse_correction(P->p, prec, &e, 1, nullptr, P->stream);
 }
 
 }  // namespace fem

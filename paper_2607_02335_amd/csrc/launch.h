@@ -146,6 +146,9 @@ hipError_t launch_convert(int sp, int dp, ProbEntry* ents, int nprob, TableStage
 // preconditioner (t dual and z primal, both in `prec`; the coarse solve in
 // FP64).  No-op when the mesh has no interior vertex.
 hipError_t run_coarse_correction(fem_problem* P, const void* t, void* z, int prec);
+// The same over several problems of degree p (entries from coarse_entry).
+hipError_t launch_coarse_correction(int p, int prec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s);
+ProbEntry coarse_entry(fem_problem* P, const void* t, void* z);
 
 // Single-problem helpers (problem handle in, stream of the handle).
 ProbEntry entry_of(const fem_problem* P);

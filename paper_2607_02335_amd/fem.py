@@ -91,6 +91,7 @@ def lib():
         "fem_batch_autotune": ([vp, i, ct.POINTER(i)], i),
         "fem_server_create": ([sz, i, i, i, d, vp, pp], i),
         "fem_server_destroy": ([vp], i),
+        "fem_server_create_pc": ([sz, i, i, i, i, d, vp, pp], i),
         "fem_server_submit": ([vp, ct.POINTER(Desc), vp, d, i, ct.POINTER(ct.c_uint64)], i),
         "fem_server_step": ([vp, ct.POINTER(i), ct.POINTER(i), ct.POINTER(i)], i),
         "fem_server_poll": ([vp, ct.c_uint64, vp, ct.POINTER(SolveInfo)], i),
@@ -572,10 +573,10 @@ class Batch:
 class Server:
     """Continuous-batching Poisson solve server (device-resident solves)."""
 
-    def __init__(self, hbm_budget, max_active=64, smoother_prec=F32, sweeps=2, omega=0.125):
+    def __init__(self, hbm_budget, max_active=64, smoother_prec=F32, sweeps=2, omega=0.125, precond=PC_SCHWARZ):
         h = ct.c_void_p()
-        check(lib().fem_server_create(int(hbm_budget), max_active, smoother_prec, sweeps, omega, _stream(),
-                                      ct.byref(h)), "fem_server_create")
+        check(lib().fem_server_create_pc(int(hbm_budget), max_active, precond, smoother_prec, sweeps, omega,
+                                         _stream(), ct.byref(h)), "fem_server_create_pc")
         self.h = h
         self.glen = {}
 

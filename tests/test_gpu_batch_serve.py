@@ -99,16 +99,17 @@ def _requests(F, count, seed):
     return out
 
 
-@pytest.mark.parametrize("sp", [0, 1])
-def test_server_matches_standalone_solves(F, sp):
+@pytest.mark.parametrize("sp,pc", [(0, 0), (1, 0), (0, 3), (1, 3)])
+def test_server_matches_standalone_solves(F, sp, pc):
     """Every served solution equals its standalone pcg_solve bit for bit and
     meets the 1e-8 target on the oracle's own residual ||b - A_D u|| / ||b||;
     a zero source is solved at once (u = 0, no iteration), as pcg_solve
     returns it."""
     reqs = _requests(F, 8, 11 + sp)
     reqs.insert(3, (3, 4, np.zeros(synth.global_len(3, (4, 4, 4)))))
-    note(f"server sp={sp}: " + " ".join(f"q{p}n{n}" for p, n, _ in reqs))
-    S = F.Server(hbm_budget=8 << 30, max_active=4, smoother_prec=sp)
+    note(f"server sp={sp} pc={pc}: " + " ".join(f"q{p}n{n}" for p, n, _ in reqs))
+    sweeps, omega = (2, 0.125) if pc == 0 else (1, 0.2)
+    S = F.Server(hbm_budget=8 << 30, max_active=4, smoother_prec=sp, precond=pc, sweeps=sweeps, omega=omega)
     tickets = [S.submit(p, n, f, rtol=1e-8, maxit=800) for p, n, f in reqs]
     results = {}
     for _ in range(100000):
@@ -126,7 +127,7 @@ def test_server_matches_standalone_solves(F, sp):
         assert info["status"] == 0 and info["relres"] <= 1e-8
         P = F.Problem(p, n)
         b = P.mass_apply(P.gather(to_dev(f)))
-        u, inf1 = P.pcg_solve(b, rtol=1e-8, maxit=800, smoother_prec=sp)
+        u, inf1 = P.pcg_solve(b, rtol=1e-8, maxit=800, smoother_prec=sp, precond=pc, sweeps=sweeps, omega=omega)
         assert inf1["iters"] == info["iters"]
         np.testing.assert_array_equal(u_srv, to_np(P.extract(u)))
         if not np.any(f):
