@@ -282,9 +282,10 @@ fem_status fem_batch_patch_inverse(fem_batch* B, void* const* r, void* const* z,
  * candidate kernel shapes on the batch's own problems (apply: register
  * (p <= 3) or plane-streamed (p >= 4) kernel, or the LDS line kernel, each x
  * two persistent grid caps; patch inverse for p <= 3: two launches through
- * the patch buffer, fused sweep from the cell copies, or fused sweep from
- * the assembled residual; for p >= 4: MFMA or line patch solves; each x two
- * grid caps) and keep the fastest for later batched calls.  choice (may be
+ * the patch buffer, fused sweep from the cell copies, fused sweep from the
+ * assembled residual, or solves with the in-tile x-combine; for p >= 4: MFMA
+ * or line patch solves; each x two grid caps) and keep the fastest for later
+ * batched calls.  choice (may be
  * NULL): int[14], choice[2(p-1)] = apply candidate index, choice[2(p-1)+1]
  * = patch-inverse candidate index of degree p, candidates in the order
  * listed with the grid cap varying fastest (untouched for absent degrees).
@@ -357,9 +358,12 @@ fem_status fem_host_fd_1d(int p, double h0, double h1, double* S, double* lambda
  * autotuner picks per batch instead).  FEM_OPT_PI_FUSED: patch_inverse for
  * p <= 3 as 0 two launches through the patch buffer, 1 one fused sweep
  * summing the residual's cell copies on chip, 2 assembly plus one fused
- * sweep reading the assembled residual; for p >= 4, 2 selects line (VALU)
- * patch solves instead of MFMA; -1 (default) picks by degree and precision
- * only (2 for p = 2 in FP64, else 0).  The p <= 3 combine of the two-launch
+ * sweep reading the assembled residual, 3 assembly plus solves that add the
+ * x-overlaps of neighbouring patches in the workgroup and write one run of
+ * global x-nodes per patch line (a buffer about 3/5 of the patch buffer at
+ * p = 3), then a combine by global node rows; for p >= 4, 2 selects line
+ * (VALU) patch solves instead of MFMA; -1 (default) picks by degree and
+ * precision only (3 for p = 2, 3 in FP64, else 0).  The p <= 3 combine of the two-launch
  * form runs by global node rows (FP64, every mesh with at least 48 cells
  * along x) or by (block, node plane), with identical results;
  * FEM_OPT_COMBINE_PER_CELL = 1 makes it use one wavefront per 64-cell block

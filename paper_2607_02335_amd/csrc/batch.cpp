@@ -182,9 +182,10 @@ extern "C" fem_status fem_batch_autotune(fem_batch* B, int prec, int* choice) {
             //        1 = LDS line kernel;
             // patch inverse, p <= 3: 0 = two launches through the patch buffer,
             //        1 = fused sweep summing cell copies, 2 = fused sweep from the
-            //        assembled residual; p >= 4: 0 = MFMA solves, 2 = line solves
+            //        assembled residual, 3 = solves with the in-tile x-combine;
+            //        p >= 4: 0 = MFMA solves, 2 = line solves
             std::vector<int> kinds = which == 0 ? std::vector<int>{0, 1}
-                                   : (p <= 3 ? std::vector<int>{0, 1, 2} : std::vector<int>{0, 2});
+                                   : (p <= 3 ? std::vector<int>{0, 1, 2, 3} : std::vector<int>{0, 2});
             std::vector<LaunchCfg> cand;
             for (int kind : kinds) {
                 for (int c : caps) {

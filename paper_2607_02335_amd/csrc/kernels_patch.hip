@@ -990,6 +990,336 @@ __global__ void __launch_bounds__(256) k_pi_solve_g(LaunchTable L) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Patch inverse for p <= 3 through an x-combined buffer (two launches after
+// the assembly).  k_pi_solve_x solves a tile of CBP patches along x that
+// share one (y, z) vertex, as k_pi_solve_g does, then adds the x-overlaps
+// of neighbouring patches of the tile in LDS: for every patch line (qy, qz)
+// the tile writes one run of global x-nodes, each the sum of its (one or
+// two) patch values in ascending vertex order, instead of every patch's
+// full (2p-1)^3 box.  Layout, per problem: row (vj, vk) of patch rows, line
+// ln = qy + (2p-1) qz, then the tiles of the row one after another; tile tx
+// (patches 1 + tx CBP ...) covers the x-nodes X0 = tx CBP p + 1 ... X0 +
+// w p + p - 2 (w = its valid patches), so consecutive tiles overlap in
+// p - 1 nodes:
+//   xoff(tx) = tx (CBP p + p - 1),  row length RL = npx p + ntx (p - 1).
+// k_pi_combine_x then adds, per global node, the tile overlap, the y- and
+// the z-patches in ascending order and writes every cell copy.
+__host__ __device__ constexpr int xrow_len(int npx, int ntx, int P) { return npx * P + ntx * (P - 1); }
+
+template <int P, typename S, int CBP, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_solve_x(LaunchTable L) {
+    using C = typename Prec<S>::C;
+    constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
+    constexpr int REC = fd_record(P);
+    constexpr int NT = 256, LPT = NT / CBP;
+    constexpr int KL = (nP2 + LPT - 1) / LPT;       // lines per thread (upper bound)
+    constexpr int SXS = nP2 | 1;                    // odd row stride of the x bases
+    constexpr int SPAN = CBP * P + P - 1;           // x-nodes of a full tile
+    static_assert(NT % CBP == 0, "patches per tile must divide the workgroup");
+    __shared__ C sv[nP3 * CBP];
+    __shared__ C sSx[CBP * SXS];
+    __shared__ C sLx[CBP * nP];
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= L.total_tiles) return;
+    const int tid = threadIdx.x;
+    const int pc = tid % CBP, grp = tid / CBP;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int t = tile - pe.tile_begin;
+    const int npx = pe.n[0] - 1, npy = pe.n[1] - 1;
+    const int tpr = (npx + CBP - 1) / CBP;
+    const int row = t / tpr, xt = t % tpr;
+    const int vj = 1 + row % npy, vk = 1 + row / npy;
+    const int vi0 = 1 + xt * CBP;
+    const int vi = vi0 + pc;
+    const bool valid = vi <= npx;
+    const int nvalid = min(CBP, npx - vi0 + 1);
+    const C* fy = static_cast<const C*>(pe.fd[1]) + (size_t)(vj - 1) * REC;
+    const C* fz = static_cast<const C*>(pe.fd[2]) + (size_t)(vk - 1) * REC;
+    C lines[KL][nP];
+    {
+        const C* g = static_cast<const C*>(pe.e);
+        const size_t G0 = (size_t)pe.n[0] * P + 1, G1 = (size_t)pe.n[1] * P + 1;
+        const size_t base = (size_t)(vi - 1) * P + 1 + G0 * (((size_t)(vj - 1) * P + 1) + G1 * ((size_t)(vk - 1) * P + 1));
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {
+            const int ln = grp + LPT * k;
+            const int qy = ln % nP, qz = ln / nP;
+            const C* src = g + base + G0 * (qy + G1 * qz);
+#pragma unroll
+            for (int i = 0; i < nP; ++i) lines[k][i] = (valid && ln < nP2) ? src[i] : (C)0;
+        }
+    }
+    {
+        const C* fx0 = static_cast<const C*>(pe.fd[0]);
+        for (int w = tid; w < CBP * (nP2 + nP); w += NT) {
+            const int c = w / (nP2 + nP), o = w % (nP2 + nP);
+            const int line = min(vi0 + c, npx) - 1;
+            const C v = fx0[(size_t)line * REC + o];
+            if (o < nP2) sSx[c * SXS + o] = v; else sLx[c * nP + o - nP2] = v;
+        }
+    }
+    __syncthreads();
+    {
+        C Sm[nP2];
+#pragma unroll
+        for (int i = 0; i < nP2; ++i) Sm[i] = sSx[pc * SXS + i];
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {                              // x forward
+            const int ln = grp + LPT * k;
+            if (ln >= nP2) break;
+#pragma unroll
+            for (int j = 0; j < nP; ++j) {
+                C s = 0;
+#pragma unroll
+                for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * lines[k][i];
+                sv[(j + nP * ln) * CBP + pc] = s;
+            }
+        }
+    }
+    __syncthreads();
+    {
+        C Sm[nP2];
+#pragma unroll
+        for (int i = 0; i < nP2; ++i) Sm[i] = fy[i];
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {                              // y forward
+            const int ln = grp + LPT * k;
+            if (ln >= nP2) break;
+            const int qx = ln % nP, qz = ln / nP;
+            C v[nP];
+#pragma unroll
+            for (int i = 0; i < nP; ++i) v[i] = sv[(qx + nP * i + nP2 * qz) * CBP + pc];
+#pragma unroll
+            for (int j = 0; j < nP; ++j) {
+                C s = 0;
+#pragma unroll
+                for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
+                sv[(qx + nP * j + nP2 * qz) * CBP + pc] = s;
+            }
+        }
+    }
+    __syncthreads();
+    {
+        C Sm[nP2], lz[nP];
+#pragma unroll
+        for (int i = 0; i < nP2; ++i) Sm[i] = fz[i];
+#pragma unroll
+        for (int i = 0; i < nP; ++i) lz[i] = fz[nP2 + i];
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {                              // z: forward, scale, backward
+            const int ln = grp + LPT * k;
+            if (ln >= nP2) break;
+            const int qx = ln % nP, qy = ln / nP;
+            const C lxy = sLx[pc * nP + qx] + fy[nP2 + qy];
+            C v[nP], w[nP];
+#pragma unroll
+            for (int i = 0; i < nP; ++i) v[i] = sv[(ln + nP2 * i) * CBP + pc];
+#pragma unroll
+            for (int j = 0; j < nP; ++j) {
+                C s = 0;
+#pragma unroll
+                for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i];
+                w[j] = s * recip(lxy + lz[j]);
+            }
+#pragma unroll
+            for (int i = 0; i < nP; ++i) {
+                C s = 0;
+#pragma unroll
+                for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * w[j];
+                sv[(ln + nP2 * i) * CBP + pc] = s;
+            }
+        }
+    }
+    __syncthreads();
+    {
+        C Sm[nP2];
+#pragma unroll
+        for (int i = 0; i < nP2; ++i) Sm[i] = fy[i];
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {                              // y backward
+            const int ln = grp + LPT * k;
+            if (ln >= nP2) break;
+            const int qx = ln % nP, qz = ln / nP;
+            C v[nP];
+#pragma unroll
+            for (int j = 0; j < nP; ++j) v[j] = sv[(qx + nP * j + nP2 * qz) * CBP + pc];
+#pragma unroll
+            for (int i = 0; i < nP; ++i) {
+                C s = 0;
+#pragma unroll
+                for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * v[j];
+                sv[(qx + nP * i + nP2 * qz) * CBP + pc] = s;
+            }
+        }
+    }
+    __syncthreads();
+    {
+        C Sm[nP2];
+#pragma unroll
+        for (int i = 0; i < nP2; ++i) Sm[i] = sSx[pc * SXS + i];
+#pragma unroll
+        for (int k = 0; k < KL; ++k) {                              // x backward, in place (own line)
+            const int ln = grp + LPT * k;
+            if (ln >= nP2) break;
+            C v[nP];
+#pragma unroll
+            for (int j = 0; j < nP; ++j) v[j] = sv[(j + nP * ln) * CBP + pc];
+#pragma unroll
+            for (int i = 0; i < nP; ++i) {
+                C s = 0;
+#pragma unroll
+                for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * v[j];
+                sv[(i + nP * ln) * CBP + pc] = s;
+            }
+        }
+    }
+    __syncthreads();
+    // x-combine: node s of the tile's span = patch pc_hi = s / p at
+    // qx = s % p, plus patch pc_hi - 1 at qx + p when that is inside it
+    const int span = nvalid * P + P - 1;
+    const int RL = xrow_len(npx, tpr, P);
+    C* xb = static_cast<C*>(pe.d) + ((size_t)row * nP2) * RL + (size_t)xt * SPAN;
+    for (int item = tid; item < nP2 * span; item += NT) {
+        const int ln = item / span, sx = item % span;
+        const int hi = sx / P, q = sx % P;
+        C v = 0;
+        if (hi >= 1 && q <= P - 2) v = sv[(q + P + nP * ln) * CBP + hi - 1];
+        if (hi < nvalid) v = v + sv[(q + nP * ln) * CBP + hi];
+        xb[(size_t)ln * RL + sx] = v;
+    }
+}
+
+// Combine of the x-combined buffer (p <= 3): one wavefront per global node
+// row (Y, Z) with lane i on cell column i.  Per node X of the row the terms
+// are the z-patches (ascending vk), within each the y-patches (ascending vj),
+// within each the overlapping tiles (ascending); the sum goes to every cell
+// copy of the node (a vertex-plane node also into the left neighbour's last
+// slot).  The first wavefront of a problem zeroes the padding cells of its
+// last storage block.  pe: d = x-combined buffer, c = z (S), alpha = damping.
+template <int P, typename S, int CBP, int ACC, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_combine_x(LaunchTable L) {
+    using C = typename Prec<S>::C;
+    constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
+    constexpr int nP = 2 * P - 1, nP2 = nP * nP;
+    constexpr int SPAN = CBP * P + P - 1;
+    const int tile = blockIdx.x;
+    if (tile >= L.total_tiles) return;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+    const int npx = n0 - 1, npy = n1 - 1;
+    const int G1 = n1 * P + 1, G2 = n2 * P + 1;
+    const int row = (tile - pe.tile_begin) * 4 + (int)(threadIdx.x / 64);
+    if (row >= G1 * G2) return;
+    const int lane = threadIdx.x % 64;
+    const int ntx = (npx + CBP - 1) / CBP;
+    const int RL = xrow_len(npx, ntx, P);
+    const C* xb = static_cast<const C*>(pe.d);
+    S* z = static_cast<S*>(pe.c);
+    const C alpha = (C)pe.alpha;
+    if (row == 0) {
+#pragma unroll 1
+        for (int l = 0; l < NN; ++l) {
+            const int e = (pe.nblk - 1) * kLanes + lane;
+            if (e >= pe.ncells) store_from(z + cell_offset(e, l, NN), (C)0);
+        }
+    }
+    const int Y = row % G1, Z = row / G1;
+    // patch rows containing the node row along y and z (ascending vertex),
+    // with the patch-local index, and the cell copies of the row
+    int vyp[2], qyp[2], nyp = 0, vzp[2], qzp[2], nzp = 0;
+    int cyc[2], byc[2], nyc = 0, czc[2], bzc[2], nzc = 0;
+    {
+        const int qy = Y / P, ry = Y - qy * P;
+        if (ry == 0) {
+            if (qy >= 1 && qy <= npy) { vyp[nyp] = qy; qyp[nyp] = P - 1; ++nyp; }
+            if (qy >= 1) { cyc[nyc] = qy - 1; byc[nyc] = P; ++nyc; }
+            if (qy <= n1 - 1) { cyc[nyc] = qy; byc[nyc] = 0; ++nyc; }
+        } else {
+            if (qy >= 1) { vyp[nyp] = qy; qyp[nyp] = ry + P - 1; ++nyp; }
+            if (qy + 1 <= npy) { vyp[nyp] = qy + 1; qyp[nyp] = ry - 1; ++nyp; }
+            cyc[nyc] = qy; byc[nyc] = ry; ++nyc;
+        }
+        const int qz = Z / P, rz = Z - qz * P;
+        if (rz == 0) {
+            if (qz >= 1 && qz <= n2 - 1) { vzp[nzp] = qz; qzp[nzp] = P - 1; ++nzp; }
+            if (qz >= 1) { czc[nzc] = qz - 1; bzc[nzc] = P; ++nzc; }
+            if (qz <= n2 - 1) { czc[nzc] = qz; bzc[nzc] = 0; ++nzc; }
+        } else {
+            if (qz >= 1) { vzp[nzp] = qz; qzp[nzp] = rz + P - 1; ++nzp; }
+            if (qz + 1 <= n2 - 1) { vzp[nzp] = qz + 1; qzp[nzp] = rz - 1; ++nzp; }
+            czc[nzc] = qz; bzc[nzc] = rz; ++nzc;
+        }
+    }
+    // run of the x-combined buffer for each (z, y) patch pair (uniform)
+    size_t rbase[2][2];
+#pragma unroll
+    for (int tz = 0; tz < 2; ++tz)
+#pragma unroll
+        for (int ty = 0; ty < 2; ++ty) {
+            const bool ok = tz < nzp && ty < nyp;
+            const int prow = ok ? (vyp[ty] - 1) + npy * (vzp[tz] - 1) : 0;
+            const int ln = ok ? qyp[ty] + nP * qzp[tz] : 0;
+            rbase[tz][ty] = ((size_t)prow * nP2 + ln) * RL;
+        }
+    for (int i0 = 0; i0 < n0; i0 += 64) {
+        const int i = i0 + lane;
+        const bool in = i < n0;
+#pragma unroll
+        for (int a = 0; a < P; ++a) {                      // node X = i P + a
+            const int X = i * P + a;
+            // tiles holding X: the last one starting at or before X, and its
+            // predecessor when X is in their overlap (ascending order)
+            int thi = (X - 1) / (CBP * P);
+            thi = thi < ntx - 1 ? thi : ntx - 1;
+            const int shi = X - (thi * CBP * P + 1);
+            const bool two = thi >= 1 && shi <= P - 2;
+            const bool xin = in && X >= 1 && X <= npx * P + P - 1;   // X is strictly inside the patch range
+            const size_t ohi = (size_t)thi * SPAN + shi;
+            const size_t olo = (size_t)(thi - 1) * SPAN + (shi + CBP * P);
+            C sum = 0;
+#pragma unroll
+            for (int tz = 0; tz < 2; ++tz) {
+#pragma unroll
+                for (int ty = 0; ty < 2; ++ty) {
+                    const bool ok = xin && tz < nzp && ty < nyp;
+                    const C vlo = xb[ok && two ? rbase[tz][ty] + olo : 0];
+                    const C vhi = xb[ok ? rbase[tz][ty] + ohi : 0];
+                    sum = ok && two ? sum + vlo : sum;
+                    sum = ok ? sum + vhi : sum;
+                }
+            }
+            if (!in) continue;
+#pragma unroll
+            for (int cz = 0; cz < 2; ++cz) {
+                if (cz >= nzc) break;
+#pragma unroll
+                for (int cy = 0; cy < 2; ++cy) {
+                    if (cy >= nyc) break;
+                    const int e = i + n0 * (cyc[cy] + n1 * czc[cz]);
+                    const int lyz = N * (byc[cy] + N * bzc[cz]);
+                    S* d0 = z + cell_offset(e, a + lyz, NN);
+                    C o0 = alpha * sum;
+                    if (ACC) o0 = load_as<C>(d0) + o0;
+                    store_from(d0, o0);
+                    if (a == 0 && i >= 1) {                    // the left cell's copy of the node
+                        S* d1 = z + cell_offset(e - 1, P + lyz, NN);
+                        C o1 = alpha * sum;
+                        if (ACC) o1 = load_as<C>(d1) + o1;
+                        store_from(d1, o1);
+                    }
+                    if (i == n0 - 1) {                         // the row's last node: no patch
+                        S* d2 = z + cell_offset(e, P + lyz, NN);
+                        C o2 = alpha * (C)0;
+                        if (ACC) o2 = load_as<C>(d2) + o2;
+                        store_from(d2, o2);
+                    }
+                }
+            }
+        }
+    }
+}
+
 // Assembly into the global-node array: one wavefront per node row (Y, Z),
 // its lanes walking X, so writes are contiguous and the row's y/z copy
 // structure is uniform over the wavefront.  Each node sums its copies in
@@ -2123,16 +2453,71 @@ static hipError_t launch_pi_slabs(int accumulate, ProbEntry e, hipStream_t s, in
     return hipGetLastError();
 }
 
+// Patch inverse for p <= 3 through the x-combined buffer: assembly, the
+// solves with the in-tile x-combine, the combine by global node rows.
+template <int P, typename S>
+static hipError_t launch_pi_xcomb(int accumulate, ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s,
+                                  int gcap) {
+    constexpr int CBP = solve_g_tile<P>();
+    hipError_t err = launch_assemble<P, S>(ents, nprob, d_tab, s, gcap);
+    if (err != hipSuccess) return err;
+    int t1 = 0;
+    for (int i = 0; i < nprob; ++i) {
+        const int npx = ents[i].n[0] - 1, npy = ents[i].n[1] - 1, npz = ents[i].n[2] - 1;
+        ents[i].tile_begin = t1;
+        ents[i].ntiles = (npx > 0 && npy > 0 && npz > 0) ? ((npx + CBP - 1) / CBP) * npy * npz : 0;
+        t1 += ents[i].ntiles;
+    }
+    if (t1 > 0) {
+        LaunchTable Lg{};
+        Lg.nprob = nprob;
+        Lg.total_tiles = t1;
+        err = stage_table(Lg, ents, nprob, d_tab, s);
+        if (err != hipSuccess) return err;
+        TraceSpan ts("pi_solve", P, Prec<S>::id, s);
+        const int grid = (t1 + 7) / 8 * 8;
+        if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_x<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, Lg);
+        else hipLaunchKernelGGL((k_pi_solve_x<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, Lg);
+        err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    int t4 = 0;
+    for (int i = 0; i < nprob; ++i) {
+        const int rows = (ents[i].n[1] * P + 1) * (ents[i].n[2] * P + 1);
+        ents[i].tile_begin = t4;
+        ents[i].ntiles = (rows + 3) / 4;
+        t4 += ents[i].ntiles;
+    }
+    LaunchTable L4{};
+    L4.nprob = nprob;
+    L4.total_tiles = t4;
+    err = stage_table(L4, ents, nprob, d_tab, s);
+    if (err != hipSuccess) return err;
+    TraceSpan ts("pi_combine", P, Prec<S>::id, s);
+    if (nprob > 1) {
+        if (accumulate) hipLaunchKernelGGL((k_pi_combine_x<P, S, CBP, 1, true>), dim3(t4), dim3(256), 0, s, L4);
+        else hipLaunchKernelGGL((k_pi_combine_x<P, S, CBP, 0, true>), dim3(t4), dim3(256), 0, s, L4);
+    } else {
+        if (accumulate) hipLaunchKernelGGL((k_pi_combine_x<P, S, CBP, 1, false>), dim3(t4), dim3(256), 0, s, L4);
+        else hipLaunchKernelGGL((k_pi_combine_x<P, S, CBP, 0, false>), dim3(t4), dim3(256), 0, s, L4);
+    }
+    return hipGetLastError();
+}
+
 template <int P, typename S>
 static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s,
                               const LaunchCfg& cfg) {
     if constexpr (P <= 3) {
         // default by degree and precision only (never by size or launch mix, so
-        // a problem gets the same variant alone and batched): the fused sweep
-        // from the assembled residual for p = 2 in FP64 (measured faster
-        // there), the two launches through the patch buffer otherwise
-        const int dflt = (P == 2 && Prec<S>::id == FEM_F64) ? 2 : 0;
+        // a problem gets the same variant alone and batched): for p = 2, 3 in
+        // FP64 the solves with the in-tile x-combine (the smaller buffer pays
+        // for the combine's traffic there), the two launches through the
+        // patch buffer otherwise (4-byte values: the plain patch buffer is
+        // the faster one)
+        const int dflt = ((P == 2 || P == 3) && Prec<S>::id == FEM_F64) ? 3 : 0;
         const int fused = cfg.pi_fused >= 0 ? cfg.pi_fused : g_pi_fused >= 0 ? g_pi_fused : dflt;
+        if (fused == 3) return launch_pi_xcomb<P, S>(accumulate, ents, nprob, d_tab, s,
+                                                      cfg.grid_cap > 0 ? cfg.grid_cap : kMaxGrid);
         if (fused == 2) return launch_pi_sweep_g<P, S>(accumulate, ents, nprob, d_tab, s);
         if (fused) return launch_pi_sweep<P, S>(accumulate, ents, nprob, d_tab, s);
     }

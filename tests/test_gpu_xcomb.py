@@ -1,0 +1,47 @@
+"""The p <= 3 patch inverse through the x-combined buffer (kernel option
+FEM_OPT_PI_FUSED = 3) against the oracle's additive Schwarz, on meshes whose
+patch rows span one tile, several tiles and a ragged last tile, in every
+precision, for the plain and the accumulating (smoother) form; the output
+is continuous bit for bit."""
+import numpy as np
+import pytest
+
+from oracle import operators, patches, solver
+from tests.gpu_util import check_err, graded, note, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+TOL = {0: 1e-12, 1: 1e-5, 2: 1e-2}
+
+
+@pytest.fixture(scope="module")
+def F():
+    import torch
+    from paper_2607_02335_amd import fem
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    fem.lib()
+    return fem
+
+
+@pytest.mark.parametrize("p,n", [(1, (70, 3, 2)), (2, (5, 4, 3)), (2, (66, 3, 2)), (2, (130, 2, 3)),
+                                 (3, (4, 5, 3)), (3, (34, 3, 3)), (3, (33, 2, 4)), (3, (65, 3, 2)), (3, (2, 2, 2)),
+                                 (3, (97, 2, 2))])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_xcombined_patch_inverse_matches_oracle(F, p, n, prec):
+    note(f"x-combined p={p} n={n} prec={prec}")
+    m, w, rng = graded(p, n, 200 + p)
+    P = F.Problem(p, n, w)
+    rd = P.pack(to_dev(rng.uniform(-1, 1, m.ncells * m.n1 ** 3)), prec)
+    r_glob = operators.scatter(m, to_np(P.unpack(rd)).astype(np.float64))
+    F.set_option(F.OPT_PI_FUSED, 3)
+    try:
+        zd = P.patch_inverse(rd)
+        zs = P.smoother_step(rd, sweeps=2, omega=0.2)
+    finally:
+        F.set_option(F.OPT_PI_FUSED, -1)
+    f = patches.SchwarzFactors(m)
+    z = to_np(P.unpack(zd))
+    check_err(z, f(r_glob)[m.dofs], TOL[prec], f"x-combined p={p} n={n} prec={prec}")
+    np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(zd), prec))), z)
+    ref = solver.smoother(m, r_glob, 2, 0.2, schwarz=f)
+    check_err(to_np(P.unpack(zs)), ref[m.dofs], TOL[prec], f"x-combined smoother p={p} n={n} prec={prec}")
