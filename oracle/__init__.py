@@ -25,6 +25,8 @@ What it computes, each from its plain definition:
   Q_1 space of the same mesh (prolongation by interpolation, Galerkin coarse
   operator, sparse LU): the two-level member of the multigrid family the
   paper's solver is built for (Remark after the equivalence theorem).
+* ``multiblock`` -- multi-block meshes (blocks glued along whole faces in any
+  orientation, Section 4.2): nodes identified geometrically, DSS = G G^T.
 * ``solver``  -- damped Richardson smoothing on additive Schwarz and the
   (flexible) preconditioned conjugate gradient of the paper's Algorithm
   "Communication-Free (F)PCG", run on assembled global vectors, which the
@@ -34,4 +36,4 @@ Readings where the paper is silent (node set, quadrature, Dirichlet
 treatment, damping) are listed in the repository's design notes; the oracle
 follows exactly those readings.
 """
-from . import basis, mesh, element, operators, patches, solver, twolevel  # noqa: F401
+from . import basis, mesh, element, multiblock, operators, patches, solver, twolevel  # noqa: F401

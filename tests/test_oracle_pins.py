@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 import scipy.sparse.linalg as spla
 
-from oracle import basis, element, operators, patches, solver, twolevel
+from oracle import basis, element, multiblock, operators, patches, solver, twolevel
 from oracle.mesh import Mesh
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -466,3 +466,55 @@ def test_two_level_is_exact_for_linear_elements_and_symmetric():
         B[:, t] = T(e)[inner]
     assert np.abs(B - B.T).max() <= 1e-12 * np.abs(B).max()
     assert np.linalg.eigvalsh((B + B.T) / 2).min() > 0
+
+
+# ------------------------------------------------ multi-block DSS (Sec. 4.2)
+def test_multiblock_cube_equals_the_single_mesh():
+    """The cube cut into 2^3 blocks with aligned axes is the 2n^3 mesh: its
+    DSS equals the single-block DSS cell by cell."""
+    p, n = 2, 3
+    mb = multiblock.split_cube(p, n)
+    m = Mesh(p, (2 * n,) * 3)
+    rng = np.random.default_rng(31)
+    v = rng.standard_normal((mb.ncells(), m.n1 ** 3))
+    # block (bx, by, bz), cell (i, j, k) -> big cell (bx n + i, ...)
+    big = []
+    for bz in range(2):
+        for by in range(2):
+            for bx in range(2):
+                for k in range(n):
+                    for j in range(n):
+                        for i in range(n):
+                            big.append((bx * n + i) + 2 * n * ((by * n + j) + 2 * n * (bz * n + k)))
+    big = np.asarray(big)
+    vb = np.zeros((m.ncells, m.n1 ** 3))
+    vb[big] = v
+    np.testing.assert_allclose(mb.dss(v), operators.dss(m, vb)[big], rtol=0, atol=1e-14)
+
+
+def test_multiblock_node_counts_and_multiplicities():
+    """3-star (three blocks around one macro-edge): by inclusion-exclusion
+    3N^3 - 3N^2 + N nodes (N = np+1 per block edge: three shared faces, one
+    line shared by all); a 5-star 5N^3 - 5N^2 + N.  Multiplicities: 3 on the
+    interior of the shared line, 6 at its cell vertices; a randomly oriented
+    split cube has the single mesh's node count and multiplicities of the
+    product form 1, 2, 4, 8."""
+    for k, p, n in ((3, 2, 3), (5, 3, 2)):
+        mb = multiblock.star(p, n, k, twist=True)
+        N = n * p + 1
+        assert mb.nglob() == k * N ** 3 - k * N ** 2 + N
+        mult = mb.dss(np.ones((mb.ncells(), mb.n1 ** 3)))
+        assert set(np.unique(mult).astype(int)) == {1, 2, 4, 8, k, 2 * k}
+    mb = multiblock.split_cube(3, 2, np.random.default_rng(3))
+    assert mb.nglob() == (2 * 2 * 3 + 1) ** 3
+    mult = mb.dss(np.ones((mb.ncells(), mb.n1 ** 3)))
+    assert set(np.unique(mult).astype(int)) == {1, 2, 4, 8}
+    # every copy of a node carries the same assembled value, and the
+    # assembled sum is preserved: sum over nodes of DSS / multiplicity
+    v = np.random.default_rng(4).standard_normal(mult.shape)
+    s = mb.dss(v)
+    ids = mb.cell_node_ids()
+    for g in np.random.default_rng(5).choice(mb.nglob(), 50, replace=False):
+        vals = s[ids == g]
+        assert np.all(vals == vals[0])
+    assert abs((s / mult).sum() - v.sum()) < 1e-10 * np.abs(v).sum()
