@@ -292,6 +292,48 @@ fem_status fem_batch_patch_inverse(fem_batch* B, void* const* r, void* const* z,
  * Synchronises the stream; allocates and frees its own scratch vectors. */
 fem_status fem_batch_autotune(fem_batch* B, int prec, int* choice);
 
+/* ------------------------------------------------- multi-block meshes */
+
+/* Direct stiffness summation on a multi-block mesh (Section 4.2, Algorithm
+ * "Unstructured Inter-Block Summation"): blocks of n[0] x n[1] x n[2] cells
+ * of degree p, each in its own local axes, glued along whole block faces in
+ * any relative orientation (rotations and reflections), so that a block
+ * edge or corner may be shared by any number of blocks.
+ *
+ * fem_mb_create: block_n = int[3 * nblocks] (cells per local direction),
+ * corners = int[8 * nblocks] vertex ids of each block's corners in local
+ * order cx + 2 cy + 4 cz (ids only identify shared corners; no coordinates
+ * are needed).  Two faces with the same four corner ids are glued; their
+ * cell counts along matching directions must agree (FEM_EINVAL otherwise,
+ * and for a face named by more than two blocks).  The plan derives each
+ * glued face's orientation bits and the sharing lists of the nodes on cell
+ * edges and corners of the inter-block skeleton (one representative copy per
+ * block) on the host, uploads them and owns them.
+ * The cell-wise vector of the mesh is the blocks' cell-wise vectors one
+ * after another, block b starting at element fem_mb_block_offset(b), each in
+ * the library's layout; fem_mb_pack/fem_mb_unpack convert from/to canonical
+ * order (blocks in order, [cell][local node] within each). */
+typedef struct fem_mb_plan fem_mb_plan;
+fem_status fem_mb_create(int p, int nblocks, const int* block_n, const int* corners, void* stream,
+                         fem_mb_plan** out);
+fem_status fem_mb_destroy(fem_mb_plan* M);
+size_t fem_mb_cell_len(const fem_mb_plan* M);
+size_t fem_mb_block_offset(const fem_mb_plan* M, int block);
+fem_status fem_mb_pack(fem_mb_plan* M, const double* canon, void* v_cell, int prec);
+fem_status fem_mb_unpack(fem_mb_plan* M, const void* v_cell, double* canon, int prec);
+/* v <- S v in place, S = G G^T of the multi-block mesh: stage 1 (stages & 1)
+ * the structured cascade inside every block (three axis passes per block),
+ * stage 2 (stages & 2) the inter-block skeleton in three launches on
+ * disjoint copies: cell-face interiors (one pairwise exchange per node, the
+ * index on the far side computed from the face orientation bits), cell-edge
+ * interiors and cell corners (one representative per block summed, the sum
+ * written to every copy).  stages = 3 is the whole summation; stage 2
+ * alone assumes stage 1 has run.  Asynchronous on the plan's stream. */
+fem_status fem_mb_dss(fem_mb_plan* M, void* v_cell, int prec, int stages);
+/* out[0..n): glued faces, face-pass threads, line entities, widest line
+ * sharing list, vertex entities, widest vertex sharing list. */
+fem_status fem_mb_stats(const fem_mb_plan* M, int* out, int n);
+
 /* ---------------------------------------------------- solve server */
 
 typedef struct fem_server fem_server;

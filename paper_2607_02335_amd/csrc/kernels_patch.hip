@@ -1270,11 +1270,13 @@ __global__ void __launch_bounds__(256) k_pi_combine_x(LaunchTable L) {
             const int X = i * P + a;
             // tiles holding X: the last one starting at or before X, and its
             // predecessor when X is in their overlap (ascending order)
-            int thi = (X - 1) / (CBP * P);
+            int thi = X >= 1 ? (X - 1) / (CBP * P) : 0;
             thi = thi < ntx - 1 ? thi : ntx - 1;
+            thi = thi > 0 ? thi : 0;
             const int shi = X - (thi * CBP * P + 1);
             const bool two = thi >= 1 && shi <= P - 2;
-            const bool xin = in && X >= 1 && X <= npx * P + P - 1;   // X is strictly inside the patch range
+            // X is strictly inside the range of some patch (none when npx = 0)
+            const bool xin = in && npx >= 1 && X >= 1 && X <= npx * P + P - 1;
             const size_t ohi = (size_t)thi * SPAN + shi;
             const size_t olo = (size_t)(thi - 1) * SPAN + (shi + CBP * P);
             C sum = 0;

@@ -617,24 +617,27 @@ hipError_t run_extract(fem_problem* P, const void* uc, double* ug, int prec) {
     return run_to_global(P, uc, ug, prec, 1);
 }
 
-hipError_t run_pack(fem_problem* P, const double* canon, void* vc, int prec, int unpack) {
-    ProbEntry e = entry_of(P);
-    const int N = P->p + 1;
-    const size_t n = (size_t)P->ncells * N * N * N;
+hipError_t run_pack_entry(ProbEntry e, const double* canon, void* vc, int prec, int unpack, hipStream_t st) {
+    const int N = e.p + 1;
+    const size_t n = (size_t)e.ncells * N * N * N;
     if (unpack) e.a = vc; else e.c = vc;
     return dispatch_prec(prec, [&](auto tag) {
         using S = decltype(tag);
         hipError_t err = hipSuccess;
         if (!unpack) {      // padding entries must be zero
-            hipLaunchKernelGGL((k_fill_zero<S>), dim3(grid_for(P->cell_len)), dim3(256), 0, P->stream,
-                               static_cast<S*>(vc), P->cell_len);
+            hipLaunchKernelGGL((k_fill_zero<S>), dim3(grid_for(e.len)), dim3(256), 0, st, static_cast<S*>(vc), e.len);
             err = hipGetLastError();
             if (err != hipSuccess) return err;
         }
-        hipLaunchKernelGGL((k_pack<S>), dim3(grid_for(n)), dim3(256), 0, P->stream, e, canon,
-                           const_cast<double*>(canon), unpack);
+        if (n == 0) return hipSuccess;
+        hipLaunchKernelGGL((k_pack<S>), dim3(grid_for(n)), dim3(256), 0, st, e, canon, const_cast<double*>(canon),
+                           unpack);
         return hipGetLastError();
     });
+}
+
+hipError_t run_pack(fem_problem* P, const double* canon, void* vc, int prec, int unpack) {
+    return run_pack_entry(entry_of(P), canon, vc, prec, unpack, P->stream);
 }
 
 template <int P_, typename S>
@@ -643,29 +646,33 @@ static void launch_dss_axis(const ProbEntry& e, int axis, long total, hipStream_
     hipLaunchKernelGGL((k_dss_axis<P_, S>), dim3((total + 255) / 256), dim3(256), 0, s, e, axis, total);
 }
 
-hipError_t run_dss_axis(fem_problem* P, void* v, int axis, int prec) {
-    ProbEntry e = entry_of(P);
-    e.c = v;
-    const int N = P->p + 1;
+hipError_t run_dss_axis_entry(int p, const ProbEntry& e, int axis, int prec, hipStream_t st) {
+    const int N = p + 1;
     long total;
-    if (axis == 0) total = (long)(P->n[0] - 1) * P->n[1] * P->n[2] * N * N;
-    else if (axis == 1) total = (long)P->n[0] * (P->n[1] - 1) * P->n[2] * N * N;
-    else total = (long)P->n[0] * P->n[1] * (P->n[2] - 1) * N * N;
+    if (axis == 0) total = (long)(e.n[0] - 1) * e.n[1] * e.n[2] * N * N;
+    else if (axis == 1) total = (long)e.n[0] * (e.n[1] - 1) * e.n[2] * N * N;
+    else total = (long)e.n[0] * e.n[1] * (e.n[2] - 1) * N * N;
     if (total <= 0) return hipSuccess;
     return dispatch_prec(prec, [&](auto tag) {
         using S = decltype(tag);
-        switch (P->p) {
-            case 1: launch_dss_axis<1, S>(e, axis, total, P->stream); break;
-            case 2: launch_dss_axis<2, S>(e, axis, total, P->stream); break;
-            case 3: launch_dss_axis<3, S>(e, axis, total, P->stream); break;
-            case 4: launch_dss_axis<4, S>(e, axis, total, P->stream); break;
-            case 5: launch_dss_axis<5, S>(e, axis, total, P->stream); break;
-            case 6: launch_dss_axis<6, S>(e, axis, total, P->stream); break;
-            case 7: launch_dss_axis<7, S>(e, axis, total, P->stream); break;
+        switch (p) {
+            case 1: launch_dss_axis<1, S>(e, axis, total, st); break;
+            case 2: launch_dss_axis<2, S>(e, axis, total, st); break;
+            case 3: launch_dss_axis<3, S>(e, axis, total, st); break;
+            case 4: launch_dss_axis<4, S>(e, axis, total, st); break;
+            case 5: launch_dss_axis<5, S>(e, axis, total, st); break;
+            case 6: launch_dss_axis<6, S>(e, axis, total, st); break;
+            case 7: launch_dss_axis<7, S>(e, axis, total, st); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
     });
+}
+
+hipError_t run_dss_axis(fem_problem* P, void* v, int axis, int prec) {
+    ProbEntry e = entry_of(P);
+    e.c = v;
+    return run_dss_axis_entry(P->p, e, axis, prec, P->stream);
 }
 
 static hipError_t finish_reduction(fem_problem* P, const ProbEntry& e, int group, int slot) {

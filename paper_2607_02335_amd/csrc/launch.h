@@ -153,10 +153,14 @@ ProbEntry coarse_entry(fem_problem* P, const void* t, void* z);
 // Single-problem helpers (problem handle in, stream of the handle).
 ProbEntry entry_of(const fem_problem* P);
 hipError_t run_dss_axis(fem_problem* P, void* v, int axis, int prec);
+// The same axis pass on the mesh of an entry (e.n, e.c = vector).
+hipError_t run_dss_axis_entry(int p, const ProbEntry& e, int axis, int prec, hipStream_t s);
 hipError_t run_gather(fem_problem* P, const double* xg, void* xc, int prec);
 hipError_t run_scatter(fem_problem* P, const void* yc, double* yg, int prec);
 hipError_t run_extract(fem_problem* P, const void* uc, double* ug, int prec);
 hipError_t run_pack(fem_problem* P, const double* canon, void* vc, int prec, int unpack);
+// The same for the mesh of an entry (e.p, e.ncells, e.len).
+hipError_t run_pack_entry(ProbEntry e, const double* canon, void* vc, int prec, int unpack, hipStream_t s);
 hipError_t run_convert(fem_problem* P, const void* src, int sp, void* dst, int dp);
 hipError_t run_fill_zero(fem_problem* P, void* v, int prec);
 // Dot product of two cell vectors into slot `slot` of the problem's

@@ -98,6 +98,14 @@ def lib():
         "fem_server_memory": ([vp, ct.POINTER(sz), ct.POINTER(sz)], i),
         "fem_server_finished": ([vp, ct.POINTER(ct.c_uint64), i], i),
         "fem_server_stats": ([vp, ct.POINTER(d), i], i),
+        "fem_mb_create": ([i, i, vp, vp, vp, pp], i),
+        "fem_mb_destroy": ([vp], i),
+        "fem_mb_cell_len": ([vp], sz),
+        "fem_mb_block_offset": ([vp, i], sz),
+        "fem_mb_pack": ([vp, vp, vp, i], i),
+        "fem_mb_unpack": ([vp, vp, vp, i], i),
+        "fem_mb_dss": ([vp, vp, i, i], i),
+        "fem_mb_stats": ([vp, ct.POINTER(i), i], i),
         "fem_host_1d_matrices": ([i, vp, vp], i),
         "fem_host_fd_1d": ([i, d, d, vp, vp], i),
         "fem_host_gll_nodes": ([i, vp], i),
@@ -641,3 +649,64 @@ class Server:
         a, b = ct.c_size_t(), ct.c_size_t()
         check(lib().fem_server_memory(self.h, ct.byref(a), ct.byref(b)), "fem_server_memory")
         return a.value, b.value
+
+
+class MultiBlockDss:
+    """DSS on a multi-block mesh: blocks glued along whole faces in any
+    orientation (structured cascade per block, then the inter-block
+    skeleton)."""
+
+    def __init__(self, p, block_n, corners):
+        bn = np.ascontiguousarray(np.asarray(block_n, dtype=np.int32).ravel())
+        cs = np.ascontiguousarray(np.asarray(corners, dtype=np.int32).ravel())
+        if bn.size % 3 or cs.size != 8 * (bn.size // 3):
+            raise ValueError("block_n needs 3 and corners 8 entries per block")
+        self.p = int(p)
+        self.nb = bn.size // 3
+        self.block_n = bn.reshape(-1, 3)
+        h = ct.c_void_p()
+        check(lib().fem_mb_create(self.p, self.nb, bn.ctypes.data, cs.ctypes.data, _stream(), ct.byref(h)),
+              "fem_mb_create")
+        self.h = h
+        self.cell_len = lib().fem_mb_cell_len(self.h)
+        self.canon_len = int(sum(int(np.prod(n)) for n in self.block_n)) * (self.p + 1) ** 3
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().fem_mb_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, canon, prec=F64):
+        _check_vec(canon, self.canon_len, F64, "canon")
+        _require_cuda(canon)
+        torch = _torch()
+        out = torch.zeros(self.cell_len, dtype=torch_dtype(prec), device="cuda")
+        check(lib().fem_mb_pack(self.h, _ptr(canon), _ptr(out), prec), "fem_mb_pack")
+        return out
+
+    def unpack(self, v):
+        _check_vec(v, self.cell_len, None, "v")
+        _require_cuda(v)
+        torch = _torch()
+        out = torch.empty(self.canon_len, dtype=torch.float64, device="cuda")
+        check(lib().fem_mb_unpack(self.h, _ptr(v), _ptr(out), prec_of(v)), "fem_mb_unpack")
+        return out
+
+    def dss(self, v, stages=3):
+        """In place: v <- S v."""
+        _check_vec(v, self.cell_len, None, "v")
+        _require_cuda(v)
+        check(lib().fem_mb_dss(self.h, _ptr(v), prec_of(v), stages), "fem_mb_dss")
+        return v
+
+    def stats(self):
+        out = (ct.c_int * 6)()
+        check(lib().fem_mb_stats(self.h, out, 6), "fem_mb_stats")
+        keys = ("faces", "face_threads", "lines", "line_width", "vertices", "vertex_width")
+        return dict(zip(keys, list(out)))

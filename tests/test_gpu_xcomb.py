@@ -45,3 +45,22 @@ def test_xcombined_patch_inverse_matches_oracle(F, p, n, prec):
     np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(zd), prec))), z)
     ref = solver.smoother(m, r_glob, 2, 0.2, schwarz=f)
     check_err(to_np(P.unpack(zs)), ref[m.dofs], TOL[prec], f"x-combined smoother p={p} n={n} prec={prec}")
+
+
+@pytest.mark.parametrize("p,n", [(3, (1, 4, 3)), (2, (4, 1, 3)), (3, (3, 4, 1)), (2, (1, 1, 1))])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_xcombined_without_interior_vertices(F, p, n, prec):
+    """A mesh with one cell along a direction has no patch: the x-combined
+    path returns exactly zero and leaves no copy unwritten."""
+    note(f"x-combined degenerate p={p} n={n} prec={prec}")
+    m, w, rng = graded(p, n, 230 + p)
+    P = F.Problem(p, n, w)
+    rd = P.pack(to_dev(rng.uniform(-1, 1, m.ncells * m.n1 ** 3)), prec)
+    z0 = P.cell_vector(prec)
+    z0.fill_(7.0)
+    F.set_option(F.OPT_PI_FUSED, 3)
+    try:
+        P.patch_inverse(rd, z0)
+    finally:
+        F.set_option(F.OPT_PI_FUSED, -1)
+    assert not np.any(to_np(z0))
