@@ -373,6 +373,39 @@ def paper_kernels(fem, torch, reps=10, n_dss=128, degrees=(2, 3, 7)):
     return out
 
 
+def layout_sweep(fem, torch, reps=5, blocks=(1, 2, 4, 8, 16, 32, 64, 128)):
+    """The layout study (block size B of the blocked element-fastest layout,
+    FP64, uniform unit-cube meshes of about 1e8 cell DoFs): volumetric mass
+    apply (best of two tile shapes) and structured DSS, in unique DoFs per
+    second, per degree and B."""
+    sizes = {2: 160, 3: 128, 4: 96, 5: 80}
+    out = {}
+    tm = Timer(torch)
+    for p, n in sizes.items():
+        u, c = unique_dofs(p, n), cell_dofs(p, n)
+        canon = torch.rand(c, dtype=torch.float64, device="cuda")
+        rows = []
+        for B in blocks:
+            L = fem.LayoutStudy(p, n, B)
+            xs = [L.pack(canon), L.pack(canon)]
+            ys = [L.vector(), L.vector()]
+            best = None
+            for tile in (16, 32):
+                L.mass(xs[0], ys[0], tile=tile)
+                t = tm.time(lambda i: L.mass(xs[i % 2], ys[i % 2], tile=tile), reps)
+                best = (t, tile) if best is None or t < best[0] else best
+            L.dss(ys[0])
+            t_dss = tm.time(lambda i: L.dss(ys[i % 2]), reps)
+            rows.append(dict(B=B, mass_s=best[0], mass_tile=best[1], mass_unique_gdofs=u / best[0] / 1e9,
+                             mass_gbs=2 * 8 * c / best[0] / 1e9, dss_s=t_dss, dss_unique_gdofs=u / t_dss / 1e9,
+                             dss_gbs=op_bytes("dss", p, n) / t_dss / 1e9))
+            del xs, ys
+        out[f"q{p}_{n}"] = rows
+        del canon
+        torch.cuda.empty_cache()
+    return out
+
+
 def batch_times(fem, torch, steps, warmup, count=256, seed=3):
     """256 independent problems (p uniform in {2,3,7}, n uniform in [4,32],
     seed 3): FP32 apply + patch inverse of all of them, one launch per degree
@@ -482,7 +515,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--mode", default="bench", choices=["bench", "calib", "serve"])
     ap.add_argument("--quick", action="store_true", help="headline workload only")
-    ap.add_argument("--only", choices=["q2_96", "q7_24", "q7_solve", "batch_256", "paper_kernels"], default=None,
+    ap.add_argument("--only", choices=["q2_96", "q7_24", "q7_solve", "batch_256", "paper_kernels", "layout"], default=None,
                     help="run one secondary workload alone (for profiling) and print its record")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--solve-reps", type=int, default=5)
@@ -523,6 +556,8 @@ def main():
             rec = batch_times(fem, torch, a.steps, a.warmup)
         elif a.only == "paper_kernels":
             rec = paper_kernels(fem, torch)
+        elif a.only == "layout":
+            rec = layout_sweep(fem, torch)
         else:
             p, n = (2, 96) if a.only == "q2_96" else (7, 24)
             prec = {"f64": fem.F64, "f32": fem.F32, "bf16": fem.BF16}[a.prec]
@@ -544,6 +579,8 @@ def main():
         extra["batch_256"] = batch_times(fem, torch, a.steps, a.warmup)
         log("mass operator, structured DSS, assembled mass at 128^3")
         extra["paper_kernels"] = paper_kernels(fem, torch)
+        log("layout study: block size sweep")
+        extra["layout_sweep"] = layout_sweep(fem, torch)
         if a.serve_requests > 0:
             from paper_2607_02335_amd import serve
             log(f"serving stream of {a.serve_requests} requests at 200/s")

@@ -334,6 +334,28 @@ fem_status fem_mb_dss(fem_mb_plan* M, void* v_cell, int prec, int stages);
  * sharing list, vertex entities, widest vertex sharing list. */
 fem_status fem_mb_stats(const fem_mb_plan* M, int* out, int n);
 
+/* ------------------------------------------------------- layout study */
+
+/* The storage block size B of the blocked element-fastest layout (Section
+ * 5.1) swept over powers of two, for the study of Section 6.1 ("Layout
+ * study", Figure "Block-size sweep"): cell e's local node l sits at
+ * (e / B) (p+1)^3 B + l B + e % B (the library's own vectors use B = 64).
+ * FP64 device vectors, a uniform mesh of the unit cube with n[3] cells,
+ * degrees 2..5, B in {1, 2, ..., 128}; FEM_EINVAL otherwise.  All
+ * asynchronous on `stream`.
+ * fem_layout_len: elements of such a vector (whole blocks).
+ * fem_layout_pack: canonical [cell][local node] (ncells (p+1)^3 values) ->
+ *   layout B (padding zeroed), or back when unpack != 0.
+ * fem_layout_mass: y = M x per cell, the volumetric mass operator (Eq. "mass
+ *   operator", no boundary conditions), `tile` = 16 or 32 cells staged in
+ *   LDS per workgroup tile (the launch shape of the sweep).
+ * fem_layout_dss: v <- G G^T v in place by the three structured axis passes
+ *   (Algorithm "Dimensionally-Split Structured Summation"). */
+size_t fem_layout_len(int p, const int* n, int B);
+fem_status fem_layout_pack(int p, const int* n, int B, const double* src, double* dst, int unpack, void* stream);
+fem_status fem_layout_mass(int p, const int* n, int B, int tile, const double* x, double* y, void* stream);
+fem_status fem_layout_dss(int p, const int* n, int B, double* v, void* stream);
+
 /* ---------------------------------------------------- solve server */
 
 typedef struct fem_server fem_server;

@@ -33,7 +33,7 @@ COMMON = [
 
 SOURCES = [
     "host_setup.cpp", "api.cpp", "batch.cpp", "trace.cpp",
-    "kernels_apply.hip", "kernels_vec.hip", "kernels_patch.hip", "kernels_coarse.hip", "multiblock.hip",
+    "kernels_apply.hip", "kernels_vec.hip", "kernels_patch.hip", "kernels_coarse.hip", "multiblock.hip", "layout.hip",
 ]
 
 

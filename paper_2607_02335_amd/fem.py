@@ -106,6 +106,10 @@ def lib():
         "fem_mb_unpack": ([vp, vp, vp, i], i),
         "fem_mb_dss": ([vp, vp, i, i], i),
         "fem_mb_stats": ([vp, ct.POINTER(i), i], i),
+        "fem_layout_len": ([i, vp, i], sz),
+        "fem_layout_pack": ([i, vp, i, vp, vp, i, vp], i),
+        "fem_layout_mass": ([i, vp, i, i, vp, vp, vp], i),
+        "fem_layout_dss": ([i, vp, i, vp, vp], i),
         "fem_host_1d_matrices": ([i, vp, vp], i),
         "fem_host_fd_1d": ([i, d, d, vp, vp], i),
         "fem_host_gll_nodes": ([i, vp], i),
@@ -710,3 +714,51 @@ class MultiBlockDss:
         check(lib().fem_mb_stats(self.h, out, 6), "fem_mb_stats")
         keys = ("faces", "face_threads", "lines", "line_width", "vertices", "vertex_width")
         return dict(zip(keys, list(out)))
+
+
+class LayoutStudy:
+    """FP64 vectors of a uniform mesh in the blocked layout with block size B
+    (the layout study): pack/unpack, mass apply, structured DSS."""
+
+    def __init__(self, p, n, B):
+        self.p, self.B = int(p), int(B)
+        self.n = (n, n, n) if isinstance(n, int) else tuple(int(v) for v in n)
+        self._n = (ct.c_int * 3)(*self.n)
+        self.len = lib().fem_layout_len(self.p, self._n, self.B)
+        if self.len == 0:
+            raise ValueError("layout study: p in 2..5, n >= 1, B a power of two <= 128")
+        self.canon_len = self.n[0] * self.n[1] * self.n[2] * (self.p + 1) ** 3
+
+    def vector(self):
+        torch = _torch()
+        return torch.zeros(self.len, dtype=torch.float64, device="cuda")
+
+    def pack(self, canon):
+        _check_vec(canon, self.canon_len, F64, "canon")
+        _require_cuda(canon)
+        out = self.vector()
+        check(lib().fem_layout_pack(self.p, self._n, self.B, _ptr(canon), _ptr(out), 0, _stream()), "fem_layout_pack")
+        return out
+
+    def unpack(self, v):
+        _check_vec(v, self.len, F64, "v")
+        _require_cuda(v)
+        torch = _torch()
+        out = torch.empty(self.canon_len, dtype=torch.float64, device="cuda")
+        check(lib().fem_layout_pack(self.p, self._n, self.B, _ptr(v), _ptr(out), 1, _stream()), "fem_layout_pack")
+        return out
+
+    def mass(self, x, y=None, tile=32):
+        _check_vec(x, self.len, F64, "x")
+        if y is not None:
+            _check_vec(y, self.len, F64, "y")
+        _require_cuda(x, y)
+        y = self.vector() if y is None else y
+        check(lib().fem_layout_mass(self.p, self._n, self.B, tile, _ptr(x), _ptr(y), _stream()), "fem_layout_mass")
+        return y
+
+    def dss(self, v):
+        _check_vec(v, self.len, F64, "v")
+        _require_cuda(v)
+        check(lib().fem_layout_dss(self.p, self._n, self.B, _ptr(v), _stream()), "fem_layout_dss")
+        return v
