@@ -408,9 +408,11 @@ def layout_sweep(fem, torch, reps=5, blocks=(1, 2, 4, 8, 16, 32, 64, 128)):
 
 def batch_times(fem, torch, steps, warmup, count=256, seed=3):
     """256 independent problems (p uniform in {2,3,7}, n uniform in [4,32],
-    seed 3): FP32 apply + patch inverse of all of them, one launch per degree
-    and operation, with the autotuned kernel shapes.  Rate = unique DoFs of
-    the whole batch per second of one pass."""
+    seed 3): FP32 apply + patch inverse of all of them.  Timed both ways:
+    one mixed-degree launch per kernel phase (default shapes), and one
+    launch per degree with the autotuned shapes; the rate is that of the way
+    the autotuner keeps.  Rate = unique DoFs of the whole batch per second of
+    one pass."""
     import synth
     wls = synth.batch_problems(count=count, seed=seed)
     B = fem.Batch([(w.p, w.n, None) for w in wls])
@@ -418,23 +420,34 @@ def batch_times(fem, torch, steps, warmup, count=256, seed=3):
     ys = [P.cell_vector(fem.F32) for P in B.problems]
     zs = [P.cell_vector(fem.F32) for P in B.problems]
     choice = B.autotune(fem.F32)
+    kept = B.mixed
 
     def step(i):
         B.apply(xs, ys)
         B.patch_inverse(ys, zs)
 
-    for i in range(warmup):
-        step(i)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(steps):
-        step(i)
-    torch.cuda.synchronize()
-    t = (time.perf_counter() - t0) / steps
+    def timed():
+        for i in range(warmup):
+            step(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            step(i)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    ways = {}
+    for mixed in (True, False):
+        B.set_mixed(mixed)
+        ways["mixed" if mixed else "per_degree"] = timed()
+    B.set_mixed(kept)
+    t = ways["mixed" if kept else "per_degree"]
     uniq = sum(unique_dofs(w.p, w.n[0]) for w in wls)
     cell = sum(cell_dofs(w.p, w.n[0]) for w in wls)
     out = dict(problems=count, unique_dofs=uniq, cell_dofs=cell, s_per_pass=t,
                unique_gdofs=uniq / t / 1e9, cell_gdofs=cell / t / 1e9,
+               launches="mixed" if kept else "per_degree",
+               s_per_pass_mixed=ways["mixed"], s_per_pass_per_degree=ways["per_degree"],
                autotuned={str(k): v for k, v in choice.items()})
     del xs, ys, zs
     B.close()

@@ -267,8 +267,14 @@ size_t fem_noalloc_scratch_bytes(void);
 
 typedef struct fem_batch fem_batch;
 
-/* A batch of independent problems sharing one stream; batched calls run
- * every problem of one degree in a single persistent launch. */
+/* A batch of independent problems sharing one stream.  Batched calls run
+ * every kernel phase either as one launch per degree present (each covering
+ * all problems of that degree), or, when the degrees are two or three of
+ * {2, 3, 7}, as one mixed-degree launch per phase: a grid whose workgroups
+ * each run one item (one workgroup's work of that degree's own kernel) of
+ * one degree.  Mixed launches use the default kernel shapes, so every
+ * problem's result equals its single-problem call bit for bit; they are the
+ * default until fem_batch_autotune decides (see there). */
 fem_status fem_batch_create(int count, const fem_desc* descs, void* stream, fem_batch** out);
 fem_status fem_batch_destroy(fem_batch* B);
 /* Borrow problem i of the batch (owned by the batch) for per-problem calls. */
@@ -289,8 +295,16 @@ fem_status fem_batch_patch_inverse(fem_batch* B, void* const* r, void* const* z,
  * NULL): int[14], choice[2(p-1)] = apply candidate index, choice[2(p-1)+1]
  * = patch-inverse candidate index of degree p, candidates in the order
  * listed with the grid cap varying fastest (untouched for absent degrees).
+ * Where mixed-degree launches are possible it then times a whole pass
+ * (apply + patch inverse) with the tuned per-degree launches and with the
+ * mixed launches and keeps the faster (fem_batch_mixed reports which).
  * Synchronises the stream; allocates and frees its own scratch vectors. */
 fem_status fem_batch_autotune(fem_batch* B, int prec, int* choice);
+/* mixed = 1: mixed-degree launches where the batch's degrees allow them;
+ * 0: one launch per degree (with the autotuned shapes). */
+fem_status fem_batch_set_mixed(fem_batch* B, int mixed);
+/* 1 if the batch's calls currently run as mixed-degree launches. */
+int fem_batch_mixed(const fem_batch* B);
 
 /* ------------------------------------------------- multi-block meshes */
 
@@ -384,11 +398,18 @@ fem_status fem_server_destroy(fem_server* S);
  * budget, FEM_OK otherwise (it is admitted when memory and a slot free up). */
 fem_status fem_server_submit(fem_server* S, const fem_desc* desc, const double* f_glob,
                              double rtol, int maxit, uint64_t* ticket);
-/* Admit queued requests that fit, then advance every active solve by one
- * iteration (one batched launch per degree and kernel), retire converged
- * ones.  n_active/n_queued/n_done (may be NULL) report the counts after the
- * step. */
+/* Admit queued requests that fit, then advance every active solve by at
+ * least one iteration (a solve smaller than the largest active one takes up
+ * to 8, as many as its size fits into the largest one's), every kernel phase
+ * as one launch over all active solves (mixed-degree launches, see
+ * fem_batch_create, or one launch per degree), retire converged ones.
+ * n_active/n_queued/n_done (may be NULL) report the counts after the step. */
 fem_status fem_server_step(fem_server* S, int* n_active, int* n_queued, int* n_done);
+/* mixed = 1 (the default): the step's degree-dependent kernels run as
+ * mixed-degree launches where the active degrees allow; 0: one launch per
+ * degree.  Results are the same either way.  May be called from any thread;
+ * takes effect at the next step. */
+fem_status fem_server_set_mixed(fem_server* S, int mixed);
 /* FEM_OK and the solution (global order, host double[global_len]; may be
  * NULL) if the ticket's solve has finished; FEM_EAGAIN if not yet;
  * FEM_ENOTFOUND for an unknown or already collected ticket. */

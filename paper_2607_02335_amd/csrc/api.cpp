@@ -31,6 +31,9 @@ fem_status check_desc(const fem_desc* d) {
                     return set_error(FEM_EINVAL, "cell widths must be positive and finite");
     }
     if (d->bc != FEM_BC_DIRICHLET && d->bc != FEM_BC_NEUMANN) return set_error(FEM_EINVAL, "unknown bc");
+    // the p >= 4 patch solves address a patch's box with 32-bit offsets
+    if (d->p >= 4 && (unsigned long long)(d->n[0] * d->p + 1) * (d->n[1] * d->p + 1) * (2 * d->p - 1) >= (1ULL << 32))
+        return set_error(FEM_EINVAL, "mesh too wide: (n0 p + 1)(n1 p + 1)(2p - 1) must stay below 2^32 for p >= 4");
     return FEM_OK;
 }
 

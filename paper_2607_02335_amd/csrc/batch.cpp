@@ -1,13 +1,15 @@
 // Batched launches over independent problems, the tile-shape autotuner, and
 // the continuous-batching solve server.
 //
-// Batches group their problems by degree: one launch per degree covers every
-// problem of that degree (the kernels walk a concatenated tile range and find
-// each tile's problem in a device table).  The server keeps every admitted
-// solve's vectors and scalars on the device and advances all of them by one
-// (F)PCG iteration per step with those batched launches; requests are
-// admitted in arrival order as slots and device memory free up.
+// A batched launch covers many problems: one launch per degree (the kernels
+// walk a concatenated tile range and find each tile's problem in a device
+// table), or, for the degrees 2, 3 and 7, one mixed-degree launch per phase
+// whose workgroups each run one degree's kernel body.  The server keeps every
+// admitted solve's vectors and scalars on the device and advances all of
+// them with such launches; requests are admitted in arrival order as slots
+// and device memory free up.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -54,8 +56,20 @@ struct fem_batch {
     std::vector<int> group[kMaxP + 1];
     LaunchCfg cfg_apply[kMaxP + 1];
     LaunchCfg cfg_pi[kMaxP + 1];
+    int mixed = 1;          // mixed-degree launches (default kernel shapes) where the degrees allow
     TableStager st;
 };
+
+// The batch's degrees allow a mixed launch: two or three of {2, 3, 7} and no other.
+static bool batch_mixable(const fem_batch* B) {
+    int present = 0;
+    for (int p = 1; p <= kMaxP; ++p) {
+        if (B->group[p].empty()) continue;
+        if (p != 2 && p != 3 && p != 7) return false;
+        ++present;
+    }
+    return present >= 2;
+}
 
 extern "C" fem_status fem_batch_create(int count, const fem_desc* descs, void* stream, fem_batch** out) {
     if (!out) return set_error(FEM_EINVAL, "out is NULL");
@@ -109,6 +123,17 @@ extern "C" fem_status fem_batch_problem(fem_batch* B, int i, fem_problem** out) 
 
 static fem_status batch_apply_cfg(fem_batch* B, void* const* x, void* const* y, int prec, const LaunchCfg* cfgs) {
     std::vector<ProbEntry> ents;
+    if (B->mixed && batch_mixable(B)) {
+        for (int i = 0; i < B->count; ++i) {
+            if (!x[i] || !y[i] || x[i] == y[i]) return set_error(FEM_EINVAL, "fem_batch_apply: bad vector pointers");
+            ProbEntry e = entry_of(B->probs[i]);
+            e.a = x[i];
+            e.c = y[i];
+            ents.push_back(e);
+        }
+        FEM_HIP(launch_apply_any(prec, 0, ents.data(), (int)ents.size(), &B->st, B->stream), "fem_batch_apply");
+        return FEM_OK;
+    }
     for (int p = 1; p <= kMaxP; ++p) {
         if (B->group[p].empty()) continue;
         ents.clear();
@@ -127,6 +152,15 @@ static fem_status batch_apply_cfg(fem_batch* B, void* const* x, void* const* y, 
 
 static fem_status batch_pi_cfg(fem_batch* B, void* const* r, void* const* z, int prec, const LaunchCfg* cfgs) {
     std::vector<ProbEntry> ents;
+    if (B->mixed && batch_mixable(B)) {
+        for (int i = 0; i < B->count; ++i) {
+            if (!r[i] || !z[i] || r[i] == z[i]) return set_error(FEM_EINVAL, "fem_batch_patch_inverse: bad pointers");
+            ents.push_back(pi_entry(B->probs[i], r[i], z[i], prec, 1.0));
+        }
+        FEM_HIP(launch_patch_inverse_any(prec, 0, ents.data(), (int)ents.size(), &B->st, B->stream),
+                "fem_batch_patch_inverse");
+        return FEM_OK;
+    }
     for (int p = 1; p <= kMaxP; ++p) {
         if (B->group[p].empty()) continue;
         ents.clear();
@@ -139,6 +173,14 @@ static fem_status batch_pi_cfg(fem_batch* B, void* const* r, void* const* z, int
     }
     return FEM_OK;
 }
+
+extern "C" fem_status fem_batch_set_mixed(fem_batch* B, int mixed) {
+    if (!B) return set_error(FEM_EINVAL, "fem_batch_set_mixed: NULL batch");
+    B->mixed = mixed ? 1 : 0;
+    return FEM_OK;
+}
+
+extern "C" int fem_batch_mixed(const fem_batch* B) { return B && B->mixed && batch_mixable(B) ? 1 : 0; }
 
 extern "C" fem_status fem_batch_apply(fem_batch* B, void* const* x, void* const* y, int prec) {
     if (!B || !x || !y) return set_error(FEM_EINVAL, "fem_batch_apply: NULL argument");
@@ -175,6 +217,7 @@ extern "C" fem_status fem_batch_autotune(fem_batch* B, int prec, int* choice) {
     hipEventCreate(&e0);
     hipEventCreate(&e1);
     fem_status result = FEM_OK;
+    B->mixed = 0;                 // per-degree shapes are tuned with one launch per degree
     for (int p = 1; p <= kMaxP && result == FEM_OK; ++p) {
         if (B->group[p].empty()) continue;
         for (int which = 0; which < 2 && result == FEM_OK; ++which) {
@@ -233,6 +276,28 @@ extern "C" fem_status fem_batch_autotune(fem_batch* B, int prec, int* choice) {
             if (choice) choice[2 * (p - 1) + which] = best_i;
         }
     }
+    // then the whole pass (apply + patch inverse): the tuned per-degree
+    // launches against the mixed-degree launches, the faster one is kept
+    if (result == FEM_OK && batch_mixable(B)) {
+        float t[2] = {0.f, 0.f};
+        for (int m = 0; m < 2 && result == FEM_OK; ++m) {
+            B->mixed = m;
+            auto run = [&]() {
+                fem_status st = batch_apply_cfg(B, x.data(), y.data(), prec, B->cfg_apply);
+                return st == FEM_OK ? batch_pi_cfg(B, y.data(), x.data(), prec, B->cfg_pi) : st;
+            };
+            fem_status st = run();
+            hipEventRecord(e0, B->stream);
+            for (int r = 0; r < 3 && st == FEM_OK; ++r) st = run();
+            hipEventRecord(e1, B->stream);
+            hipEventSynchronize(e1);
+            if (st != FEM_OK) result = st;
+            hipEventElapsedTime(&t[m], e0, e1);
+        }
+        B->mixed = t[1] <= t[0] ? 1 : 0;
+    } else {
+        B->mixed = 1;
+    }
     hipStreamSynchronize(B->stream);
     hipEventDestroy(e0);
     hipEventDestroy(e1);
@@ -287,6 +352,7 @@ struct fem_server {
     int sp = FEM_F32, sweeps = 2, variant = FEM_CG_FCG;
     int pc = FEM_PC_SCHWARZ;       // FEM_PC_SCHWARZ or FEM_PC_TWO_LEVEL
     double omega = 0.125;
+    std::atomic<int> mix{1};       // mixed-degree launches (set from any thread)
     hipStream_t stream = nullptr;
     uint64_t next_ticket = 1;
     std::deque<Request> queue;
@@ -429,14 +495,24 @@ extern "C" fem_status fem_server_create_pc(size_t hbm_budget, int max_active, in
     S->omega = omega;
     S->variant = smoother_prec == FEM_F64 ? FEM_CG_PCG : FEM_CG_FCG;
     S->stream = static_cast<hipStream_t>(stream);
-    if (S->st.init(2 * max_active) != hipSuccess ||
-        hipMalloc((void**)&S->d_collect, sizeof(double) * 4 * max_active) != hipSuccess ||
-        hipHostMalloc((void**)&S->h_collect, sizeof(double) * 4 * max_active, hipHostMallocDefault) != hipSuccess ||
-        hipMalloc((void**)&S->arena, hbm_budget) != hipSuccess ||
-        hipEventCreateWithFlags(&S->ev_scalars, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&S->ev_up, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&S->ev_ext, hipEventDisableTiming) != hipSuccess ||
-        hipStreamCreateWithFlags(&S->copy, hipStreamNonBlocking) != hipSuccess) {
+    const char* what = nullptr;
+    hipError_t herr = hipSuccess;
+    if ((herr = S->st.init(2 * max_active)) != hipSuccess) what = "entry tables";
+    else if ((herr = hipMalloc((void**)&S->d_collect, sizeof(double) * 4 * max_active)) != hipSuccess)
+        what = "scalar read-back";
+    else if ((herr = hipHostMalloc((void**)&S->h_collect, sizeof(double) * 4 * max_active, hipHostMallocDefault)) !=
+             hipSuccess)
+        what = "pinned scalar read-back";
+    else if ((herr = hipMalloc((void**)&S->arena, hbm_budget)) != hipSuccess) what = "arena of hbm_budget bytes";
+    else if ((herr = hipEventCreateWithFlags(&S->ev_scalars, hipEventDisableTiming)) != hipSuccess ||
+             (herr = hipEventCreateWithFlags(&S->ev_up, hipEventDisableTiming)) != hipSuccess ||
+             (herr = hipEventCreateWithFlags(&S->ev_ext, hipEventDisableTiming)) != hipSuccess)
+        what = "events";
+    else if ((herr = hipStreamCreateWithFlags(&S->copy, hipStreamNonBlocking)) != hipSuccess) what = "copy stream";
+    if (what) {
+        hipGetLastError();
+        const std::string msg =
+            std::string("fem_server_create: allocation failed (") + what + ": " + hipGetErrorString(herr) + ")";
         S->st.destroy();
         hipFree(S->d_collect);
         if (S->h_collect) hipHostFree(S->h_collect);
@@ -446,7 +522,7 @@ extern "C" fem_status fem_server_create_pc(size_t hbm_budget, int max_active, in
         if (S->ev_ext) hipEventDestroy(S->ev_ext);
         if (S->copy) hipStreamDestroy(S->copy);
         delete S;
-        return set_error(FEM_ENOMEM, "fem_server_create: allocation failed");
+        return set_error(FEM_ENOMEM, msg.c_str());
     }
     S->free_blocks[0] = hbm_budget;
     *out = S;
@@ -764,106 +840,107 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
             reps[i] = (int)std::min<size_t>(kInnerMax, std::max<size_t>(1, maxlen / len));
             kmax = std::max(kmax, reps[i]);
         }
+        const bool mix = S->mix.load(std::memory_order_relaxed) != 0;
         for (int it = 0; it < kmax; ++it) {
-            for (int p = 1; p <= kMaxP; ++p) {
-                std::vector<Active*> g;
-                for (int i = 0; i < na; ++i)
-                    if (S->active[i]->P->p == p && reps[i] > it) g.push_back(S->active[i]);
-                if (g.empty()) continue;
-                const int n = (int)g.size();
-                ents.resize(n);
-                // q = A p, <q,p>, r -= alpha q, residual norm (and the smoother's
-                // copy of r), the convergence test
-                for (int i = 0; i < n; ++i) {
-                    ents[i] = entry_of(g[i]->P);
-                    ents[i].a = g[i]->p;
-                    ents[i].c = g[i]->q;
-                }
-                FEM_HIP(launch_apply(p, FEM_F64, 0, ents.data(), n, &S->st, s), "server apply");
-                for (int i = 0; i < n; ++i) {
-                    ents[i] = entry_of(g[i]->P);
-                    ents[i].a = g[i]->q;
-                    ents[i].b = g[i]->p;
-                }
-                FEM_HIP(launch_dot(FEM_F64, FEM_F64, ents.data(), n, &S->st, s, kSlotQP), "server dot");
-                for (int i = 0; i < n; ++i) {
-                    ents[i] = entry_of(g[i]->P);
-                    ents[i].b = g[i]->q;
-                    ents[i].d = g[i]->r;
-                }
-                FEM_HIP(launch_cg_ur(ents.data(), n, &S->st, s), "server update");
-                for (int i = 0; i < n; ++i) {
-                    ents[i] = entry_of(g[i]->P);
-                    ents[i].a = g[i]->r;
-                    ents[i].c = g[i]->rs;
-                }
-                if (S->sp == FEM_F64) FEM_HIP(launch_anorm(p, ents.data(), n, &S->st, s, kSlotRN), "server norm");
-                else FEM_HIP(launch_distribute(p, S->sp, ents.data(), n, &S->st, s, kSlotRN), "server norm");
-                for (int i = 0; i < n; ++i) ents[i] = entry_of(g[i]->P);
-                FEM_HIP(launch_cg_check(ents.data(), n, &S->st, s), "server convergence");
-                // smoother, pairings and the new direction (with the u step of
-                // this iteration's r update, which completes a finishing solve's u)
-                // z = P(rs): Schwarz sweeps, or for the two-level method
-                // pre-sweeps, the coarse correction and post-sweeps
-                auto residual = [&]() -> fem_status {       // tmp = rs - A z
-                    for (int i = 0; i < n; ++i) {
-                        ents[i] = entry_of(g[i]->P);
-                        ents[i].a = g[i]->z;
-                        ents[i].b = g[i]->rs;
-                        ents[i].c = g[i]->P->d_tmp;
-                    }
-                    FEM_HIP(launch_apply(p, S->sp, 1, ents.data(), n, &S->st, s), "server smoother residual");
-                    return FEM_OK;
-                };
-                auto sweep_acc = [&]() -> fem_status {      // z += omega P_AS tmp
-                    for (int i = 0; i < n; ++i) ents[i] = pi_entry(g[i]->P, g[i]->P->d_tmp, g[i]->z, S->sp, S->omega);
-                    FEM_HIP(launch_patch_inverse(p, S->sp, 1, ents.data(), n, &S->st, s), "server smoother");
-                    return FEM_OK;
-                };
-                for (int i = 0; i < n; ++i) ents[i] = pi_entry(g[i]->P, g[i]->rs, g[i]->z, S->sp, S->omega);
-                FEM_HIP(launch_patch_inverse(p, S->sp, 0, ents.data(), n, &S->st, s), "server smoother");
-                for (int sw = 1; sw < S->sweeps; ++sw) {
-                    fem_status sst = residual();
-                    if (sst == FEM_OK) sst = sweep_acc();
-                    if (sst != FEM_OK) return sst;
-                }
-                if (S->pc == FEM_PC_TWO_LEVEL) {
-                    fem_status sst = residual();
-                    if (sst != FEM_OK) return sst;
-                    for (int i = 0; i < n; ++i) ents[i] = coarse_entry(g[i]->P, g[i]->P->d_tmp, g[i]->z);
-                    FEM_HIP(launch_coarse_correction(p, S->sp, ents.data(), n, &S->st, s), "server coarse correction");
-                    for (int sw = 0; sw < S->sweeps; ++sw) {
-                        sst = residual();
-                        if (sst == FEM_OK) sst = sweep_acc();
-                        if (sst != FEM_OK) return sst;
-                    }
-                }
-                if (S->variant == FEM_CG_PCG) {
-                    for (int i = 0; i < n; ++i) ents[i] = entry_of(g[i]->P);
-                    FEM_HIP(launch_slot_copy(ents.data(), n, &S->st, s, kSlotRZOld, kSlotRZ), "server slots");
-                    for (int i = 0; i < n; ++i) {
-                        ents[i] = entry_of(g[i]->P);
-                        ents[i].a = g[i]->r;
-                        ents[i].b = g[i]->z;
-                    }
-                    FEM_HIP(launch_dot(FEM_F64, S->sp, ents.data(), n, &S->st, s, kSlotRZ), "server dot");
-                } else {
-                    for (int i = 0; i < n; ++i) {
-                        ents[i] = entry_of(g[i]->P);
-                        ents[i].a = g[i]->q;
-                        ents[i].d = g[i]->r;
-                        ents[i].b = g[i]->z;
-                    }
-                    FEM_HIP(launch_dot_qz_rz(S->sp, ents.data(), n, &S->st, s), "server dots");
-                }
+            // the solves taking this inner iteration, all degrees together:
+            // the degree-dependent kernels run as mixed-degree launches
+            // (degrees 2, 3, 7; else one launch per degree), the vector
+            // kernels over all of them at once
+            std::vector<Active*> g;
+            for (int i = 0; i < na; ++i)
+                if (reps[i] > it) g.push_back(S->active[i]);
+            const int n = (int)g.size();
+            ents.resize(n);
+            // q = A p, <q,p>, r -= alpha q, residual norm (and the smoother's
+            // copy of r), the convergence test
+            for (int i = 0; i < n; ++i) {
+                ents[i] = entry_of(g[i]->P);
+                ents[i].a = g[i]->p;
+                ents[i].c = g[i]->q;
+            }
+            FEM_HIP(launch_apply_any(FEM_F64, 0, ents.data(), n, &S->st, s, mix), "server apply");
+            for (int i = 0; i < n; ++i) {
+                ents[i] = entry_of(g[i]->P);
+                ents[i].a = g[i]->q;
+                ents[i].b = g[i]->p;
+            }
+            FEM_HIP(launch_dot(FEM_F64, FEM_F64, ents.data(), n, &S->st, s, kSlotQP), "server dot");
+            for (int i = 0; i < n; ++i) {
+                ents[i] = entry_of(g[i]->P);
+                ents[i].b = g[i]->q;
+                ents[i].d = g[i]->r;
+            }
+            FEM_HIP(launch_cg_ur(ents.data(), n, &S->st, s), "server update");
+            for (int i = 0; i < n; ++i) {
+                ents[i] = entry_of(g[i]->P);
+                ents[i].a = g[i]->r;
+                ents[i].c = g[i]->rs;
+            }
+            FEM_HIP(launch_norm_any(S->sp, ents.data(), n, &S->st, s, kSlotRN, mix), "server norm");
+            for (int i = 0; i < n; ++i) ents[i] = entry_of(g[i]->P);
+            FEM_HIP(launch_cg_check(ents.data(), n, &S->st, s), "server convergence");
+            // smoother, pairings and the new direction (with the u step of
+            // this iteration's r update, which completes a finishing solve's u)
+            // z = P(rs): Schwarz sweeps, or for the two-level method
+            // pre-sweeps, the coarse correction and post-sweeps
+            auto residual = [&]() -> fem_status {       // tmp = rs - A z
                 for (int i = 0; i < n; ++i) {
                     ents[i] = entry_of(g[i]->P);
                     ents[i].a = g[i]->z;
-                    ents[i].c = g[i]->p;
-                    ents[i].d = g[i]->u;
+                    ents[i].b = g[i]->rs;
+                    ents[i].c = g[i]->P->d_tmp;
                 }
-                FEM_HIP(launch_cg_p(S->sp, S->variant, ents.data(), n, &S->st, s), "server direction");
+                FEM_HIP(launch_apply_any(S->sp, 1, ents.data(), n, &S->st, s, mix), "server smoother residual");
+                return FEM_OK;
+            };
+            auto sweep_acc = [&]() -> fem_status {      // z += omega P_AS tmp
+                for (int i = 0; i < n; ++i) ents[i] = pi_entry(g[i]->P, g[i]->P->d_tmp, g[i]->z, S->sp, S->omega);
+                FEM_HIP(launch_patch_inverse_any(S->sp, 1, ents.data(), n, &S->st, s, mix), "server smoother");
+                return FEM_OK;
+            };
+            for (int i = 0; i < n; ++i) ents[i] = pi_entry(g[i]->P, g[i]->rs, g[i]->z, S->sp, S->omega);
+            FEM_HIP(launch_patch_inverse_any(S->sp, 0, ents.data(), n, &S->st, s, mix), "server smoother");
+            for (int sw = 1; sw < S->sweeps; ++sw) {
+                fem_status sst = residual();
+                if (sst == FEM_OK) sst = sweep_acc();
+                if (sst != FEM_OK) return sst;
             }
+            if (S->pc == FEM_PC_TWO_LEVEL) {
+                fem_status sst = residual();
+                if (sst != FEM_OK) return sst;
+                for (int i = 0; i < n; ++i) ents[i] = coarse_entry(g[i]->P, g[i]->P->d_tmp, g[i]->z);
+                FEM_HIP(launch_coarse_any(S->sp, ents.data(), n, &S->st, s, mix), "server coarse correction");
+                for (int sw = 0; sw < S->sweeps; ++sw) {
+                    sst = residual();
+                    if (sst == FEM_OK) sst = sweep_acc();
+                    if (sst != FEM_OK) return sst;
+                }
+            }
+            if (S->variant == FEM_CG_PCG) {
+                for (int i = 0; i < n; ++i) ents[i] = entry_of(g[i]->P);
+                FEM_HIP(launch_slot_copy(ents.data(), n, &S->st, s, kSlotRZOld, kSlotRZ), "server slots");
+                for (int i = 0; i < n; ++i) {
+                    ents[i] = entry_of(g[i]->P);
+                    ents[i].a = g[i]->r;
+                    ents[i].b = g[i]->z;
+                }
+                FEM_HIP(launch_dot(FEM_F64, S->sp, ents.data(), n, &S->st, s, kSlotRZ), "server dot");
+            } else {
+                for (int i = 0; i < n; ++i) {
+                    ents[i] = entry_of(g[i]->P);
+                    ents[i].a = g[i]->q;
+                    ents[i].d = g[i]->r;
+                    ents[i].b = g[i]->z;
+                }
+                FEM_HIP(launch_dot_qz_rz(S->sp, ents.data(), n, &S->st, s), "server dots");
+            }
+            for (int i = 0; i < n; ++i) {
+                ents[i] = entry_of(g[i]->P);
+                ents[i].a = g[i]->z;
+                ents[i].c = g[i]->p;
+                ents[i].d = g[i]->u;
+            }
+            FEM_HIP(launch_cg_p(S->sp, S->variant, ents.data(), n, &S->st, s), "server direction");
         }
         // 3. one read-back of every solve's convergence state
         ents.resize(na);
@@ -911,6 +988,12 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
     std::lock_guard<std::mutex> lk(S->mu);
     if (n_queued) *n_queued = (int)S->queue.size();
     if (n_done) *n_done = (int)S->done.size();
+    return FEM_OK;
+}
+
+extern "C" fem_status fem_server_set_mixed(fem_server* S, int mixed) {
+    if (!S) return set_error(FEM_EINVAL, "fem_server_set_mixed: NULL server");
+    S->mix.store(mixed ? 1 : 0, std::memory_order_relaxed);
     return FEM_OK;
 }
 

@@ -23,6 +23,7 @@
 //    the three directions with one thread per 1D line.
 #include "fem_internal.h"
 #include "launch.h"
+#include "mixed.h"
 #include "trace.h"
 
 namespace fem {
@@ -64,14 +65,16 @@ __device__ __forceinline__ bool on_boundary(const CellGeom<C>& g, int a, int b, 
 // ---------------------------------------------------------------------------
 // One thread per cell, register resident.  Tile = one storage block (64
 // cells) per wavefront.
+// The kernel body takes the workgroup index and the grid size as arguments
+// (here and below), so that a mixed-degree launch can run it on its items.
 template <int P, typename S, int MODE, bool MULTI>
-__global__ void __launch_bounds__(256)
-k_apply_reg(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
+__device__ __forceinline__ void apply_reg_body(const LaunchTable& L, const RefMats<P, typename Prec<S>::C>& R,
+                                               int item, int items) {
     using C = typename Prec<S>::C;
     constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    for (int tile = blockIdx.x * 4 + wv; tile < L.total_tiles; tile += gridDim.x * 4) {
+    for (int tile = item * 4 + wv; tile < L.total_tiles; tile += items * 4) {
         const ProbEntry& pe = entry<MULTI>(L, tile);
         const int blk = tile - pe.tile_begin;
         const int e = blk * kLanes + lane;
@@ -185,6 +188,12 @@ k_apply_reg(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
                 }
         }
     }
+}
+
+template <int P, typename S, int MODE, bool MULTI>
+__global__ void __launch_bounds__(256)
+k_apply_reg(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
+    apply_reg_body<P, S, MODE, MULTI>(L, R, blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -362,25 +371,31 @@ static RefMats<P, C> ref_mats() {
 // LDS.  The mass apply keeps the T2/P2 chain: y = vol Mz (My Mx u).
 // Workgroup shape of the plane-streamed apply (threads, z planes per step).
 // A 512-thread, four-plane shape for 8-byte values measured slower.
-template <int P, typename C> struct PlanesShape { static constexpr int NT = 256, KP = 2; };
+template <int P, typename C> struct PlanesShape {
+    static constexpr int NT = 256, KP = 2;
+    static constexpr int CB = 16;                                   // cells per workgroup
+    static constexpr int SL = KP * (P + 1) * (P + 1) * CB;          // values per LDS array
+    static constexpr int kLds = (2 * SL + 2 * (P + 1) * (P + 1)) * (int)sizeof(C);
+};
 
 template <int P, typename S, int MODE, bool MULTI>
-__global__ void __launch_bounds__((PlanesShape<P, typename Prec<S>::C>::NT))
-k_apply_planes(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
+__device__ __forceinline__ void apply_planes_body(const LaunchTable& L, const RefMats<P, typename Prec<S>::C>& R,
+                                                  int item, int items, char* smem) {
     using C = typename Prec<S>::C;
     constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
     constexpr int NT = PlanesShape<P, C>::NT;
-    constexpr int CB = 16;                 // cells per workgroup
+    constexpr int CB = PlanesShape<P, C>::CB;
     constexpr int KP = PlanesShape<P, C>::KP;   // z planes per step
     constexpr int NSTEP = (N + KP - 1) / KP;
-    constexpr int SL = KP * N2 * CB;       // values per LDS array
+    constexpr int SL = PlanesShape<P, C>::SL;
     constexpr int ZL = N2 * CB;            // z lines per workgroup
     constexpr int ZPT = (ZL + NT - 1) / NT;  // z lines per thread
-    __shared__ C s1[SL];                   // u -> T1 -> P1
-    __shared__ C s2[SL];                   // T2 -> P2
+    C* s1 = reinterpret_cast<C*>(smem);    // u -> T1 -> P1
+    C* s2 = s1 + SL;                       // T2 -> P2
     // the 1D matrices (2 (p+1)^2 values) do not fit the scalar registers for
     // p = 7, so they are read as LDS broadcasts instead of being spilled
-    __shared__ C sM[N2], sK[N2];
+    C* sM = s2 + SL;
+    C* sK = sM + N2;
     static_assert(NT % CB == 0 && kLanes % CB == 0, "cells per workgroup must divide the block");
     const int tid = threadIdx.x;
     for (int i = tid; i < N2; i += NT) {
@@ -389,7 +404,7 @@ k_apply_planes(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
     }
     __syncthreads();
     const int cl = tid % CB;               // the cell this thread serves in line passes
-    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+    for (int tile = item; tile < L.total_tiles; tile += items) {
         const ProbEntry& pe = entry<MULTI>(L, tile);
         const int t = tile - pe.tile_begin;
         const int blk = t / (kLanes / CB), lane0 = (t % (kLanes / CB)) * CB;
@@ -507,6 +522,13 @@ k_apply_planes(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
     }
 }
 
+template <int P, typename S, int MODE, bool MULTI>
+__global__ void __launch_bounds__((PlanesShape<P, typename Prec<S>::C>::NT))
+k_apply_planes(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
+    __shared__ __align__(16) char smem[PlanesShape<P, typename Prec<S>::C>::kLds];
+    apply_planes_body<P, S, MODE, MULTI>(L, R, blockIdx.x, gridDim.x, smem);
+}
+
 template <int P> constexpr int lds_cells(int bytes) {
     // largest power of two <= 64 with two LDS arrays within 64 KiB
     int cb = 64;
@@ -579,6 +601,69 @@ static hipError_t launch_apply_p(int prec, int mode, ProbEntry* e, int n, TableS
         case FEM_F32: return launch_apply_m<P, float>(mode, e, n, t, s, fl);
         default: return launch_apply_m<P, bf16_t>(mode, e, n, t, s, fl);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Mixed-degree apply: the register body for p = 2, 3 (four storage blocks
+// per item, one per wavefront) and the plane-streamed body for p = 7 (16
+// cells per item), in one persistent launch.
+template <int P, typename S, int MODE>
+struct ApplyBody {
+    using C = typename Prec<S>::C;
+    using Arg = RefMats<P, C>;
+    static constexpr int kLds = P <= 3 ? 0 : PlanesShape<P, C>::kLds;
+    __device__ static __forceinline__ void run(const LaunchTable& L, const Arg& R, int item, int items, char* smem) {
+        if constexpr (P <= 3) apply_reg_body<P, S, MODE, true>(L, R, item, items);
+        else apply_planes_body<P, S, MODE, true>(L, R, item, items, smem);
+    }
+};
+
+template <typename S, int MODE>
+static hipError_t launch_apply_mixed_t(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s) {
+    using C = typename Prec<S>::C;
+    static_assert(mix_degree(0) == 7 && mix_degree(1) == 3 && mix_degree(2) == 2, "segment degrees");
+    MixTable T{};
+    int grid = 0;
+    auto tiles = [](int p, const ProbEntry& e) { return p <= 3 ? e.nblk : e.nblk * (kLanes / 16); };
+    auto items = [](int p, int t) { return p <= 3 ? (t + 3) / 4 : t; };
+    hipError_t err = mix_build(ents, nprob, st, s, tiles, items, T, grid);
+    if (err != hipSuccess || grid == 0) return err;
+    TraceSpan ts(MODE == kApplyLaplace ? "apply" : MODE == kApplyResidual ? "apply_residual" : "mass_apply", 0,
+                 Prec<S>::id, s);
+    hipLaunchKernelGGL((k_mixed<ApplyBody<7, S, MODE>, ApplyBody<3, S, MODE>, ApplyBody<2, S, MODE>>), dim3(grid),
+                       dim3(256), 0, s, T, ref_mats<7, C>(), ref_mats<3, C>(), ref_mats<2, C>());
+    return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t launch_apply_mixed_m(int mode, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s) {
+    switch (mode) {
+        case kApplyLaplace: return launch_apply_mixed_t<S, kApplyLaplace>(ents, nprob, st, s);
+        case kApplyResidual: return launch_apply_mixed_t<S, kApplyResidual>(ents, nprob, st, s);
+        default: return launch_apply_mixed_t<S, kApplyMass>(ents, nprob, st, s);
+    }
+}
+
+hipError_t launch_apply_any(int prec, int mode, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s,
+                            bool mix) {
+    if (nprob <= 0) return hipSuccess;
+    if (mix && mix_degrees(ents, nprob) >= 2) {
+        switch (prec) {
+            case FEM_F64: return launch_apply_mixed_m<double>(mode, ents, nprob, st, s);
+            case FEM_F32: return launch_apply_mixed_m<float>(mode, ents, nprob, st, s);
+            default: return launch_apply_mixed_m<bf16_t>(mode, ents, nprob, st, s);
+        }
+    }
+    std::vector<ProbEntry> g;
+    for (int p = 1; p <= kMaxP; ++p) {
+        g.clear();
+        for (int i = 0; i < nprob; ++i)
+            if (ents[i].p == p) g.push_back(ents[i]);
+        if (g.empty()) continue;
+        hipError_t err = launch_apply(p, prec, mode, g.data(), (int)g.size(), st, s);
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_apply(int p, int prec, int mode, ProbEntry* ents, int nprob, TableStager* d_tab,

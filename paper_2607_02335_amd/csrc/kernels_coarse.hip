@@ -21,6 +21,7 @@
 #include "fem_internal.h"
 #include "host_api.h"
 #include "launch.h"
+#include "mixed.h"
 #include "trace.h"
 
 namespace fem {
@@ -49,9 +50,9 @@ __device__ __forceinline__ int coarse_m(const ProbEntry& pe, int d) { return pe.
 // storage block, so every load is a contiguous run); sums in FP64, streamed
 // over the z node planes.  corner[(sx + 2 sy + 4 sz) * nblk * 64 + e].
 template <int P, typename S, bool MULTI>
-__global__ void __launch_bounds__(256) k_restrict_cells(LaunchTable L, GllNodes g) {
+__device__ __forceinline__ void restrict_cells_body(const LaunchTable& L, const GllNodes& g, int item, int items) {
     constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
-    const int tile = blockIdx.x;
+    const int tile = item;
     if (tile >= L.total_tiles) return;
     const ProbEntry& pe = entry<MULTI>(L, tile);
     const int stride = pe.nblk * kLanes;
@@ -96,6 +97,11 @@ __global__ void __launch_bounds__(256) k_restrict_cells(LaunchTable L, GllNodes 
     double* corner = static_cast<double*>(pe.d);
 #pragma unroll
     for (int i = 0; i < 8; ++i) corner[(size_t)i * stride + e] = out[i];
+}
+
+template <int P, typename S, bool MULTI>
+__global__ void __launch_bounds__(256) k_restrict_cells(LaunchTable L, GllNodes g) {
+    restrict_cells_body<P, S, MULTI>(L, g, blockIdx.x, gridDim.x);
 }
 
 // Corner sums -> coarse right-hand side at the interior vertices (the first
@@ -169,10 +175,10 @@ __global__ void __launch_bounds__(256) k_coarse_pass(LaunchTable L, int axis, in
 // copies of a node shared by several cells add the same terms in the same
 // order (bitwise continuous).
 template <int P, typename S, bool MULTI>
-__global__ void __launch_bounds__(256) k_prolong_add(LaunchTable L, GllNodes g) {
+__device__ __forceinline__ void prolong_add_body(const LaunchTable& L, const GllNodes& g, int item, int items) {
     using C = typename Prec<S>::C;
     constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
-    const int tile = blockIdx.x;
+    const int tile = item;
     if (tile >= L.total_tiles) return;
     const ProbEntry& pe = entry<MULTI>(L, tile);
     const int e = (tile - pe.tile_begin) * 256 + threadIdx.x;
@@ -221,6 +227,11 @@ __global__ void __launch_bounds__(256) k_prolong_add(LaunchTable L, GllNodes g) 
     }
 }
 
+template <int P, typename S, bool MULTI>
+__global__ void __launch_bounds__(256) k_prolong_add(LaunchTable L, GllNodes g) {
+    prolong_add_body<P, S, MULTI>(L, g, blockIdx.x, gridDim.x);
+}
+
 template <typename F>
 static hipError_t by_prec(int prec, F&& f) {
     switch (prec) {
@@ -228,6 +239,13 @@ static hipError_t by_prec(int prec, F&& f) {
         case FEM_F32: return f(float{});
         default: return f(bf16_t{});
     }
+}
+
+// Tiles of the cell kernels (256 cells each); a problem without interior
+// vertices has no coarse space and takes no correction.
+static int coarse_cell_tiles(const ProbEntry& e) {
+    const bool any = e.n[0] > 1 && e.n[1] > 1 && e.n[2] > 1;
+    return any ? (e.nblk * kLanes + 255) / 256 : 0;
 }
 
 template <int P>
@@ -241,7 +259,7 @@ static hipError_t coarse_p(int prec, ProbEntry* ents, int nprob, TableStager* st
     int tc = 0;
     for (int i = 0; i < nprob; ++i) {
         ents[i].tile_begin = tc;
-        ents[i].ntiles = (ents[i].nblk * kLanes + 255) / 256;
+        ents[i].ntiles = coarse_cell_tiles(ents[i]);
         tc += ents[i].ntiles;
     }
     Lc.nprob = nprob;
@@ -281,6 +299,94 @@ static hipError_t coarse_p(int prec, ProbEntry* ents, int nprob, TableStager* st
         else hipLaunchKernelGGL((k_prolong_add<P, S, false>), dim3(tc), dim3(256), 0, s, Lc, g);
         return hipGetLastError();
     });
+}
+
+// Mixed-degree coarse correction: restriction and prolongation as mixed
+// launches (cell tiles of the degrees 7, 3, 2), the vertex sums and the six
+// solve passes (the same for every degree) over all problems at once.
+template <int P, typename S>
+struct RestrictBody {
+    using Arg = GllNodes;
+    static constexpr int kLds = 0;
+    __device__ static __forceinline__ void run(const LaunchTable& L, const GllNodes& g, int item, int items, char*) {
+        restrict_cells_body<P, S, true>(L, g, item, items);
+    }
+};
+
+template <int P, typename S>
+struct ProlongBody {
+    using Arg = GllNodes;
+    static constexpr int kLds = 0;
+    __device__ static __forceinline__ void run(const LaunchTable& L, const GllNodes& g, int item, int items, char*) {
+        prolong_add_body<P, S, true>(L, g, item, items);
+    }
+};
+
+static GllNodes gll_arg(int p) {
+    GllNodes g{};
+    const std::vector<double>& xi = gll_cached(p);
+    for (int a = 0; a <= p; ++a) g.xi[a] = xi[a];
+    return g;
+}
+
+static hipError_t coarse_mixed(int prec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s) {
+    static_assert(mix_degree(0) == 7 && mix_degree(1) == 3 && mix_degree(2) == 2, "segment degrees");
+    // coarse-value tables (vertex sums, solve passes) over all problems
+    LaunchTable Lv{};
+    int tv = 0;
+    for (int i = 0; i < nprob; ++i) {
+        long nv = 1;
+        for (int d = 0; d < 3; ++d) nv *= ents[i].n[d] > 1 ? ents[i].n[d] - 1 : 0;
+        ents[i].tile_begin = tv;
+        ents[i].ntiles = (int)((nv + 255) / 256);
+        tv += ents[i].ntiles;
+    }
+    Lv.nprob = nprob;
+    Lv.total_tiles = tv;
+    if (tv == 0) return hipSuccess;                 // no interior vertex anywhere: no coarse space
+    hipError_t err = stage_table(Lv, ents, nprob, st, s);
+    if (err != hipSuccess) return err;
+    MixTable T{};
+    int grid = 0;
+    auto tiles = [](int, const ProbEntry& e) { return coarse_cell_tiles(e); };
+    auto items = [](int, int t) { return t; };
+    err = mix_build(ents, nprob, st, s, tiles, items, T, grid);
+    if (err != hipSuccess) return err;
+    const GllNodes g7 = gll_arg(7), g3 = gll_arg(3), g2 = gll_arg(2);
+    const bool multi = nprob > 1;
+    return by_prec(prec, [&](auto tag) {
+        using S = decltype(tag);
+        TraceSpan ts("coarse_correction", 0, Prec<S>::id, s);
+        if (grid > 0)
+            hipLaunchKernelGGL((k_mixed<RestrictBody<7, S>, RestrictBody<3, S>, RestrictBody<2, S>>), dim3(grid),
+                               dim3(256), 0, s, T, g7, g3, g2);
+        if (multi) hipLaunchKernelGGL(k_restrict_vertices<true>, dim3(tv), dim3(256), 0, s, Lv);
+        else hipLaunchKernelGGL(k_restrict_vertices<false>, dim3(tv), dim3(256), 0, s, Lv);
+        const int axis[6] = {0, 1, 2, 2, 1, 0}, fwd[6] = {1, 1, 1, 0, 0, 0};
+        for (int k = 0; k < 6; ++k) {
+            if (multi) hipLaunchKernelGGL(k_coarse_pass<true>, dim3(tv), dim3(256), 0, s, Lv, axis[k], fwd[k], k % 2, k == 2 ? 1 : 0);
+            else hipLaunchKernelGGL(k_coarse_pass<false>, dim3(tv), dim3(256), 0, s, Lv, axis[k], fwd[k], k % 2, k == 2 ? 1 : 0);
+        }
+        if (grid > 0)
+            hipLaunchKernelGGL((k_mixed<ProlongBody<7, S>, ProlongBody<3, S>, ProlongBody<2, S>>), dim3(grid),
+                               dim3(256), 0, s, T, g7, g3, g2);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch_coarse_any(int prec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, bool mix) {
+    if (nprob <= 0) return hipSuccess;
+    if (mix && mix_degrees(ents, nprob) >= 2) return coarse_mixed(prec, ents, nprob, st, s);
+    std::vector<ProbEntry> g;
+    for (int p = 1; p <= kMaxP; ++p) {
+        g.clear();
+        for (int i = 0; i < nprob; ++i)
+            if (ents[i].p == p) g.push_back(ents[i]);
+        if (g.empty()) continue;
+        hipError_t err = launch_coarse_correction(p, prec, g.data(), (int)g.size(), st, s);
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
 }
 
 // Entry of a problem for the coarse kernels: a = t, c = z.

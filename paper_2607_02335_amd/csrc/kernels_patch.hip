@@ -23,6 +23,7 @@
 
 #include "fem_internal.h"
 #include "launch.h"
+#include "mixed.h"
 #include "trace.h"
 
 namespace fem {
@@ -819,8 +820,13 @@ template <> struct SweepShape<3, bf16_t> { static constexpr int TX = 8, TY = 4, 
 // lanes of a wavefront hit distinct banks.
 template <int P> constexpr int solve_g_tile() { return P >= 3 ? 32 : 64; }
 
+template <int P, typename C, int CBP> constexpr int solve_g_lds() {
+    return ((2 * P - 1) * (2 * P - 1) * (2 * P - 1) * CBP + CBP * (((2 * P - 1) * (2 * P - 1)) | 1) + CBP * (2 * P - 1)) *
+           (int)sizeof(C);
+}
+
 template <int P, typename S, int CBP, bool MULTI>
-__global__ void __launch_bounds__(256) k_pi_solve_g(LaunchTable L) {
+__device__ __forceinline__ void pi_solve_g_body(const LaunchTable& L, int item, int items, char* smem) {
     using C = typename Prec<S>::C;
     constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
     constexpr int REC = fd_record(P);
@@ -828,10 +834,10 @@ __global__ void __launch_bounds__(256) k_pi_solve_g(LaunchTable L) {
     constexpr int KL = (nP2 + LPT - 1) / LPT;       // lines per thread (upper bound)
     constexpr int SXS = nP2 | 1;                    // odd row stride of the x bases
     static_assert(NT % CBP == 0, "patches per tile must divide the workgroup");
-    __shared__ C sv[nP3 * CBP];
-    __shared__ C sSx[CBP * SXS];
-    __shared__ C sLx[CBP * nP];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    C* sv = reinterpret_cast<C*>(smem);
+    C* sSx = sv + nP3 * CBP;
+    C* sLx = sSx + CBP * SXS;
+    const int tile = xcd_tile(item, items);
     if (tile >= L.total_tiles) return;
     const int tid = threadIdx.x;
     const int pc = tid % CBP, grp = tid / CBP;
@@ -990,6 +996,12 @@ __global__ void __launch_bounds__(256) k_pi_solve_g(LaunchTable L) {
     }
 }
 
+template <int P, typename S, int CBP, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_solve_g(LaunchTable L) {
+    __shared__ __align__(16) char smem[solve_g_lds<P, typename Prec<S>::C, CBP>()];
+    pi_solve_g_body<P, S, CBP, MULTI>(L, blockIdx.x, gridDim.x, smem);
+}
+
 // ---------------------------------------------------------------------------
 // Patch inverse for p <= 3 through an x-combined buffer (two launches after
 // the assembly).  k_pi_solve_x solves a tile of CBP patches along x that
@@ -1007,8 +1019,10 @@ __global__ void __launch_bounds__(256) k_pi_solve_g(LaunchTable L) {
 // the z-patches in ascending order and writes every cell copy.
 __host__ __device__ constexpr int xrow_len(int npx, int ntx, int P) { return npx * P + ntx * (P - 1); }
 
+template <int P, typename C, int CBP> constexpr int solve_x_lds() { return solve_g_lds<P, C, CBP>(); }
+
 template <int P, typename S, int CBP, bool MULTI>
-__global__ void __launch_bounds__(256) k_pi_solve_x(LaunchTable L) {
+__device__ __forceinline__ void pi_solve_x_body(const LaunchTable& L, int item, int items, char* smem) {
     using C = typename Prec<S>::C;
     constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
     constexpr int REC = fd_record(P);
@@ -1017,10 +1031,10 @@ __global__ void __launch_bounds__(256) k_pi_solve_x(LaunchTable L) {
     constexpr int SXS = nP2 | 1;                    // odd row stride of the x bases
     constexpr int SPAN = CBP * P + P - 1;           // x-nodes of a full tile
     static_assert(NT % CBP == 0, "patches per tile must divide the workgroup");
-    __shared__ C sv[nP3 * CBP];
-    __shared__ C sSx[CBP * SXS];
-    __shared__ C sLx[CBP * nP];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    C* sv = reinterpret_cast<C*>(smem);
+    C* sSx = sv + nP3 * CBP;
+    C* sLx = sSx + CBP * SXS;
+    const int tile = xcd_tile(item, items);
     if (tile >= L.total_tiles) return;
     const int tid = threadIdx.x;
     const int pc = tid % CBP, grp = tid / CBP;
@@ -1190,6 +1204,12 @@ __global__ void __launch_bounds__(256) k_pi_solve_x(LaunchTable L) {
     }
 }
 
+template <int P, typename S, int CBP, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_solve_x(LaunchTable L) {
+    __shared__ __align__(16) char smem[solve_x_lds<P, typename Prec<S>::C, CBP>()];
+    pi_solve_x_body<P, S, CBP, MULTI>(L, blockIdx.x, gridDim.x, smem);
+}
+
 // Combine of the x-combined buffer (p <= 3): one wavefront per global node
 // row (Y, Z) with lane i on cell column i.  Per node X of the row the terms
 // are the z-patches (ascending vk), within each the y-patches (ascending vj),
@@ -1198,12 +1218,12 @@ __global__ void __launch_bounds__(256) k_pi_solve_x(LaunchTable L) {
 // slot).  The first wavefront of a problem zeroes the padding cells of its
 // last storage block.  pe: d = x-combined buffer, c = z (S), alpha = damping.
 template <int P, typename S, int CBP, int ACC, bool MULTI>
-__global__ void __launch_bounds__(256) k_pi_combine_x(LaunchTable L) {
+__device__ __forceinline__ void pi_combine_x_body(const LaunchTable& L, int item, int items) {
     using C = typename Prec<S>::C;
     constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
     constexpr int nP = 2 * P - 1, nP2 = nP * nP;
     constexpr int SPAN = CBP * P + P - 1;
-    const int tile = blockIdx.x;
+    const int tile = item;
     if (tile >= L.total_tiles) return;
     const ProbEntry& pe = entry<MULTI>(L, tile);
     const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
@@ -1322,15 +1342,20 @@ __global__ void __launch_bounds__(256) k_pi_combine_x(LaunchTable L) {
     }
 }
 
+template <int P, typename S, int CBP, int ACC, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_combine_x(LaunchTable L) {
+    pi_combine_x_body<P, S, CBP, ACC, MULTI>(L, blockIdx.x, gridDim.x);
+}
+
 // Assembly into the global-node array: one wavefront per node row (Y, Z),
 // its lanes walking X, so writes are contiguous and the row's y/z copy
 // structure is uniform over the wavefront.  Each node sums its copies in
 // ascending cell order along z, y, x, the same order for every node.
 // pe: a = r (S), e = global array (C); ntiles = ceil(rows / 4).
 template <int P, typename S, typename C, bool MULTI>
-__global__ void __launch_bounds__(256) k_assemble_nodes(LaunchTable L) {
+__device__ __forceinline__ void assemble_nodes_body(const LaunchTable& L, int item, int items) {
     constexpr int N = P + 1, NN = N * N * N;
-    const int tile = blockIdx.x;
+    const int tile = item;
     if (tile >= L.total_tiles) return;
     const ProbEntry& pe = entry<MULTI>(L, tile);
     const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
@@ -1379,6 +1404,11 @@ __global__ void __launch_bounds__(256) k_assemble_nodes(LaunchTable L) {
     }
 }
 
+template <int P, typename S, typename C, bool MULTI>
+__global__ void __launch_bounds__(256) k_assemble_nodes(LaunchTable L) {
+    assemble_nodes_body<P, S, C, MULTI>(L, blockIdx.x, gridDim.x);
+}
+
 // The same assembly for long rows: one wavefront per node row (Y, Z) with
 // lane i on cell column i (64 cells per pass along x).  For each of the
 // row's y/z copies (uniform over the wavefront) a lane loads its cell's p+1
@@ -1388,9 +1418,9 @@ __global__ void __launch_bounds__(256) k_assemble_nodes(LaunchTable L) {
 // order as k_assemble_nodes (ascending cell order along z, y, x), so the two
 // kernels give identical results.
 template <int P, typename S, typename C, bool MULTI>
-__global__ void __launch_bounds__(256) k_assemble_cells(LaunchTable L) {
+__device__ __forceinline__ void assemble_cells_body(const LaunchTable& L, int item, int items) {
     constexpr int N = P + 1, NN = N * N * N;
-    const int tile = blockIdx.x;
+    const int tile = item;
     if (tile >= L.total_tiles) return;
     const ProbEntry& pe = entry<MULTI>(L, tile);
     const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
@@ -1453,6 +1483,11 @@ __global__ void __launch_bounds__(256) k_assemble_cells(LaunchTable L) {
             }
         }
     }
+}
+
+template <int P, typename S, typename C, bool MULTI>
+__global__ void __launch_bounds__(256) k_assemble_cells(LaunchTable L) {
+    assemble_cells_body<P, S, C, MULTI>(L, blockIdx.x, gridDim.x);
 }
 
 // Fused sweep from the assembled residual (p <= 3): like k_pi_sweep, but the
@@ -1845,7 +1880,7 @@ static hipError_t launch_pi_sweep(int accumulate, ProbEntry* ents, int nprob, Ta
 template <int P> constexpr int combine_brows() { return P <= 3 ? P + 1 : 2; }
 
 template <int P, typename S, int ACC, bool MULTI>
-__global__ void __launch_bounds__(256) k_pi_combine_planes(LaunchTable L) {
+__device__ __forceinline__ void pi_combine_planes_body(const LaunchTable& L, int item, int items) {
     using C = typename Prec<S>::C;
     constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
     constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
@@ -1854,7 +1889,7 @@ __global__ void __launch_bounds__(256) k_pi_combine_planes(LaunchTable L) {
     const int lane = threadIdx.x & 63;
     // consecutive storage blocks (cell rows that read the same patch rows)
     // on one XCD, so its L2 serves the shared patch values
-    const int tile = xcd_tile(blockIdx.x, gridDim.x) * 4 + (threadIdx.x >> 6);
+    const int tile = xcd_tile(item, items) * 4 + (threadIdx.x >> 6);
     if (tile >= L.total_tiles) return;
     const ProbEntry& pe = entry<MULTI>(L, tile);
     const int blk = (tile - pe.tile_begin) / (N * NBG);
@@ -1926,6 +1961,11 @@ __global__ void __launch_bounds__(256) k_pi_combine_planes(LaunchTable L) {
             if (ACC) out = load_as<C>(z + l * kLanes) + out;
             store_from(z + l * kLanes, out);
         }
+}
+
+template <int P, typename S, int ACC, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_combine_planes(LaunchTable L) {
+    pi_combine_planes_body<P, S, ACC, MULTI>(L, blockIdx.x, gridDim.x);
 }
 
 // Combine by global node rows, for long rows (p <= 3): one wavefront per
@@ -2120,17 +2160,20 @@ __device__ __forceinline__ void mfma_pass(C* pv, C* dump, const C (&a)[4], int l
 // corner patch are rows of contiguous values.  The sums go through LDS
 // (padded rows) and leave as coalesced cell-wise stores.  Terms are added in
 // ascending vertex order along z, y, x for every copy of a node.
+template <typename C> constexpr int pm_cells() { return sizeof(C) >= 8 ? kLanes / 2 : kLanes; }
+template <int P, typename C> constexpr int pm_lds() { return (P + 1) * (P + 1) * (pm_cells<C>() + 1) * (int)sizeof(C); }
+
 template <int P, typename S, int ACC, bool MULTI>
-__global__ void __launch_bounds__(256) k_pi_combine_pm(LaunchTable L) {
+__device__ __forceinline__ void pi_combine_pm_body(const LaunchTable& L, int item, int items, char* smem) {
     using C = typename Prec<S>::C;
     constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
     constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
     // cells per LDS pass: half a block for 8-byte values keeps the LDS at
     // about 16 KB per workgroup
-    constexpr int CH = sizeof(C) >= 8 ? kLanes / 2 : kLanes;
+    constexpr int CH = pm_cells<C>();
     constexpr int RS = CH + 1;                      // padded LDS row
-    __shared__ C sz[N2 * RS];
-    const int tile = xcd_tile(blockIdx.x, gridDim.x);      // neighbouring blocks on one XCD
+    C* sz = reinterpret_cast<C*>(smem);
+    const int tile = xcd_tile(item, items);      // neighbouring blocks on one XCD
     if (tile >= L.total_tiles) return;
     const ProbEntry& pe = entry<MULTI>(L, tile);
     const int blk = (tile - pe.tile_begin) / N;
@@ -2195,6 +2238,12 @@ __global__ void __launch_bounds__(256) k_pi_combine_pm(LaunchTable L) {
     }
 }
 
+template <int P, typename S, int ACC, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_combine_pm(LaunchTable L) {
+    __shared__ __align__(16) char smem[pm_lds<P, typename Prec<S>::C>()];
+    pi_combine_pm_body<P, S, ACC, MULTI>(L, blockIdx.x, gridDim.x, smem);
+}
+
 // The x pair (forward product, scaling by 1/(lambda_x+lambda_y+lambda_z),
 // backward product) of every 16-line tile chained in registers: the
 // forward product's accumulators are the backward product's B operand.  A
@@ -2246,23 +2295,27 @@ __device__ __forceinline__ void mfma_pass_x2(C* pv, C* dump, const C (&af)[4], c
 // tiles over the whole workgroup for more waves in flight per LDS byte.
 template <int P> constexpr int mfma_waves_per_patch() { return P >= 6 ? 2 : 1; }
 
+template <int P, typename C> constexpr int mfma_lds() {
+    return ((4 / mfma_waves_per_patch<P>()) * (2 * P - 1) * (2 * P - 1) * (2 * P - 1) + 4 * 64) * (int)sizeof(C);
+}
+
 // pe: e = assembled global residual (C), d = patch buffer (C), fd = FD data (C)
 template <int P, typename S, typename C, bool MULTI>
-__global__ void __launch_bounds__(256) k_pi_solve_mfma(LaunchTable L) {
+__device__ __forceinline__ void pi_solve_mfma_body(const LaunchTable& L, int item, int items, char* smem) {
     constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
     constexpr int REC = fd_record(P);
     constexpr int WPP = mfma_waves_per_patch<P>();   // wavefronts per patch
     constexpr int PPW = 4 / WPP;                      // patches per workgroup
     static_assert(nP <= 16, "one MFMA tile per contraction");
-    __shared__ C spv[PPW][nP3];
-    __shared__ C sdump[4][64];                        // per-wavefront sink for rows outside the patch
+    C (*spv)[nP3] = reinterpret_cast<C (*)[nP3]>(smem);
+    C (*sdump)[64] = reinterpret_cast<C (*)[64]>(smem + sizeof(C) * PPW * nP3);   // per-wavefront sink for rows outside the patch
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int slot = wv / WPP, sub = wv % WPP;
     // a workgroup's patches are consecutive tiles.  A slot past the last
     // patch (the tail of an odd patch count) solves the last patch again in
     // its own LDS slot and stores nothing, so every wavefront of the
     // workgroup reaches every barrier
-    const int tile_raw = blockIdx.x * PPW + slot;
+    const int tile_raw = item * PPW + slot;
     const bool active = tile_raw < L.total_tiles;
     const int tile = active ? tile_raw : L.total_tiles - 1;
     const ProbEntry& pe = entry<MULTI>(L, tile);
@@ -2288,18 +2341,21 @@ __global__ void __launch_bounds__(256) k_pi_solve_mfma(LaunchTable L) {
     const int t64 = sub * 64 + lane;                  // thread index within the patch's wavefronts
     // restrict: the patch's box of the assembled residual
     {
-        const C* g = static_cast<const C*>(pe.e);
         const size_t G0 = (size_t)pe.n[0] * P + 1, G1 = (size_t)pe.n[1] * P + 1;
         const size_t I0 = (size_t)(vi - 1) * P + 1, J0 = (size_t)(vj - 1) * P + 1, K0 = (size_t)(vk - 1) * P + 1;
+        // the box origin is uniform over the patch's wavefronts; offsets
+        // within the box stay below G0 G1 nP < 2^32 (checked at set-up)
+        const C* g = static_cast<const C*>(pe.e) + (I0 + G0 * (J0 + G1 * K0));
         // element q = qx + nP qy + nP^2 qz; the thread's (qx, qy, qz) advance
         // by the fixed stride without divisions, and all loads are issued
         // before the first LDS store
         constexpr int STEP = 64 * WPP, NIT = (nP3 + STEP - 1) / STEP;
         constexpr int DX = STEP % nP, DY = (STEP / nP) % nP, DZ = STEP / nP2;
         int qx = t64 % nP, qy = (t64 / nP) % nP;
-        size_t off = (I0 + qx) + G0 * ((J0 + qy) + G1 * (K0 + (size_t)(t64 / nP2)));
-        const size_t dstep = DX + G0 * (DY + G1 * DZ);              // uniform node-offset steps
-        const size_t cx = G0 - nP, cy = G0 * (G1 - nP);             // carries into y and z
+        const uint32_t g0 = (uint32_t)G0, g1 = (uint32_t)G1;
+        uint32_t off = qx + g0 * (qy + g1 * (uint32_t)(t64 / nP2));
+        const uint32_t dstep = DX + g0 * (DY + g1 * DZ);            // uniform node-offset steps
+        const uint32_t cx = g0 - nP, cy = g0 * (g1 - nP);           // carries into y and z
         C vals[NIT];
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
@@ -2341,6 +2397,12 @@ __global__ void __launch_bounds__(256) k_pi_solve_mfma(LaunchTable L) {
     C* out = static_cast<C*>(pe.d) + (size_t)pidx * nP3;
     if (active)
         for (int q = t64; q < nP3; q += 64 * WPP) out[q] = pv[q];
+}
+
+template <int P, typename S, typename C, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_solve_mfma(LaunchTable L) {
+    __shared__ __align__(16) char smem[mfma_lds<P, C>()];
+    pi_solve_mfma_body<P, S, C, MULTI>(L, blockIdx.x, gridDim.x, smem);
 }
 
 template <int P, typename S>
@@ -2506,6 +2568,10 @@ static hipError_t launch_pi_xcomb(int accumulate, ProbEntry* ents, int nprob, Ta
     return hipGetLastError();
 }
 
+// Default patch-inverse variant for p <= 3: solves with the in-tile
+// x-combine for p = 2, 3 in FP64, else the two launches through the patch buffer.
+template <int P, typename S> constexpr bool pi_xcomb_default() { return (P == 2 || P == 3) && Prec<S>::id == FEM_F64; }
+
 template <int P, typename S>
 static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s,
                               const LaunchCfg& cfg) {
@@ -2516,7 +2582,7 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
         // for the combine's traffic there), the two launches through the
         // patch buffer otherwise (4-byte values: the plain patch buffer is
         // the faster one)
-        const int dflt = ((P == 2 || P == 3) && Prec<S>::id == FEM_F64) ? 3 : 0;
+        const int dflt = pi_xcomb_default<P, S>() ? 3 : 0;
         const int fused = cfg.pi_fused >= 0 ? cfg.pi_fused : g_pi_fused >= 0 ? g_pi_fused : dflt;
         if (fused == 3) return launch_pi_xcomb<P, S>(accumulate, ents, nprob, d_tab, s,
                                                       cfg.grid_cap > 0 ? cfg.grid_cap : kMaxGrid);
@@ -2693,6 +2759,143 @@ static hipError_t launch_pi_p(int prec, int acc, ProbEntry* e, int n, TableStage
         case FEM_F32: return launch_pi_t<P, float>(acc, e, n, t, s, cfg);
         default: return launch_pi_t<P, bf16_t>(acc, e, n, t, s, cfg);
     }
+}
+
+// ---------------------------------------------------------------------------
+// Mixed-degree patch inverse: every degree's default variant (p = 2, 3:
+// solves with the in-tile x-combine in FP64, solves through the patch buffer
+// in FP32/BF16; p = 7: MFMA solves), each of its three phases (assembly,
+// solves, combine) one persistent launch over all degrees.
+// (the assembly with lanes over nodes: the same sums as the long-row variant
+// with lanes over cells, whose registers would bound the whole launch)
+template <int P, typename S>
+struct AssembleBody {
+    using Arg = NoArg;
+    static constexpr int kLds = 0;
+    __device__ static __forceinline__ void run(const LaunchTable& L, const NoArg&, int item, int items, char*) {
+        assemble_nodes_body<P, S, typename Prec<S>::C, true>(L, item, items);
+    }
+};
+
+template <int P, typename S>
+struct SolveBody {
+    using C = typename Prec<S>::C;
+    using Arg = NoArg;
+    static constexpr int CBP = solve_g_tile<P>();
+    static constexpr int kLds = P >= 4 ? mfma_lds<P, C>()
+                              : pi_xcomb_default<P, S>() ? solve_x_lds<P, C, CBP>() : solve_g_lds<P, C, CBP>();
+    __device__ static __forceinline__ void run(const LaunchTable& L, const NoArg&, int item, int items, char* smem) {
+        if constexpr (P >= 4) pi_solve_mfma_body<P, S, C, true>(L, item, items, smem);
+        else if constexpr (pi_xcomb_default<P, S>()) pi_solve_x_body<P, S, CBP, true>(L, item, items, smem);
+        else pi_solve_g_body<P, S, CBP, true>(L, item, items, smem);
+    }
+};
+
+template <int P, typename S, int ACC>
+struct CombineBody {
+    using C = typename Prec<S>::C;
+    using Arg = NoArg;
+    static constexpr int kLds = P >= 4 ? pm_lds<P, C>() : 0;
+    __device__ static __forceinline__ void run(const LaunchTable& L, const NoArg&, int item, int items, char* smem) {
+        if constexpr (P >= 4) pi_combine_pm_body<P, S, ACC, true>(L, item, items, smem);
+        else if constexpr (pi_xcomb_default<P, S>()) pi_combine_x_body<P, S, solve_g_tile<P>(), ACC, true>(L, item, items);
+        else pi_combine_planes_body<P, S, ACC, true>(L, item, items);
+    }
+};
+
+// Tiles and items of each phase, as the single-degree launches count them.
+template <int P, typename S> static int pi_solve_tiles(const ProbEntry& e) {
+    const int npx = e.n[0] - 1, npy = e.n[1] - 1, npz = e.n[2] - 1;
+    if (npx <= 0 || npy <= 0 || npz <= 0) return 0;
+    if constexpr (P >= 4) return npx * npy * npz;
+    else return ((npx + solve_g_tile<P>() - 1) / solve_g_tile<P>()) * npy * npz;
+}
+template <int P> static int pi_solve_items(int t) {
+    if constexpr (P >= 4) return (t + 4 / mfma_waves_per_patch<P>() - 1) / (4 / mfma_waves_per_patch<P>());
+    else return t;
+}
+template <int P, typename S> static int pi_combine_tiles(const ProbEntry& e) {
+    if constexpr (P >= 4) return e.nblk * (P + 1);
+    else if constexpr (pi_xcomb_default<P, S>()) return ((e.n[1] * P + 1) * (e.n[2] * P + 1) + 3) / 4;
+    else return e.nblk * (P + 1) * ((P + 1 + combine_brows<P>() - 1) / combine_brows<P>());
+}
+template <int P, typename S> static int pi_combine_items(int t) {
+    if constexpr (P >= 4 || pi_xcomb_default<P, S>()) return t;
+    else return (t + 3) / 4;
+}
+
+template <typename S, int ACC>
+static hipError_t launch_pi_mixed_t(ProbEntry* ents, int nprob, TableStager* st, hipStream_t s) {
+    static_assert(mix_degree(0) == 7 && mix_degree(1) == 3 && mix_degree(2) == 2, "segment degrees");
+    MixTable T{};
+    int grid = 0;
+    // 1. assembly into each problem's global-node array
+    auto rows4 = [](int p, const ProbEntry& e) { return ((e.n[1] * p + 1) * (e.n[2] * p + 1) + 3) / 4; };
+    auto same = [](int, int t) { return t; };
+    hipError_t err = mix_build(ents, nprob, st, s, rows4, same, T, grid);
+    if (err != hipSuccess) return err;
+    if (grid > 0) {
+        TraceSpan ts("pi_assemble", 0, Prec<S>::id, s);
+        hipLaunchKernelGGL((k_mixed<AssembleBody<7, S>, AssembleBody<3, S>, AssembleBody<2, S>>), dim3(grid),
+                           dim3(256), 0, s, T, NoArg{}, NoArg{}, NoArg{});
+        err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    // 2. patch solves
+    auto stiles = [](int p, const ProbEntry& e) {
+        return p == 7 ? pi_solve_tiles<7, S>(e) : p == 3 ? pi_solve_tiles<3, S>(e) : pi_solve_tiles<2, S>(e);
+    };
+    auto sitems = [](int p, int t) { return p == 7 ? pi_solve_items<7>(t) : t; };
+    err = mix_build(ents, nprob, st, s, stiles, sitems, T, grid);
+    if (err != hipSuccess) return err;
+    if (grid > 0) {
+        TraceSpan ts("pi_solve", 0, Prec<S>::id, s);
+        hipLaunchKernelGGL((k_mixed<SolveBody<7, S>, SolveBody<3, S>, SolveBody<2, S>>), dim3(grid), dim3(256), 0, s,
+                           T, NoArg{}, NoArg{}, NoArg{});
+        err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    // 3. combine into the cells
+    auto ctiles = [](int p, const ProbEntry& e) {
+        return p == 7 ? pi_combine_tiles<7, S>(e) : p == 3 ? pi_combine_tiles<3, S>(e) : pi_combine_tiles<2, S>(e);
+    };
+    auto citems = [](int p, int t) {
+        return p == 7 ? pi_combine_items<7, S>(t) : p == 3 ? pi_combine_items<3, S>(t) : pi_combine_items<2, S>(t);
+    };
+    err = mix_build(ents, nprob, st, s, ctiles, citems, T, grid);
+    if (err != hipSuccess || grid == 0) return err;
+    TraceSpan ts("pi_combine", 0, Prec<S>::id, s);
+    hipLaunchKernelGGL((k_mixed<CombineBody<7, S, ACC>, CombineBody<3, S, ACC>, CombineBody<2, S, ACC>>), dim3(grid),
+                       dim3(256), 0, s, T, NoArg{}, NoArg{}, NoArg{});
+    return hipGetLastError();
+}
+
+template <typename S>
+static hipError_t launch_pi_mixed_a(int accumulate, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s) {
+    return accumulate ? launch_pi_mixed_t<S, 1>(ents, nprob, st, s) : launch_pi_mixed_t<S, 0>(ents, nprob, st, s);
+}
+
+hipError_t launch_patch_inverse_any(int prec, int accumulate, ProbEntry* ents, int nprob, TableStager* st,
+                                    hipStream_t s, bool mix) {
+    if (nprob <= 0) return hipSuccess;
+    // the mixed bodies are the default variants: no process-wide override
+    if (mix && g_pi_fused < 0 && !g_restrict_from_cells && !g_combine_per_cell && mix_degrees(ents, nprob) >= 2) {
+        switch (prec) {
+            case FEM_F64: return launch_pi_mixed_a<double>(accumulate, ents, nprob, st, s);
+            case FEM_F32: return launch_pi_mixed_a<float>(accumulate, ents, nprob, st, s);
+            default: return launch_pi_mixed_a<bf16_t>(accumulate, ents, nprob, st, s);
+        }
+    }
+    std::vector<ProbEntry> g;
+    for (int p = 1; p <= kMaxP; ++p) {
+        g.clear();
+        for (int i = 0; i < nprob; ++i)
+            if (ents[i].p == p) g.push_back(ents[i]);
+        if (g.empty()) continue;
+        hipError_t err = launch_patch_inverse(p, prec, accumulate, g.data(), (int)g.size(), st, s);
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_patch_inverse(int p, int prec, int accumulate, ProbEntry* ents, int nprob,

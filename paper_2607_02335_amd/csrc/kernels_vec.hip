@@ -12,6 +12,7 @@
 
 #include "fem_internal.h"
 #include "launch.h"
+#include "mixed.h"
 #include "trace.h"
 
 namespace fem {
@@ -64,11 +65,11 @@ __global__ void __launch_bounds__(256) k_red_final(LaunchTable L, int group, int
 // Each global node is owned by its copy in the lowest-numbered cell along
 // every direction; the owner sums all copies (fixed order) and squares.
 template <int P, typename S, bool MULTI>
-__global__ void __launch_bounds__(256) k_anorm(LaunchTable L, int group) {
+__device__ __forceinline__ void anorm_body(const LaunchTable& L, int group, int item, int items, char* smem) {
     constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
-    __shared__ double sh[4];
+    double* sh = reinterpret_cast<double*>(smem);
     const int lane = threadIdx.x % kLanes, lq = threadIdx.x / kLanes;
-    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+    for (int tile = item; tile < L.total_tiles; tile += items) {
         const ProbEntry& pe = entry<MULTI>(L, tile);
         const int t = tile - pe.tile_begin;
         size_t lo, hi;
@@ -106,6 +107,12 @@ __global__ void __launch_bounds__(256) k_anorm(LaunchTable L, int group) {
     }
 }
 
+template <int P, typename S, bool MULTI>
+__global__ void __launch_bounds__(256) k_anorm(LaunchTable L, int group) {
+    __shared__ __align__(16) char smem[4 * sizeof(double)];
+    anorm_body<P, S, MULTI>(L, group, blockIdx.x, gridDim.x, smem);
+}
+
 // ------------------------------------- assembled residual for a demoted smoother
 // rs(copy) = (G^T r)(node) / multiplicity(node), summed in FP64 over all copies
 // in ascending cell order (the same order for every copy), then rounded to
@@ -134,11 +141,12 @@ struct Diag1D {
 };
 
 template <int P, typename RS, int MODE, bool MULTI>
-__global__ void __launch_bounds__(256) k_distribute(LaunchTable L, int group, Diag1D dg) {
+__device__ __forceinline__ void distribute_body(const LaunchTable& L, int group, const Diag1D& dg, int item, int items,
+                                                char* smem) {
     constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
-    __shared__ double sh[4];
+    double* sh = reinterpret_cast<double*>(smem);
     const int lane = threadIdx.x % kLanes, lq = threadIdx.x / kLanes;
-    for (int tile = blockIdx.x; tile < L.total_tiles; tile += gridDim.x) {
+    for (int tile = item; tile < L.total_tiles; tile += items) {
         const ProbEntry& pe = entry<MULTI>(L, tile);
         const int t = tile - pe.tile_begin;
         size_t lo, hi;
@@ -202,6 +210,12 @@ __global__ void __launch_bounds__(256) k_distribute(LaunchTable L, int group, Di
         const double r = block_sum(acc, sh);
         if (threadIdx.x == 0) pe.red[group * kRedParts + t] = r;
     }
+}
+
+template <int P, typename RS, int MODE, bool MULTI>
+__global__ void __launch_bounds__(256) k_distribute(LaunchTable L, int group, Diag1D dg) {
+    __shared__ __align__(16) char smem[4 * sizeof(double)];
+    distribute_body<P, RS, MODE, MULTI>(L, group, dg, blockIdx.x, gridDim.x, smem);
 }
 
 // ------------------------------------------------------------ DSS axis pass
@@ -944,6 +958,78 @@ hipError_t launch_distribute(int p, int prec, ProbEntry* ents, int nprob, TableS
     return final_multi(L, s, 2, slot);
 }
 
+// Mixed-degree norm passes (the FP64 assembled norm, or the norm with the
+// smoother's copy of the residual): one item per reduction tile; the
+// per-problem finals run over the whole table.
+template <int P, typename S>
+struct AnormBody {
+    using Arg = NoArg;
+    static constexpr int kLds = 4 * sizeof(double);
+    __device__ static __forceinline__ void run(const LaunchTable& L, const NoArg&, int item, int items, char* smem) {
+        anorm_body<P, S, true>(L, 1, item, items, smem);
+    }
+};
+
+template <int P, typename RS>
+struct DistributeBody {
+    using Arg = NoArg;
+    static constexpr int kLds = 4 * sizeof(double);
+    __device__ static __forceinline__ void run(const LaunchTable& L, const NoArg&, int item, int items, char* smem) {
+        distribute_body<P, RS, kDistMean, true>(L, 2, Diag1D{}, item, items, smem);
+    }
+};
+
+static hipError_t launch_norm_mixed(int kind, int prec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s,
+                                    int slot) {
+    static_assert(mix_degree(0) == 7 && mix_degree(1) == 3 && mix_degree(2) == 2, "segment degrees");
+    MixTable T{};
+    int grid = 0;
+    auto tiles = [](int, const ProbEntry& e) { return e.ntiles_red; };
+    auto items = [](int, int t) { return t; };
+    hipError_t err = mix_build(ents, nprob, st, s, tiles, items, T, grid);
+    if (err != hipSuccess) return err;
+    if (grid > 0) {
+        if (kind == 1) {
+            TraceSpan ts("anorm", 0, FEM_F64, s);
+            hipLaunchKernelGGL((k_mixed<AnormBody<7, double>, AnormBody<3, double>, AnormBody<2, double>>), dim3(grid),
+                               dim3(256), 0, s, T, NoArg{}, NoArg{}, NoArg{});
+        } else {
+            err = dispatch_prec(prec, [&](auto tag) {
+                using S = decltype(tag);
+                TraceSpan ts("distribute", 0, Prec<S>::id, s);
+                hipLaunchKernelGGL((k_mixed<DistributeBody<7, S>, DistributeBody<3, S>, DistributeBody<2, S>>),
+                                   dim3(grid), dim3(256), 0, s, T, NoArg{}, NoArg{}, NoArg{});
+                return hipGetLastError();
+            });
+        }
+        if (err == hipSuccess) err = hipGetLastError();
+        if (err != hipSuccess) return err;
+    }
+    // the whole table (segment 0 starts it) for the per-problem finals
+    LaunchTable Lall{};
+    Lall.nprob = nprob;
+    Lall.tab = T.seg[0].L.tab;
+    return final_multi(Lall, s, kind, slot);
+}
+
+hipError_t launch_norm_any(int smoother_prec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int slot,
+                           bool mix) {
+    if (nprob <= 0) return hipSuccess;
+    const int kind = smoother_prec == FEM_F64 ? 1 : 2;
+    if (mix && mix_degrees(ents, nprob) >= 2) return launch_norm_mixed(kind, smoother_prec, ents, nprob, st, s, slot);
+    std::vector<ProbEntry> g;
+    for (int p = 1; p <= kMaxP; ++p) {
+        g.clear();
+        for (int i = 0; i < nprob; ++i)
+            if (ents[i].p == p) g.push_back(ents[i]);
+        if (g.empty()) continue;
+        hipError_t err = kind == 1 ? launch_anorm(p, g.data(), (int)g.size(), st, s, slot)
+                                   : launch_distribute(p, smoother_prec, g.data(), (int)g.size(), st, s, slot);
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
+}
+
 template <int P>
 static void launch_anorm_p(LaunchTable& L, int grid, hipStream_t s) {
     if (L.nprob > 1) hipLaunchKernelGGL((k_anorm<P, double, true>), dim3(grid), dim3(256), 0, s, L, 1);
@@ -1093,11 +1179,14 @@ hipError_t launch_convert(int sp, int dp, ProbEntry* ents, int nprob, TableStage
 // ------------------------------------------------------------- stager
 hipError_t TableStager::init(int cap_entries) {
     cap = cap_entries;
+    const size_t slot = sizeof(ProbEntry) * cap;
+    hipError_t e = hipHostMalloc((void**)&host_block, slot * kSlots, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    e = hipMalloc((void**)&dev_block, slot * kSlots);
+    if (e != hipSuccess) return e;
     for (int i = 0; i < kSlots; ++i) {
-        hipError_t e = hipHostMalloc((void**)&host[i], sizeof(ProbEntry) * cap, hipHostMallocDefault);
-        if (e != hipSuccess) return e;
-        e = hipMalloc((void**)&dev[i], sizeof(ProbEntry) * cap);
-        if (e != hipSuccess) return e;
+        host[i] = host_block + (size_t)i * cap;
+        dev[i] = dev_block + (size_t)i * cap;
         e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
         if (e != hipSuccess) return e;
         used[i] = false;
@@ -1108,13 +1197,16 @@ hipError_t TableStager::init(int cap_entries) {
 void TableStager::destroy() {
     for (int i = 0; i < kSlots; ++i) {
         if (used[i]) hipEventSynchronize(ev[i]);
-        if (host[i]) hipHostFree(host[i]);
-        if (dev[i]) hipFree(dev[i]);
         if (ev[i]) hipEventDestroy(ev[i]);
         host[i] = nullptr;
         dev[i] = nullptr;
         ev[i] = nullptr;
+        used[i] = false;
     }
+    if (host_block) hipHostFree(host_block);
+    if (dev_block) hipFree(dev_block);
+    host_block = nullptr;
+    dev_block = nullptr;
 }
 
 hipError_t TableStager::upload(const ProbEntry* ents, int n, hipStream_t s, const ProbEntry** out) {

@@ -65,8 +65,12 @@ const double* ref_stiff(int p);
 // only after the copy that read it has run (event), and the device side only
 // by work later on the same stream.
 struct TableStager {
-    static constexpr int kSlots = 64;
+    // enough slots for the uploads of many launches in flight (a server step
+    // stages a table per launch), so the host seldom waits for a slot
+    static constexpr int kSlots = 256;
     int cap = 0;
+    ProbEntry* host_block = nullptr;   // kSlots * cap entries, pinned
+    ProbEntry* dev_block = nullptr;    // kSlots * cap entries
     ProbEntry* host[kSlots] = {};
     ProbEntry* dev[kSlots] = {};
     hipEvent_t ev[kSlots] = {};
@@ -101,10 +105,19 @@ inline hipError_t stage_table(LaunchTable& L, const ProbEntry* ents, int nprob, 
 // apply: mode 0 y=Ax (a=x, c=y), 1 y=b-Ax (a=x, b=b, c=y), 2 y=Mx.
 hipError_t launch_apply(int p, int prec, int mode, ProbEntry* ents, int nprob, TableStager* st,
                         hipStream_t s, const LaunchCfg& cfg = LaunchCfg());
+// apply over problems of any degrees: with `mix`, one mixed-degree launch
+// when the degrees are two or three of {2, 3, 7}, else one launch per degree
+// (the same kernel bodies and results either way)
+hipError_t launch_apply_any(int prec, int mode, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s,
+                            bool mix = true);
 // patch inverse: a = r (dual), c = z (primal), d = patch buffer,
 // alpha = damping; accumulate: z = (acc ? z : 0) + alpha * P_AS r.
 hipError_t launch_patch_inverse(int p, int prec, int accumulate, ProbEntry* ents, int nprob,
                                 TableStager* st, hipStream_t s, const LaunchCfg& cfg = LaunchCfg());
+
+// patch inverse over problems of any degrees (as launch_apply_any)
+hipError_t launch_patch_inverse_any(int prec, int accumulate, ProbEntry* ents, int nprob, TableStager* st,
+                                    hipStream_t s, bool mix = true);
 
 // Multi-problem vector operations (all problems in `ents`, any degrees where
 // noted).  Operands in the entries as for the single-problem versions.
@@ -113,6 +126,10 @@ hipError_t launch_dot(int pa, int pb, ProbEntry* ents, int nprob, TableStager* s
 // distribute + norm (one degree p): a = r (FP64), c = out (prec); slot <- ||G^T r||^2
 hipError_t launch_distribute(int p, int prec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s,
                              int slot);
+// residual norm over problems of any degrees (as launch_apply_any): the
+// assembled norm for an FP64 smoother, else distribute + norm
+hipError_t launch_norm_any(int smoother_prec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int slot,
+                           bool mix = true);
 // assembled norm (one degree p): a = r (FP64); slot <- ||G^T r||^2
 hipError_t launch_anorm(int p, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, int slot);
 // r -= alpha q with alpha = <r,z>/<q,p> (saved in kSlotAlpha); entries b = q,
@@ -148,6 +165,8 @@ hipError_t launch_convert(int sp, int dp, ProbEntry* ents, int nprob, TableStage
 hipError_t run_coarse_correction(fem_problem* P, const void* t, void* z, int prec);
 // The same over several problems of degree p (entries from coarse_entry).
 hipError_t launch_coarse_correction(int p, int prec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s);
+// The same over problems of any degrees (as launch_apply_any).
+hipError_t launch_coarse_any(int prec, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s, bool mix = true);
 ProbEntry coarse_entry(fem_problem* P, const void* t, void* z);
 
 // Single-problem helpers (problem handle in, stream of the handle).

@@ -89,6 +89,9 @@ def lib():
         "fem_batch_apply": ([vp, pp, pp, i], i),
         "fem_batch_patch_inverse": ([vp, pp, pp, i], i),
         "fem_batch_autotune": ([vp, i, ct.POINTER(i)], i),
+        "fem_batch_set_mixed": ([vp, i], i),
+        "fem_batch_mixed": ([vp], i),
+        "fem_server_set_mixed": ([vp, i], i),
         "fem_server_create": ([sz, i, i, i, d, vp, pp], i),
         "fem_server_destroy": ([vp], i),
         "fem_server_create_pc": ([sz, i, i, i, i, d, vp, pp], i),
@@ -518,24 +521,27 @@ class Problem:
 
 
 class Batch:
-    """Independent problems launched together (one launch per degree)."""
+    """Independent problems launched together: one mixed-degree launch per
+    kernel phase when the degrees are two or three of {2, 3, 7}, else one
+    launch per degree."""
 
     def __init__(self, problems):
-        """problems: list of (p, n, widths-or-None)."""
+        """problems: list of (p, n, widths-or-None) or (p, n, widths-or-None, bc)."""
         descs = (Desc * len(problems))()
         self._descs = []
-        for i, (p, n, w) in enumerate(problems):
-            d = make_desc(p, n, w)
+        spec = [(t[0], t[1], t[2], t[3] if len(t) > 3 else DIRICHLET) for t in problems]
+        for i, (p, n, w, bc) in enumerate(spec):
+            d = make_desc(p, n, w, bc)
             self._descs.append(d)
             descs[i] = d
         h = ct.c_void_p()
         check(lib().fem_batch_create(len(problems), descs, _stream(), ct.byref(h)), "fem_batch_create")
         self.h = h
         self.problems = []
-        for i, (p, n, w) in enumerate(problems):
+        for i, (p, n, w, bc) in enumerate(spec):
             ph = ct.c_void_p()
             check(lib().fem_batch_problem(self.h, i, ct.byref(ph)), "fem_batch_problem")
-            self.problems.append(Problem(p, n, w, _handle=ph))
+            self.problems.append(Problem(p, n, w, bc, _handle=ph))
 
     def close(self):
         if getattr(self, "h", None):
@@ -581,6 +587,14 @@ class Batch:
         return {p: (choice[2 * (p - 1)], choice[2 * (p - 1) + 1]) for p in range(1, 8)
                 if choice[2 * (p - 1)] >= 0}
 
+    def set_mixed(self, mixed):
+        check(lib().fem_batch_set_mixed(self.h, 1 if mixed else 0), "fem_batch_set_mixed")
+
+    @property
+    def mixed(self):
+        """True if the batched calls run as mixed-degree launches."""
+        return bool(lib().fem_batch_mixed(self.h))
+
 
 class Server:
     """Continuous-batching Poisson solve server (device-resident solves)."""
@@ -615,6 +629,9 @@ class Server:
               "fem_server_submit")
         self.glen[t.value] = f.size
         return t.value
+
+    def set_mixed(self, mixed):
+        check(lib().fem_server_set_mixed(self.h, 1 if mixed else 0), "fem_server_set_mixed")
 
     def step(self):
         a, q, dn = ct.c_int(), ct.c_int(), ct.c_int()
