@@ -286,8 +286,9 @@ fem_status fem_batch_apply(fem_batch* B, void* const* x, void* const* y, int pre
 fem_status fem_batch_patch_inverse(fem_batch* B, void* const* r, void* const* z, int prec);
 /* Tile-shape autotuner: for each degree present in the batch, time the
  * candidate kernel shapes on the batch's own problems (apply: register
- * (p <= 3) or plane-streamed (p >= 4) kernel, or the LDS line kernel, each x
- * two persistent grid caps; patch inverse for p <= 3: two launches through
+ * (p <= 3) or plane-streamed (p >= 4; for p = 7 in FP64 the matrix-core
+ * kernel) kernel, or the LDS line kernel, and for p = 7 also the
+ * plane-streamed kernel, each x two persistent grid caps; patch inverse for p <= 3: two launches through
  * the patch buffer, fused sweep from the cell copies, fused sweep from the
  * assembled residual, or solves with the in-tile x-combine; for p >= 4: MFMA
  * or line patch solves; each x two grid caps) and keep the fastest for later
@@ -458,14 +459,17 @@ fem_status fem_host_fd_1d(int p, double h0, double h1, double* S, double* lambda
  * m > 0 runs the p <= 3 two-launch patch inverse of a single problem in
  * z-slabs of about m MB of patch results each (solve, then combine what is
  * complete), so the results are re-read from the Infinity Cache; 0 (default)
- * launches each phase once.  Every variant gives
+ * launches each phase once.  FEM_OPT_APPLY_PLANES_P7 = 1 runs the p = 7
+ * FP64 Laplace and residual applies on the plane-streamed VALU kernel
+ * instead of the matrix-core (MFMA) one.  Every variant gives
  * the same result up to the rounding of the summation order (bitwise
  * continuous in all cases).  Unknown options or values are FEM_EINVAL. */
 typedef enum fem_option {
     FEM_OPT_PI_FUSED = 1,
     FEM_OPT_COMBINE_PER_CELL = 2,
     FEM_OPT_RESTRICT_FROM_CELLS = 3,
-    FEM_OPT_PI_SLAB_MB = 4
+    FEM_OPT_PI_SLAB_MB = 4,
+    FEM_OPT_APPLY_PLANES_P7 = 5
 } fem_option;
 fem_status fem_set_option(int option, int value);
 

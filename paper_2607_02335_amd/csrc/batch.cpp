@@ -221,13 +221,14 @@ extern "C" fem_status fem_batch_autotune(fem_batch* B, int prec, int* choice) {
     for (int p = 1; p <= kMaxP && result == FEM_OK; ++p) {
         if (B->group[p].empty()) continue;
         for (int which = 0; which < 2 && result == FEM_OK; ++which) {
-            // apply: 0 = register (p <= 3) / plane-streamed (p >= 4) kernel,
-            //        1 = LDS line kernel;
+            // apply: 0 = register (p <= 3) / plane-streamed (p >= 4; matrix-core
+            //        for p = 7 in FP64) kernel, 1 = LDS line kernel,
+            //        2 = plane-streamed (p = 7);
             // patch inverse, p <= 3: 0 = two launches through the patch buffer,
             //        1 = fused sweep summing cell copies, 2 = fused sweep from the
             //        assembled residual, 3 = solves with the in-tile x-combine;
             //        p >= 4: 0 = MFMA solves, 2 = line solves
-            std::vector<int> kinds = which == 0 ? std::vector<int>{0, 1}
+            std::vector<int> kinds = which == 0 ? (p == 7 ? std::vector<int>{0, 1, 2} : std::vector<int>{0, 1})
                                    : (p <= 3 ? std::vector<int>{0, 1, 2, 3} : std::vector<int>{0, 2});
             std::vector<LaunchCfg> cand;
             for (int kind : kinds) {

@@ -360,7 +360,13 @@ int host_gen_eig(int n, const std::vector<double>& M, const std::vector<double>&
 
 using namespace fem;
 
-namespace fem { extern int g_pi_fused; extern int g_combine_per_cell; extern int g_restrict_from_cells; extern int g_pi_slab_mb; }
+namespace fem {
+extern int g_pi_fused;
+extern int g_combine_per_cell;
+extern int g_restrict_from_cells;
+extern int g_pi_slab_mb;
+extern int g_apply_planes_p7;
+}  // namespace fem
 
 extern "C" fem_status fem_set_option(int option, int value) {
     switch (option) {
@@ -374,6 +380,7 @@ extern "C" fem_status fem_set_option(int option, int value) {
             if (value < 0) return set_error(FEM_EINVAL, "fem_set_option: FEM_OPT_PI_SLAB_MB >= 0");
             fem::g_pi_slab_mb = value;
             return FEM_OK;
+        case FEM_OPT_APPLY_PLANES_P7: fem::g_apply_planes_p7 = value ? 1 : 0; return FEM_OK;
         default: return set_error(FEM_EINVAL, "fem_set_option: unknown option");
     }
 }

@@ -23,10 +23,15 @@
 //    the three directions with one thread per 1D line.
 #include "fem_internal.h"
 #include "launch.h"
+#include "mfma.h"
 #include "mixed.h"
 #include "trace.h"
 
 namespace fem {
+
+// Process-wide switch for comparisons (FEM_OPT_APPLY_PLANES_P7): 1 runs the
+// p = 7 Laplace and residual applies on the plane-streamed VALU kernel.
+int g_apply_planes_p7 = 0;
 
 enum ApplyMode { kApplyLaplace = 0, kApplyResidual = 1, kApplyMass = 2 };
 
@@ -529,6 +534,217 @@ k_apply_planes(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
     apply_planes_body<P, S, MODE, MULTI>(L, R, blockIdx.x, gridDim.x, smem);
 }
 
+// The matrix-core apply serves p = 7 in the Laplace and residual modes in
+// FP64; with 4-byte values the plane-streamed kernel measured faster.
+template <int P, int MODE, typename C> constexpr bool apply_mfma_default() {
+    return P == 7 && MODE != kApplyMass && sizeof(C) == 8;
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-core apply for p = 7 (Laplace and residual modes).  Each 1D
+// contraction of a cell is a dense 16x16 product on the MFMA units, one cell
+// per wavefront, with the cell's 64 lines of a direction in four 16-line
+// tiles (the B operand, from LDS) and the 1D matrices stacked into a 16-row
+// A operand held in registers:
+//   z: [Mz; Kz] (16 x 8) u                     -> A = Mz u, Bz = Kz u
+//   y: [[My, 0], [cy Ky, cz My]] [A; Bz]        -> D = My A, C
+//   x: [[Mx, cx Kx], [0, 0]] [C; D]             -> y (rows 0..7)
+// so a cell takes 8 + 16 + 16 products, the cell's geometry entering only
+// through the A operands.  Between passes the tiles go through the cell's
+// LDS region (a 16-row matrix, rows padded to an odd stride) to the next
+// direction's line order.  A workgroup stages 8 consecutive cells of a
+// storage block (64-byte runs of every node in FP64) in LDS, each of its
+// four wavefronts computes two of them, and the results leave through the
+// same region as coalesced stores.
+template <typename C> struct ApplyMfmaShape {
+    static constexpr int CB = 8;                 // cells per workgroup tile
+    static constexpr int KS = 65;                // row stride of the 16-row intermediates
+    static constexpr int RG = 16 * KS + 24;      // per-cell region (8 mod 32: staged cells on distinct banks)
+    static constexpr int kLds = CB * RG * (int)sizeof(C);
+};
+
+// node l of the cell's input / output (rows of 8 padded to 9)
+__device__ __forceinline__ int mfma_node(int l) { return l + (l >> 3); }
+
+template <int P, typename S, int MODE, bool MULTI>
+__device__ __forceinline__ void apply_mfma_body(const LaunchTable& L, const RefMats<P, typename Prec<S>::C>& R,
+                                                int item, int items, char* smem) {
+    using C = typename Prec<S>::C;
+    using M = Mfma<C>;
+    static_assert(P == 7, "the matrix-core apply is written for 8 nodes per direction");
+    constexpr int N = P + 1, NN = N * N * N;
+    constexpr int CB = ApplyMfmaShape<C>::CB, KS = ApplyMfmaShape<C>::KS, RG = ApplyMfmaShape<C>::RG;
+    static_assert(256 % CB == 0 && kLanes % CB == 0 && (NN * CB) % 256 == 0, "staging shape");
+    constexpr int LPT = NN * CB / 256;               // staged values per thread
+    C* reg = reinterpret_cast<C*>(smem);
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int g = lane >> 4, col = lane & 15;
+    // cell-independent A operands (lane: row col, k = 4 ks + g)
+    C az[2], ayb[4], axb[4];
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+        const int k = 4 * ks + g;
+        az[ks] = col < N ? R.M[col * N + k] : R.K[(col - N) * N + k];
+    }
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+        const int k = 4 * ks + g, kk = k % N;
+        if (ks < 2) ayb[ks] = col < N ? R.M[col * N + kk] : R.K[(col - N) * N + kk];
+        else ayb[ks] = col < N ? (C)0 : R.M[(col - N) * N + kk];
+        axb[ks] = col < N ? (ks < 2 ? R.M[col * N + kk] : R.K[col * N + kk]) : (C)0;
+    }
+    // staging: thread tid moves cell scell's nodes l = l0 + 32 i (i < 16),
+    // i.e. a = l0 % 8 (fixed), b = wv + 4 (i % 2), c = i / 2
+    static_assert(CB == 8 && LPT == 16, "staging map");
+    const int scell = tid % CB, l0 = tid / CB, sa = l0 % N;
+    C pre[LPT];                                      // the next tile's staged values
+    // boundary copies of the staged cell (Dirichlet), as masks over i
+    auto stage_mask = [&](const ProbEntry& pe, int e) -> uint32_t {
+        if (e >= pe.ncells) return 0xffffu;
+        const CellGeom<C> gs = cell_geom<C>(pe, e);
+        const bool xm = (sa == 0 && gs.xlo) || (sa == P && gs.xhi);
+        uint32_t m = 0;
+#pragma unroll
+        for (int i = 0; i < LPT; ++i) {
+            const int b = wv + 4 * (i % 2), c = i / 2;
+            const bool bm = xm || (b == 0 && gs.ylo) || (b == P && gs.yhi) || (c == 0 && gs.zlo) || (c == P && gs.zhi);
+            m |= (bm ? 1u : 0u) << i;
+        }
+        return m;
+    };
+    auto fetch = [&](int tile) {
+        const ProbEntry& pe = entry<MULTI>(L, tile);
+        const int t = tile - pe.tile_begin;
+        const int blk = t / (kLanes / CB), lane0 = (t % (kLanes / CB)) * CB;
+        const S* __restrict__ x = static_cast<const S*>(pe.a) + (size_t)blk * NN * kLanes + lane0 + scell +
+                                  (size_t)l0 * kLanes;
+        const uint32_t m = stage_mask(pe, blk * kLanes + lane0 + scell);
+#pragma unroll
+        for (int i = 0; i < LPT; ++i)
+            pre[i] = ((m >> i) & 1u) ? (C)0 : load_as<C>(x + (size_t)(32 * i) * kLanes);
+    };
+    if (item < L.total_tiles) fetch(item);
+    for (int tile = item; tile < L.total_tiles; tile += items) {
+        const ProbEntry& pe = entry<MULTI>(L, tile);
+        const int t = tile - pe.tile_begin;
+        const int blk = t / (kLanes / CB), lane0 = (t % (kLanes / CB)) * CB;
+        const size_t base = (size_t)blk * NN * kLanes + lane0;
+        S* __restrict__ y = static_cast<S*>(pe.c) + base;
+        const uint32_t smask = stage_mask(pe, blk * kLanes + lane0 + scell);
+#pragma unroll
+        for (int i = 0; i < LPT; ++i) reg[scell * RG + mfma_node(l0 + 32 * i)] = pre[i];
+        __syncthreads();
+        // the next tile's loads are in flight while this one computes
+        if (tile + items < L.total_tiles) fetch(tile + items);
+#pragma unroll 1
+        for (int cc = wv; cc < CB; cc += 4) {
+            const int e = blk * kLanes + lane0 + cc;
+            if (e >= pe.ncells) continue;                // uniform over the wavefront
+            const CellGeom<C> gc = cell_geom<C>(pe, e);
+            C* rg = reg + cc * RG;
+            typename M::V acc[4];
+            // z: lines (a, b) = (col % 8, 2 t + col / 8), k = c
+            {
+                C bz[4][2];
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+                    for (int ks = 0; ks < 2; ++ks) bz[tt][ks] = rg[mfma_node(col + 16 * tt + 64 * (4 * ks + g))];
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt) {
+                    acc[tt] = typename M::V{0, 0, 0, 0};
+#pragma unroll
+                    for (int ks = 0; ks < 2; ++ks) acc[tt] = M::mma(az[ks], bz[tt][ks], acc[tt]);
+                }
+                wave_sync();
+                // row j < 8: A at c' = j, else Bz at c' = j - 8; stored as the y
+                // pass's rows k = b (A) and 8 + b (Bz), lines (a, c')
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int j = M::row(lane, r), a = col % N, b = 2 * tt + col / N;
+                        const int k = j < N ? b : N + b;
+                        rg[k * KS + (j % N) * N + a] = acc[tt][r];
+                    }
+                wave_sync();
+            }
+            // y: lines (a, c') = (col % 8, 2 t + col / 8), k over [A; Bz]
+            {
+                C ay[4], by[4][4];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) ay[ks] = col < N ? ayb[ks] : ayb[ks] * (ks < 2 ? gc.cy : gc.cz);
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) by[tt][ks] = rg[(4 * ks + g) * KS + 16 * tt + col];
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt) {
+                    acc[tt] = typename M::V{0, 0, 0, 0};
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) acc[tt] = M::mma(ay[ks], by[tt][ks], acc[tt]);
+                }
+                wave_sync();
+                // row j < 8: D at b' = j, else C at b' = j - 8; stored as the x
+                // pass's rows k = a (C) and 8 + a (D), lines (b', c')
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int j = M::row(lane, r), a = col % N, c = 2 * tt + col / N;
+                        const int k = j < N ? N + a : a;
+                        rg[k * KS + c * N + (j % N)] = acc[tt][r];
+                    }
+                wave_sync();
+            }
+            // x: lines (b', c') = (col % 8, 2 t + col / 8), k over [C; D]
+            {
+                C ax[4], bx[4][4];
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) ax[ks] = ks < 2 ? axb[ks] : axb[ks] * gc.cx;
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) bx[tt][ks] = rg[(4 * ks + g) * KS + 16 * tt + col];
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt) {
+                    acc[tt] = typename M::V{0, 0, 0, 0};
+#pragma unroll
+                    for (int ks = 0; ks < 4; ++ks) acc[tt] = M::mma(ax[ks], bx[tt][ks], acc[tt]);
+                }
+                wave_sync();
+                // rows 0..7: y at a = j, node j + 8 b' + 64 c'
+#pragma unroll
+                for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int j = M::row(lane, r);
+                        if (j < N) rg[mfma_node(j + N * (col % N) + N * N * (2 * tt + col / N))] = acc[tt][r];
+                    }
+            }
+        }
+        __syncthreads();
+        // store: node l0 + 32 i of cell scell
+        const S* __restrict__ rres = (MODE == kApplyResidual) ? static_cast<const S*>(pe.b) + base : nullptr;
+#pragma unroll
+        for (int i = 0; i < LPT; ++i) {
+            const int l = l0 + 32 * i;
+            const size_t off = (size_t)l * kLanes + scell;
+            C v = reg[scell * RG + mfma_node(l)];
+            if (MODE == kApplyResidual) v = load_as<C>(rres + off) - v;
+            if ((smask >> i) & 1u) v = (C)0;
+            store_from(y + off, v);
+        }
+        __syncthreads();
+    }
+}
+
+template <int P, typename S, int MODE, bool MULTI>
+__global__ void __launch_bounds__(256) k_apply_mfma(LaunchTable L, RefMats<P, typename Prec<S>::C> R) {
+    __shared__ __align__(16) char smem[ApplyMfmaShape<typename Prec<S>::C>::kLds];
+    apply_mfma_body<P, S, MODE, MULTI>(L, R, blockIdx.x, gridDim.x, smem);
+}
+
 template <int P> constexpr int lds_cells(int bytes) {
     // largest power of two <= 64 with two LDS arrays within 64 KiB
     int cb = 64;
@@ -544,13 +760,19 @@ static hipError_t launch_apply_t(ProbEntry* ents, int nprob, TableStager* d_tab,
     using C = typename Prec<S>::C;
     const RefMats<P, C> R = ref_mats<P, C>();
     const bool use_reg = (P <= 3) && !force_lds;
-    const bool use_planes = (P >= 4) && !force_lds;
+    // p = 7 (Laplace, residual): the matrix-core apply unless the plane-streamed
+    // one is asked for (apply_lds = 2, or the process-wide option)
+    const bool use_mfma = apply_mfma_default<P, MODE, C>() && !force_lds && g_apply_planes_p7 == 0;
+    const bool use_planes = (P >= 4) && !use_mfma && (force_lds == 0 || force_lds == 2);
     constexpr int CB = lds_cells<P>((int)sizeof(C));
+    constexpr int MCB = ApplyMfmaShape<C>::CB;
     LaunchTable L{};
     int tiles = 0;
     for (int i = 0; i < nprob; ++i) {
         ents[i].tile_begin = tiles;
-        ents[i].ntiles = use_reg ? ents[i].nblk : use_planes ? ents[i].nblk * (kLanes / 16) : ents[i].nblk * (kLanes / CB);
+        ents[i].ntiles = use_reg ? ents[i].nblk
+                       : use_mfma ? ents[i].nblk * (kLanes / MCB)
+                       : use_planes ? ents[i].nblk * (kLanes / 16) : ents[i].nblk * (kLanes / CB);
         tiles += ents[i].ntiles;
     }
     L.nprob = nprob;
@@ -565,6 +787,14 @@ static hipError_t launch_apply_t(ProbEntry* ents, int nprob, TableStager* d_tab,
             const int grid = (tiles + 3) / 4 < gcap ? (tiles + 3) / 4 : gcap;
             if (nprob > 1) hipLaunchKernelGGL((k_apply_reg<P, S, MODE, true>), dim3(grid), dim3(256), 0, s, L, R);
             else hipLaunchKernelGGL((k_apply_reg<P, S, MODE, false>), dim3(grid), dim3(256), 0, s, L, R);
+            return hipGetLastError();
+        }
+    }
+    if constexpr (apply_mfma_default<P, MODE, C>()) {
+        if (use_mfma) {
+            const int grid = tiles < gcap ? tiles : gcap;
+            if (nprob > 1) hipLaunchKernelGGL((k_apply_mfma<P, S, MODE, true>), dim3(grid), dim3(256), 0, s, L, R);
+            else hipLaunchKernelGGL((k_apply_mfma<P, S, MODE, false>), dim3(grid), dim3(256), 0, s, L, R);
             return hipGetLastError();
         }
     }
@@ -607,6 +837,9 @@ static hipError_t launch_apply_p(int prec, int mode, ProbEntry* e, int n, TableS
 // Mixed-degree apply: the register body for p = 2, 3 (four storage blocks
 // per item, one per wavefront) and the plane-streamed body for p = 7 (16
 // cells per item), in one persistent launch.
+// (p = 7 takes the plane-streamed body: the mixed launch serves 4-byte
+// values only when p = 7 is present, see launch_apply_any, and the
+// matrix-core body's accumulator registers would bound the whole launch)
 template <int P, typename S, int MODE>
 struct ApplyBody {
     using C = typename Prec<S>::C;
@@ -647,7 +880,12 @@ static hipError_t launch_apply_mixed_m(int mode, ProbEntry* ents, int nprob, Tab
 hipError_t launch_apply_any(int prec, int mode, ProbEntry* ents, int nprob, TableStager* st, hipStream_t s,
                             bool mix) {
     if (nprob <= 0) return hipSuccess;
-    if (mix && mix_degrees(ents, nprob) >= 2) {
+    // the mixed p = 7 body is the plane-streamed one, the default for 4-byte
+    // values and the mass apply; FP64 Laplace and residual applies with p = 7
+    // present take one launch per degree (p = 7 on the matrix cores)
+    bool p7_mfma = false;
+    for (int i = 0; i < nprob; ++i) p7_mfma = p7_mfma || (ents[i].p == 7 && prec == FEM_F64 && mode != kApplyMass);
+    if (mix && mix_degrees(ents, nprob) >= 2 && (!p7_mfma || g_apply_planes_p7 != 0)) {
         switch (prec) {
             case FEM_F64: return launch_apply_mixed_m<double>(mode, ents, nprob, st, s);
             case FEM_F32: return launch_apply_mixed_m<float>(mode, ents, nprob, st, s);

@@ -23,6 +23,7 @@
 
 #include "fem_internal.h"
 #include "launch.h"
+#include "mfma.h"
 #include "mixed.h"
 #include "trace.h"
 
@@ -2094,27 +2095,6 @@ __global__ void __launch_bounds__(256) k_pi_combine_rows(LaunchTable L) {
 // is first assembled into a global-node array (k_assemble_nodes), so a patch
 // reads its (2p-1)^3 box without summing copies, and the results go to a
 // patch-major buffer (one contiguous run per patch) for k_pi_combine_pm.
-typedef double v4d_t __attribute__((ext_vector_type(4)));
-typedef float v4f_t __attribute__((ext_vector_type(4)));
-
-template <typename C> struct Mfma;
-template <> struct Mfma<double> {
-    using V = v4d_t;
-    __device__ static V mma(double a, double b, V c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
-    // row of output register r held by lane l (column l % 16)
-    __device__ static int row(int l, int r) { return 4 * r + l / 16; }
-};
-template <> struct Mfma<float> {
-    using V = v4f_t;
-    __device__ static V mma(float a, float b, V c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-    __device__ static int row(int l, int r) { return 4 * (l / 16) + r; }
-};
-
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-}
-
 // out(j, line) = sum_i Op(j, i) v(i, line) in place over all lines of the
 // patch; Op's 16x4 slices for the four k-steps are in `a`.  The patch's WPP
 // wavefronts (sub = this one's index) take every WPP-th 16-line tile.

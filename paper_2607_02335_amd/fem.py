@@ -227,6 +227,7 @@ OPT_PI_FUSED = 1
 OPT_COMBINE_PER_CELL = 2
 OPT_RESTRICT_FROM_CELLS = 3
 OPT_PI_SLAB_MB = 4
+OPT_APPLY_PLANES_P7 = 5
 
 
 def set_option(option, value):
