@@ -580,6 +580,8 @@ static fem_status pcg_core(fem_problem* P, const double* b, double* u, double rt
     if (st != FEM_OK) return finish(st, 0, NAN);
     const double bn = std::sqrt(P->h_red[kSlotB2]);
     double rel = bn > 0 ? std::sqrt(P->h_red[kSlotRN]) / bn : 0.0;
+    // a non-finite right-hand side or initial residual: no iteration on it
+    if (!std::isfinite(bn) || !std::isfinite(rel)) return finish(FEM_EBREAKDOWN, 0, rel);
     if (bn == 0.0 || rel <= rtol) return finish(FEM_OK, 0, rel);
     // reduced-precision smoothers get the residual assembled in FP64 first
     if (schwarz && sp != FEM_F64) FEM_HIP(run_distribute(P, r, rs, sp, kSlotTmp), "pcg_solve distribute");
