@@ -15,6 +15,7 @@
 // Each 1D problem is reduced to a symmetric one by the Cholesky factor of M
 // and solved by cyclic Jacobi rotations in FP64.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -361,11 +362,11 @@ int host_gen_eig(int n, const std::vector<double>& M, const std::vector<double>&
 using namespace fem;
 
 namespace fem {
-extern int g_pi_fused;
-extern int g_combine_per_cell;
-extern int g_restrict_from_cells;
-extern int g_pi_slab_mb;
-extern int g_apply_planes_p7;
+extern std::atomic<int> g_pi_fused;
+extern std::atomic<int> g_combine_per_cell;
+extern std::atomic<int> g_restrict_from_cells;
+extern std::atomic<int> g_pi_slab_mb;
+extern std::atomic<int> g_apply_planes_p7;
 }  // namespace fem
 
 extern "C" fem_status fem_set_option(int option, int value) {

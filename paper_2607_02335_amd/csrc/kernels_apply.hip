@@ -21,6 +21,8 @@
 //    input cell plus a few planes.
 //  * k_apply_lds (any p): a workgroup owns CB cells staged in LDS and walks
 //    the three directions with one thread per 1D line.
+#include <atomic>
+
 #include "fem_internal.h"
 #include "launch.h"
 #include "mfma.h"
@@ -29,9 +31,10 @@
 
 namespace fem {
 
-// Process-wide switch for comparisons (FEM_OPT_APPLY_PLANES_P7): 1 runs the
-// p = 7 Laplace and residual applies on the plane-streamed VALU kernel.
-int g_apply_planes_p7 = 0;
+// Process-wide switch for comparisons (FEM_OPT_APPLY_PLANES_P7; atomic: any
+// thread may set it): 1 runs the p = 7 FP64 Laplace and residual applies on
+// the plane-streamed VALU kernel.
+std::atomic<int> g_apply_planes_p7{0};
 
 enum ApplyMode { kApplyLaplace = 0, kApplyResidual = 1, kApplyMass = 2 };
 

@@ -20,6 +20,7 @@
 //   global node, so all copies of a node receive bitwise identical values:
 //   the output is continuous exactly, not just to rounding.
 #include <algorithm>
+#include <atomic>
 
 #include "fem_internal.h"
 #include "launch.h"
@@ -29,19 +30,20 @@
 
 namespace fem {
 
-// 1: use the fused sweep (no patch buffer) for p <= 3; selected by
-// fem_set_option.  The two-phase path is the default: on MI355X it is faster
-// for every measured workload (the sweep's per-layer chain is latency-bound).
-int g_pi_fused = -1;
+// Process-wide kernel-variant switches (fem_set_option, for comparisons),
+// atomic because any thread may set them while others launch.
+// Patch-inverse variant: -1 picks by degree and precision, else the
+// FEM_OPT_PI_FUSED value.
+std::atomic<int> g_pi_fused{-1};
 // 1: combine the two-phase patch results with one wavefront per storage
 // block (all planes) instead of one per (block, plane).
-int g_combine_per_cell = 0;
+std::atomic<int> g_combine_per_cell{0};
 // 1: phase 1 of the p <= 3 patch inverse sums the copies from the cell-wise
 // vector itself instead of reading the owner-assembled global-node array.
-int g_restrict_from_cells = 0;
+std::atomic<int> g_restrict_from_cells{0};
 // Patch results per z-slab (MB) of the single-problem two-phase patch
 // inverse for p <= 3; 0 runs one solve and one combine launch.
-int g_pi_slab_mb = 0;
+std::atomic<int> g_pi_slab_mb{0};
 
 // Reciprocal of a positive normal value (the FD eigenvalue sums): the
 // hardware estimate refined by Newton-Raphson steps r <- r + r (1 - d r),
@@ -2563,7 +2565,8 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
         // patch buffer otherwise (4-byte values: the plain patch buffer is
         // the faster one)
         const int dflt = pi_xcomb_default<P, S>() ? 3 : 0;
-        const int fused = cfg.pi_fused >= 0 ? cfg.pi_fused : g_pi_fused >= 0 ? g_pi_fused : dflt;
+        const int gf = g_pi_fused.load(std::memory_order_relaxed);
+        const int fused = cfg.pi_fused >= 0 ? cfg.pi_fused : gf >= 0 ? gf : dflt;
         if (fused == 3) return launch_pi_xcomb<P, S>(accumulate, ents, nprob, d_tab, s,
                                                       cfg.grid_cap > 0 ? cfg.grid_cap : kMaxGrid);
         if (fused == 2) return launch_pi_sweep_g<P, S>(accumulate, ents, nprob, d_tab, s);
@@ -2571,7 +2574,8 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
     }
     const int gcap = cfg.grid_cap > 0 ? cfg.grid_cap : kMaxGrid;
     if constexpr (P >= 4) {
-        const int mode = cfg.pi_fused >= 0 ? cfg.pi_fused : g_pi_fused >= 0 ? g_pi_fused : 0;
+        const int gf = g_pi_fused.load(std::memory_order_relaxed);
+        const int mode = cfg.pi_fused >= 0 ? cfg.pi_fused : gf >= 0 ? gf : 0;
         if (mode != 2) return launch_pi_mfma<P, S>(accumulate, ents, nprob, d_tab, s, gcap);
     }
     using C = typename Prec<S>::C;
@@ -2581,7 +2585,8 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
             // slabs of at most ~pi_slab_bytes of patch results (one slab: plain two launches)
             const size_t pbytes = (size_t)(ents[0].n[0] - 1) * (ents[0].n[1] - 1) * (ents[0].n[2] - 1) *
                                   (2 * P - 1) * (2 * P - 1) * (2 * P - 1) * sizeof(C);
-            int nslab = g_pi_slab_mb > 0 ? (int)((pbytes + ((size_t)g_pi_slab_mb << 20) - 1) / ((size_t)g_pi_slab_mb << 20)) : 1;
+            const size_t slab_mb = (size_t)g_pi_slab_mb.load(std::memory_order_relaxed);
+            int nslab = slab_mb > 0 ? (int)((pbytes + (slab_mb << 20) - 1) / (slab_mb << 20)) : 1;
             nslab = std::max(1, std::min(nslab, std::max(1, ents[0].n[2] - 1)));
             if (nslab > 1) return launch_pi_slabs<P, S>(accumulate, ents[0], s, nslab, gcap);
         }
