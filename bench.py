@@ -5,7 +5,7 @@ widths U[0.5,1.5] (seed 1), FP64, x ~ U[-1,1]) is one pass of the operator
 and the smoother's patch solve:  y = A x (fe_apply), then z = P_AS y
 (patch_inverse).  The reported rate counts unique DoFs ((64*3+1)^3) per
 second of that pass; the per-operation rates, the Q2 (96^3) and Q7 (24^3)
-workloads, the Q7 solve times with FP64/FP32/BF16 smoothers, the 256-problem
+workloads, the Q7 solve times with FP64/FP32/BF16/FP16 smoothers, the 256-problem
 batch, the paper's own kernels (mass operator, structured DSS, assembled
 mass) and the 10,000-request serving stream (p50/p99 latency, solved DoF/s)
 are reported beside it.
@@ -456,7 +456,7 @@ def batch_times(fem, torch, steps, warmup, count=256, seed=3):
 
 
 def solve_times(fem, torch, reps):
-    """Q7 24^3 graded solve to 1e-8 with FP64/FP32/BF16 smoothers, for the
+    """Q7 24^3 graded solve to 1e-8 with FP64/FP32/BF16/FP16 smoothers, for the
     Schwarz smoother alone and for the two-level preconditioner."""
     import synth
     wl = synth.workload_q7_graded()
@@ -469,7 +469,7 @@ def solve_times(fem, torch, reps):
     # the Schwarz smoother (2 sweeps, omega 1/8) and the two-level method
     # (1 + 1 sweeps, omega 1/5, exact FP64 coarse correction)
     for pre, pc, sweeps, omega in (("", fem.PC_SCHWARZ, 2, 0.125), ("two_level_", fem.PC_TWO_LEVEL, 1, 0.2)):
-        for name, sp in (("fp64", fem.F64), ("fp32", fem.F32), ("bf16", fem.BF16)):
+        for name, sp in (("fp64", fem.F64), ("fp32", fem.F32), ("bf16", fem.BF16), ("fp16", fem.F16)):
             times, iters = [], None
             P.pcg_solve(b, smoother_prec=sp, precond=pc, sweeps=sweeps, omega=omega)          # warm
             for _ in range(reps):
@@ -535,7 +535,7 @@ def main():
     ap.add_argument("--requests", type=int, default=10000, help="serving mode: stream length")
     ap.add_argument("--serve-requests", type=int, default=10000,
                     help="requests of the serving stream in the default run (0: skip)")
-    ap.add_argument("--prec", choices=["f64", "f32", "bf16"], default="f64",
+    ap.add_argument("--prec", choices=["f64", "f32", "bf16", "f16"], default="f64",
                     help="storage precision of --only q2_96 / q7_24")
     a = ap.parse_args()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -573,7 +573,7 @@ def main():
             rec = layout_sweep(fem, torch)
         else:
             p, n = (2, 96) if a.only == "q2_96" else (7, 24)
-            prec = {"f64": fem.F64, "f32": fem.F32, "bf16": fem.BF16}[a.prec]
+            prec = {"f64": fem.F64, "f32": fem.F32, "bf16": fem.BF16, "f16": fem.F16}[a.prec]
             rec = measure_workload(fem, torch, p, n, 1, a.steps, a.warmup, prec)
             rec["prec"] = a.prec
         print(json.dumps({a.only: rec}))

@@ -33,7 +33,9 @@
  *          (i p + a, j p + b, k p + c).
  * Cell-wise vectors.  fem_cell_len() elements of the precision in use
  *          (FEM_F64: double, FEM_F32: float, FEM_BF16: bfloat16 bit pattern
- *          in uint16_t).  The order inside is private to the library; use
+ *          in uint16_t, FEM_F16: IEEE binary16 bit pattern in uint16_t; the
+ *          two 16-bit formats are computed in FP32 and rounded to nearest
+ *          even when stored).  The order inside is private to the library; use
  *          fem_pack/fem_unpack (canonical [cell][local node] order) or
  *          fem_gather/fem_scatter/fem_extract (global order) to move data in
  *          and out.  Padding entries are kept at zero by every call.
@@ -74,7 +76,7 @@ typedef enum fem_status {
     FEM_ENOTFOUND = 7     /* server: unknown ticket                            */
 } fem_status;
 
-typedef enum fem_prec { FEM_F64 = 0, FEM_F32 = 1, FEM_BF16 = 2 } fem_prec;
+typedef enum fem_prec { FEM_F64 = 0, FEM_F32 = 1, FEM_BF16 = 2, FEM_F16 = 3 } fem_prec;
 typedef enum fem_bc { FEM_BC_DIRICHLET = 0, FEM_BC_NEUMANN = 1 } fem_bc;
 typedef enum fem_cg_variant { FEM_CG_AUTO = 0, FEM_CG_PCG = 1, FEM_CG_FCG = 2 } fem_cg_variant;
 /* Preconditioners of the solver: the additive Schwarz smoother over vertex

@@ -23,9 +23,12 @@ ARCH = "gfx950"
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 # Packed FP32 instructions are disabled for all device code (hipcc -O3 would
-# otherwise form them from scalar float code).
+# otherwise form them from scalar float code).  Multiply-adds are fused only
+# within one source expression (-ffp-contract=on), so a kernel body rounds
+# the same way in every kernel it is compiled into (single-problem,
+# per-degree and mixed-degree launches give the same bits).
 COMMON = [
-    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+    "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=on",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-private-field",
     "-I" + os.path.join(HERE, "..", "include"),

@@ -318,7 +318,8 @@ extern "C" size_t fem_num_patches(const fem_problem* P) { return P ? P->npatch :
 
 // -------------------------------------------------------------- helpers
 static fem_status check_prec(int prec) {
-    if (prec != FEM_F64 && prec != FEM_F32 && prec != FEM_BF16) return set_error(FEM_EINVAL, "unknown precision");
+    if (prec != FEM_F64 && prec != FEM_F32 && prec != FEM_BF16 && prec != FEM_F16)
+        return set_error(FEM_EINVAL, "unknown precision");
     return FEM_OK;
 }
 #define CHECK_P(P) \
@@ -574,8 +575,9 @@ static fem_status pcg_core(fem_problem* P, const double* b, double* u, double rt
         FEM_HIP(launch_apply(P->p, FEM_F64, 1, &e, 1, nullptr, P->stream), "pcg_solve residual");
     }
     FEM_HIP(run_assembled_norm2(P, b, FEM_F64, kSlotB2), "pcg_solve norm");
-    if (schwarz) FEM_HIP(run_assembled_norm2(P, r, FEM_F64, kSlotRN), "pcg_solve norm");
-    else FEM_HIP(run_simple_precond(P, pc, r, z, sp, kSlotRN), "pcg_solve preconditioner");
+    // (FP16 copies take their scale from the norm slot: fill it first)
+    if (schwarz || sp == FEM_F16) FEM_HIP(run_assembled_norm2(P, r, FEM_F64, kSlotRN), "pcg_solve norm");
+    if (!schwarz) FEM_HIP(run_simple_precond(P, pc, r, z, sp, kSlotRN, true), "pcg_solve preconditioner");
     fem_status st = read_slots(P);
     if (st != FEM_OK) return finish(st, 0, NAN);
     const double bn = std::sqrt(P->h_red[kSlotB2]);
@@ -584,7 +586,7 @@ static fem_status pcg_core(fem_problem* P, const double* b, double* u, double rt
     if (!std::isfinite(bn) || !std::isfinite(rel)) return finish(FEM_EBREAKDOWN, 0, rel);
     if (bn == 0.0 || rel <= rtol) return finish(FEM_OK, 0, rel);
     // reduced-precision smoothers get the residual assembled in FP64 first
-    if (schwarz && sp != FEM_F64) FEM_HIP(run_distribute(P, r, rs, sp, kSlotTmp), "pcg_solve distribute");
+    if (schwarz && sp != FEM_F64) FEM_HIP(run_distribute(P, r, rs, sp, kSlotTmp, true), "pcg_solve distribute");
 
     st = precondition();
     if (st != FEM_OK) return finish(st, 0, rel);
@@ -599,9 +601,9 @@ static fem_status pcg_core(fem_problem* P, const double* b, double* u, double rt
         FEM_HIP(launch_apply(P->p, FEM_F64, 0, &e, 1, nullptr, P->stream), "pcg_solve apply");
         FEM_HIP(run_dot(P, q, FEM_F64, p, FEM_F64, kSlotQP), "pcg_solve dot");
         FEM_HIP(run_cg_update_r(P, r, q, nullptr, FEM_F64), "pcg_solve update");
-        if (!schwarz) FEM_HIP(run_simple_precond(P, pc, r, z, sp, kSlotRN), "pcg_solve preconditioner");
+        if (!schwarz) FEM_HIP(run_simple_precond(P, pc, r, z, sp, kSlotRN, true), "pcg_solve preconditioner");
         else if (sp == FEM_F64) FEM_HIP(run_assembled_norm2(P, r, FEM_F64, kSlotRN), "pcg_solve norm");
-        else FEM_HIP(run_distribute(P, r, rs, sp, kSlotRN), "pcg_solve distribute");
+        else FEM_HIP(run_distribute(P, r, rs, sp, kSlotRN, true), "pcg_solve distribute");
         st = read_slots(P);
         if (st != FEM_OK) return finish(st, k, rel);
         ++k;

@@ -184,13 +184,13 @@ extern "C" int fem_batch_mixed(const fem_batch* B) { return B && B->mixed && bat
 
 extern "C" fem_status fem_batch_apply(fem_batch* B, void* const* x, void* const* y, int prec) {
     if (!B || !x || !y) return set_error(FEM_EINVAL, "fem_batch_apply: NULL argument");
-    if (prec < FEM_F64 || prec > FEM_BF16) return set_error(FEM_EINVAL, "unknown precision");
+    if (prec < FEM_F64 || prec > FEM_F16) return set_error(FEM_EINVAL, "unknown precision");
     return batch_apply_cfg(B, x, y, prec, B->cfg_apply);
 }
 
 extern "C" fem_status fem_batch_patch_inverse(fem_batch* B, void* const* r, void* const* z, int prec) {
     if (!B || !r || !z) return set_error(FEM_EINVAL, "fem_batch_patch_inverse: NULL argument");
-    if (prec < FEM_F64 || prec > FEM_BF16) return set_error(FEM_EINVAL, "unknown precision");
+    if (prec < FEM_F64 || prec > FEM_F16) return set_error(FEM_EINVAL, "unknown precision");
     return batch_pi_cfg(B, r, z, prec, B->cfg_pi);
 }
 
@@ -200,7 +200,7 @@ extern "C" fem_status fem_batch_patch_inverse(fem_batch* B, void* const* r, void
 // patch inverse = {two-phase, fused sweep (p <= 3)} x {grid cap}.
 extern "C" fem_status fem_batch_autotune(fem_batch* B, int prec, int* choice) {
     if (!B) return set_error(FEM_EINVAL, "fem_batch_autotune: NULL batch");
-    if (prec < FEM_F64 || prec > FEM_BF16) return set_error(FEM_EINVAL, "unknown precision");
+    if (prec < FEM_F64 || prec > FEM_F16) return set_error(FEM_EINVAL, "unknown precision");
     const int caps[2] = {kMaxGrid, 4 * 256};
     std::vector<void*> x(B->count), y(B->count);
     for (int i = 0; i < B->count; ++i) {
@@ -482,7 +482,7 @@ extern "C" fem_status fem_server_create_pc(size_t hbm_budget, int max_active, in
                                            int sweeps, double omega, void* stream, fem_server** out) {
     if (!out) return set_error(FEM_EINVAL, "out is NULL");
     *out = nullptr;
-    if (max_active < 1 || sweeps < 1 || smoother_prec < FEM_F64 || smoother_prec > FEM_BF16 || !std::isfinite(omega))
+    if (max_active < 1 || sweeps < 1 || smoother_prec < FEM_F64 || smoother_prec > FEM_F16 || !std::isfinite(omega))
         return set_error(FEM_EINVAL, "fem_server_create: bad arguments");
     if (precond != FEM_PC_SCHWARZ && precond != FEM_PC_TWO_LEVEL)
         return set_error(FEM_EINVAL, "fem_server_create: preconditioner must be FEM_PC_SCHWARZ or FEM_PC_TWO_LEVEL");
@@ -693,7 +693,11 @@ static fem_status activate(fem_server* S, Active* A) {
     }
     FEM_HIP(hipMemcpyAsync(A->r, A->b, sizeof(double) * len, hipMemcpyDeviceToDevice, s), "server init");
     FEM_HIP(run_assembled_norm2(P, A->b, FEM_F64, kSlotB2), "server norm");
-    if (S->sp != FEM_F64) FEM_HIP(run_distribute(P, A->r, A->rs, S->sp, kSlotRN), "server distribute");
+    // the residual norm first (FP16 copies take their scale from it), then the
+    // smoother's copy: the same sequence as pcg_solve, so a served solve's
+    // iterates equal the standalone ones bit for bit
+    FEM_HIP(run_assembled_norm2(P, A->r, FEM_F64, kSlotRN), "server norm");
+    if (S->sp != FEM_F64) FEM_HIP(run_distribute(P, A->r, A->rs, S->sp, kSlotTmp, true), "server distribute");
     st = S->pc == FEM_PC_TWO_LEVEL ? two_level_run(P, A->rs, A->z, S->sp, S->sweeps, S->omega)
                                    : smoother_run(P, A->rs, A->z, S->sp, S->sweeps, S->omega);
     if (st != FEM_OK) return st;
@@ -876,6 +880,7 @@ extern "C" fem_status fem_server_step(fem_server* S, int* n_active, int* n_queue
                 ents[i] = entry_of(g[i]->P);
                 ents[i].a = g[i]->r;
                 ents[i].c = g[i]->rs;
+                ents[i].alpha = 1.0;                // a solver's residual copy (FP16: scaled)
             }
             FEM_HIP(launch_norm_any(S->sp, ents.data(), n, &S->st, s, kSlotRN, mix), "server norm");
             for (int i = 0; i < n; ++i) ents[i] = entry_of(g[i]->P);

@@ -31,10 +31,16 @@ constexpr int kMaxP = 7;
 // FP32; conversions round to nearest even.
 struct bf16_t { uint16_t bits; };
 
+// FP16 (IEEE binary16) is stored as its bit pattern and computed in FP32;
+// its range ends at 65504 and its normal range at 6.1e-5, so the solver
+// stores FP16 copies of residuals scaled by a power of two (k_distribute).
+struct f16_t { uint16_t bits; };
+
 template <typename S> struct Prec;
 template <> struct Prec<double> { using C = double; static constexpr int id = FEM_F64; };
 template <> struct Prec<float>  { using C = float;  static constexpr int id = FEM_F32; };
 template <> struct Prec<bf16_t> { using C = float;  static constexpr int id = FEM_BF16; };
+template <> struct Prec<f16_t>  { using C = float;  static constexpr int id = FEM_F16; };
 
 __host__ __device__ inline float bf16_to_f32(uint16_t b) {
     uint32_t u = static_cast<uint32_t>(b) << 16;
@@ -54,12 +60,17 @@ __host__ __device__ inline uint16_t f32_to_bf16(float f) {
 template <typename C> __device__ __forceinline__ C load_as(const double* p) { return (C)*p; }
 template <typename C> __device__ __forceinline__ C load_as(const float* p) { return (C)*p; }
 template <typename C> __device__ __forceinline__ C load_as(const bf16_t* p) { return (C)bf16_to_f32(p->bits); }
+__device__ __forceinline__ float f16_to_f32(uint16_t b) { return (float)__builtin_bit_cast(_Float16, b); }
+__device__ __forceinline__ uint16_t f32_to_f16(float f) { return __builtin_bit_cast(uint16_t, (_Float16)f); }
+template <typename C> __device__ __forceinline__ C load_as(const f16_t* p) { return (C)f16_to_f32(p->bits); }
 __device__ __forceinline__ void store_from(double* p, double v) { *p = v; }
 __device__ __forceinline__ void store_from(double* p, float v) { *p = (double)v; }
 __device__ __forceinline__ void store_from(float* p, float v) { *p = v; }
 __device__ __forceinline__ void store_from(float* p, double v) { *p = (float)v; }
 __device__ __forceinline__ void store_from(bf16_t* p, float v) { p->bits = f32_to_bf16(v); }
 __device__ __forceinline__ void store_from(bf16_t* p, double v) { p->bits = f32_to_bf16((float)v); }
+__device__ __forceinline__ void store_from(f16_t* p, float v) { p->bits = f32_to_f16(v); }
+__device__ __forceinline__ void store_from(f16_t* p, double v) { p->bits = f32_to_f16((float)v); }
 
 // --------------------------------------------------------------------------
 // One problem's entry in a launch.  Kernels walk a flat range of tiles; a

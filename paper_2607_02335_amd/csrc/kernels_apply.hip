@@ -832,6 +832,7 @@ static hipError_t launch_apply_p(int prec, int mode, ProbEntry* e, int n, TableS
     switch (prec) {
         case FEM_F64: return launch_apply_m<P, double>(mode, e, n, t, s, fl);
         case FEM_F32: return launch_apply_m<P, float>(mode, e, n, t, s, fl);
+        case FEM_F16: return launch_apply_m<P, f16_t>(mode, e, n, t, s, fl);
         default: return launch_apply_m<P, bf16_t>(mode, e, n, t, s, fl);
     }
 }
@@ -892,6 +893,7 @@ hipError_t launch_apply_any(int prec, int mode, ProbEntry* ents, int nprob, Tabl
         switch (prec) {
             case FEM_F64: return launch_apply_mixed_m<double>(mode, ents, nprob, st, s);
             case FEM_F32: return launch_apply_mixed_m<float>(mode, ents, nprob, st, s);
+            case FEM_F16: return launch_apply_mixed_m<f16_t>(mode, ents, nprob, st, s);
             default: return launch_apply_mixed_m<bf16_t>(mode, ents, nprob, st, s);
         }
     }

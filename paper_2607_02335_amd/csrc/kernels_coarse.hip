@@ -237,6 +237,7 @@ static hipError_t by_prec(int prec, F&& f) {
     switch (prec) {
         case FEM_F64: return f(double{});
         case FEM_F32: return f(float{});
+        case FEM_F16: return f(f16_t{});
         default: return f(bf16_t{});
     }
 }

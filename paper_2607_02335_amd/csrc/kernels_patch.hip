@@ -810,6 +810,7 @@ template <> struct SweepShape<2, double> { static constexpr int TX = 16, TY = 2,
 template <> struct SweepShape<3, double> { static constexpr int TX = 8, TY = 2, NS = 32; };
 template <> struct SweepShape<3, float> { static constexpr int TX = 8, TY = 4, NS = 64; };
 template <> struct SweepShape<3, bf16_t> { static constexpr int TX = 8, TY = 4, NS = 64; };
+template <> struct SweepShape<3, f16_t> { static constexpr int TX = 8, TY = 4, NS = 64; };
 
 // Phase 1 for p <= 3 reading the assembled residual.  A tile is CBP patches
 // along x sharing one (y, z) vertex; thread (pc, group) takes patch pc and
@@ -2742,6 +2743,7 @@ static hipError_t launch_pi_p(int prec, int acc, ProbEntry* e, int n, TableStage
     switch (prec) {
         case FEM_F64: return launch_pi_t<P, double>(acc, e, n, t, s, cfg);
         case FEM_F32: return launch_pi_t<P, float>(acc, e, n, t, s, cfg);
+        case FEM_F16: return launch_pi_t<P, f16_t>(acc, e, n, t, s, cfg);
         default: return launch_pi_t<P, bf16_t>(acc, e, n, t, s, cfg);
     }
 }
@@ -2868,6 +2870,7 @@ hipError_t launch_patch_inverse_any(int prec, int accumulate, ProbEntry* ents, i
         switch (prec) {
             case FEM_F64: return launch_pi_mixed_a<double>(accumulate, ents, nprob, st, s);
             case FEM_F32: return launch_pi_mixed_a<float>(accumulate, ents, nprob, st, s);
+            case FEM_F16: return launch_pi_mixed_a<f16_t>(accumulate, ents, nprob, st, s);
             default: return launch_pi_mixed_a<bf16_t>(accumulate, ents, nprob, st, s);
         }
     }

@@ -140,6 +140,24 @@ struct Diag1D {
     double m[kMaxP + 1];    // diagonal of the 1D reference mass
 };
 
+// FP16 copies of a solver's residual are stored scaled by a power of two
+// (exact), chosen so that the residual's root-mean-square node value lands
+// in [1, 2): late in a solve the values are far below FP16's normal range.
+// The scale comes from the problem's residual norm slot (the current or the
+// previous ||G^T r||^2, which the solver keeps there).  Every preconditioner
+// here is linear, and the (F)PCG iterates do not change when z is scaled by
+// a positive factor (alpha and beta absorb it), so the solver uses the
+// scaled z as it is.  Entries with alpha = 0 (the public conversion calls)
+// are not scaled.
+__device__ __forceinline__ double f16_residual_scale(const ProbEntry& pe) {
+    const double rn = red_slots(pe.red)[kSlotRN];
+    if (pe.alpha == 0.0 || !(rn > 0.0) || !__builtin_isfinite(rn)) return 1.0;
+    const double nodes = ((double)pe.n[0] * pe.p + 1) * ((double)pe.n[1] * pe.p + 1) * ((double)pe.n[2] * pe.p + 1);
+    int ex;
+    frexp(sqrt(rn / nodes), &ex);
+    return ldexp(1.0, 1 - ex);
+}
+
 template <int P, typename RS, int MODE, bool MULTI>
 __device__ __forceinline__ void distribute_body(const LaunchTable& L, int group, const Diag1D& dg, int item, int items,
                                                 char* smem) {
@@ -154,6 +172,8 @@ __device__ __forceinline__ void distribute_body(const LaunchTable& L, int group,
         const double* v = static_cast<const double*>(pe.a);
         RS* out = static_cast<RS*>(pe.c);
         const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+        double os = 1.0;                     // scale of the stored copies
+        if constexpr (Prec<RS>::id == FEM_F16) os = f16_residual_scale(pe);
         double acc = 0.0;
         for (size_t base = lo - lo % ((size_t)NN * kLanes); base < hi; base += (size_t)NN * kLanes) {
             const int blk = (int)(base / ((size_t)NN * kLanes));
@@ -202,6 +222,7 @@ __device__ __forceinline__ void distribute_body(const LaunchTable& L, int group,
                                                       (c == 0 && k == 0) || (c == P && k == n2 - 1));
                     o = bnd ? 0.0 : (MODE == kDistJacobi ? s / d : s);
                 }
+                if constexpr (Prec<RS>::id == FEM_F16) o *= os;
                 store_from(out + base + (size_t)l * kLanes + lane, (typename Prec<RS>::C)o);
                 // owner copy: lowest cell along every direction
                 if (ci[0] == i && cj[0] == j && ck[0] == k) acc += s * s;
@@ -580,6 +601,7 @@ static hipError_t dispatch_prec(int prec, F&& f) {
         case FEM_F64: return f(double{});
         case FEM_F32: return f(float{});
         case FEM_BF16: return f(bf16_t{});
+        case FEM_F16: return f(f16_t{});
         default: return hipErrorInvalidValue;
     }
 }
@@ -765,10 +787,11 @@ static void launch_distribute_one(LaunchTable& L, hipStream_t s, const Diag1D& d
 
 template <int MODE>
 static hipError_t run_distribute_mode(fem_problem* P, const double* r, void* out, int prec, int slot,
-                                      const char* label) {
+                                      const char* label, bool solver) {
     ProbEntry e = entry_of(P);
     e.a = r;
     e.c = out;
+    e.alpha = solver ? 1.0 : 0.0;            // FP16 residual scaling (solver copies only)
     e.tile_begin = 0;
     LaunchTable L{};
     L.nprob = 1;
@@ -794,13 +817,14 @@ static hipError_t run_distribute_mode(fem_problem* P, const double* r, void* out
     return finish_reduction(P, e, 2, slot);
 }
 
-hipError_t run_distribute(fem_problem* P, const double* r, void* out, int prec, int slot) {
-    return run_distribute_mode<kDistMean>(P, r, out, prec, slot, "distribute");
+hipError_t run_distribute(fem_problem* P, const double* r, void* out, int prec, int slot, bool solver) {
+    return run_distribute_mode<kDistMean>(P, r, out, prec, slot, "distribute", solver);
 }
 
-hipError_t run_simple_precond(fem_problem* P, int kind, const double* r, void* z, int prec, int slot) {
-    if (kind == FEM_PC_DSS) return run_distribute_mode<kDistDss>(P, r, z, prec, slot, "precond_dss");
-    if (kind == FEM_PC_JACOBI) return run_distribute_mode<kDistJacobi>(P, r, z, prec, slot, "precond_jacobi");
+hipError_t run_simple_precond(fem_problem* P, int kind, const double* r, void* z, int prec, int slot, bool solver) {
+    if (kind == FEM_PC_DSS) return run_distribute_mode<kDistDss>(P, r, z, prec, slot, "precond_dss", solver);
+    if (kind == FEM_PC_JACOBI)
+        return run_distribute_mode<kDistJacobi>(P, r, z, prec, slot, "precond_jacobi", solver);
     return hipErrorInvalidValue;
 }
 

@@ -188,11 +188,16 @@ hipError_t run_dot(fem_problem* P, const void* a, int pa, const void* b, int pb,
 // ||G^T r||^2 into slot `slot`.
 hipError_t run_assembled_norm2(fem_problem* P, const void* r, int prec, int slot);
 // out = G^T r / multiplicity per copy, assembled in FP64 and rounded to
-// `prec`; ||G^T r||^2 into slot `slot` (same pass).
-hipError_t run_distribute(fem_problem* P, const double* r, void* out, int prec, int slot);
+// `prec`; ||G^T r||^2 into slot `slot` (same pass).  solver: out is a
+// solver's copy of its residual (FP16 copies are then scaled by a power of
+// two chosen from the residual norm slot, which must hold the current or the
+// previous ||G^T r||^2).
+hipError_t run_distribute(fem_problem* P, const double* r, void* out, int prec, int slot, bool solver = false);
 // z = S r (kind FEM_PC_DSS) or z = D_cell^{-1} S r (FEM_PC_JACOBI), zero on a
-// Dirichlet boundary, from the FP64 dual r; ||G^T r||^2 into slot `slot`.
-hipError_t run_simple_precond(fem_problem* P, int kind, const double* r, void* z, int prec, int slot);
+// Dirichlet boundary, from the FP64 dual r; ||G^T r||^2 into slot `slot`;
+// solver as for run_distribute.
+hipError_t run_simple_precond(fem_problem* P, int kind, const double* r, void* z, int prec, int slot,
+                              bool solver = false);
 // (F)PCG vector updates, scalars read from the device slots.
 // r -= alpha q (alpha saved for the next u update); optionally rs = r in the
 // smoother precision.

@@ -460,19 +460,22 @@ static fem_status mb_pack(fem_mb_plan* M, const double* canon, void* v, int prec
 
 extern "C" fem_status fem_mb_pack(fem_mb_plan* M, const double* canon, void* v, int prec) {
     if (!M || !canon || !v) return set_error(FEM_EINVAL, "fem_mb_pack: NULL argument");
-    if (prec != FEM_F64 && prec != FEM_F32 && prec != FEM_BF16) return set_error(FEM_EINVAL, "unknown precision");
+    if (prec != FEM_F64 && prec != FEM_F32 && prec != FEM_BF16 && prec != FEM_F16)
+        return set_error(FEM_EINVAL, "unknown precision");
     return mb_pack(M, canon, v, prec, 0);
 }
 
 extern "C" fem_status fem_mb_unpack(fem_mb_plan* M, const void* v, double* canon, int prec) {
     if (!M || !canon || !v) return set_error(FEM_EINVAL, "fem_mb_unpack: NULL argument");
-    if (prec != FEM_F64 && prec != FEM_F32 && prec != FEM_BF16) return set_error(FEM_EINVAL, "unknown precision");
+    if (prec != FEM_F64 && prec != FEM_F32 && prec != FEM_BF16 && prec != FEM_F16)
+        return set_error(FEM_EINVAL, "unknown precision");
     return mb_pack(M, canon, const_cast<void*>(v), prec, 1);
 }
 
 extern "C" fem_status fem_mb_dss(fem_mb_plan* M, void* v, int prec, int stages) {
     if (!M || !v) return set_error(FEM_EINVAL, "fem_mb_dss: NULL argument");
-    if (prec != FEM_F64 && prec != FEM_F32 && prec != FEM_BF16) return set_error(FEM_EINVAL, "unknown precision");
+    if (prec != FEM_F64 && prec != FEM_F32 && prec != FEM_BF16 && prec != FEM_F16)
+        return set_error(FEM_EINVAL, "unknown precision");
     if (stages < 1 || stages > 3) return set_error(FEM_EINVAL, "fem_mb_dss: stages is 1, 2 or 3");
     const size_t es = prec == FEM_F64 ? 8 : prec == FEM_F32 ? 4 : 2;
     if (stages & 1) {
@@ -489,6 +492,7 @@ extern "C" fem_status fem_mb_dss(fem_mb_plan* M, void* v, int prec, int stages) 
         hipError_t err;
         if (prec == FEM_F64) err = mb_dispatch(M, static_cast<double*>(v));
         else if (prec == FEM_F32) err = mb_dispatch(M, static_cast<float*>(v));
+        else if (prec == FEM_F16) err = mb_dispatch(M, static_cast<f16_t*>(v));
         else err = mb_dispatch(M, static_cast<bf16_t*>(v));
         FEM_HIP(err, "fem_mb_dss inter-block");
     }

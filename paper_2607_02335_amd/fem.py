@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "libfem_mi355x.so")
 HEADER = os.path.join(HERE, "..", "include", "fem.h")
 
 FEM_OK, FEM_EINVAL, FEM_ENOMEM, FEM_EHIP, FEM_ENOTCONV, FEM_EBREAKDOWN, FEM_EAGAIN, FEM_ENOTFOUND = range(8)
-F64, F32, BF16 = 0, 1, 2
+F64, F32, BF16, F16 = 0, 1, 2, 3
 DIRICHLET, NEUMANN = 0, 1
 CG_AUTO, CG_PCG, CG_FCG = 0, 1, 2
 PC_SCHWARZ, PC_DSS, PC_JACOBI, PC_TWO_LEVEL = 0, 1, 2, 3
@@ -161,12 +161,12 @@ def _torch():
 
 def torch_dtype(prec):
     torch = _torch()
-    return {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16}[prec]
+    return {F64: torch.float64, F32: torch.float32, BF16: torch.bfloat16, F16: torch.float16}[prec]
 
 
 def prec_of(t):
     torch = _torch()
-    return {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16}[t.dtype]
+    return {torch.float64: F64, torch.float32: F32, torch.bfloat16: BF16, torch.float16: F16}[t.dtype]
 
 
 def _check_vec(t, length, prec=None, name="vector"):
@@ -179,7 +179,7 @@ def _check_vec(t, length, prec=None, name="vector"):
         raise ValueError(f"{name}: expected a torch tensor, got {type(t).__name__}")
     if t.numel() != length:
         raise ValueError(f"{name}: has {t.numel()} elements, expected {length}")
-    if t.dtype not in (torch.float64, torch.float32, torch.bfloat16):
+    if t.dtype not in (torch.float64, torch.float32, torch.bfloat16, torch.float16):
         raise ValueError(f"{name}: unsupported dtype {t.dtype}")
     if prec is not None and t.dtype != torch_dtype(prec):
         raise ValueError(f"{name}: dtype {t.dtype} does not match precision {prec} ({torch_dtype(prec)})")
