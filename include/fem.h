@@ -216,9 +216,17 @@ fem_status fem_assembled_norm(fem_problem* P, const void* r, int prec, double* r
  * cell-wise vector, initial guess in and solution out.  All vectors, pairings
  * and scalars stay on the device in FP64; the stopping test is
  * ||G^T r_k||_2 <= rtol ||G^T b||_2.  variant FEM_CG_AUTO uses PCG for an
- * FP64 smoother and FCG otherwise.  Synchronises the stream at exit.
- * Returns FEM_ENOTCONV at maxit, FEM_EBREAKDOWN on a non-finite or
- * non-positive <q,p>; info (may be NULL) is filled in every case. */
+ * FP64 smoother and FCG otherwise.  With an FP16 smoother the residual
+ * copies handed to the smoother are scaled by a power of two that brings
+ * the root-mean-square entry of G^T r_k into [2^-10, 2^-9) (late
+ * residuals lie far below FP16's normal range, and the patch inverse
+ * multiplies them by up to about 10^3 before z is stored in FP16);
+ * the direction z then carries the same factor, which the step lengths of
+ * (F)PCG absorb, so the iterates are those of the unscaled method up to
+ * rounding.  Synchronises the stream at exit.  Returns FEM_ENOTCONV at
+ * maxit, FEM_EBREAKDOWN on a non-finite ||G^T b|| (before iterating) or a
+ * non-finite or non-positive <q,p>; info (may be NULL) is filled in every
+ * case. */
 fem_status pcg_solve(fem_problem* P, const double* b_cell, double* u_cell, double rtol,
                      int maxit, int smoother_prec, int sweeps, double omega, int variant,
                      fem_solve_info* info);

@@ -142,7 +142,12 @@ struct Diag1D {
 
 // FP16 copies of a solver's residual are stored scaled by a power of two
 // (exact), chosen so that the residual's root-mean-square node value lands
-// in [1, 2): late in a solve the values are far below FP16's normal range.
+// in [2^-10, 2^-9): late in a solve the values are far below FP16's normal
+// range, while the patch inverse multiplies them by up to 1/lambda_min of a
+// patch operator (about 2.5e3 for p = 7 on 48^3 cells, more on graded
+// cells), and the smoother stores that result in FP16 too, whose largest
+// value is 65504.  Entries more than 16 times below the mean are subnormal;
+// their absolute spacing 2^-24 stays under the rounding of a typical entry.
 // The scale comes from the problem's residual norm slot (the current or the
 // previous ||G^T r||^2, which the solver keeps there).  Every preconditioner
 // here is linear, and the (F)PCG iterates do not change when z is scaled by
@@ -155,7 +160,7 @@ __device__ __forceinline__ double f16_residual_scale(const ProbEntry& pe) {
     const double nodes = ((double)pe.n[0] * pe.p + 1) * ((double)pe.n[1] * pe.p + 1) * ((double)pe.n[2] * pe.p + 1);
     int ex;
     frexp(sqrt(rn / nodes), &ex);
-    return ldexp(1.0, 1 - ex);
+    return ldexp(1.0, -9 - ex);
 }
 
 template <int P, typename RS, int MODE, bool MULTI>

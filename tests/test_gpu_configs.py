@@ -5,8 +5,8 @@ benchmark times.
   patch inverse on sampled cells (first, last, ragged-block and random
   cells) vs dense LU of the eight surrounding patch operators.
 * Q7, 24^3 graded cells (seed 1): full apply; patch inverse on sampled
-  cells; solves of the sine + noise right-hand side to 1e-8 with FP64, FP32
-  and BF16 smoothers, each checked by the oracle's own apply (true residual).
+  cells; solves of the sine + noise right-hand side to 1e-8 with FP64, FP32,
+  BF16 and FP16 smoothers, each checked by the oracle's own apply (true residual).
 """
 import numpy as np
 import pytest
@@ -110,7 +110,7 @@ def test_q7_24_solves_mixed_precision(F):
     b_glob = operators.mass_global(m, f)
     assert l2_rel(to_np(P.scatter(bd)), b_glob) <= 1e-13
     sol = {}
-    for name, sp in (("fp64", 0), ("fp32", 1), ("bf16", 2)):
+    for name, sp in (("fp64", 0), ("fp32", 1), ("bf16", 2), ("fp16", 3)):
         note(f"q7 24^3 solve smoother={name}")
         u, info = P.pcg_solve(bd, rtol=1e-8, maxit=3000, smoother_prec=sp)
         assert info["status"] == 0 and info["relres"] <= 1e-8, info
@@ -120,7 +120,7 @@ def test_q7_24_solves_mixed_precision(F):
         sol[name] = ug
         print(f"{name}: {info['iters']} iterations, recursive {info['relres']:.2e}, true {true:.2e}, "
               f"{info['seconds']:.3f} s", flush=True)
-    for name in ("fp32", "bf16"):
+    for name in ("fp32", "bf16", "fp16"):
         assert l2_rel(sol[name], sol["fp64"]) <= 1e-5
 
 

@@ -7,7 +7,7 @@
 * pcg_solve_pc(FEM_PC_TWO_LEVEL): the first iterates equal the oracle's
   assembled PCG iterates with the same preconditioner (equivalence theorem,
   Section 3.2); solves reach 1e-8 on the oracle's true residual with FP64,
-  FP32 and BF16 smoothers, and the iteration count does not grow with the
+  FP32, BF16 and FP16 smoothers, and the iteration count does not grow with the
   mesh (the coarse level carries the low frequencies).
 """
 import numpy as np
@@ -99,7 +99,7 @@ def test_q7_24_two_level_solves(F):
     bd = P.mass_apply(P.gather(to_dev(f)))
     b_glob = operators.mass_global(m, f)
     sol = {}
-    for name, sp in (("fp64", 0), ("fp32", 1), ("bf16", 2)):
+    for name, sp in (("fp64", 0), ("fp32", 1), ("bf16", 2), ("fp16", 3)):
         note(f"q7 24^3 two-level solve smoother={name}")
         u, info = P.pcg_solve(bd, rtol=1e-8, maxit=1000, smoother_prec=sp, precond=F.PC_TWO_LEVEL, sweeps=1,
                               omega=0.2)
@@ -109,5 +109,5 @@ def test_q7_24_two_level_solves(F):
         print(f"{name}: {info['iters']} iterations, true {true:.2e}, {info['seconds']:.3f} s", flush=True)
         assert true <= 2e-8, (name, true)
         sol[name] = ug
-    for name in ("fp32", "bf16"):
+    for name in ("fp32", "bf16", "fp16"):
         assert l2_rel(sol[name], sol["fp64"]) <= 1e-5
