@@ -457,9 +457,12 @@ fem_status fem_host_fd_1d(int p, double h0, double h1, double* S, double* lambda
  * sweep reading the assembled residual, 3 assembly plus solves that add the
  * x-overlaps of neighbouring patches in the workgroup and write one run of
  * global x-nodes per patch line (a buffer about 3/5 of the patch buffer at
- * p = 3), then a combine by global node rows; for p >= 4, 2 selects line
- * (VALU) patch solves instead of MFMA; -1 (default) picks by degree and
- * precision only (3 for p = 2, 3 in FP64, else 0).  The p <= 3 combine of the two-launch
+ * p = 3), then a combine by global node rows, 4 the same with one wavefront
+ * per tile of floor(64 / (2p-1)) patches (x and y contractions on a lane's
+ * patch plane in registers, two transposes through LDS instead of four);
+ * for p >= 4, 2 selects line (VALU) patch solves instead of MFMA; -1
+ * (default) picks by degree and precision only (4 for p = 2, 3 for p = 3
+ * in FP64, else 0).  The p <= 3 combine of the two-launch
  * form runs by global node rows (FP64, every mesh with at least 48 cells
  * along x) or by (block, node plane), with identical results;
  * FEM_OPT_COMBINE_PER_CELL = 1 makes it use one wavefront per 64-cell block

@@ -226,10 +226,11 @@ extern "C" fem_status fem_batch_autotune(fem_batch* B, int prec, int* choice) {
             //        2 = plane-streamed (p = 7);
             // patch inverse, p <= 3: 0 = two launches through the patch buffer,
             //        1 = fused sweep summing cell copies, 2 = fused sweep from the
-            //        assembled residual, 3 = solves with the in-tile x-combine;
+            //        assembled residual, 3 = solves with the in-tile x-combine,
+            //        4 = the same with one wavefront per tile;
             //        p >= 4: 0 = MFMA solves, 2 = line solves
             std::vector<int> kinds = which == 0 ? (p == 7 ? std::vector<int>{0, 1, 2} : std::vector<int>{0, 1})
-                                   : (p <= 3 ? std::vector<int>{0, 1, 2, 3} : std::vector<int>{0, 2});
+                                   : (p <= 3 ? std::vector<int>{0, 1, 2, 3, 4} : std::vector<int>{0, 2});
             std::vector<LaunchCfg> cand;
             for (int kind : kinds) {
                 for (int c : caps) {

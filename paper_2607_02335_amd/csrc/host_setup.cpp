@@ -372,7 +372,7 @@ extern std::atomic<int> g_apply_planes_p7;
 extern "C" fem_status fem_set_option(int option, int value) {
     switch (option) {
         case FEM_OPT_PI_FUSED:
-            if (value < -1 || value > 3) return set_error(FEM_EINVAL, "fem_set_option: FEM_OPT_PI_FUSED is -1..3");
+            if (value < -1 || value > 4) return set_error(FEM_EINVAL, "fem_set_option: FEM_OPT_PI_FUSED is -1..4");
             fem::g_pi_fused = value;
             return FEM_OK;
         case FEM_OPT_COMBINE_PER_CELL: fem::g_combine_per_cell = value ? 1 : 0; return FEM_OK;

@@ -1214,6 +1214,220 @@ __global__ void __launch_bounds__(256) k_pi_solve_x(LaunchTable L) {
     pi_solve_x_body<P, S, CBP, MULTI>(L, blockIdx.x, gridDim.x, smem);
 }
 
+// The same solves and in-tile x-combine with one wavefront per tile of
+// CW = floor(64 / (2p-1)) patches along x (12 at p = 3, 21 at p = 2) and
+// four independent tiles per workgroup.  Lane (pc, q) holds plane z = q of
+// patch pc (all y, x) and applies the x and y contractions in registers; one
+// transpose through LDS gives it the y-line q (all z, x) for the z
+// contractions and the eigenvalue scaling, a second one brings the planes
+// back for y and x backward.  The patch thus passes through LDS twice
+// instead of four times, with no workgroup barrier.  The x-overlap of the
+// left neighbour comes from the lane to the left by a cross-lane read.  (A
+// variant staging the tile's runs through LDS for coalesced loads and
+// stores measured slower.)  The contractions, the scaling and the overlap
+// sums are those of k_pi_solve_x term by term; the buffer layout is the
+// same with CBP = CW.
+template <int P> constexpr int solve_w_tile() { return 64 / (2 * P - 1); }
+template <int P, typename C> constexpr int solve_w_lds() {
+    return 4 * solve_w_tile<P>() * (2 * P - 1) * (2 * P - 1) * (2 * P - 1) * (int)sizeof(C);
+}
+
+template <int P, typename S, bool MULTI>
+__device__ __forceinline__ void pi_solve_w_body(const LaunchTable& L, int item, int items, char* smem) {
+    using C = typename Prec<S>::C;
+    constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
+    constexpr int REC = fd_record(P);
+    constexpr int CW = solve_w_tile<P>();
+    constexpr int SPAN = CW * P + P - 1;               // x-nodes of a full tile
+    constexpr int NLO = P > 1 ? P - 1 : 1;
+    const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+    const int lane = threadIdx.x % 64;
+    const int tile = xcd_tile(item, items) * 4 + wave;
+    if (tile >= L.total_tiles) return;                 // per wavefront: no workgroup barrier follows
+    C* sv = reinterpret_cast<C*>(smem) + wave * (CW * nP3);
+    const int pc = lane % CW, q = lane / CW;           // q == nP: lane without a patch line
+    const bool act = q < nP;
+    const int qq = act ? q : 0;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int t = tile - pe.tile_begin;
+    const int npx = pe.n[0] - 1, npy = pe.n[1] - 1;
+    const int tpr = (npx + CW - 1) / CW;
+    const int row = t / tpr, xt = t % tpr;
+    const int vj = 1 + row % npy, vk = 1 + row / npy;
+    const int vi0 = 1 + xt * CW;
+    const int nvalid = min(CW, npx - vi0 + 1);
+    const bool valid = act && pc < nvalid;
+    const int pcc = min(pc, nvalid - 1);               // lanes past the row end work on its last patch
+    const C* fx = static_cast<const C*>(pe.fd[0]) + (size_t)(vi0 + pcc - 1) * REC;
+    const C* fy = static_cast<const C*>(pe.fd[1]) + (size_t)(vj - 1) * REC;
+    const C* fz = static_cast<const C*>(pe.fd[2]) + (size_t)(vk - 1) * REC;
+    C* const pl = sv + pc * nP3;                       // this lane's patch in LDS, [z][y][x]
+    C v[nP][nP];                                       // plane z = q: [y][x]
+    {
+        const C* g = static_cast<const C*>(pe.e);
+        const size_t G0 = (size_t)pe.n[0] * P + 1, G1 = (size_t)pe.n[1] * P + 1;
+        const C* src = g + (size_t)(vi0 + pcc - 1) * P + 1 +
+                       G0 * (((size_t)(vj - 1) * P + 1) + G1 * ((size_t)(vk - 1) * P + 1 + qq));
+#pragma unroll
+        for (int y = 0; y < nP; ++y)
+#pragma unroll
+            for (int x = 0; x < nP; ++x) v[y][x] = src[G0 * y + x];
+    }
+    {
+        C Sm[nP2];
+#pragma unroll
+        for (int i = 0; i < nP2; ++i) Sm[i] = fx[i];
+#pragma unroll
+        for (int y = 0; y < nP; ++y) {                              // x forward
+            C u[nP];
+#pragma unroll
+            for (int j = 0; j < nP; ++j) {
+                C s = 0;
+#pragma unroll
+                for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[y][i];
+                u[j] = s;
+            }
+#pragma unroll
+            for (int j = 0; j < nP; ++j) v[y][j] = u[j];
+        }
+    }
+    {
+        C Sm[nP2];
+#pragma unroll
+        for (int i = 0; i < nP2; ++i) Sm[i] = fy[i];
+#pragma unroll
+        for (int x = 0; x < nP; ++x) {                              // y forward
+            C u[nP];
+#pragma unroll
+            for (int j = 0; j < nP; ++j) {
+                C s = 0;
+#pragma unroll
+                for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i][x];
+                u[j] = s;
+            }
+#pragma unroll
+            for (int j = 0; j < nP; ++j) v[j][x] = u[j];
+        }
+    }
+    if (act) {                                                      // plane q out
+#pragma unroll
+        for (int y = 0; y < nP; ++y)
+#pragma unroll
+            for (int x = 0; x < nP; ++x) pl[qq * nP2 + y * nP + x] = v[y][x];
+    }
+    wave_sync();
+    {
+        // y-line q in: v[z][x]; z forward, scaling, z backward
+#pragma unroll
+        for (int z = 0; z < nP; ++z)
+#pragma unroll
+            for (int x = 0; x < nP; ++x) v[z][x] = pl[z * nP2 + qq * nP + x];
+        C Sm[nP2], lz[nP];
+#pragma unroll
+        for (int i = 0; i < nP2; ++i) Sm[i] = fz[i];
+#pragma unroll
+        for (int i = 0; i < nP; ++i) lz[i] = fz[nP2 + i];
+        const C ly = fy[nP2 + qq];
+#pragma unroll
+        for (int x = 0; x < nP; ++x) {
+            const C lxy = fx[nP2 + x] + ly;
+            C w[nP];
+#pragma unroll
+            for (int j = 0; j < nP; ++j) {
+                C s = 0;
+#pragma unroll
+                for (int i = 0; i < nP; ++i) s += Sm[i * nP + j] * v[i][x];
+                w[j] = s * recip(lxy + lz[j]);
+            }
+#pragma unroll
+            for (int i = 0; i < nP; ++i) {
+                C s = 0;
+#pragma unroll
+                for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * w[j];
+                v[i][x] = s;
+            }
+        }
+        if (act) {
+#pragma unroll
+            for (int z = 0; z < nP; ++z)
+#pragma unroll
+                for (int x = 0; x < nP; ++x) pl[z * nP2 + qq * nP + x] = v[z][x];
+        }
+    }
+    wave_sync();
+#pragma unroll
+    for (int y = 0; y < nP; ++y)                                    // plane q back
+#pragma unroll
+        for (int x = 0; x < nP; ++x) v[y][x] = pl[qq * nP2 + y * nP + x];
+    {
+        C Sm[nP2];
+#pragma unroll
+        for (int i = 0; i < nP2; ++i) Sm[i] = fy[i];
+#pragma unroll
+        for (int x = 0; x < nP; ++x) {                              // y backward
+            C u[nP];
+#pragma unroll
+            for (int i = 0; i < nP; ++i) {
+                C s = 0;
+#pragma unroll
+                for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * v[j][x];
+                u[i] = s;
+            }
+#pragma unroll
+            for (int i = 0; i < nP; ++i) v[i][x] = u[i];
+        }
+    }
+    {
+        C Sm[nP2];
+#pragma unroll
+        for (int i = 0; i < nP2; ++i) Sm[i] = fx[i];
+#pragma unroll
+        for (int y = 0; y < nP; ++y) {                              // x backward
+            C u[nP];
+#pragma unroll
+            for (int i = 0; i < nP; ++i) {
+                C s = 0;
+#pragma unroll
+                for (int j = 0; j < nP; ++j) s += Sm[i * nP + j] * v[y][j];
+                u[i] = s;
+            }
+#pragma unroll
+            for (int i = 0; i < nP; ++i) v[y][i] = u[i];
+        }
+    }
+    // x-combine: tile node s = pc p + a (a < p) is the left patch's value at
+    // x = a + p (a <= p - 2) plus this patch's at x = a; the last valid
+    // patch also writes its x = p ... 2p - 2 alone.
+    const int RL = xrow_len(npx, tpr, P);
+    C* xb = static_cast<C*>(pe.d) + ((size_t)row * nP2) * RL + (size_t)xt * SPAN;
+#pragma unroll
+    for (int y = 0; y < nP; ++y) {
+        C lo[NLO];
+#pragma unroll
+        for (int a = 0; a < P - 1; ++a) lo[a] = __shfl_up(v[y][a + P], 1, 64);
+        if (valid) {
+            C* dst = xb + (size_t)(y + nP * qq) * RL + pc * P;
+#pragma unroll
+            for (int a = 0; a < P; ++a) {
+                C o = 0;
+                if (a <= P - 2 && pc >= 1) o = lo[a < P - 1 ? a : 0];
+                o = o + v[y][a];
+                dst[a] = o;
+            }
+            if (pc == nvalid - 1) {
+#pragma unroll
+                for (int a = 0; a < P - 1; ++a) dst[P + a] = v[y][a + P];
+            }
+        }
+    }
+}
+
+template <int P, typename S, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_solve_w(LaunchTable L) {
+    __shared__ __align__(16) char smem[solve_w_lds<P, typename Prec<S>::C>()];
+    pi_solve_w_body<P, S, MULTI>(L, blockIdx.x, gridDim.x, smem);
+}
+
 // Combine of the x-combined buffer (p <= 3): one wavefront per global node
 // row (Y, Z) with lane i on cell column i.  Per node X of the row the terms
 // are the z-patches (ascending vk), within each the y-patches (ascending vj),
@@ -2502,10 +2716,10 @@ static hipError_t launch_pi_slabs(int accumulate, ProbEntry e, hipStream_t s, in
 
 // Patch inverse for p <= 3 through the x-combined buffer: assembly, the
 // solves with the in-tile x-combine, the combine by global node rows.
-template <int P, typename S>
+template <int P, typename S, bool WAVE>
 static hipError_t launch_pi_xcomb(int accumulate, ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s,
                                   int gcap) {
-    constexpr int CBP = solve_g_tile<P>();
+    constexpr int CBP = WAVE ? solve_w_tile<P>() : solve_g_tile<P>();
     hipError_t err = launch_assemble<P, S>(ents, nprob, d_tab, s, gcap);
     if (err != hipSuccess) return err;
     int t1 = 0;
@@ -2522,9 +2736,15 @@ static hipError_t launch_pi_xcomb(int accumulate, ProbEntry* ents, int nprob, Ta
         err = stage_table(Lg, ents, nprob, d_tab, s);
         if (err != hipSuccess) return err;
         TraceSpan ts("pi_solve", P, Prec<S>::id, s);
-        const int grid = (t1 + 7) / 8 * 8;
-        if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_x<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, Lg);
-        else hipLaunchKernelGGL((k_pi_solve_x<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, Lg);
+        if constexpr (WAVE) {
+            const int grid = ((t1 + 3) / 4 + 7) / 8 * 8;             // four tiles per workgroup
+            if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_w<P, S, true>), dim3(grid), dim3(256), 0, s, Lg);
+            else hipLaunchKernelGGL((k_pi_solve_w<P, S, false>), dim3(grid), dim3(256), 0, s, Lg);
+        } else {
+            const int grid = (t1 + 7) / 8 * 8;
+            if (nprob > 1) hipLaunchKernelGGL((k_pi_solve_x<P, S, CBP, true>), dim3(grid), dim3(256), 0, s, Lg);
+            else hipLaunchKernelGGL((k_pi_solve_x<P, S, CBP, false>), dim3(grid), dim3(256), 0, s, Lg);
+        }
         err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
@@ -2551,25 +2771,36 @@ static hipError_t launch_pi_xcomb(int accumulate, ProbEntry* ents, int nprob, Ta
     return hipGetLastError();
 }
 
-// Default patch-inverse variant for p <= 3: solves with the in-tile
-// x-combine for p = 2, 3 in FP64, else the two launches through the patch buffer.
-template <int P, typename S> constexpr bool pi_xcomb_default() { return (P == 2 || P == 3) && Prec<S>::id == FEM_F64; }
+// Default patch-inverse variant for p <= 3 (by degree and precision only):
+// p = 2 in every precision, the wavefront-tiled solves with the in-tile
+// x-combine; p = 3 in FP64, the workgroup-tiled ones; otherwise the two
+// launches through the patch buffer.
+template <int P, typename S> constexpr bool pi_wave_default() { return P == 2; }
+template <int P, typename S> constexpr bool pi_xcomb_default() {
+    return pi_wave_default<P, S>() || (P == 3 && Prec<S>::id == FEM_F64);
+}
+template <int P, typename S> constexpr int pi_xcomb_tile() {
+    return pi_wave_default<P, S>() ? solve_w_tile<P>() : solve_g_tile<P>();
+}
 
 template <int P, typename S>
 static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableStager* d_tab, hipStream_t s,
                               const LaunchCfg& cfg) {
     if constexpr (P <= 3) {
         // default by degree and precision only (never by size or launch mix, so
-        // a problem gets the same variant alone and batched): for p = 2, 3 in
-        // FP64 the solves with the in-tile x-combine (the smaller buffer pays
-        // for the combine's traffic there), the two launches through the
-        // patch buffer otherwise (4-byte values: the plain patch buffer is
-        // the faster one)
-        const int dflt = pi_xcomb_default<P, S>() ? 3 : 0;
+        // a problem gets the same variant alone and batched): the solves with
+        // the in-tile x-combine where they measured faster (p = 2: one
+        // wavefront per tile, in every precision; p = 3 in FP64: one
+        // workgroup per tile), the two launches through the patch buffer
+        // otherwise
+        const int dflt = pi_wave_default<P, S>() ? 4 : pi_xcomb_default<P, S>() ? 3 : 0;
         const int gf = g_pi_fused.load(std::memory_order_relaxed);
         const int fused = cfg.pi_fused >= 0 ? cfg.pi_fused : gf >= 0 ? gf : dflt;
-        if (fused == 3) return launch_pi_xcomb<P, S>(accumulate, ents, nprob, d_tab, s,
-                                                      cfg.grid_cap > 0 ? cfg.grid_cap : kMaxGrid);
+        if (fused == 3 || fused == 4) {
+            const int gc = cfg.grid_cap > 0 ? cfg.grid_cap : kMaxGrid;
+            return fused == 4 ? launch_pi_xcomb<P, S, true>(accumulate, ents, nprob, d_tab, s, gc)
+                              : launch_pi_xcomb<P, S, false>(accumulate, ents, nprob, d_tab, s, gc);
+        }
         if (fused == 2) return launch_pi_sweep_g<P, S>(accumulate, ents, nprob, d_tab, s);
         if (fused) return launch_pi_sweep<P, S>(accumulate, ents, nprob, d_tab, s);
     }
@@ -2770,9 +3001,11 @@ struct SolveBody {
     using Arg = NoArg;
     static constexpr int CBP = solve_g_tile<P>();
     static constexpr int kLds = P >= 4 ? mfma_lds<P, C>()
+                              : pi_wave_default<P, S>() ? solve_w_lds<P, C>()
                               : pi_xcomb_default<P, S>() ? solve_x_lds<P, C, CBP>() : solve_g_lds<P, C, CBP>();
     __device__ static __forceinline__ void run(const LaunchTable& L, const NoArg&, int item, int items, char* smem) {
         if constexpr (P >= 4) pi_solve_mfma_body<P, S, C, true>(L, item, items, smem);
+        else if constexpr (pi_wave_default<P, S>()) pi_solve_w_body<P, S, true>(L, item, items, smem);
         else if constexpr (pi_xcomb_default<P, S>()) pi_solve_x_body<P, S, CBP, true>(L, item, items, smem);
         else pi_solve_g_body<P, S, CBP, true>(L, item, items, smem);
     }
@@ -2785,7 +3018,7 @@ struct CombineBody {
     static constexpr int kLds = P >= 4 ? pm_lds<P, C>() : 0;
     __device__ static __forceinline__ void run(const LaunchTable& L, const NoArg&, int item, int items, char* smem) {
         if constexpr (P >= 4) pi_combine_pm_body<P, S, ACC, true>(L, item, items, smem);
-        else if constexpr (pi_xcomb_default<P, S>()) pi_combine_x_body<P, S, solve_g_tile<P>(), ACC, true>(L, item, items);
+        else if constexpr (pi_xcomb_default<P, S>()) pi_combine_x_body<P, S, pi_xcomb_tile<P, S>(), ACC, true>(L, item, items);
         else pi_combine_planes_body<P, S, ACC, true>(L, item, items);
     }
 };
@@ -2795,10 +3028,12 @@ template <int P, typename S> static int pi_solve_tiles(const ProbEntry& e) {
     const int npx = e.n[0] - 1, npy = e.n[1] - 1, npz = e.n[2] - 1;
     if (npx <= 0 || npy <= 0 || npz <= 0) return 0;
     if constexpr (P >= 4) return npx * npy * npz;
+    else if constexpr (pi_wave_default<P, S>()) return ((npx + solve_w_tile<P>() - 1) / solve_w_tile<P>()) * npy * npz;
     else return ((npx + solve_g_tile<P>() - 1) / solve_g_tile<P>()) * npy * npz;
 }
-template <int P> static int pi_solve_items(int t) {
+template <int P, typename S> static int pi_solve_items(int t) {
     if constexpr (P >= 4) return (t + 4 / mfma_waves_per_patch<P>() - 1) / (4 / mfma_waves_per_patch<P>());
+    else if constexpr (pi_wave_default<P, S>()) return (t + 3) / 4;     // four tiles per workgroup
     else return t;
 }
 template <int P, typename S> static int pi_combine_tiles(const ProbEntry& e) {
@@ -2832,7 +3067,9 @@ static hipError_t launch_pi_mixed_t(ProbEntry* ents, int nprob, TableStager* st,
     auto stiles = [](int p, const ProbEntry& e) {
         return p == 7 ? pi_solve_tiles<7, S>(e) : p == 3 ? pi_solve_tiles<3, S>(e) : pi_solve_tiles<2, S>(e);
     };
-    auto sitems = [](int p, int t) { return p == 7 ? pi_solve_items<7>(t) : t; };
+    auto sitems = [](int p, int t) {
+        return p == 7 ? pi_solve_items<7, S>(t) : p == 3 ? pi_solve_items<3, S>(t) : pi_solve_items<2, S>(t);
+    };
     err = mix_build(ents, nprob, st, s, stiles, sitems, T, grid);
     if (err != hipSuccess) return err;
     if (grid > 0) {

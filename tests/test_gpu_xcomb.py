@@ -1,8 +1,9 @@
 """The p <= 3 patch inverse through the x-combined buffer (kernel option
-FEM_OPT_PI_FUSED = 3) against the oracle's additive Schwarz, on meshes whose
-patch rows span one tile, several tiles and a ragged last tile, in every
-precision, for the plain and the accumulating (smoother) form; the output
-is continuous bit for bit."""
+FEM_OPT_PI_FUSED = 3: workgroup tiles of 32 or 64 patches; 4: one
+wavefront per tile of 12 or 21 patches) against the oracle's additive
+Schwarz, on meshes whose patch rows span one tile, several tiles and a
+ragged last tile, in every precision, for the plain and the accumulating
+(smoother) form; the output is continuous bit for bit."""
 import numpy as np
 import pytest
 
@@ -27,13 +28,14 @@ def F():
                                  (3, (4, 5, 3)), (3, (34, 3, 3)), (3, (33, 2, 4)), (3, (65, 3, 2)), (3, (2, 2, 2)),
                                  (3, (97, 2, 2))])
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_xcombined_patch_inverse_matches_oracle(F, p, n, prec):
-    note(f"x-combined p={p} n={n} prec={prec}")
+@pytest.mark.parametrize("mode", [3, 4])
+def test_xcombined_patch_inverse_matches_oracle(F, p, n, prec, mode):
+    note(f"x-combined mode={mode} p={p} n={n} prec={prec}")
     m, w, rng = graded(p, n, 200 + p)
     P = F.Problem(p, n, w)
     rd = P.pack(to_dev(rng.uniform(-1, 1, m.ncells * m.n1 ** 3)), prec)
     r_glob = operators.scatter(m, to_np(P.unpack(rd)).astype(np.float64))
-    F.set_option(F.OPT_PI_FUSED, 3)
+    F.set_option(F.OPT_PI_FUSED, mode)
     try:
         zd = P.patch_inverse(rd)
         zs = P.smoother_step(rd, sweeps=2, omega=0.2)
@@ -41,24 +43,25 @@ def test_xcombined_patch_inverse_matches_oracle(F, p, n, prec):
         F.set_option(F.OPT_PI_FUSED, -1)
     f = patches.SchwarzFactors(m)
     z = to_np(P.unpack(zd))
-    check_err(z, f(r_glob)[m.dofs], TOL[prec], f"x-combined p={p} n={n} prec={prec}")
+    check_err(z, f(r_glob)[m.dofs], TOL[prec], f"x-combined mode={mode} p={p} n={n} prec={prec}")
     np.testing.assert_array_equal(to_np(P.unpack(P.gather(P.extract(zd), prec))), z)
     ref = solver.smoother(m, r_glob, 2, 0.2, schwarz=f)
-    check_err(to_np(P.unpack(zs)), ref[m.dofs], TOL[prec], f"x-combined smoother p={p} n={n} prec={prec}")
+    check_err(to_np(P.unpack(zs)), ref[m.dofs], TOL[prec], f"x-combined smoother mode={mode} p={p} n={n} prec={prec}")
 
 
 @pytest.mark.parametrize("p,n", [(3, (1, 4, 3)), (2, (4, 1, 3)), (3, (3, 4, 1)), (2, (1, 1, 1))])
 @pytest.mark.parametrize("prec", [0, 1])
-def test_xcombined_without_interior_vertices(F, p, n, prec):
+@pytest.mark.parametrize("mode", [3, 4])
+def test_xcombined_without_interior_vertices(F, p, n, prec, mode):
     """A mesh with one cell along a direction has no patch: the x-combined
     path returns exactly zero and leaves no copy unwritten."""
-    note(f"x-combined degenerate p={p} n={n} prec={prec}")
+    note(f"x-combined degenerate mode={mode} p={p} n={n} prec={prec}")
     m, w, rng = graded(p, n, 230 + p)
     P = F.Problem(p, n, w)
     rd = P.pack(to_dev(rng.uniform(-1, 1, m.ncells * m.n1 ** 3)), prec)
     z0 = P.cell_vector(prec)
     z0.fill_(7.0)
-    F.set_option(F.OPT_PI_FUSED, 3)
+    F.set_option(F.OPT_PI_FUSED, mode)
     try:
         P.patch_inverse(rd, z0)
     finally:
