@@ -72,6 +72,20 @@ __device__ __forceinline__ void store_from(bf16_t* p, double v) { p->bits = f32_
 __device__ __forceinline__ void store_from(f16_t* p, float v) { p->bits = f32_to_f16(v); }
 __device__ __forceinline__ void store_from(f16_t* p, double v) { p->bits = f32_to_f16((float)v); }
 
+// Streaming (nontemporal) access for FP64 data that one pass reads or writes
+// once and that the next kernels do not read back soon: the patch inverse's
+// cell-wise input in the assembly and its cell-wise output in the row
+// combine.  Keeping those lines out of the Infinity Cache leaves it to the
+// intermediate arrays that are re-read (measured on the Q3 64^3 FP64 step:
+// 286 -> 267 us; other precisions keep cached accesses, their problems are
+// small enough to live in the caches).
+template <typename C> __device__ __forceinline__ C load_stream(const double* p) {
+    return (C)__builtin_nontemporal_load(p);
+}
+template <typename C, typename S> __device__ __forceinline__ C load_stream(const S* p) { return load_as<C>(p); }
+__device__ __forceinline__ void store_stream(double* p, double v) { __builtin_nontemporal_store(v, p); }
+template <typename S, typename C> __device__ __forceinline__ void store_stream(S* p, C v) { store_from(p, v); }
+
 // --------------------------------------------------------------------------
 // One problem's entry in a launch.  Kernels walk a flat range of tiles; a
 // launch over several problems (of one degree) concatenates their tile

@@ -1541,18 +1541,18 @@ __device__ __forceinline__ void pi_combine_x_body(const LaunchTable& L, int item
                     S* d0 = z + cell_offset(e, a + lyz, NN);
                     C o0 = alpha * sum;
                     if (ACC) o0 = load_as<C>(d0) + o0;
-                    store_from(d0, o0);
+                    store_stream(d0, o0);
                     if (a == 0 && i >= 1) {                    // the left cell's copy of the node
                         S* d1 = z + cell_offset(e - 1, P + lyz, NN);
                         C o1 = alpha * sum;
                         if (ACC) o1 = load_as<C>(d1) + o1;
-                        store_from(d1, o1);
+                        store_stream(d1, o1);
                     }
                     if (i == n0 - 1) {                         // the row's last node: no patch
                         S* d2 = z + cell_offset(e, P + lyz, NN);
                         C o2 = alpha * (C)0;
                         if (ACC) o2 = load_as<C>(d2) + o2;
-                        store_from(d2, o2);
+                        store_stream(d2, o2);
                     }
                 }
             }
@@ -1670,7 +1670,7 @@ __device__ __forceinline__ void assemble_cells_body(const LaunchTable& L, int it
                     const int lyz = N * ((y ? 0 : by0) + N * (z ? 0 : bz0));
                     if (in) {
 #pragma unroll
-                        for (int a = 0; a < N; ++a) val[z][y][a] = load_as<double>(v + cell_offset(e, a + lyz, NN));
+                        for (int a = 0; a < N; ++a) val[z][y][a] = load_stream<double>(v + cell_offset(e, a + lyz, NN));
                     }
                     left[z][y] = __shfl_up(val[z][y][P], 1, 64);
                     if (lane == 0 && i0 > 0) left[z][y] = load_as<double>(v + cell_offset(e - 1, P + lyz, NN));
