@@ -466,7 +466,10 @@ fem_status fem_host_fd_1d(int p, double h0, double h1, double* S, double* lambda
  * form runs by global node rows (FP64, every mesh with at least 48 cells
  * along x) or by (block, node plane), with identical results;
  * FEM_OPT_COMBINE_PER_CELL = 1 makes it use one wavefront per 64-cell block
- * (all node planes) instead.  FEM_OPT_RESTRICT_FROM_CELLS = 1 makes
+ * (all node planes) instead.  For p >= 4 the combine runs by global node
+ * rows in FP64 and per (64-cell block, node plane) otherwise, with
+ * identical results; FEM_OPT_COMBINE_PER_CELL = 1 selects the latter and 2
+ * the former for every precision (0, the default, picks by precision).  FEM_OPT_RESTRICT_FROM_CELLS = 1 makes
  * the p <= 3 patch solves sum the residual copies from the cell vector
  * instead of reading the assembled global-node array.  FEM_OPT_PI_SLAB_MB =
  * m > 0 runs the p <= 3 two-launch patch inverse of a single problem in

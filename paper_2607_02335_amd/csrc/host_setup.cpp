@@ -375,7 +375,10 @@ extern "C" fem_status fem_set_option(int option, int value) {
             if (value < -1 || value > 4) return set_error(FEM_EINVAL, "fem_set_option: FEM_OPT_PI_FUSED is -1..4");
             fem::g_pi_fused = value;
             return FEM_OK;
-        case FEM_OPT_COMBINE_PER_CELL: fem::g_combine_per_cell = value ? 1 : 0; return FEM_OK;
+        case FEM_OPT_COMBINE_PER_CELL:
+            if (value < 0 || value > 2) return set_error(FEM_EINVAL, "fem_set_option: FEM_OPT_COMBINE_PER_CELL is 0..2");
+            fem::g_combine_per_cell = value;
+            return FEM_OK;
         case FEM_OPT_RESTRICT_FROM_CELLS: fem::g_restrict_from_cells = value ? 1 : 0; return FEM_OK;
         case FEM_OPT_PI_SLAB_MB:
             if (value < 0) return set_error(FEM_EINVAL, "fem_set_option: FEM_OPT_PI_SLAB_MB >= 0");

@@ -2441,6 +2441,134 @@ __global__ void __launch_bounds__(256) k_pi_combine_pm(LaunchTable L) {
     pi_combine_pm_body<P, S, ACC, MULTI>(L, blockIdx.x, gridDim.x, smem);
 }
 
+// The same combine by global node rows (p >= 4): a workgroup takes one node
+// row (Y, Z) in chunks of 32 cells along x.  Thread t first sums node
+// X = 32 i0 p + t of the chunk over the patches containing it (z, then y,
+// then x patches in ascending vertex order, as k_pi_combine_pm), reading
+// runs of consecutive x-nodes of each patch line, so every patch value is
+// read once; the sums go through LDS and leave with threads on (node a,
+// cell), a store covering up to 32 consecutive cells of a storage block.
+// Bitwise equal to k_pi_combine_pm.  The first row of a problem zeroes the
+// padding cells of its last storage block.
+constexpr int kNrCells = 32;
+// default p >= 4 combine by precision only: node rows for FP64 (measured
+// faster there), per (block, plane) for 4- and 2-byte values
+template <typename S> constexpr bool pm_rows_default() { return Prec<S>::id == FEM_F64; }
+template <int P, typename C> constexpr int nr_lds() { return (kNrCells * P + 1) * (int)sizeof(C); }
+
+template <int P, typename S, int ACC, bool MULTI>
+__device__ __forceinline__ void pi_combine_nr_body(const LaunchTable& L, int item, int items, char* smem) {
+    using C = typename Prec<S>::C;
+    constexpr int N = P + 1, N2 = N * N, NN = N2 * N;
+    constexpr int nP = 2 * P - 1, nP2 = nP * nP, nP3 = nP2 * nP;
+    constexpr int CC = kNrCells;
+    static_assert(CC * P + 1 <= 256 && N * CC <= 256, "one chunk per workgroup pass");
+    C* sx = reinterpret_cast<C*>(smem);
+    const int tile = xcd_tile(item, items);      // neighbouring rows on one XCD
+    if (tile >= L.total_tiles) return;
+    const ProbEntry& pe = entry<MULTI>(L, tile);
+    const int n0 = pe.n[0], n1 = pe.n[1], n2 = pe.n[2];
+    const int npx = n0 - 1, npy = n1 - 1;
+    const int G1 = n1 * P + 1;
+    const int row = tile - pe.tile_begin;
+    const C* pbuf = static_cast<const C*>(pe.d);
+    S* z = static_cast<S*>(pe.c);
+    const C alpha = (C)pe.alpha;
+    const int tid = threadIdx.x;
+    if (row == 0) {
+        for (int w = tid; w < NN * kLanes; w += 256) {
+            const int e = (pe.nblk - 1) * kLanes + w % kLanes;
+            if (e >= pe.ncells) store_from(z + cell_offset(e, w / kLanes, NN), (C)0);
+        }
+    }
+    const int Y = row % G1, Z = row / G1;
+    // patches containing the row along y and z (ascending vertex, with the
+    // patch-local index), and the row's cell copies
+    int vyp[2], qyp[2], nyp = 0, vzp[2], qzp[2], nzp = 0;
+    int cyc[2], byc[2], nyc = 0, czc[2], bzc[2], nzc = 0;
+    {
+        const int qy = Y / P, ry = Y - qy * P;
+        if (ry == 0) {
+            if (qy >= 1 && qy <= npy) { vyp[nyp] = qy; qyp[nyp] = P - 1; ++nyp; }
+            if (qy >= 1) { cyc[nyc] = qy - 1; byc[nyc] = P; ++nyc; }
+            if (qy <= n1 - 1) { cyc[nyc] = qy; byc[nyc] = 0; ++nyc; }
+        } else {
+            if (qy >= 1) { vyp[nyp] = qy; qyp[nyp] = ry + P - 1; ++nyp; }
+            if (qy + 1 <= npy) { vyp[nyp] = qy + 1; qyp[nyp] = ry - 1; ++nyp; }
+            cyc[nyc] = qy; byc[nyc] = ry; ++nyc;
+        }
+        const int qz = Z / P, rz = Z - qz * P;
+        if (rz == 0) {
+            if (qz >= 1 && qz <= n2 - 1) { vzp[nzp] = qz; qzp[nzp] = P - 1; ++nzp; }
+            if (qz >= 1) { czc[nzc] = qz - 1; bzc[nzc] = P; ++nzc; }
+            if (qz <= n2 - 1) { czc[nzc] = qz; bzc[nzc] = 0; ++nzc; }
+        } else {
+            if (qz >= 1) { vzp[nzp] = qz; qzp[nzp] = rz + P - 1; ++nzp; }
+            if (qz + 1 <= n2 - 1) { vzp[nzp] = qz + 1; qzp[nzp] = rz - 1; ++nzp; }
+            czc[nzc] = qz; bzc[nzc] = rz; ++nzc;
+        }
+    }
+    for (int i0 = 0; i0 < n0; i0 += CC) {
+        const int nc = min(CC, n0 - i0);
+        if (tid <= nc * P) {
+            const int X = i0 * P + tid;
+            const int qx = X / P, rx = X - qx * P;
+            int vxp[2], qxp[2], nxp = 0;
+            if (rx == 0) {
+                if (qx >= 1 && qx <= npx) { vxp[nxp] = qx; qxp[nxp] = P - 1; ++nxp; }
+            } else {
+                if (qx >= 1) { vxp[nxp] = qx; qxp[nxp] = rx + P - 1; ++nxp; }
+                if (qx + 1 <= npx) { vxp[nxp] = qx + 1; qxp[nxp] = rx - 1; ++nxp; }
+            }
+            // every term is loaded (a missing one from element 0) and dropped
+            // by a select, so the loads are in flight together
+            C sum = 0;
+#pragma unroll
+            for (int tz = 0; tz < 2; ++tz)
+#pragma unroll
+                for (int ty = 0; ty < 2; ++ty)
+#pragma unroll
+                    for (int tx = 0; tx < 2; ++tx) {
+                        const bool ok = tz < nzp && ty < nyp && tx < nxp;
+                        const size_t off =
+                            ok ? (size_t)((vxp[tx] - 1) + npx * ((vyp[ty] - 1) + npy * (vzp[tz] - 1))) * nP3 + qxp[tx] +
+                                     nP * qyp[ty] + nP2 * qzp[tz]
+                               : 0;
+                        const C v = pbuf[off];
+                        sum = ok ? sum + v : sum;
+                    }
+            sx[tid] = sum;
+        }
+        __syncthreads();
+        {
+            const int a = tid / CC, c = tid % CC;
+            if (a < N && c < nc) {
+                const C v = sx[c * P + a];
+#pragma unroll
+                for (int cz = 0; cz < 2; ++cz) {
+                    if (cz >= nzc) break;
+#pragma unroll
+                    for (int cy = 0; cy < 2; ++cy) {
+                        if (cy >= nyc) break;
+                        const int e = i0 + c + n0 * (cyc[cy] + n1 * czc[cz]);
+                        S* d = z + cell_offset(e, a + N * (byc[cy] + N * bzc[cz]), NN);
+                        C out = alpha * v;
+                        if (ACC) out = load_as<C>(d) + out;
+                        store_from(d, out);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <int P, typename S, int ACC, bool MULTI>
+__global__ void __launch_bounds__(256) k_pi_combine_nr(LaunchTable L) {
+    __shared__ __align__(16) char smem[nr_lds<P, typename Prec<S>::C>()];
+    pi_combine_nr_body<P, S, ACC, MULTI>(L, blockIdx.x, gridDim.x, smem);
+}
+
 // The x pair (forward product, scaling by 1/(lambda_x+lambda_y+lambda_z),
 // backward product) of every 16-line tile chained in registers: the
 // forward product's accumulators are the backward product's B operand.  A
@@ -2641,11 +2769,14 @@ static hipError_t launch_pi_mfma(int accumulate, ProbEntry* ents, int nprob, Tab
         err = hipGetLastError();
         if (err != hipSuccess) return err;
     }
-    // 3. combine into the cells
+    // 3. combine into the cells: by global node rows, or per (storage
+    //    block, node plane) with the per-cell switch
+    const int cpc = g_combine_per_cell.load(std::memory_order_relaxed);
+    const bool rows = cpc == 2 || (cpc == 0 && pm_rows_default<S>());
     int tiles2 = 0;
     for (int i = 0; i < nprob; ++i) {
         ents[i].tile_begin = tiles2;
-        ents[i].ntiles = ents[i].nblk * (P + 1);
+        ents[i].ntiles = rows ? (ents[i].n[1] * P + 1) * (ents[i].n[2] * P + 1) : ents[i].nblk * (P + 1);
         tiles2 += ents[i].ntiles;
     }
     LaunchTable L2{};
@@ -2655,6 +2786,16 @@ static hipError_t launch_pi_mfma(int accumulate, ProbEntry* ents, int nprob, Tab
     if (err != hipSuccess) return err;
     const int grid2 = (tiles2 + 7) / 8 * 8;
     TraceSpan ts("pi_combine", P, Prec<S>::id, s);
+    if (rows) {
+        if (nprob > 1) {
+            if (accumulate) hipLaunchKernelGGL((k_pi_combine_nr<P, S, 1, true>), dim3(grid2), dim3(256), 0, s, L2);
+            else hipLaunchKernelGGL((k_pi_combine_nr<P, S, 0, true>), dim3(grid2), dim3(256), 0, s, L2);
+        } else {
+            if (accumulate) hipLaunchKernelGGL((k_pi_combine_nr<P, S, 1, false>), dim3(grid2), dim3(256), 0, s, L2);
+            else hipLaunchKernelGGL((k_pi_combine_nr<P, S, 0, false>), dim3(grid2), dim3(256), 0, s, L2);
+        }
+        return hipGetLastError();
+    }
     if (nprob > 1) {
         if (accumulate) hipLaunchKernelGGL((k_pi_combine_pm<P, S, 1, true>), dim3(grid2), dim3(256), 0, s, L2);
         else hipLaunchKernelGGL((k_pi_combine_pm<P, S, 0, true>), dim3(grid2), dim3(256), 0, s, L2);
@@ -2813,7 +2954,7 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
     using C = typename Prec<S>::C;
     constexpr int CBP = pi_patches_per_tile<P, C>();
     if constexpr (P <= 3) {
-        if (nprob == 1 && !g_restrict_from_cells && !g_combine_per_cell) {
+        if (nprob == 1 && !g_restrict_from_cells && g_combine_per_cell != 1) {
             // slabs of at most ~pi_slab_bytes of patch results (one slab: plain two launches)
             const size_t pbytes = (size_t)(ents[0].n[0] - 1) * (ents[0].n[1] - 1) * (ents[0].n[2] - 1) *
                                   (2 * P - 1) * (2 * P - 1) * (2 * P - 1) * sizeof(C);
@@ -2893,7 +3034,7 @@ static hipError_t launch_pi_t(int accumulate, ProbEntry* ents, int nprob, TableS
     err = stage_table(L2, ents, nprob, d_tab, s);
     if (err != hipSuccess) return err;
     if constexpr (P <= 3) {
-        if (g_combine_per_cell) {
+        if (g_combine_per_cell == 1) {
             const int grid = (tiles2 + 3) / 4;
             TraceSpan ts("pi_combine", P, Prec<S>::id, s);
             if (nprob > 1) {
@@ -3015,9 +3156,10 @@ template <int P, typename S, int ACC>
 struct CombineBody {
     using C = typename Prec<S>::C;
     using Arg = NoArg;
-    static constexpr int kLds = P >= 4 ? pm_lds<P, C>() : 0;
+    static constexpr int kLds = P >= 4 ? (pm_rows_default<S>() ? nr_lds<P, C>() : pm_lds<P, C>()) : 0;
     __device__ static __forceinline__ void run(const LaunchTable& L, const NoArg&, int item, int items, char* smem) {
-        if constexpr (P >= 4) pi_combine_pm_body<P, S, ACC, true>(L, item, items, smem);
+        if constexpr (P >= 4 && pm_rows_default<S>()) pi_combine_nr_body<P, S, ACC, true>(L, item, items, smem);
+        else if constexpr (P >= 4) pi_combine_pm_body<P, S, ACC, true>(L, item, items, smem);
         else if constexpr (pi_xcomb_default<P, S>()) pi_combine_x_body<P, S, pi_xcomb_tile<P, S>(), ACC, true>(L, item, items);
         else pi_combine_planes_body<P, S, ACC, true>(L, item, items);
     }
@@ -3037,7 +3179,8 @@ template <int P, typename S> static int pi_solve_items(int t) {
     else return t;
 }
 template <int P, typename S> static int pi_combine_tiles(const ProbEntry& e) {
-    if constexpr (P >= 4) return e.nblk * (P + 1);
+    if constexpr (P >= 4 && pm_rows_default<S>()) return (e.n[1] * P + 1) * (e.n[2] * P + 1);
+    else if constexpr (P >= 4) return e.nblk * (P + 1);
     else if constexpr (pi_xcomb_default<P, S>()) return ((e.n[1] * P + 1) * (e.n[2] * P + 1) + 3) / 4;
     else return e.nblk * (P + 1) * ((P + 1 + combine_brows<P>() - 1) / combine_brows<P>());
 }
