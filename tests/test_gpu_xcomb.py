@@ -67,3 +67,28 @@ def test_xcombined_without_interior_vertices(F, p, n, prec, mode):
     finally:
         F.set_option(F.OPT_PI_FUSED, -1)
     assert not np.any(to_np(z0))
+
+
+@pytest.mark.parametrize("mode", [3, 4])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_xcombined_batched_equals_single(F, mode, prec):
+    """The multi-problem launches of both tilings (problems of one degree in
+    one launch, tiles found by binary search) equal the single-problem ones
+    bit for bit."""
+    probs = [(3, (14, 3, 2)), (3, (5, 4, 3)), (3, (40, 2, 3)), (2, (30, 3, 2)), (2, (4, 5, 3))]
+    note(f"x-combined batched mode={mode} prec={prec}")
+    B = F.Batch([(p, n, None) for p, n in probs])
+    B.set_mixed(False)
+    rng = np.random.default_rng(250 + mode)
+    rs = [P.pack(to_dev(rng.uniform(-1, 1, int(np.prod(n)) * (p + 1) ** 3)), prec)
+          for P, (p, n) in zip(B.problems, probs)]
+    zs = [P.cell_vector(prec) for P in B.problems]
+    F.set_option(F.OPT_PI_FUSED, mode)
+    try:
+        B.patch_inverse(rs, zs)
+        singles = [P.patch_inverse(r) for P, r in zip(B.problems, rs)]
+    finally:
+        F.set_option(F.OPT_PI_FUSED, -1)
+    for z, z1 in zip(zs, singles):
+        assert bool((z == z1).all())
+    B.close()
