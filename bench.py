@@ -524,8 +524,8 @@ def cpu_baseline(steps_budget_s=20.0):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--mode", default="bench", choices=["bench", "calib", "serve"])
     ap.add_argument("--quick", action="store_true", help="headline workload only")
     ap.add_argument("--only", choices=["q2_96", "q7_24", "q7_solve", "batch_256", "paper_kernels", "layout"], default=None,
