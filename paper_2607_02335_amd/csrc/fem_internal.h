@@ -77,8 +77,8 @@ __device__ __forceinline__ void store_from(f16_t* p, double v) { p->bits = f32_t
 // cell-wise input in the assembly and its cell-wise output in the row
 // combine.  Keeping those lines out of the Infinity Cache leaves it to the
 // intermediate arrays that are re-read (measured on the Q3 64^3 FP64 step:
-// 286 -> 267 us; other precisions keep cached accesses, their problems are
-// small enough to live in the caches).
+// 286 -> 267 us).  The other precisions keep cached accesses: their arrays
+// are a half or a quarter of the size, and streaming was not measured there.
 template <typename C> __device__ __forceinline__ C load_stream(const double* p) {
     return (C)__builtin_nontemporal_load(p);
 }
